@@ -1,0 +1,204 @@
+/*
+ * khop.h -- C ABI of libkhop.so, an MI355X (gfx950) engine for the k-hop
+ * neighborhood count benchmarked in RedisGraph (Cailliau et al.,
+ * arXiv:1905.01294, Section III: "k-hop neighborhood count", k = 1, 2, 3, 6).
+ *
+ * The count of a seed s at depth k is |{ v : 1 <= dist(s, v) <= k }|, the
+ * number of vertices at hop distance 1..k.  As in the paper's Section II, one
+ * hop is a sparse matrix-vector product of the adjacency matrix with the
+ * frontier over the boolean (OR, AND) semiring, masked by the complement of
+ * the visited set; after l products the visited set is { v : dist(s, v) <= l }.
+ *
+ * Conventions for every entry point:
+ *   - the return value is a status: KHOP_OK (0) or a negative KHOP_E* code;
+ *   - on error, output arguments are left untouched and khop_last_error()
+ *     returns a message (thread local, valid until the thread's next call);
+ *   - no C++ exception crosses this boundary;
+ *   - input arrays are borrowed for the duration of the call only; output
+ *     arrays are owned by the caller;
+ *   - argument validation happens before any device work, so invalid calls
+ *     fail the same way with or without a GPU;
+ *   - a HIP runtime failure maps to KHOP_EDEVICE, a failed device allocation
+ *     to KHOP_ENOMEM.
+ */
+#ifndef KHOP_H
+#define KHOP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct khop_graph khop_graph;   /* opaque; immutable once loaded */
+typedef struct khop_server khop_server; /* opaque */
+
+enum khop_status {
+    KHOP_OK = 0,
+    KHOP_EINVAL = -1,     /* NULL pointer with a nonzero length, bad id, k < 0, bad option */
+    KHOP_ERANGE = -2,     /* a size the engine's index types cannot hold */
+    KHOP_ENOMEM = -3,     /* host or device allocation failed */
+    KHOP_EDEVICE = -4,    /* no usable gfx950 device, or a HIP runtime error */
+    KHOP_EBUSY = -5,      /* the server's request queue is full */
+    KHOP_ETIMEDOUT = -6,  /* a served request passed its deadline before it ran */
+    KHOP_EINTERNAL = -7   /* unexpected internal failure */
+};
+
+/* flags for graph_load_csr */
+enum { KHOP_UNDIRECTED = 0, KHOP_DIRECTED = 1 };
+
+/*
+ * Build the device graph from raw edge tuples (src[i], dst[i]), i < num_edges,
+ * over vertices [0, num_vertices).  The adjacency matrix of the paper's
+ * storage model (Section II: graphs kept as sparse adjacency matrices in a
+ * compressed representation) is built as CSR with int64 row pointers and
+ * int32 column indices, neighbors ascending:
+ *   - self-loops and duplicate tuples are dropped;
+ *   - KHOP_UNDIRECTED stores every tuple in both directions;
+ *   - KHOP_DIRECTED follows tuples from src to dst and also keeps the
+ *     transpose (in-edges) for bottom-up expansion.
+ * src/dst are host pointers (int32, length num_edges).  Errors: NULL with
+ * num_edges > 0, num_vertices <= 0, an endpoint outside [0, num_vertices) or
+ * unknown flags -> KHOP_EINVAL (the whole load is rejected);
+ * num_vertices > INT32_MAX or more than 2^62 arcs -> KHOP_ERANGE.  On success
+ * *out owns the graph until graph_free.
+ */
+int graph_load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, int64_t num_vertices,
+                   uint32_t flags, khop_graph **out);
+
+/* Release a graph and its device memory.  NULL is accepted (KHOP_OK). */
+int graph_free(khop_graph *g);
+
+/* Sizes of a loaded graph: vertices, stored arcs (after cleanup) and directedness. */
+int graph_info(const khop_graph *g, int64_t *num_vertices, int64_t *num_arcs, int32_t *directed);
+
+/* Out-degree of every vertex (stored arcs, self-loops and duplicates dropped) into deg[num_vertices] (host). */
+int graph_degrees(const khop_graph *g, int64_t *deg);
+
+/*
+ * Plain single-query path (the paper's protocol in Section III: seeds run one
+ * after another, each answered by its own count).  For each seeds[i] in order,
+ * one launch sequence computes counts[i] = |{ v : 1 <= dist(seeds[i], v) <= k }|
+ * and, when traversed_edges is not NULL, traversed_edges[i] = the sum of the
+ * out-degrees of the vertices at distance 0..k-1 (the edges a top-down search
+ * inspects; the numerator of TEPS).  Host pointers, length num_seeds.  Each
+ * query is complete (count copied to the host) before the next starts.
+ * Errors: a seed outside [0, n) or k < 0 -> KHOP_EINVAL.  k == 0 gives 0.
+ * num_seeds == 0 is a no-op.  Duplicate seeds give identical answers.
+ */
+int khop_count(khop_graph *g, const int32_t *seeds, int64_t num_seeds, int32_t k, int64_t *counts,
+               int64_t *traversed_edges);
+
+/*
+ * Same computation with device-resident arrays, enqueued on `hip_stream`
+ * (a hipStream_t; NULL means the null stream) without host synchronisation:
+ * d_seeds (int32), d_counts and d_traversed_edges (int64, may be NULL) are
+ * device pointers of length num_seeds.  Seeds are validated on the device:
+ * a seed outside [0, n) yields count -1 and traversed edges -1 for that query.
+ * The caller synchronises the stream before reading the outputs.
+ */
+int khop_count_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
+                   int64_t *d_traversed_edges, void *hip_stream);
+
+/*
+ * Batched multi-source path: seeds travel together as per-vertex 64-bit seed
+ * bitsets, so each hop becomes a boolean sparse matrix - dense bit-matrix
+ * product (OR-accumulate), masked by the complement of each seed's visited
+ * bits.  counts[i] is the k-hop count of seeds[i] at depth ks[i] (mixed k in
+ * one call).  Host pointers of length num_seeds.  Errors as khop_count.
+ */
+int khop_count_batched(khop_graph *g, const int32_t *seeds, const int32_t *ks, int64_t num_seeds,
+                       int64_t *counts);
+
+/* Device-pointer form of khop_count_batched, enqueued on hip_stream without host synchronisation. */
+int khop_count_batched_dev(khop_graph *g, const int32_t *d_seeds, const int32_t *d_ks, int64_t num_seeds,
+                           int64_t *d_counts, void *hip_stream);
+
+/* Engine options (per graph). */
+enum khop_option {
+    KHOP_OPT_DIRECTION = 1,     /* KHOP_DIR_AUTO (default), KHOP_DIR_PUSH or KHOP_DIR_PULL */
+    KHOP_OPT_ALPHA = 2,         /* push -> pull when frontier edges * alpha > unvisited edges */
+    KHOP_OPT_BETA = 3,          /* pull -> push when frontier vertices * beta < n */
+    KHOP_OPT_PULL_LIGHT = 4,    /* bottom-up: degree up to which one lane scans a vertex alone */
+    KHOP_OPT_BATCH_SEEDS = 5,   /* seeds per batched launch: 64, 128, 256, 512 or 1024 */
+    KHOP_OPT_BATCH_HEAVY = 6,   /* batched bottom-up: degree above which a whole wave takes a vertex */
+    KHOP_OPT_BATCH_PUSH = 7     /* batched: frontier-degree fraction (1/x of arcs) under which a level goes top-down */
+};
+enum { KHOP_DIR_AUTO = 0, KHOP_DIR_PUSH = 1, KHOP_DIR_PULL = 2 };
+
+int khop_set_option(khop_graph *g, int32_t option, int64_t value);
+int khop_get_option(const khop_graph *g, int32_t option, int64_t *value);
+
+/*
+ * Autotuner: times candidate settings (direction thresholds, bottom-up lane
+ * threshold, batched seeds per launch and heavy-vertex threshold) on the
+ * resident graph with seeds drawn from its non-isolated vertices, keeps the
+ * fastest, and leaves the graph's options set to it.  seeds_per_launch > 0
+ * restricts the batched search to that batch size.  Results are cached per
+ * (device, graph content hash).
+ */
+int khop_autotune(khop_graph *g, int32_t seeds_per_launch);
+
+/* Per-kernel timing of the engine, measured with HIP events on the stream each kernel runs on. */
+typedef struct {
+    char name[32];
+    int64_t launches;
+    double total_ms;          /* summed event-to-event time of the launches */
+    double algorithmic_bytes; /* summed bytes the launches must move, from the per-unit traffic model */
+} khop_kernel_stat;
+
+/* enable != 0 starts collecting (and clears previous statistics); 0 stops. */
+int khop_profile(khop_graph *g, int32_t enable);
+/* Copy up to max entries of the statistics collected so far; *n_out receives the count. */
+int khop_profile_read(khop_graph *g, khop_kernel_stat *out, int32_t max, int32_t *n_out);
+
+/* ------------------------------------------------------------ serving */
+
+typedef struct {
+    uint64_t ticket;
+    int32_t status;       /* KHOP_OK or KHOP_ETIMEDOUT */
+    int32_t graph_id;
+    int32_t seed;
+    int32_t k;
+    int64_t count;
+    int64_t t_submit_ns;  /* CLOCK_MONOTONIC at submission */
+    int64_t t_admit_ns;   /* when the request's seed bit entered a running batch */
+    int64_t t_done_ns;    /* when its count reached the host */
+} khop_result;
+
+/*
+ * A continuous-batching server for k-hop queries (the throughput-oriented
+ * serving model of the paper's Section II, where a pool of workers answers
+ * concurrent queries).  Graphs stay resident; requests of mixed seed and k are
+ * admitted into free bit slots of running batched traversals at hop
+ * boundaries, while the batch keeps advancing; each graph has its own HIP
+ * stream so work for different graphs overlaps on the device.
+ * mem_budget_bytes bounds the bitset memory of all running batches (each
+ * 64 slots of a graph with n vertices take 3 * 8 * n bytes); requests wait
+ * while no slot fits.  max_batch_seeds (64..1024, a multiple of 64) bounds
+ * the slots of one graph's batch.
+ */
+int khop_server_create(int64_t mem_budget_bytes, int32_t max_batch_seeds, khop_server **out);
+/* Register a loaded graph (borrowed; it must outlive the server). */
+int khop_server_add_graph(khop_server *s, khop_graph *g, int32_t *graph_id);
+/* Queue one query; deadline_ns is an absolute CLOCK_MONOTONIC time, 0 = none. */
+int khop_server_submit(khop_server *s, int32_t graph_id, int32_t seed, int32_t k, int64_t deadline_ns,
+                       uint64_t *ticket);
+/* Move up to max finished results into out (host array); *n_out receives how many. */
+int khop_server_poll(khop_server *s, khop_result *out, int64_t max, int64_t *n_out);
+/* Block until every submitted request has a result (or timeout_ms passes; then KHOP_ETIMEDOUT). */
+int khop_server_drain(khop_server *s, int64_t timeout_ms);
+/* Stop the scheduler; unfinished requests are dropped.  NULL is accepted. */
+int khop_server_destroy(khop_server *s);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *khop_last_error(void);
+
+/* Library version string. */
+const char *khop_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KHOP_H */

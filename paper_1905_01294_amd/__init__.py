@@ -1,0 +1,344 @@
+"""Python binding of libkhop.so, the MI355X k-hop neighborhood-count engine.
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  The functions keep the C names (graph_load_csr, khop_count, ...);
+`Graph` and `Server` wrap them for convenience.  Device arrays are passed as
+torch tensors (device memory and streams only), host arrays as numpy arrays.
+
+The library must be built (`python -m paper_1905_01294_amd.build`); importing
+the binding without it raises ImportError -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkhop.so")
+
+KHOP_OK = 0
+KHOP_EINVAL = -1
+KHOP_ERANGE = -2
+KHOP_ENOMEM = -3
+KHOP_EDEVICE = -4
+KHOP_EBUSY = -5
+KHOP_ETIMEDOUT = -6
+KHOP_EINTERNAL = -7
+STATUS_NAMES = {0: "KHOP_OK", -1: "KHOP_EINVAL", -2: "KHOP_ERANGE", -3: "KHOP_ENOMEM", -4: "KHOP_EDEVICE",
+                -5: "KHOP_EBUSY", -6: "KHOP_ETIMEDOUT", -7: "KHOP_EINTERNAL"}
+
+KHOP_UNDIRECTED = 0
+KHOP_DIRECTED = 1
+
+KHOP_OPT_DIRECTION = 1
+KHOP_OPT_ALPHA = 2
+KHOP_OPT_BETA = 3
+KHOP_OPT_PULL_LIGHT = 4
+KHOP_OPT_BATCH_SEEDS = 5
+KHOP_OPT_BATCH_HEAVY = 6
+KHOP_OPT_BATCH_PUSH = 7
+KHOP_DIR_AUTO = 0
+KHOP_DIR_PUSH = 1
+KHOP_DIR_PULL = 2
+
+# Every entry point declared in include/khop.h.
+EXPORTS = ("graph_load_csr", "graph_free", "graph_info", "graph_degrees", "khop_count", "khop_count_dev",
+           "khop_count_batched", "khop_count_batched_dev", "khop_set_option", "khop_get_option", "khop_autotune",
+           "khop_profile", "khop_profile_read", "khop_server_create", "khop_server_add_graph",
+           "khop_server_submit", "khop_server_poll", "khop_server_drain", "khop_server_destroy",
+           "khop_last_error", "khop_version")
+
+
+class KhopError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("algorithmic_bytes", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("graph_id", ctypes.c_int32),
+                ("seed", ctypes.c_int32), ("k", ctypes.c_int32), ("count", ctypes.c_int64),
+                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+def _share_torch_runtime():
+    """Load PyTorch's HIP runtime first when PyTorch is installed.
+
+    PyTorch ships its own libamdhip64 with the same soname as the system one;
+    whichever is loaded first serves the whole process.  Loading PyTorch's
+    first makes libkhop bind to it too, so device pointers and streams handed
+    over from PyTorch belong to the runtime that launches the kernels."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+
+
+def _load():
+    _share_torch_runtime()
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1905_01294_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "graph_load_csr": ([_i32p, _i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(_vp)],),
+        "graph_free": ([_vp],),
+        "graph_info": ([_vp, _i64p, _i64p, _i32p],),
+        "graph_degrees": ([_vp, _i64p],),
+        "khop_count": ([_vp, _i32p, ctypes.c_int64, ctypes.c_int32, _i64p, _i64p],),
+        "khop_count_dev": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp],),
+        "khop_count_batched": ([_vp, _i32p, _i32p, ctypes.c_int64, _i64p],),
+        "khop_count_batched_dev": ([_vp, _vp, _vp, ctypes.c_int64, _vp, _vp],),
+        "khop_set_option": ([_vp, ctypes.c_int32, ctypes.c_int64],),
+        "khop_get_option": ([_vp, ctypes.c_int32, _i64p],),
+        "khop_autotune": ([_vp, ctypes.c_int32],),
+        "khop_profile": ([_vp, ctypes.c_int32],),
+        "khop_profile_read": ([_vp, ctypes.POINTER(KernelStat), ctypes.c_int32, _i32p],),
+        "khop_server_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_vp)],),
+        "khop_server_add_graph": ([_vp, _vp, _i32p],),
+        "khop_server_submit": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_uint64)],),
+        "khop_server_poll": ([_vp, ctypes.POINTER(Result), ctypes.c_int64, _i64p],),
+        "khop_server_drain": ([_vp, ctypes.c_int64],),
+        "khop_server_destroy": ([_vp],),
+    }
+    for name, (args,) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.khop_last_error.argtypes = []
+    lib.khop_last_error.restype = ctypes.c_char_p
+    lib.khop_version.argtypes = []
+    lib.khop_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def _check(rc: int):
+    if rc != KHOP_OK:
+        raise KhopError(rc, (_lib.khop_last_error() or b"").decode())
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(_i32p)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def _dev_ptr(t, dtype_name):
+    if t is None:
+        return None
+    if not t.is_cuda or str(t.dtype) != dtype_name or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype_name} device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ C-named functions
+
+def khop_version() -> str:
+    return _lib.khop_version().decode()
+
+
+def khop_last_error() -> str:
+    return (_lib.khop_last_error() or b"").decode()
+
+
+def graph_load_csr(src, dst, num_vertices: int, flags: int = KHOP_UNDIRECTED):
+    """Returns an opaque graph handle (ctypes.c_void_p)."""
+    s, sp = _i32(src)
+    d, dp = _i32(dst)
+    if s.shape != d.shape:
+        raise ValueError("src and dst differ in length")
+    h = _vp()
+    _check(_lib.graph_load_csr(sp, dp, s.shape[0], int(num_vertices), int(flags), ctypes.byref(h)))
+    return h
+
+
+def graph_free(h) -> None:
+    _check(_lib.graph_free(h))
+
+
+def graph_info(h):
+    n, m, d = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    _check(_lib.graph_info(h, ctypes.byref(n), ctypes.byref(m), ctypes.byref(d)))
+    return int(n.value), int(m.value), bool(d.value)
+
+
+def graph_degrees(h, n: int) -> np.ndarray:
+    out = np.empty(n, dtype=np.int64)
+    _check(_lib.graph_degrees(h, out.ctypes.data_as(_i64p)))
+    return out
+
+
+def khop_count(h, seeds, k: int, with_te: bool = False):
+    s, sp = _i32(seeds)
+    counts = np.empty(s.shape[0], dtype=np.int64)
+    te = np.empty(s.shape[0], dtype=np.int64) if with_te else None
+    _check(_lib.khop_count(h, sp, s.shape[0], int(k), counts.ctypes.data_as(_i64p),
+                           te.ctypes.data_as(_i64p) if te is not None else None))
+    return (counts, te) if with_te else counts
+
+
+def khop_count_dev(h, d_seeds, k: int, d_counts, d_te=None, stream=None) -> None:
+    n = int(d_seeds.numel())
+    if int(d_counts.numel()) < n or (d_te is not None and int(d_te.numel()) < n):
+        raise ValueError("output tensors shorter than the seed tensor")
+    _check(_lib.khop_count_dev(h, _dev_ptr(d_seeds, "torch.int32"), n, int(k), _dev_ptr(d_counts, "torch.int64"),
+                               _dev_ptr(d_te, "torch.int64"), _stream_ptr(stream)))
+
+
+def khop_count_batched(h, seeds, ks) -> np.ndarray:
+    s, sp = _i32(seeds)
+    kk, kp = _i32(np.broadcast_to(np.asarray(ks, dtype=np.int32), s.shape))
+    counts = np.empty(s.shape[0], dtype=np.int64)
+    _check(_lib.khop_count_batched(h, sp, kp, s.shape[0], counts.ctypes.data_as(_i64p)))
+    return counts
+
+
+def khop_count_batched_dev(h, d_seeds, d_ks, d_counts, stream=None) -> None:
+    n = int(d_seeds.numel())
+    if int(d_ks.numel()) < n or int(d_counts.numel()) < n:
+        raise ValueError("tensors shorter than the seed tensor")
+    _check(_lib.khop_count_batched_dev(h, _dev_ptr(d_seeds, "torch.int32"), _dev_ptr(d_ks, "torch.int32"), n,
+                                       _dev_ptr(d_counts, "torch.int64"), _stream_ptr(stream)))
+
+
+def khop_set_option(h, option: int, value: int) -> None:
+    _check(_lib.khop_set_option(h, int(option), int(value)))
+
+
+def khop_get_option(h, option: int) -> int:
+    v = ctypes.c_int64()
+    _check(_lib.khop_get_option(h, int(option), ctypes.byref(v)))
+    return int(v.value)
+
+
+def khop_autotune(h, seeds_per_launch: int = 0) -> None:
+    _check(_lib.khop_autotune(h, int(seeds_per_launch)))
+
+
+def khop_profile(h, enable: bool) -> None:
+    _check(_lib.khop_profile(h, 1 if enable else 0))
+
+
+def khop_profile_read(h):
+    buf = (KernelStat * 32)()
+    n = ctypes.c_int32()
+    _check(_lib.khop_profile_read(h, buf, 32, ctypes.byref(n)))
+    return {buf[i].name.decode(): {"launches": int(buf[i].launches), "total_ms": float(buf[i].total_ms),
+                                   "algorithmic_bytes": float(buf[i].algorithmic_bytes)} for i in range(n.value)}
+
+
+def khop_server_create(mem_budget_bytes: int, max_batch_seeds: int = 1024):
+    h = _vp()
+    _check(_lib.khop_server_create(int(mem_budget_bytes), int(max_batch_seeds), ctypes.byref(h)))
+    return h
+
+
+def khop_server_add_graph(server, graph) -> int:
+    gid = ctypes.c_int32()
+    _check(_lib.khop_server_add_graph(server, graph, ctypes.byref(gid)))
+    return int(gid.value)
+
+
+def khop_server_submit(server, graph_id: int, seed: int, k: int, deadline_ns: int = 0) -> int:
+    t = ctypes.c_uint64()
+    _check(_lib.khop_server_submit(server, int(graph_id), int(seed), int(k), int(deadline_ns), ctypes.byref(t)))
+    return int(t.value)
+
+
+def khop_server_poll(server, max_results: int = 4096):
+    buf = (Result * max_results)()
+    n = ctypes.c_int64()
+    _check(_lib.khop_server_poll(server, buf, max_results, ctypes.byref(n)))
+    return [buf[i] for i in range(n.value)]
+
+
+def khop_server_drain(server, timeout_ms: int = 60000) -> None:
+    _check(_lib.khop_server_drain(server, int(timeout_ms)))
+
+
+def khop_server_destroy(server) -> None:
+    _check(_lib.khop_server_destroy(server))
+
+
+# ------------------------------------------------------------------ convenience wrappers
+
+class Graph:
+    """A device-resident graph built from raw edge tuples."""
+
+    def __init__(self, src, dst, num_vertices: int, directed: bool = False):
+        self._h = graph_load_csr(src, dst, num_vertices, KHOP_DIRECTED if directed else KHOP_UNDIRECTED)
+        self.n, self.num_arcs, self.directed = graph_info(self._h)
+
+    @classmethod
+    def from_edgelist(cls, el) -> "Graph":
+        return cls(el.src, el.dst, el.n, el.directed)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h is not None:
+            graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def degrees(self) -> np.ndarray:
+        return graph_degrees(self._h, self.n)
+
+    def count(self, seeds, k: int, with_te: bool = False):
+        return khop_count(self._h, seeds, k, with_te)
+
+    def count_dev(self, d_seeds, k: int, d_counts, d_te=None, stream=None):
+        khop_count_dev(self._h, d_seeds, k, d_counts, d_te, stream)
+
+    def count_batched(self, seeds, ks):
+        return khop_count_batched(self._h, seeds, ks)
+
+    def count_batched_dev(self, d_seeds, d_ks, d_counts, stream=None):
+        khop_count_batched_dev(self._h, d_seeds, d_ks, d_counts, stream)
+
+    def set_option(self, option: int, value: int):
+        khop_set_option(self._h, option, value)
+
+    def get_option(self, option: int) -> int:
+        return khop_get_option(self._h, option)
+
+    def autotune(self, seeds_per_launch: int = 0):
+        khop_autotune(self._h, seeds_per_launch)
+
+    def profile(self, enable: bool):
+        khop_profile(self._h, enable)
+
+    def profile_read(self):
+        return khop_profile_read(self._h)

@@ -1,0 +1,492 @@
+// Batched multi-source k-hop count on gfx950.
+//
+// Up to 64*W seeds share one traversal: each vertex carries W 64-bit words
+// of seed bits (vertex-major, word w of vertex v at v*W + w).  A hop is then
+// the boolean product of the paper's Section II with a dense bit matrix in
+// place of the frontier vector,
+//     N[v] = (OR over in-neighbors u of F[u]) AND NOT V[v] AND active_l,
+// where active_l keeps the seeds whose own k is at least l (mixed k in one
+// batch), followed by V |= N, F <- N.
+//   hop 1     top-down from the seeds: a block per seed ORs its bit into the
+//             out-neighbors' words (atomicOr), then `apply` masks by NOT V;
+//   hop >= 2  bottom-up: a group of G lanes (one per active word) per vertex
+//             gathers F[u] over the in-neighbors, stopping as soon as every
+//             still-needed bit of the vertex is found; vertices above the
+//             heavy threshold get a whole wave each (64/G edge streams);
+//   count     per seed column: 64 ballots per 64 vertex words, one lane per
+//             bit accumulating popcounts, minus the seed itself.
+// Seeds arrive sorted by k (largest first), so at hop l only the leading
+// words still hold active seeds and the lane groups shrink with them.
+#include <algorithm>
+
+#include "khop_impl.h"
+#include "wave.h"
+
+namespace khop {
+
+using namespace dev;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+__global__ void __launch_bounds__(kBlock) batch_zero_kernel(uint64_t *a, uint64_t *b, uint64_t *c, int64_t words,
+                                                           int64_t *acc, int64_t nacc, int32_t *flags, int nflags) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride) {
+        a[i] = 0;
+        b[i] = 0;
+        c[i] = 0;
+    }
+    if (blockIdx.x == 0) {
+        for (int64_t i = threadIdx.x; i < nacc; i += kBlock) acc[i] = 0;
+        for (int i = threadIdx.x; i < nflags; i += kBlock) flags[i] = 0;
+    }
+}
+
+// V and F get bit j at seed j.
+__global__ void __launch_bounds__(kBlock) batch_seed_kernel(uint64_t *V, uint64_t *F, const int32_t *seeds,
+                                                           const int32_t *perm, int nslots, int W) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= nslots) return;
+    const int32_t s = seeds[perm[j]];
+    const int64_t at = (int64_t)s * W + (j >> 6);
+    const unsigned long long bit = 1ull << (j & 63);
+    atomicOr((unsigned long long *)&V[at], bit);
+    atomicOr((unsigned long long *)&F[at], bit);
+}
+
+// Hop 1: one block per seed slot with k >= 1 ORs its bit into N of each out-neighbor.
+__global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t *__restrict__ rowptr,
+                                                                 const int32_t *__restrict__ colidx,
+                                                                 const int32_t *seeds, const int32_t *perm,
+                                                                 const int32_t *ks_sorted, int nslots, int W,
+                                                                 uint64_t *N) {
+    for (int j = blockIdx.x; j < nslots; j += gridDim.x) {
+        if (ks_sorted[j] < 1) continue;
+        const int32_t s = seeds[perm[j]];
+        const int64_t b = rowptr[s], e = rowptr[s + 1];
+        const unsigned long long bit = 1ull << (j & 63);
+        const int w = j >> 6;
+        for (int64_t x = b + threadIdx.x; x < e; x += kBlock) {
+            const int32_t v = colidx[x];
+            atomicOr((unsigned long long *)&N[(int64_t)v * W + w], bit);
+        }
+    }
+}
+
+// After hop 1: x = N AND NOT V AND active; V |= x; F = x; N = 0.
+__global__ void __launch_bounds__(kBlock) batch_apply_kernel(uint64_t *V, uint64_t *F, uint64_t *N, int64_t n,
+                                                            int W, const uint64_t *act, int32_t *flag) {
+    const int64_t total = n * W;
+    bool any = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const uint64_t nv = N[i];
+        const uint64_t x = nv & ~V[i] & act[i % W];
+        if (x) {
+            V[i] |= x;
+            any = true;
+        }
+        F[i] = x;
+        if (nv) N[i] = 0;
+    }
+    if (ballot(any) && lane_id() == 0) atomicOr(flag, 1);
+}
+
+// Hop >= 2, light vertices: G lanes per vertex (lane word = lane % G).
+template <int G>
+__global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__restrict__ in_rowptr,
+                                                           const int32_t *__restrict__ in_colidx,
+                                                           uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
+                                                           uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
+                                                           const uint64_t *__restrict__ act, int heavy,
+                                                           const int32_t *prev_flag, int32_t *flag,
+                                                           int64_t *units) {
+    if (*prev_flag == 0) return;  // empty frontier: nothing left to find
+    constexpr int VPW = kWave / G;  // vertices per wave
+    const int lane = lane_id();
+    const int grp = lane / G;
+    const int wi = lane % G;
+    const uint64_t grp_bits = (G == 64) ? ~0ull : (((1ull << G) - 1) << (grp * G));
+    const uint64_t actw = wi < wact ? act[wi] : 0ull;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    bool any = false;
+    int64_t examined = 0, scanned = 0;
+    for (int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; wv * VPW < n; wv += nwaves) {
+        const int64_t v = wv * VPW + grp;
+        const bool valid = v < n && wi < wact;
+        const int64_t at = v * W + wi;
+        uint64_t need = 0;
+        int64_t b = 0, e = 0;
+        if (valid) {
+            need = ~V[at] & actw;
+        }
+        // the group works on v only if some lane still needs a bit
+        const bool grp_need = (ballot(need != 0) & grp_bits) != 0;
+        if (grp_need && v < n) {
+            b = in_rowptr[v];
+            e = in_rowptr[v + 1];
+            if (e - b > heavy) e = b;  // the heavy kernel takes it
+        }
+        uint64_t acc = 0;
+        bool active = grp_need && (e > b);
+        if (grp_need && e - b > 0) scanned += (wi == 0);
+        int64_t x = b;
+        while (true) {
+            const bool done_lane = (acc & need) == need;
+            const uint64_t dm = ballot(!active || done_lane);
+            if ((dm & grp_bits) == grp_bits) active = false;
+            if (!ballot(active)) break;
+            if (active) {
+                // up to 4 in-neighbors per round
+                const int64_t r = std::min<int64_t>(4, e - x);
+                const int32_t u0 = in_colidx[x];
+                const int32_t u1 = r > 1 ? in_colidx[x + 1] : u0;
+                const int32_t u2 = r > 2 ? in_colidx[x + 2] : u0;
+                const int32_t u3 = r > 3 ? in_colidx[x + 3] : u0;
+                if (wi < wact) {
+                    acc |= F[(int64_t)u0 * W + wi] | F[(int64_t)u1 * W + wi] | F[(int64_t)u2 * W + wi] |
+                           F[(int64_t)u3 * W + wi];
+                }
+                if (wi == 0) examined += r;
+                x += r;
+                if (x >= e) active = false;
+            }
+        }
+        if (valid && grp_need) {
+            const uint64_t nx = acc & need;
+            Fn[at] = nx;
+            if (nx) {
+                V[at] |= nx;
+                any = true;
+            }
+        } else if (valid) {
+            Fn[at] = 0;
+        }
+    }
+    if (ballot(any) && lane == 0) atomicOr(flag, 1);
+    if (units) {
+        const int64_t ex = wave_sum(examined), sc = wave_sum(scanned);
+        if (lane == 0 && (ex | sc)) {
+            atomicAdd((unsigned long long *)&units[1], (unsigned long long)ex);
+            atomicAdd((unsigned long long *)&units[2], (unsigned long long)sc);
+        }
+    }
+}
+
+template <int G>
+__device__ __forceinline__ uint64_t subgroup_or(uint64_t v) {
+#pragma unroll
+    for (int off = G; off < kWave; off <<= 1) v |= (uint64_t)__shfl_xor((long long)v, off, kWave);
+    return v;
+}
+
+// Hop >= 2, heavy vertices: one wave per vertex, 64/G interleaved edge streams.
+template <int G>
+__global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
+    const int64_t *__restrict__ in_rowptr, const int32_t *__restrict__ in_colidx, uint64_t *__restrict__ V,
+    const uint64_t *__restrict__ F, uint64_t *__restrict__ Fn, int W, int wact, const uint64_t *__restrict__ act,
+    const int32_t *__restrict__ heavy_list, int64_t n_heavy, const int32_t *prev_flag, int32_t *flag,
+    int64_t *units) {
+    if (*prev_flag == 0) return;
+    constexpr int S = kWave / G;  // edge streams
+    const int lane = lane_id();
+    const int wi = lane % G;
+    const int sg = lane / G;
+    const uint64_t actw = wi < wact ? act[wi] : 0ull;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    bool any = false;
+    int64_t examined = 0;
+    for (int64_t h = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; h < n_heavy; h += nwaves) {
+        const int64_t v = heavy_list[h];
+        const int64_t at = v * W + wi;
+        const uint64_t need = wi < wact ? (~V[at] & actw) : 0ull;
+        if (!ballot(need != 0)) {
+            if (sg == 0 && wi < wact) Fn[at] = 0;
+            continue;
+        }
+        const int64_t b = in_rowptr[v], e = in_rowptr[v + 1];
+        uint64_t acc = 0;
+        for (int64_t x0 = b; x0 < e; x0 += 4 * S) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t x = x0 + r * S + sg;
+                if (x < e && wi < wact) acc |= F[(int64_t)in_colidx[x] * W + wi];
+            }
+            examined += std::min<int64_t>(4 * S, e - x0);
+            const uint64_t full = subgroup_or<G>(acc);
+            if (!ballot((full & need) != need)) break;
+        }
+        acc = subgroup_or<G>(acc);
+        if (sg == 0 && wi < wact) {
+            const uint64_t nx = acc & need;
+            Fn[at] = nx;
+            if (nx) {
+                V[at] |= nx;
+                any = true;
+            }
+        }
+    }
+    if (ballot(any) && lane == 0) atomicOr(flag, 1);
+    if (units && lane == 0 && examined) {
+        atomicAdd((unsigned long long *)&units[1], (unsigned long long)examined);
+    }
+}
+
+// counts_acc[w*64 + bit] += number of vertices whose word w has that bit.
+__global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__restrict__ V, int64_t n, int W,
+                                                            int64_t *counts_acc) {
+    const int w = blockIdx.y;
+    const int lane = lane_id();
+    __shared__ int64_t s_acc[kWavesPerBlock][kWave];
+    int64_t acc = 0;
+    const int64_t nchunks = (n + kWave - 1) / kWave;
+    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c < nchunks;
+         c += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int64_t v = c * kWave + lane;
+        const uint64_t x = v < n ? V[v * W + w] : 0ull;
+        if (!ballot(x != 0)) continue;
+#pragma unroll 8
+        for (int bit = 0; bit < kWave; ++bit) {
+            const int cnt = __popcll(ballot((x >> bit) & 1ull));
+            if (lane == bit) acc += cnt;
+        }
+    }
+    s_acc[threadIdx.x / kWave][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        int64_t t = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += s_acc[i][threadIdx.x];
+        if (t) atomicAdd((unsigned long long *)&counts_acc[w * kWave + threadIdx.x], (unsigned long long)t);
+    }
+}
+
+__global__ void batch_output_kernel(const int64_t *counts_acc, const int32_t *perm, int nslots, int64_t *out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nslots) out[perm[j]] = counts_acc[j] - 1;
+}
+
+}  // namespace
+
+struct BatchCtx {
+    khop_graph *g = nullptr;
+    int W = 0;  // words per vertex (power of two)
+    uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
+    int64_t *acc = nullptr;    // 64 * W counters
+    uint64_t *act = nullptr;   // kMaxLevels * W active masks
+    int32_t *flags = nullptr;  // kMaxLevels + 1 frontier-nonempty flags
+    int32_t *perm = nullptr;   // slot -> caller index
+    int32_t *ks = nullptr;     // k per slot (sorted)
+    void *arena = nullptr;
+    // pinned staging of the per-batch tables, reusable once stage_ev has fired
+    uint64_t *h_act = nullptr;
+    int32_t *h_perm = nullptr;
+    int32_t *h_ks = nullptr;
+    void *h_arena = nullptr;
+    hipEvent_t stage_ev = nullptr;
+    static constexpr int kMaxLevels = 4096;
+};
+
+BatchCtx *batch_ctx_create(khop_graph *g, int words) {
+    BatchCtx *c = new BatchCtx();
+    c->g = g;
+    c->W = words;
+    const int64_t n = g->n;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t bits = al((size_t)n * words * 8);
+    size_t off = 0;
+    const size_t oV = off;
+    off += bits;
+    const size_t oF = off;
+    off += bits;
+    const size_t oN = off;
+    off += bits;
+    const size_t oacc = off;
+    off += al(64 * (size_t)words * 8);
+    const size_t oact = off;
+    off += al((size_t)BatchCtx::kMaxLevels * words * 8);
+    const size_t oflags = off;
+    off += al((BatchCtx::kMaxLevels + 1) * 4);
+    const size_t operm = off;
+    off += al(64 * (size_t)words * 4);
+    const size_t oks = off;
+    off += al(64 * (size_t)words * 4);
+    hipError_t e = hipMalloc(&c->arena, off);
+    if (e != hipSuccess) {
+        delete c;
+        (void)hipGetLastError();
+        fail(KHOP_ENOMEM, "device allocation of " + std::to_string(off) + " bytes for a batch context failed");
+    }
+    char *b = (char *)c->arena;
+    c->V = (uint64_t *)(b + oV);
+    c->F = (uint64_t *)(b + oF);
+    c->N = (uint64_t *)(b + oN);
+    c->acc = (int64_t *)(b + oacc);
+    c->act = (uint64_t *)(b + oact);
+    c->flags = (int32_t *)(b + oflags);
+    c->perm = (int32_t *)(b + operm);
+    c->ks = (int32_t *)(b + oks);
+    const size_t hbytes = (size_t)BatchCtx::kMaxLevels * words * 8 + 2 * 64 * (size_t)words * 4;
+    if (hipHostMalloc(&c->h_arena, hbytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(c->arena);
+        delete c;
+        fail(KHOP_ENOMEM, "pinned host allocation for a batch context failed");
+    }
+    c->h_act = (uint64_t *)c->h_arena;
+    c->h_perm = (int32_t *)(c->h_act + (size_t)BatchCtx::kMaxLevels * words);
+    c->h_ks = c->h_perm + 64 * words;
+    KHOP_HIP(hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming));
+    KHOP_HIP(hipEventRecord(c->stage_ev, nullptr));
+    return c;
+}
+
+void batch_ctx_destroy(BatchCtx *c) {
+    if (!c) return;
+    if (c->stage_ev) {
+        (void)hipEventSynchronize(c->stage_ev);
+        (void)hipEventDestroy(c->stage_ev);
+    }
+    if (c->h_arena) (void)hipHostFree(c->h_arena);
+    if (c->arena) (void)hipFree(c->arena);
+    delete c;
+}
+
+int batch_ctx_words(const BatchCtx *c) { return c->W; }
+
+void ensure_heavy_list(khop_graph *g, hipStream_t st) {
+    const int thr = g->params.batch_heavy;
+    if (g->heavy_threshold == thr && (g->d_heavy || g->n_heavy == 0)) return;
+    std::vector<int32_t> hv;
+    for (int64_t v = 0; v < g->n; ++v)
+        if (g->h_indeg[v] > thr) hv.push_back((int32_t)v);
+    if (g->d_heavy) {
+        KHOP_HIP(hipStreamSynchronize(st));
+        KHOP_HIP(hipFree(g->d_heavy));
+        g->d_heavy = nullptr;
+    }
+    g->n_heavy = (int64_t)hv.size();
+    if (!hv.empty()) {
+        if (hipMalloc(&g->d_heavy, hv.size() * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(KHOP_ENOMEM, "device allocation for the heavy-vertex list failed");
+        }
+        KHOP_HIP(hipMemcpy(g->d_heavy, hv.data(), hv.size() * 4, hipMemcpyHostToDevice));
+    }
+    g->heavy_threshold = thr;
+}
+
+template <int G>
+static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, hipStream_t st, uint64_t *F, uint64_t *Fn) {
+    const int64_t n = g->n;
+    const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
+                                                                 (int64_t)g->cu_count * 16));
+    const uint64_t *act = c->act + (int64_t)(L - 1) * c->W;
+    {
+        ProfScope ps(g, KK_BATCH_PULL, st);
+        hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx,
+                           c->V, F, Fn, n, c->W, wact, act, g->params.batch_heavy, c->flags + (L - 1),
+                           c->flags + L, ps.units());
+        // bytes: 4 per examined edge + 8 per gathered word, 16 per scanned vertex, V/F/Fn words
+        ps.end(3.0 * 8.0 * (double)n * wact, 0, 4.0 + 8.0 * wact, 16.0);
+    }
+    if (g->n_heavy > 0) {
+        const int hgrid = (int)std::max<int64_t>(
+            1, std::min<int64_t>((g->n_heavy + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
+        ProfScope ps(g, KK_BATCH_PULL_HEAVY, st);
+        hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_rowptr,
+                           g->d_in_colidx, c->V, F, Fn, c->W, wact, act, g->d_heavy, g->n_heavy,
+                           c->flags + (L - 1), c->flags + L, ps.units());
+        ps.end(16.0 * (double)g->n_heavy, 0, 4.0 + 8.0 * wact);
+    }
+}
+
+void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
+               const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st) {
+    const int W = c->W;
+    const int nslots = (int)num_seeds;
+    const int64_t n = g->n;
+    int kmax = 0;
+    for (int j = 0; j < nslots; ++j) kmax = std::max(kmax, h_ks_sorted[j]);
+    const int levels = (int)std::min<int64_t>(kmax, std::min<int64_t>(n, BatchCtx::kMaxLevels - 1));
+    // the staging buffer may still feed the previous batch's copies
+    KHOP_HIP(hipEventSynchronize(c->stage_ev));
+    // active masks and active word counts per level
+    uint64_t *act = c->h_act;
+    std::fill(act, act + (size_t)std::max(levels, 1) * W, 0ull);
+    std::vector<int> wact(std::max(levels, 1) + 1, 0);
+    for (int L = 1; L <= levels; ++L) {
+        for (int j = 0; j < nslots; ++j)
+            if (h_ks_sorted[j] >= L) {
+                act[(size_t)(L - 1) * W + (j >> 6)] |= 1ull << (j & 63);
+                wact[L] = std::max(wact[L], (j >> 6) + 1);
+            }
+    }
+    std::copy(h_perm, h_perm + nslots, c->h_perm);
+    std::copy(h_ks_sorted, h_ks_sorted + nslots, c->h_ks);
+    if (levels > 0)
+        KHOP_HIP(hipMemcpyAsync(c->act, act, (size_t)levels * W * 8, hipMemcpyHostToDevice, st));
+    KHOP_HIP(hipMemcpyAsync(c->perm, c->h_perm, (size_t)nslots * 4, hipMemcpyHostToDevice, st));
+    KHOP_HIP(hipMemcpyAsync(c->ks, c->h_ks, (size_t)nslots * 4, hipMemcpyHostToDevice, st));
+    KHOP_HIP(hipEventRecord(c->stage_ev, st));
+    const int zgrid = (int)std::min<int64_t>(((int64_t)n * W + kBlock - 1) / kBlock, (int64_t)g->cu_count * 8);
+    {
+        ProfScope ps(g, KK_BATCH_INIT, st);
+        hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, c->F, c->N,
+                           (int64_t)n * W, c->acc, (int64_t)64 * W, c->flags, levels + 1);
+        ps.end(3.0 * 8.0 * n * W);
+    }
+    hipLaunchKernelGGL(batch_seed_kernel, dim3((nslots + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->V, c->F,
+                       d_seeds, c->perm, nslots, W);
+    uint64_t *F = c->F, *Nb = c->N;
+    if (levels >= 1) {
+        {
+            ProfScope ps(g, KK_BATCH_PUSH, st);
+            hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots, 4096)), dim3(kBlock), 0, st,
+                               g->d_rowptr, g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, Nb);
+            ps.end(0);
+        }
+        {
+            ProfScope ps(g, KK_BATCH_APPLY, st);
+            hipLaunchKernelGGL(batch_apply_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, F, Nb, n,
+                               W, c->act, c->flags + 1);
+            ps.end(4.0 * 8.0 * n * W);
+        }
+        ensure_heavy_list(g, st);
+    }
+    for (int L = 2; L <= levels; ++L) {
+        const int wa = wact[L];
+        if (wa == 0) break;
+        int G = 1;
+        while (G < wa) G <<= 1;
+        switch (G) {
+            case 1: launch_pull<1>(g, c, L, wa, st, F, Nb); break;
+            case 2: launch_pull<2>(g, c, L, wa, st, F, Nb); break;
+            case 4: launch_pull<4>(g, c, L, wa, st, F, Nb); break;
+            case 8: launch_pull<8>(g, c, L, wa, st, F, Nb); break;
+            default: launch_pull<16>(g, c, L, wa, st, F, Nb); break;
+        }
+        std::swap(F, Nb);
+        if ((L % 8) == 0 && L < levels) {
+            // long traversals: stop once the frontier is empty
+            int32_t flag = 1;
+            KHOP_HIP(hipMemcpyAsync(&flag, c->flags + L, 4, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipStreamSynchronize(st));
+            if (!flag) break;
+        }
+    }
+    {
+        ProfScope ps(g, KK_BATCH_COUNT, st);
+        const int cgx = (int)std::max<int64_t>(1, std::min<int64_t>((n + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock),
+                                                                     (int64_t)g->cu_count * 2));
+        hipLaunchKernelGGL(batch_count_kernel, dim3(cgx, W), dim3(kBlock), 0, st, c->V, n, W, c->acc);
+        ps.end(8.0 * n * W);
+    }
+    hipLaunchKernelGGL(batch_output_kernel, dim3((nslots + 255) / 256), dim3(256), 0, st, c->acc, c->perm, nslots,
+                       d_counts);
+    KHOP_HIP(hipGetLastError());
+}
+
+}  // namespace khop

@@ -1,0 +1,168 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "khop.h"
+
+namespace khop {
+
+// Thrown inside the library, mapped to a status at the C boundary.
+struct Error {
+    int status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int status, const std::string &msg);
+[[noreturn]] void hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define KHOP_HIP(call)                                                  \
+    do {                                                                \
+        hipError_t e_ = (call);                                         \
+        if (e_ != hipSuccess) ::khop::hip_fail(e_, #call, __FILE__, __LINE__); \
+    } while (0)
+
+// Host-side CSR produced by the graph builder.
+struct HostCSR {
+    int64_t n = 0;
+    std::vector<int64_t> rowptr;  // n + 1
+    std::vector<int32_t> colidx;  // rowptr[n]
+};
+
+// Arcs a[i] -> b[i] (plus b[i] -> a[i] when `both`), self-loops and duplicates
+// dropped, neighbors ascending.
+HostCSR build_csr(const int32_t *a, const int32_t *b, int64_t m, int64_t n, bool both);
+uint64_t csr_hash(const HostCSR &c);
+int host_threads();
+
+// Tunable engine parameters (per graph).
+struct Params {
+    int dir_mode = KHOP_DIR_AUTO;
+    int alpha = 14;        // push -> pull when mf * alpha > mu
+    int beta = 24;         // pull -> push when nf * beta < n
+    int pull_light = 32;   // plain bottom-up: lane-serial scan up to this degree
+    int words_per_block = 16;  // plain compaction / bottom-up word range per block
+    int batch_seeds = 1024;    // batched: seeds per launch (64 * words)
+    int batch_heavy = 256;     // batched bottom-up: wave-per-vertex above this in-degree
+    int batch_push_div = 64;   // batched: top-down level when frontier arcs * div < total arcs
+};
+
+struct PlainCtx;
+struct BatchCtx;
+
+// A pooled context remembers the stream and completion event of its last use.
+struct CtxUse {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+enum KernelKind {
+    KK_PLAIN_INIT = 0,
+    KK_PLAIN_EXPAND,
+    KK_PLAIN_COMPACT,
+    KK_PLAIN_QUEUE,
+    KK_BATCH_INIT,
+    KK_BATCH_PUSH,
+    KK_BATCH_APPLY,
+    KK_BATCH_PULL,
+    KK_BATCH_PULL_HEAVY,
+    KK_BATCH_COUNT,
+    KK_COUNT_KINDS
+};
+extern const char *const kKernelNames[KK_COUNT_KINDS];
+
+// Per-kernel profiling with HIP events.  Each profiled launch may also own a
+// slot of 4 int64 device counters that the kernel fills with the sizes its
+// traffic depends on (edges examined, frontier size, ...).
+struct Profiler {
+    bool on = false;
+    int64_t *d_units = nullptr;  // cap * 4
+    int64_t cap = 0;
+    int64_t next_slot = 0;
+    struct Pending {
+        int kind;
+        hipEvent_t e0, e1;
+        double fixed_bytes;
+        int64_t slot;
+        double w[4];
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> events;
+    int64_t launches[KK_COUNT_KINDS] = {};
+    double ms[KK_COUNT_KINDS] = {};
+    double bytes[KK_COUNT_KINDS] = {};
+};
+
+// Brackets one kernel launch with HIP events when profiling is on.
+class ProfScope {
+   public:
+    ProfScope(khop_graph *g, int kind, hipStream_t st);
+    // Device counter slot for the kernel (-1 when not profiling).
+    int64_t *units() const { return units_; }
+    // bytes = fixed + sum_i w[i] * units[i]
+    void end(double fixed_bytes, double w0 = 0, double w1 = 0, double w2 = 0, double w3 = 0);
+
+   private:
+    khop_graph *g_;
+    int kind_;
+    hipStream_t st_;
+    hipEvent_t e0_ = nullptr;
+    int64_t slot_ = -1;
+    int64_t *units_ = nullptr;
+};
+
+void prof_collect(khop_graph *g);  // caller holds g->mu
+
+}  // namespace khop
+
+struct khop_graph {
+    int device = 0;
+    int64_t n = 0;
+    int64_t nnz = 0;  // stored arcs (out)
+    int directed = 0;
+    int64_t *d_rowptr = nullptr;
+    int32_t *d_colidx = nullptr;
+    int64_t *d_in_rowptr = nullptr;  // == d_rowptr when undirected
+    int32_t *d_in_colidx = nullptr;
+    int32_t *d_heavy = nullptr;      // vertices with in-degree > params.batch_heavy, ascending
+    int64_t n_heavy = 0;
+    int heavy_threshold = -1;        // threshold d_heavy was built for
+    std::vector<int64_t> h_outdeg;   // host copy of out-degrees
+    std::vector<int64_t> h_indeg;
+    uint64_t hash = 0;
+    khop::Params params;
+    hipStream_t stream = nullptr;    // stream of the host-pointer entry points
+    std::mutex mu;                   // guards the context pools, heavy list and profiler
+    std::vector<khop::PlainCtx *> plain_free;
+    std::vector<khop::BatchCtx *> batch_free;
+    std::mutex prof_mu;
+    khop::Profiler prof;
+    int cu_count = 256;
+};
+
+namespace khop {
+
+// plain.hip
+PlainCtx *plain_ctx_create(khop_graph *g);
+void plain_ctx_destroy(PlainCtx *c);
+void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k,
+               int64_t *d_counts, int64_t *d_te, hipStream_t st);
+void plain_fill_zero_outputs(int64_t *d_counts, int64_t *d_te, int64_t n, hipStream_t st);
+
+// batched.hip
+BatchCtx *batch_ctx_create(khop_graph *g, int words);
+void batch_ctx_destroy(BatchCtx *c);
+int batch_ctx_words(const BatchCtx *c);
+// Runs one batch of at most 64 * words seeds.  Slot j is seed d_seeds[h_perm[j]]
+// at depth h_ks_sorted[j] (non-increasing in j); its count goes to d_counts[h_perm[j]].
+void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
+               const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st);
+void ensure_heavy_list(khop_graph *g, hipStream_t st);
+
+}  // namespace khop

@@ -1,0 +1,219 @@
+"""GPU parity of the plain single-query path against the CPU oracle (bit exact).
+
+Counts are integers, so the bar is equality, for every seed, at every k, in
+every direction mode (auto, forced top-down, forced bottom-up); the traversed-
+edge credit must match the oracle's too."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import graphs
+
+pytestmark = pytest.mark.gpu
+
+KS = (1, 2, 3, 6)
+MODES = ("auto", "push", "pull")
+
+
+def _say(*a):
+    print("[gpu-plain]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def K():
+    import paper_1905_01294_amd as K
+    return K
+
+
+def _set_mode(K, g, mode):
+    g.set_option(K.KHOP_OPT_DIRECTION, {"auto": K.KHOP_DIR_AUTO, "push": K.KHOP_DIR_PUSH,
+                                        "pull": K.KHOP_DIR_PULL}[mode])
+
+
+@pytest.fixture(scope="module")
+def g0_gpu(K, g0):
+    el, _ = g0
+    return K.Graph.from_edgelist(el)
+
+
+def test_g0_graph_shape(K, g0, g0_gpu, g0_oracle):
+    el, _ = g0
+    assert g0_gpu.n == el.n
+    assert g0_gpu.num_arcs == g0_oracle.num_arcs
+    assert np.array_equal(g0_gpu.degrees(), g0_oracle.degrees())
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_g0_all_seeds(K, g0, g0_gpu, g0_oracle, mode):
+    el, seeds = g0
+    _set_mode(K, g0_gpu, mode)
+    for k in KS:
+        _say("g0 32 seeds", mode, "k", k)
+        c, te = g0_gpu.count(seeds, k, with_te=True)
+        oc, ote = g0_oracle.count(seeds, k)
+        assert np.array_equal(c, oc), (mode, k)
+        assert np.array_equal(te, ote), (mode, k)
+    _set_mode(K, g0_gpu, "auto")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_g0_every_nonisolated_vertex_dev(K, g0_gpu, g0_oracle, mode):
+    import torch
+    seeds = np.nonzero(g0_oracle.degrees() > 0)[0].astype(np.int32)
+    _set_mode(K, g0_gpu, mode)
+    d_seeds = torch.from_numpy(seeds).cuda()
+    for k in KS:
+        _say("g0 every vertex dev", mode, "k", k, "seeds", len(seeds))
+        d_c = torch.empty(len(seeds), dtype=torch.int64, device="cuda")
+        d_t = torch.empty(len(seeds), dtype=torch.int64, device="cuda")
+        g0_gpu.count_dev(d_seeds, k, d_c, d_t)
+        torch.cuda.synchronize()
+        oc, ote = g0_oracle.count(seeds, k)
+        assert np.array_equal(d_c.cpu().numpy(), oc), (mode, k)
+        assert np.array_equal(d_t.cpu().numpy(), ote), (mode, k)
+    _set_mode(K, g0_gpu, "auto")
+
+
+def test_g0_regression_fixture(K, g0_gpu):
+    import json
+    import os
+    fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "g0_rmat10_counts.json")))
+    seeds = np.array(fx["seeds"], np.int32)
+    for k, row in fx["counts"].items():
+        c, te = g0_gpu.count(seeds, int(k), with_te=True)
+        assert c.tolist() == row and te.tolist() == fx["te"][k]
+
+
+CLOSED = [
+    ("path", graphs.path(70), lambda n, s, k: min(k, s) + min(k, n - 1 - s)),
+    ("cycle", graphs.cycle(131), lambda n, s, k: min(2 * k, n - 1)),
+    ("star", graphs.star(200), lambda n, s, k: (n - 1) * (k >= 1) if s == 0 else (k >= 1) + (n - 2) * (k >= 2)),
+    ("complete", graphs.complete(65), lambda n, s, k: (n - 1) * (k >= 1)),
+    ("dpath", graphs.path(100, directed=True), lambda n, s, k: min(k, n - 1 - s)),
+    ("dcycle", graphs.cycle(129, directed=True), lambda n, s, k: min(k, n - 1)),
+]
+
+
+@pytest.mark.parametrize("name,gr,f", CLOSED, ids=[c[0] for c in CLOSED])
+@pytest.mark.parametrize("mode", MODES)
+def test_closed_forms(K, name, gr, f, mode):
+    src, dst, n, d = gr
+    g = K.Graph(src, dst, n, d)
+    _set_mode(K, g, mode)
+    seeds = np.array(sorted({0, 1, n // 2, n - 2, n - 1}), np.int32)
+    for k in (0, 1, 2, 3, 6, 40, 200):
+        _say(name, mode, "k", k)
+        c = g.count(seeds, k)
+        assert c.tolist() == [f(n, int(s), k) for s in seeds], (name, mode, k)
+    g.free()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_random_graphs_against_oracle(K, mode):
+    rng = np.random.default_rng(2024)
+    for trial in range(12):
+        n = int(rng.integers(1, 700))
+        m = int(rng.integers(0, 4 * n + 1))
+        directed = bool(trial % 2)
+        src, dst, n, d = graphs.random_graph(rng, n, m, directed)
+        _say("random", mode, trial, n, m, directed)
+        g = K.Graph(src, dst, n, d)
+        _set_mode(K, g, mode)
+        og = oracle.OracleGraph(src, dst, n, d)
+        seeds = rng.integers(0, n, size=min(n, 24)).astype(np.int32)
+        for k in (1, 2, 3, 6, 1000):
+            c, te = g.count(seeds, k, with_te=True)
+            oc, ote = og.count(seeds, k)
+            assert np.array_equal(c, oc) and np.array_equal(te, ote), (trial, mode, k)
+        g.free()
+
+
+def test_edge_cases(K):
+    # one vertex, no edges
+    g = K.Graph(np.zeros(0, np.int32), np.zeros(0, np.int32), 1)
+    assert g.count(np.array([0], np.int32), 3).tolist() == [0]
+    assert g.count(np.zeros(0, np.int32), 3).tolist() == []
+    g.free()
+    # isolated seed and the last vertex of a ragged final word
+    src, dst = np.array([0, 1, 2], np.int32), np.array([1, 2, 99], np.int32)
+    g = K.Graph(src, dst, 100)
+    assert g.count(np.array([50, 99, 0], np.int32), 6).tolist() == [0, 3, 3]
+    assert g.count(np.array([99], np.int32), 0).tolist() == [0]
+    # duplicate seeds answer identically
+    assert g.count(np.array([1, 1, 1], np.int32), 1).tolist() == [2, 2, 2]
+    with pytest.raises(K.KhopError) as ei:
+        g.count(np.array([100], np.int32), 1)
+    assert ei.value.status == K.KHOP_EINVAL
+    with pytest.raises(K.KhopError):
+        g.count(np.array([0], np.int32), -1)
+    g.free()
+
+
+def test_device_path_marks_bad_seed(K):
+    import torch
+    g = K.Graph(np.array([0], np.int32), np.array([1], np.int32), 3)
+    d_s = torch.tensor([0, 7, 1, -1], dtype=torch.int32, device="cuda")
+    d_c = torch.zeros(4, dtype=torch.int64, device="cuda")
+    g.count_dev(d_s, 2, d_c)
+    torch.cuda.synchronize()
+    assert d_c.cpu().tolist() == [1, -1, 1, -1]
+    g.free()
+
+
+def test_input_invariance(K, g0, g0_oracle):
+    el, seeds = g0
+    rng = np.random.default_rng(3)
+    order = rng.permutation(el.m)
+    dup = rng.integers(0, el.m, size=el.m // 2)
+    loops = rng.integers(0, el.n, size=300).astype(np.int32)
+    g2 = K.Graph(np.concatenate([el.src[order], el.src[dup], loops]),
+                 np.concatenate([el.dst[order], el.dst[dup], loops]), el.n)
+    perm = graphgen.permutation(el.n, seed=5, tag=9)
+    g3 = K.Graph(perm[el.src], perm[el.dst], el.n)
+    for k in KS:
+        oc, _ = g0_oracle.count(seeds, k)
+        assert np.array_equal(g2.count(seeds, k), oc)
+        assert np.array_equal(g3.count(perm[seeds], k), oc)
+    g2.free()
+    g3.free()
+
+
+def test_repeat_runs_bit_identical(K, g0_gpu, g0):
+    _, seeds = g0
+    first = [g0_gpu.count(seeds, k) for k in KS]
+    for _ in range(20):
+        for k, ref in zip(KS, first):
+            assert np.array_equal(g0_gpu.count(seeds, k), ref)
+
+
+def test_directed_power_law_small(K):
+    el = graphgen.chung_lu(60_000, 900_000, 6.0, seed=4)
+    g = K.Graph.from_edgelist(el)
+    og = oracle.OracleGraph.from_edgelist(el)
+    seeds = graphgen.draw_seeds(el, 40, seed=1)
+    for mode in MODES:
+        _set_mode(K, g, mode)
+        for k in KS:
+            _say("chung-lu 60k", mode, k)
+            c, te = g.count(seeds, k, with_te=True)
+            oc, ote = og.count(seeds, k)
+            assert np.array_equal(c, oc) and np.array_equal(te, ote), (mode, k)
+    g.free()
+
+
+def test_torch_side_stream(K, g0, g0_gpu, g0_oracle):
+    """Device tensors and a non-default stream from PyTorch drive the library directly."""
+    import torch
+    _, seeds = g0
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d_seeds = torch.from_numpy(seeds).cuda()
+        d_c = torch.empty(len(seeds), dtype=torch.int64, device="cuda")
+        g0_gpu.count_dev(d_seeds, 3, d_c, stream=s)
+        d_b = torch.empty(len(seeds), dtype=torch.int64, device="cuda")
+        g0_gpu.count_batched_dev(d_seeds, torch.full_like(d_seeds, 3), d_b, stream=s)
+    s.synchronize()
+    expect = g0_oracle.count(seeds, 3)[0]
+    assert np.array_equal(d_c.cpu().numpy(), expect)
+    assert np.array_equal(d_b.cpu().numpy(), expect)
