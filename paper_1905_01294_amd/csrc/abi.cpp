@@ -22,7 +22,7 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line) {
 }
 
 const char *const kKernelNames[KK_COUNT_KINDS] = {
-    "plain_init", "plain_expand", "plain_compact", "plain_queue", "batch_init",
+    "plain_init", "plain_expand", "plain_count", "plain_finish", "plain_pull_heavy", "batch_init",
     "batch_push", "batch_apply",  "batch_pull",    "batch_pull_heavy", "batch_count"};
 
 template <class F>
@@ -434,7 +434,7 @@ int graph_free(khop_graph *g) {
         if (g->d_in_colidx && g->d_in_colidx != g->d_colidx) (void)hipFree(g->d_in_colidx);
         if (g->d_rowptr) (void)hipFree(g->d_rowptr);
         if (g->d_colidx) (void)hipFree(g->d_colidx);
-        if (g->d_heavy) (void)hipFree(g->d_heavy);
+        heavy_tables_free(g);
         if (g->prof.d_units) (void)hipFree(g->prof.d_units);
         for (auto e : g->prof.events) (void)hipEventDestroy(e);
         if (g->stream) (void)hipStreamDestroy(g->stream);
@@ -609,6 +609,10 @@ int khop_set_option(khop_graph *g, int32_t option, int64_t value) {
                 if (value < 1 || value > (1 << 30)) fail(KHOP_EINVAL, "batch push divisor out of range");
                 P.batch_push_div = (int)value;
                 break;
+            case KHOP_OPT_PULL_HEAVY:
+                if (value < 64 || value > INT32_MAX) fail(KHOP_EINVAL, "pull heavy threshold out of range [64, 2^31)");
+                P.pull_heavy = (int)value;
+                break;
             default:
                 fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
@@ -628,6 +632,7 @@ int khop_get_option(const khop_graph *g, int32_t option, int64_t *value) {
             case KHOP_OPT_BATCH_SEEDS: *value = P.batch_seeds; break;
             case KHOP_OPT_BATCH_HEAVY: *value = P.batch_heavy; break;
             case KHOP_OPT_BATCH_PUSH: *value = P.batch_push_div; break;
+            case KHOP_OPT_PULL_HEAVY: *value = P.pull_heavy; break;
             default: fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
     });

@@ -182,13 +182,14 @@ __device__ __forceinline__ uint64_t subgroup_or(uint64_t v) {
     return v;
 }
 
-// Hop >= 2, heavy vertices: one wave per vertex, 64/G interleaved edge streams.
+// Hop >= 2, heavy vertices: one wave per edge chunk of a heavy vertex, 64/G
+// interleaved edge streams; the chunk's findings are ORed into the vertex's
+// next-frontier and visited words atomically (the light kernel left zeros).
 template <int G>
 __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
-    const int64_t *__restrict__ in_rowptr, const int32_t *__restrict__ in_colidx, uint64_t *__restrict__ V,
-    const uint64_t *__restrict__ F, uint64_t *__restrict__ Fn, int W, int wact, const uint64_t *__restrict__ act,
-    const int32_t *__restrict__ heavy_list, int64_t n_heavy, const int32_t *prev_flag, int32_t *flag,
-    int64_t *units) {
+    const int32_t *__restrict__ in_colidx, uint64_t *V, const uint64_t *__restrict__ F, uint64_t *Fn, int W, int wact,
+    const uint64_t *__restrict__ act, const int32_t *__restrict__ hvert, const int64_t *__restrict__ hbegin,
+    const int64_t *__restrict__ hend, int64_t n_items, const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;
     constexpr int S = kWave / G;  // edge streams
     const int lane = lane_id();
@@ -198,15 +199,13 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     bool any = false;
     int64_t examined = 0;
-    for (int64_t h = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; h < n_heavy; h += nwaves) {
-        const int64_t v = heavy_list[h];
+    for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; i < n_items; i += nwaves) {
+        const int64_t v = hvert[i];
         const int64_t at = v * W + wi;
-        const uint64_t need = wi < wact ? (~V[at] & actw) : 0ull;
-        if (!ballot(need != 0)) {
-            if (sg == 0 && wi < wact) Fn[at] = 0;
-            continue;
-        }
-        const int64_t b = in_rowptr[v], e = in_rowptr[v + 1];
+        uint64_t need = 0;
+        if (wi < wact) need = ~__hip_atomic_load(&V[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & actw;
+        if (!ballot(need != 0)) continue;
+        const int64_t b = hbegin[i], e = hend[i];
         uint64_t acc = 0;
         for (int64_t x0 = b; x0 < e; x0 += 4 * S) {
 #pragma unroll
@@ -221,9 +220,9 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
         acc = subgroup_or<G>(acc);
         if (sg == 0 && wi < wact) {
             const uint64_t nx = acc & need;
-            Fn[at] = nx;
             if (nx) {
-                V[at] |= nx;
+                atomicOr((unsigned long long *)&Fn[at], (unsigned long long)nx);
+                atomicOr((unsigned long long *)&V[at], (unsigned long long)nx);
                 any = true;
             }
         }
@@ -355,28 +354,6 @@ void batch_ctx_destroy(BatchCtx *c) {
 
 int batch_ctx_words(const BatchCtx *c) { return c->W; }
 
-void ensure_heavy_list(khop_graph *g, hipStream_t st) {
-    const int thr = g->params.batch_heavy;
-    if (g->heavy_threshold == thr && (g->d_heavy || g->n_heavy == 0)) return;
-    std::vector<int32_t> hv;
-    for (int64_t v = 0; v < g->n; ++v)
-        if (g->h_indeg[v] > thr) hv.push_back((int32_t)v);
-    if (g->d_heavy) {
-        KHOP_HIP(hipStreamSynchronize(st));
-        KHOP_HIP(hipFree(g->d_heavy));
-        g->d_heavy = nullptr;
-    }
-    g->n_heavy = (int64_t)hv.size();
-    if (!hv.empty()) {
-        if (hipMalloc(&g->d_heavy, hv.size() * 4) != hipSuccess) {
-            (void)hipGetLastError();
-            fail(KHOP_ENOMEM, "device allocation for the heavy-vertex list failed");
-        }
-        KHOP_HIP(hipMemcpy(g->d_heavy, hv.data(), hv.size() * 4, hipMemcpyHostToDevice));
-    }
-    g->heavy_threshold = thr;
-}
-
 template <int G>
 static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, hipStream_t st, uint64_t *F, uint64_t *Fn) {
     const int64_t n = g->n;
@@ -387,19 +364,20 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, hipStream_t
     {
         ProfScope ps(g, KK_BATCH_PULL, st);
         hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx,
-                           c->V, F, Fn, n, c->W, wact, act, g->params.batch_heavy, c->flags + (L - 1),
+                           c->V, F, Fn, n, c->W, wact, act, batch_heavy_table(g).threshold, c->flags + (L - 1),
                            c->flags + L, ps.units());
         // bytes: 4 per examined edge + 8 per gathered word, 16 per scanned vertex, V/F/Fn words
         ps.end(3.0 * 8.0 * (double)n * wact, 0, 4.0 + 8.0 * wact, 16.0);
     }
-    if (g->n_heavy > 0) {
+    const HeavyTable &ht = batch_heavy_table(g);
+    if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
-            1, std::min<int64_t>((g->n_heavy + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
+            1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         ProfScope ps(g, KK_BATCH_PULL_HEAVY, st);
-        hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_rowptr,
-                           g->d_in_colidx, c->V, F, Fn, c->W, wact, act, g->d_heavy, g->n_heavy,
-                           c->flags + (L - 1), c->flags + L, ps.units());
-        ps.end(16.0 * (double)g->n_heavy, 0, 4.0 + 8.0 * wact);
+        hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, F,
+                           Fn, c->W, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, c->flags + (L - 1),
+                           c->flags + L, ps.units());
+        ps.end(16.0 * (double)ht.n, 0, 4.0 + 8.0 * wact);
     }
 }
 
@@ -454,7 +432,6 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
                                W, c->act, c->flags + 1);
             ps.end(4.0 * 8.0 * n * W);
         }
-        ensure_heavy_list(g, st);
     }
     for (int L = 2; L <= levels; ++L) {
         const int wa = wact[L];

@@ -47,7 +47,7 @@ struct Params {
     int alpha = 14;        // push -> pull when mf * alpha > mu
     int beta = 24;         // pull -> push when nf * beta < n
     int pull_light = 32;   // plain bottom-up: lane-serial scan up to this degree
-    int words_per_block = 16;  // plain compaction / bottom-up word range per block
+    int pull_heavy = 4096; // plain bottom-up: edge chunks above this in-degree
     int batch_seeds = 1024;    // batched: seeds per launch (64 * words)
     int batch_heavy = 256;     // batched bottom-up: wave-per-vertex above this in-degree
     int batch_push_div = 64;   // batched: top-down level when frontier arcs * div < total arcs
@@ -55,6 +55,17 @@ struct Params {
 
 struct PlainCtx;
 struct BatchCtx;
+
+// Edge chunks of the vertices whose in-degree exceeds a threshold, so that a
+// bottom-up scan of a hub is shared by many waves.
+struct HeavyTable {
+    int threshold = -1;
+    int64_t chunk = 0;
+    int32_t *d_vert = nullptr;
+    int64_t *d_begin = nullptr;
+    int64_t *d_end = nullptr;
+    int64_t n = 0;
+};
 
 // A pooled context remembers the stream and completion event of its last use.
 struct CtxUse {
@@ -67,6 +78,7 @@ enum KernelKind {
     KK_PLAIN_EXPAND,
     KK_PLAIN_COMPACT,
     KK_PLAIN_QUEUE,
+    KK_PLAIN_PULL_HEAVY,
     KK_BATCH_INIT,
     KK_BATCH_PUSH,
     KK_BATCH_APPLY,
@@ -130,9 +142,8 @@ struct khop_graph {
     int32_t *d_colidx = nullptr;
     int64_t *d_in_rowptr = nullptr;  // == d_rowptr when undirected
     int32_t *d_in_colidx = nullptr;
-    int32_t *d_heavy = nullptr;      // vertices with in-degree > params.batch_heavy, ascending
-    int64_t n_heavy = 0;
-    int heavy_threshold = -1;        // threshold d_heavy was built for
+    khop::HeavyTable plain_heavy;    // chunks for the plain bottom-up hop
+    khop::HeavyTable batch_heavy;    // chunks for the batched bottom-up hop
     std::vector<int64_t> h_outdeg;   // host copy of out-degrees
     std::vector<int64_t> h_indeg;
     uint64_t hash = 0;
@@ -163,6 +174,10 @@ int batch_ctx_words(const BatchCtx *c);
 // at depth h_ks_sorted[j] (non-increasing in j); its count goes to d_counts[h_perm[j]].
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
                const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st);
-void ensure_heavy_list(khop_graph *g, hipStream_t st);
+
+// heavy.cpp: (re)built when the threshold option changes; valid until the next change.
+const HeavyTable &plain_heavy_table(khop_graph *g);
+const HeavyTable &batch_heavy_table(khop_graph *g);
+void heavy_tables_free(khop_graph *g);
 
 }  // namespace khop

@@ -2,23 +2,31 @@
 //
 // One hop is the masked boolean product of the paper's Section II: the next
 // frontier is (A^T f) AND NOT visited over the (OR, AND) semiring.  Each hop
-// runs as
-//   expand   top-down (push): edge-balanced sweep over the frontier queue,
-//            marking unvisited heads in a byte map (benign same-value races,
-//            no atomics); or bottom-up (pull): every unvisited vertex scans
-//            its in-neighbors against the frontier bitmap and stops at the
-//            first hit, one wave per 64-vertex word writing the next-frontier
-//            word straight from a ballot (single writer, no atomics);
-//   compact  after a push: ballot(next byte AND NOT visited) per 64-vertex
-//            word -> next-frontier word, visited |= word, level popcount;
-//   queue    when the next hop is a push: the ascending frontier queue and
-//            the exclusive prefix of its out-degrees, from per-block counts
-//            and LDS prefix sums (two passes, no atomics).
-// The last block to finish an expand/compact launch (one ticket atomic per
-// block) reduces the per-block partials, adds the level popcount to the count,
-// and picks the next direction (Beamer-style thresholds on frontier and
-// unvisited edge counts), so no hop needs a host round trip.
+// runs as three launches, with every cross-block hand-off at a kernel boundary
+// (no intra-kernel fences, which on a multi-XCD part would write back L2):
+//   expand  top-down (push): edge-balanced sweep over the frontier queue that
+//           marks unvisited heads in a byte map (same-value races, no
+//           atomics); or bottom-up (pull): each unvisited vertex scans its
+//           in-neighbors against the frontier bitmap and stops at the first
+//           hit; one wave per 64-vertex word writes the next-frontier word
+//           straight from a ballot (single writer).  Vertices above the heavy
+//           threshold are split into edge chunks that many waves scan.
+//   count   per block of words: after a push, ballot(mark AND NOT visited)
+//           gives each next-frontier word and visited |= word; then the
+//           block's level popcount, queue length and frontier degree sums go
+//           to a per-block slot and, by one atomic per field, to the block's
+//           superblock total.
+//   finish  every block adds up the superblock totals (identical in every
+//           block, so the direction choice needs no broadcast) and its own
+//           prefix; block 0 advances the level state; when the next hop is a
+//           push each block writes its part of the ascending frontier queue
+//           and the exclusive prefix of the queue's out-degrees (LDS prefix
+//           sums, no atomics).
+// The level state is double buffered by level parity so that blocks of a
+// finish launch never read what block 0 of the same launch writes.  No hop
+// needs a host round trip; the host only enqueues.
 #include <algorithm>
+#include <cmath>
 
 #include "khop_impl.h"
 #include "wave.h"
@@ -31,25 +39,25 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kPart = 6;  // per-block partials: cnt, qcnt, mf, din, pull edges, pull vertices
+constexpr int kPart = 4;  // per-block partials: cnt, qcnt, mf, din
 enum { DIR_PUSH = KHOP_DIR_PUSH, DIR_PULL = KHOP_DIR_PULL };
 
-struct PlainCtl {
+struct LevelState {
     int64_t count;  // vertices at distance 1..level
     int64_t te;     // out-degree sum of levels 0..min(level, k-1)
     int64_t nf;     // frontier size (vertices at distance == level)
     int64_t qlen;   // frontier vertices with out-degree > 0 (queue length)
     int64_t mf;     // out-degree sum of the frontier
     int64_t mu;     // in-degree sum of unvisited vertices
+    int32_t dir;    // direction of the next expansion
+    int32_t done;   // the count is final and written out
+};
+
+struct PlainCtl {
+    LevelState st[2];  // state after level l lives in st[l & 1]
     int64_t *out_count;
     int64_t *out_te;
-    int32_t dir;    // direction of the next expansion
-    int32_t level;  // completed levels
-    int32_t done;   // the count is final and written out
-    int32_t k;
-    int32_t dir_mode, alpha, beta, pad0;
-    uint32_t ticket;
-    uint32_t pad1;
+    int32_t k, dir_mode, alpha, beta;
 };
 
 struct Graph {
@@ -60,53 +68,33 @@ struct Graph {
     int64_t n;
     int64_t nw;  // 64-vertex words
     int directed;
+    int heavy;   // bottom-up: in-degree above which the chunk kernel takes a vertex
 };
 
 struct State {
-    uint64_t *V;      // visited bitmap
-    uint64_t *F0;     // frontier bitmaps, double buffered by level parity
+    uint64_t *V;     // visited bitmap
+    uint64_t *F0;    // frontier bitmaps, double buffered by level parity
     uint64_t *F1;
-    uint8_t *nextb;   // top-down mark bytes, all zero between hops
-    int32_t *q;       // frontier queue
-    int64_t *qoff;    // exclusive prefix of queue out-degrees, qoff[qlen] = mf
-    int64_t *part;    // per-block partials
-    int64_t *boff;    // per-block queue / degree offsets
-    int wpb;          // words per block
-    int nblk;         // blocks of the word-range kernels
+    uint8_t *nextb;  // top-down mark bytes, all zero between hops
+    int32_t *q;      // frontier queue
+    int64_t *qoff;   // exclusive prefix of queue out-degrees, qoff[qlen] = mf
+    int64_t *part;   // per-block partials (nblk * kPart)
+    int64_t *sup;    // superblock totals, 2 * nsup * kPart (level parity)
+    int wpb;         // words per block of the count / finish kernels
+    int nblk;        // blocks of the count / finish kernels
+    int sb;          // blocks per superblock
+    int nsup;        // superblocks
+};
+
+struct HeavyChunks {
+    const int32_t *vert;   // vertex of each chunk
+    const int64_t *begin;  // first in-edge of each chunk
+    const int64_t *end;    // one past its last in-edge
+    int64_t n;
 };
 
 __device__ __forceinline__ uint64_t *frontier(const State &s, int completed_levels) {
     return (completed_levels & 1) ? s.F1 : s.F0;
-}
-
-__device__ __forceinline__ int64_t ld_relaxed(const int64_t *p) {
-    return __hip_atomic_load(const_cast<int64_t *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Block-wide exclusive scan of two values; totals returned through t0/t1.
-__device__ void block_scan2(int64_t a, int64_t b, int64_t &ea, int64_t &eb, int64_t &t0, int64_t &t1) {
-    __shared__ int64_t s_a[kWavesPerBlock], s_b[kWavesPerBlock];
-    const int lane = lane_id(), wv = threadIdx.x / kWave;
-    int64_t xa = wave_exclusive_sum(a), xb = wave_exclusive_sum(b);
-    if (lane == kWave - 1) {
-        s_a[wv] = xa + a;
-        s_b[wv] = xb + b;
-    }
-    __syncthreads();
-    int64_t pa = 0, pb = 0, ta = 0, tb = 0;
-    for (int i = 0; i < kWavesPerBlock; ++i) {
-        if (i < wv) {
-            pa += s_a[i];
-            pb += s_b[i];
-        }
-        ta += s_a[i];
-        tb += s_b[i];
-    }
-    __syncthreads();
-    ea = xa + pa;
-    eb = xb + pb;
-    t0 = ta;
-    t1 = tb;
 }
 
 __device__ int64_t block_sum(int64_t v) {
@@ -120,83 +108,8 @@ __device__ int64_t block_sum(int64_t v) {
     return t;
 }
 
-// One ticket per block; true in every thread of the last block to arrive.
-__device__ bool arrive_last(PlainCtl *ctl, int nblk) {
-    __shared__ int s_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = __hip_atomic_fetch_add(&ctl->ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (t == (uint32_t)nblk - 1);
-    }
-    __syncthreads();
-    if (s_last) __threadfence();
-    return s_last != 0;
-}
-
-// Executed by the last block: reduce partials, prefix the queue offsets, advance the level.
-__device__ void finalize_level(PlainCtl *ctl, int L, const State &s, const Graph &g, int64_t *units) {
-    int64_t run_q = 0, run_d = 0, tot_c = 0, tot_i = 0, tot_pe = 0, tot_pv = 0;
-    for (int base = 0; base < s.nblk; base += kBlock) {
-        const int b = base + threadIdx.x;
-        int64_t c = 0, qc = 0, md = 0, di = 0, pe = 0, pv = 0;
-        if (b < s.nblk) {
-            const int64_t *p = s.part + (int64_t)b * kPart;
-            c = ld_relaxed(p + 0);
-            qc = ld_relaxed(p + 1);
-            md = ld_relaxed(p + 2);
-            di = ld_relaxed(p + 3);
-            pe = ld_relaxed(p + 4);
-            pv = ld_relaxed(p + 5);
-        }
-        int64_t eq, ed, tq, td;
-        block_scan2(qc, md, eq, ed, tq, td);
-        if (b < s.nblk) {
-            s.boff[2 * (int64_t)b] = run_q + eq;
-            s.boff[2 * (int64_t)b + 1] = run_d + ed;
-        }
-        run_q += tq;
-        run_d += td;
-        tot_c += block_sum(c);
-        tot_i += block_sum(di);
-        tot_pe += block_sum(pe);
-        tot_pv += block_sum(pv);
-    }
-    if (threadIdx.x == 0) {
-        const int64_t cnt = tot_c;
-        ctl->count += cnt;
-        ctl->level = L;
-        ctl->nf = cnt;
-        ctl->qlen = run_q;
-        ctl->mf = run_d;
-        ctl->mu -= tot_i;
-        s.qoff[run_q] = run_d;
-        if (L < ctl->k) ctl->te += run_d;
-        const int done = (cnt == 0) || (L >= ctl->k);
-        int dir = ctl->dir;
-        if (ctl->dir_mode == DIR_PUSH) {
-            dir = DIR_PUSH;
-        } else if (ctl->dir_mode == DIR_PULL) {
-            dir = DIR_PULL;
-        } else if (dir == DIR_PUSH) {
-            if (run_d * (int64_t)ctl->alpha > ctl->mu) dir = DIR_PULL;
-        } else {
-            if (cnt * (int64_t)ctl->beta < g.n) dir = DIR_PUSH;
-        }
-        ctl->dir = dir;
-        ctl->done = done;
-        if (done) {
-            *ctl->out_count = ctl->count;
-            if (ctl->out_te) *ctl->out_te = ctl->te;
-        }
-        ctl->ticket = 0;
-        if (units) {
-            // bottom-up hop: 4 B per examined in-edge, 16 B row pointers per scanned
-            // vertex, visited read + frontier write of n/8 B each
-            units[0] = 4 * tot_pe + 16 * tot_pv + 2 * ((g.n + 7) / 8);
-            units[1] = tot_pe;
-            units[2] = tot_pv;
-        }
-    }
+__device__ __forceinline__ void unit_add(int64_t *units, int i, int64_t v) {
+    if (units && v) atomicAdd((unsigned long long *)&units[i], (unsigned long long)v);
 }
 
 // ------------------------------------------------------------------ init
@@ -214,18 +127,24 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
         s.V[w] = x;
         s.F0[w] = x;
     }
+    if (blockIdx.x == 0) {
+        // superblock totals of level 1 start at zero
+        int64_t *sup1 = s.sup + (int64_t)s.nsup * kPart;
+        for (int i = threadIdx.x; i < s.nsup * kPart; i += kBlock) sup1[i] = 0;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->out_count = out_count + qi;
         ctl->out_te = out_te ? out_te + qi : nullptr;
-        ctl->ticket = 0;
         ctl->dir_mode = dir_mode;
         ctl->alpha = alpha;
         ctl->beta = beta;
         ctl->k = k;
-        ctl->level = 0;
-        ctl->count = 0;
+        LevelState &st = ctl->st[0];
+        st.count = 0;
+        // the other parity slot is read at hop 2; it must not keep the previous query's state
+        ctl->st[1].done = (!valid || k == 0) ? 1 : 0;
         if (!valid) {
-            ctl->done = 1;
+            st.done = 1;
             out_count[qi] = -1;
             if (out_te) out_te[qi] = -1;
             return;
@@ -237,13 +156,13 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
             s.q[0] = seed;
             s.qoff[1] = od;
         }
-        ctl->qlen = od > 0 ? 1 : 0;
-        ctl->nf = 1;
-        ctl->mf = od;
-        ctl->mu = nnz_in - id;
-        ctl->te = k >= 1 ? od : 0;
-        ctl->dir = dir_mode == DIR_PULL ? DIR_PULL : DIR_PUSH;
-        ctl->done = (k == 0) ? 1 : 0;
+        st.qlen = od > 0 ? 1 : 0;
+        st.nf = 1;
+        st.mf = od;
+        st.mu = nnz_in - id;
+        st.te = k >= 1 ? od : 0;
+        st.dir = dir_mode == DIR_PULL ? DIR_PULL : DIR_PUSH;
+        st.done = (k == 0) ? 1 : 0;
         if (k == 0) {
             out_count[qi] = 0;
             if (out_te) out_te[qi] = 0;
@@ -257,13 +176,14 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
 // Edge-balanced sweep: wave w owns edges [E*w/W, E*(w+1)/W) of the frontier's
 // concatenated adjacency lists.  Within a 64-edge window the owning queue
 // entry of each lane is base - 1 + (number of list starts at or before it).
-__device__ void push_expand(const PlainCtl *ctl, const Graph &g, const State &s) {
+__device__ void push_expand(const LevelState &st, const Graph &g, const State &s, int64_t *units) {
     const int lane = lane_id();
-    const int64_t qlen = ctl->qlen;
-    const int64_t E = ctl->mf;
+    const int64_t qlen = st.qlen;
+    const int64_t E = st.mf;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t e0 = E * wid / nwaves, e1 = E * (wid + 1) / nwaves;
+    if (units && wid == 0 && lane == 0) unit_add(units, 0, 4 * E + 20 * qlen);
     if (e0 >= e1) return;
     __shared__ uint64_t s_mask[kWavesPerBlock];
     uint64_t *smask = &s_mask[threadIdx.x / kWave];
@@ -331,21 +251,23 @@ __device__ void push_expand(const PlainCtl *ctl, const Graph &g, const State &s)
 
 // ------------------------------------------------------------------ bottom-up
 
-__device__ void pull_expand(PlainCtl *ctl, int L, const Graph &g, const State &s, int light, int64_t *units) {
+// Each wave takes 64-vertex words in turn.  Unvisited vertices of in-degree up
+// to `light` scan alone (4 in-edges per round); heavier ones up to g.heavy are
+// scanned by the whole wave, 256 in-edges per round; heavier still are left
+// for the chunk kernel.
+__device__ void pull_expand(int L, const Graph &g, const State &s, int light, int64_t *units) {
     const int lane = lane_id();
-    const int wv = threadIdx.x / kWave;
     const uint64_t *__restrict__ Fc = frontier(s, L - 1);
     uint64_t *__restrict__ Fn = frontier(s, L);
-    const int64_t w0 = (int64_t)blockIdx.x * s.wpb;
-    const int64_t w1 = std::min<int64_t>(w0 + s.wpb, g.nw);
-    int64_t c_cnt = 0, c_q = 0, c_mf = 0, c_din = 0, c_pe = 0, c_pv = 0;  // lane-0 totals
-    for (int64_t w = w0 + wv; w < w1; w += kWavesPerBlock) {
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    int64_t c_pe = 0, c_pv = 0;
+    for (int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < g.nw; w += nwaves) {
         const uint64_t vis = s.V[w];
         const int64_t v = w * kWave + lane;
         const bool unv = v < g.n && !((vis >> lane) & 1ull);
         uint64_t found_mask = 0;
-        int64_t b = 0, e = 0;
         if (ballot(unv)) {
+            int64_t b = 0, e = 0;
             if (unv) {
                 b = g.in_rowptr[v];
                 e = g.in_rowptr[v + 1];
@@ -377,10 +299,10 @@ __device__ void pull_expand(PlainCtl *ctl, int L, const Graph &g, const State &s
                     }
                 }
             }
-            uint64_t heavy = ballot(unv && d > light);
-            while (heavy) {
-                const int h = __builtin_ctzll(heavy);
-                heavy &= heavy - 1;
+            uint64_t medium = ballot(unv && d > light && d <= g.heavy);
+            while (medium) {
+                const int h = __builtin_ctzll(medium);
+                medium &= medium - 1;
                 const int64_t hb = shfl64(b, h), he = shfl64(e, h);
                 bool hit = false;
                 int64_t scanned = 0;
@@ -403,73 +325,80 @@ __device__ void pull_expand(PlainCtl *ctl, int L, const Graph &g, const State &s
                 }
             }
             found_mask = ballot(found);
-            c_pe += wave_sum(examined);
-            c_pv += __popcll(ballot(unv));
+            if (units) {
+                c_pe += wave_sum(examined);
+                c_pv += __popcll(ballot(unv && d <= g.heavy));
+            }
         }
         if (lane == 0) {
             Fn[w] = found_mask;
             if (found_mask) s.V[w] = vis | found_mask;
         }
-        if (found_mask) {
-            const bool f = (found_mask >> lane) & 1ull;
-            int64_t od = 0, din = 0;
-            if (f) {
-                din = e - b;
-                od = g.directed ? g.rowptr[v + 1] - g.rowptr[v] : din;
-            }
-            c_cnt += __popcll(found_mask);
-            c_q += __popcll(ballot(f && od > 0));
-            c_mf += wave_sum(od);
-            c_din += wave_sum(din);
-        }
     }
-    // block partials (lane values are wave-uniform; count each wave once)
-    const bool l0 = lane == 0;
-    const int64_t t_cnt = block_sum(l0 ? c_cnt : 0), t_q = block_sum(l0 ? c_q : 0);
-    const int64_t t_mf = block_sum(l0 ? c_mf : 0), t_din = block_sum(l0 ? c_din : 0);
-    const int64_t t_pe = block_sum(l0 ? c_pe : 0), t_pv = block_sum(l0 ? c_pv : 0);
-    if (threadIdx.x == 0) {
-        int64_t *p = s.part + (int64_t)blockIdx.x * kPart;
-        p[0] = t_cnt;
-        p[1] = t_q;
-        p[2] = t_mf;
-        p[3] = t_din;
-        p[4] = t_pe;
-        p[5] = t_pv;
+    if (units && lane == 0) {
+        // 4 B per examined in-edge, 16 B of row pointers per scanned vertex
+        unit_add(units, 0, 4 * c_pe + 16 * c_pv);
+        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, 2 * ((g.n + 7) / 8));
     }
-    if (arrive_last(ctl, s.nblk)) finalize_level(ctl, L, s, g, units);
 }
 
-__global__ void __launch_bounds__(kBlock) plain_expand_kernel(PlainCtl *ctl, int L, Graph g, State s, int light,
+__global__ void __launch_bounds__(kBlock) plain_expand_kernel(const PlainCtl *ctl, int L, Graph g, State s, int light,
                                                              int64_t *units) {
-    const int done = ctl->done, level = ctl->level, dir = ctl->dir;
-    if (done || level != L - 1) {
-        if (units && blockIdx.x == 0 && threadIdx.x == 0) units[0] = 0;
-        return;
-    }
-    if (dir == DIR_PUSH) {
-        if (units && blockIdx.x == 0 && threadIdx.x == 0) {
-            // top-down hop: 4 B per frontier edge, 16 B row pointers + 4 B queue entry per frontier vertex
-            units[0] = 4 * ctl->mf + 20 * ctl->qlen;
-            units[1] = ctl->mf;
-            units[2] = ctl->qlen;
-        }
-        push_expand(ctl, g, s);
+    const LevelState &st = ctl->st[(L - 1) & 1];
+    if (st.done) return;
+    if (st.dir == DIR_PUSH) {
+        push_expand(st, g, s, units);
     } else {
-        pull_expand(ctl, L, g, s, light, units);
+        pull_expand(L, g, s, light, units);
     }
 }
 
-// ------------------------------------------------------------------ compaction
-
-__global__ void __launch_bounds__(kBlock) plain_compact_kernel(PlainCtl *ctl, int L, Graph g, State s,
-                                                              int64_t *units) {
-    const int done = ctl->done, level = ctl->level;
-    if (done || level != L - 1) {  // a bottom-up hop already compacted
-        if (units && blockIdx.x == 0 && threadIdx.x == 0) units[0] = 0;
-        return;
+// Bottom-up chunks of heavy vertices: a wave scans one chunk of in-edges of a
+// still-unvisited vertex; a hit sets its frontier and visited bits atomically.
+__global__ void __launch_bounds__(kBlock) plain_pull_heavy_kernel(const PlainCtl *ctl, int L, Graph g, State s,
+                                                                 HeavyChunks hc, int64_t *units) {
+    const LevelState &st = ctl->st[(L - 1) & 1];
+    if (st.done || st.dir != DIR_PULL) return;
+    const int lane = lane_id();
+    const uint64_t *__restrict__ Fc = frontier(s, L - 1);
+    uint64_t *Fn = frontier(s, L);
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    int64_t examined = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; i < hc.n; i += nwaves) {
+        const int32_t v = hc.vert[i];
+        const uint64_t bit = 1ull << (v & 63);
+        // visited before this hop, or already found by another chunk
+        if (__hip_atomic_load(&s.V[v >> 6], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit) continue;
+        const int64_t b = hc.begin[i], e = hc.end[i];
+        bool hit = false;
+        for (int64_t x0 = b; x0 < e; x0 += 4 * kWave) {
+            bool any = false;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t x = x0 + r * kWave + lane;
+                if (x < e) any |= test_bit(Fc, g.in_colidx[x]);
+            }
+            examined += std::min<int64_t>(4 * kWave, e - x0);
+            if (ballot(any)) {
+                hit = true;
+                break;
+            }
+        }
+        if (hit && lane == 0) {
+            atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+            atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
+        }
     }
-    if (units && blockIdx.x == 0 && threadIdx.x == 0) units[0] = g.n + (g.n + 7) / 8;
+    if (units && lane == 0) unit_add(units, 0, 4 * examined);
+}
+
+// ------------------------------------------------------------------ count
+
+__global__ void __launch_bounds__(kBlock) plain_count_kernel(const PlainCtl *ctl, int L, Graph g, State s,
+                                                            int64_t *units) {
+    const LevelState &st = ctl->st[(L - 1) & 1];
+    if (st.done) return;
+    const bool pushed = st.dir == DIR_PUSH;
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
     uint64_t *__restrict__ Fn = frontier(s, L);
@@ -478,16 +407,21 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(PlainCtl *ctl, in
     int64_t c_cnt = 0, c_q = 0, c_mf = 0, c_din = 0;
     for (int64_t w = w0 + wv; w < w1; w += kWavesPerBlock) {
         const int64_t v = w * kWave + lane;
-        const uint8_t nb = v < g.n ? s.nextb[v] : 0;
-        const uint64_t vis = s.V[w];
-        const bool fresh = nb && !((vis >> lane) & 1ull);
-        const uint64_t m = ballot(fresh);
-        if (nb) s.nextb[v] = 0;
-        if (lane == 0) {
-            Fn[w] = m;
-            if (m) s.V[w] = vis | m;
+        uint64_t m;
+        if (pushed) {
+            const uint8_t nb = v < g.n ? s.nextb[v] : 0;
+            const uint64_t vis = s.V[w];
+            m = ballot(nb && !((vis >> lane) & 1ull));
+            if (nb) s.nextb[v] = 0;
+            if (lane == 0) {
+                Fn[w] = m;
+                if (m) s.V[w] = vis | m;
+            }
+        } else {
+            m = Fn[w];
         }
         if (m) {
+            const bool fresh = (m >> lane) & 1ull;
             int64_t od = 0, din = 0;
             if (fresh) {
                 od = g.rowptr[v + 1] - g.rowptr[v];
@@ -502,32 +436,91 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(PlainCtl *ctl, in
     const bool l0 = lane == 0;
     const int64_t t_cnt = block_sum(l0 ? c_cnt : 0), t_q = block_sum(l0 ? c_q : 0);
     const int64_t t_mf = block_sum(l0 ? c_mf : 0), t_din = block_sum(l0 ? c_din : 0);
-    if (threadIdx.x == 0) {
-        int64_t *p = s.part + (int64_t)blockIdx.x * kPart;
-        p[0] = t_cnt;
-        p[1] = t_q;
-        p[2] = t_mf;
-        p[3] = t_din;
-        p[4] = 0;
-        p[5] = 0;
+    if (threadIdx.x < kPart) {
+        const int64_t val = threadIdx.x == 0 ? t_cnt : threadIdx.x == 1 ? t_q : threadIdx.x == 2 ? t_mf : t_din;
+        s.part[(int64_t)blockIdx.x * kPart + threadIdx.x] = val;
+        int64_t *sup = s.sup + ((int64_t)(L & 1) * s.nsup + blockIdx.x / s.sb) * kPart;
+        if (val) atomicAdd((unsigned long long *)&sup[threadIdx.x], (unsigned long long)val);
     }
-    if (arrive_last(ctl, s.nblk)) finalize_level(ctl, L, s, g, nullptr);
+    if (units && threadIdx.x == 0) {
+        if (blockIdx.x == 0) unit_add(units, 0, pushed ? g.n + 2 * ((g.n + 7) / 8) : (g.n + 7) / 8);
+        unit_add(units, 0, 16 * t_cnt);
+    }
 }
 
-// ------------------------------------------------------------------ queue
+// ------------------------------------------------------------------ finish
 
-// Ascending frontier queue + out-degree prefix: each wave takes a contiguous
-// quarter of the block's words; pass A totals, LDS exchange, pass B writes.
-__global__ void __launch_bounds__(kBlock) plain_queue_kernel(PlainCtl *ctl, int L, Graph g, State s,
-                                                            int64_t *units) {
-    const int done = ctl->done, level = ctl->level, dir = ctl->dir;
-    if (done || level != L || dir != DIR_PUSH) {
-        if (units && blockIdx.x == 0 && threadIdx.x == 0) units[0] = 0;
-        return;
-    }
-    if (units && blockIdx.x == 0 && threadIdx.x == 0) units[0] = (g.n + 7) / 8 + 12 * ctl->qlen + 16 * ctl->nf;
+__global__ void __launch_bounds__(kBlock) plain_finish_kernel(PlainCtl *ctl, int L, Graph g, State s,
+                                                             int64_t *units) {
+    const LevelState &st = ctl->st[(L - 1) & 1];
+    if (st.done) return;
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
+    const int64_t *sup = s.sup + (int64_t)(L & 1) * s.nsup * kPart;
+    // level totals and this block's exclusive queue / degree offsets
+    const int my_sup = blockIdx.x / s.sb;
+    int64_t t_cnt = 0, t_q = 0, t_mf = 0, t_din = 0, o_q = 0, o_mf = 0;
+    for (int i = threadIdx.x; i < s.nsup; i += kBlock) {
+        const int64_t *p = sup + (int64_t)i * kPart;
+        t_cnt += p[0];
+        t_q += p[1];
+        t_mf += p[2];
+        t_din += p[3];
+        if (i < my_sup) {
+            o_q += p[1];
+            o_mf += p[2];
+        }
+    }
+    for (int b = my_sup * s.sb + threadIdx.x; b < blockIdx.x; b += kBlock) {
+        o_q += s.part[(int64_t)b * kPart + 1];
+        o_mf += s.part[(int64_t)b * kPart + 2];
+    }
+    t_cnt = block_sum(t_cnt);
+    t_q = block_sum(t_q);
+    t_mf = block_sum(t_mf);
+    t_din = block_sum(t_din);
+    o_q = block_sum(o_q);
+    o_mf = block_sum(o_mf);
+    // next state (every block computes the same)
+    const int64_t mu = st.mu - t_din;
+    const int done = (t_cnt == 0) || (L >= ctl->k);
+    int dir = st.dir;
+    if (ctl->dir_mode == DIR_PUSH) {
+        dir = DIR_PUSH;
+    } else if (ctl->dir_mode == DIR_PULL) {
+        dir = DIR_PULL;
+    } else if (dir == DIR_PUSH) {
+        if (t_mf * (int64_t)ctl->alpha > mu) dir = DIR_PULL;
+    } else {
+        if (t_cnt * (int64_t)ctl->beta < g.n) dir = DIR_PUSH;
+    }
+    if (blockIdx.x == 0) {
+        int64_t *nsup = s.sup + (int64_t)((L + 1) & 1) * s.nsup * kPart;
+        if (!done)
+            for (int i = threadIdx.x; i < s.nsup * kPart; i += kBlock) nsup[i] = 0;
+        if (threadIdx.x == 0) {
+            LevelState &nx = ctl->st[L & 1];
+            nx.count = st.count + t_cnt;
+            nx.te = st.te + (L < ctl->k ? t_mf : 0);
+            nx.nf = t_cnt;
+            nx.qlen = t_q;
+            nx.mf = t_mf;
+            nx.mu = mu;
+            nx.dir = dir;
+            nx.done = done;
+            if (done) {
+                // later hops read either parity slot; both must say done
+                ctl->st[(L + 1) & 1].done = 1;
+                *ctl->out_count = nx.count;
+                if (ctl->out_te) *ctl->out_te = nx.te;
+            } else if (dir == DIR_PUSH) {
+                s.qoff[t_q] = t_mf;
+            }
+            if (units && !done && dir == DIR_PUSH) unit_add(units, 0, (g.n + 7) / 8 + 28 * t_q);
+        }
+    }
+    if (done || dir != DIR_PUSH) return;
+    // ascending queue: each wave takes a contiguous quarter of the block's words
     const uint64_t *__restrict__ Fn = frontier(s, L);
     const int64_t w0 = (int64_t)blockIdx.x * s.wpb;
     const int per = (s.wpb + kWavesPerBlock - 1) / kWavesPerBlock;
@@ -549,7 +542,7 @@ __global__ void __launch_bounds__(kBlock) plain_queue_kernel(PlainCtl *ctl, int 
         s_d[wv] = td;
     }
     __syncthreads();
-    int64_t qpos = s.boff[2 * (int64_t)blockIdx.x], dpos = s.boff[2 * (int64_t)blockIdx.x + 1];
+    int64_t qpos = o_q, dpos = o_mf;
     for (int i = 0; i < wv; ++i) {
         qpos += s_q[i];
         dpos += s_d[i];
@@ -585,6 +578,7 @@ struct PlainCtx {
     khop_graph *g = nullptr;
     PlainCtl *ctl = nullptr;
     State s{};
+    int expand_grid = 1;
     void *arena = nullptr;
 };
 
@@ -592,8 +586,12 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     PlainCtx *c = new PlainCtx();
     c->g = g;
     const int64_t n = g->n, nw = (n + 63) / 64;
-    const int wpb = g->params.words_per_block;
+    // word ranges for count / finish: at most about 4096 blocks
+    int wpb = (int)std::max<int64_t>(16, (nw + 4095) / 4096);
+    wpb = (wpb + 3) & ~3;
     const int nblk = (int)((nw + wpb - 1) / wpb);
+    const int sb = std::max(8, (int)std::ceil(std::sqrt((double)nblk)));
+    const int nsup = (nblk + sb - 1) / sb;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
     const size_t o_ctl = off;
@@ -612,8 +610,8 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     off += al((n + 1) * 8);
     const size_t o_part = off;
     off += al((size_t)nblk * kPart * 8);
-    const size_t o_boff = off;
-    off += al((size_t)nblk * 2 * 8);
+    const size_t o_sup = off;
+    off += al((size_t)2 * nsup * kPart * 8);
     hipError_t e = hipMalloc(&c->arena, off);
     if (e != hipSuccess) {
         delete c;
@@ -629,9 +627,12 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     c->s.q = (int32_t *)(base + o_q);
     c->s.qoff = (int64_t *)(base + o_qoff);
     c->s.part = (int64_t *)(base + o_part);
-    c->s.boff = (int64_t *)(base + o_boff);
+    c->s.sup = (int64_t *)(base + o_sup);
     c->s.wpb = wpb;
     c->s.nblk = nblk;
+    c->s.sb = sb;
+    c->s.nsup = nsup;
+    c->expand_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 15) / 16, (int64_t)g->cu_count * 8));
     KHOP_HIP(hipMemset(c->arena, 0, off));
     KHOP_HIP(hipDeviceSynchronize());
     return c;
@@ -657,10 +658,15 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         plain_fill_zero_outputs(d_counts, d_te, num_seeds, st);
         return;
     }
-    Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed};
     const Params &P = g->params;
+    const HeavyTable &ht = plain_heavy_table(g);
+    Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
+             ht.threshold};
+    HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
     const int nblk = c->s.nblk;
-    const int init_grid = (int)std::max<int64_t>(1, std::min<int64_t>((gr.nw + kBlock - 1) / kBlock, 1024));
+    const int init_grid = (int)std::max<int64_t>(1, std::min<int64_t>((gr.nw + kBlock - 1) / kBlock, 256));
+    const int heavy_grid =
+        (int)std::max<int64_t>(1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, g->cu_count * 8));
     const int64_t nnz_in = g->nnz;
     for (int64_t i = 0; i < num_seeds; ++i) {
         {
@@ -672,19 +678,25 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         for (int L = 1; L <= k; ++L) {
             {
                 ProfScope ps(g, KK_PLAIN_EXPAND, st);
-                hipLaunchKernelGGL(plain_expand_kernel, dim3(nblk), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
-                                   P.pull_light, ps.units());
+                hipLaunchKernelGGL(plain_expand_kernel, dim3(c->expand_grid), dim3(kBlock), 0, st, c->ctl, L, gr,
+                                   c->s, P.pull_light, ps.units());
+                ps.end(0, 1);
+            }
+            if (ht.n > 0 && P.dir_mode != KHOP_DIR_PUSH) {
+                ProfScope ps(g, KK_PLAIN_PULL_HEAVY, st);
+                hipLaunchKernelGGL(plain_pull_heavy_kernel, dim3(heavy_grid), dim3(kBlock), 0, st, c->ctl, L, gr,
+                                   c->s, hc, ps.units());
                 ps.end(0, 1);
             }
             {
                 ProfScope ps(g, KK_PLAIN_COMPACT, st);
-                hipLaunchKernelGGL(plain_compact_kernel, dim3(nblk), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
+                hipLaunchKernelGGL(plain_count_kernel, dim3(nblk), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
                                    ps.units());
                 ps.end(0, 1);
             }
-            if (L < k) {
+            {
                 ProfScope ps(g, KK_PLAIN_QUEUE, st);
-                hipLaunchKernelGGL(plain_queue_kernel, dim3(nblk), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
+                hipLaunchKernelGGL(plain_finish_kernel, dim3(nblk), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
                                    ps.units());
                 ps.end(0, 1);
             }

@@ -187,17 +187,35 @@ def test_repeat_runs_bit_identical(K, g0_gpu, g0):
             assert np.array_equal(g0_gpu.count(seeds, k), ref)
 
 
-def test_directed_power_law_small(K):
+@pytest.mark.parametrize("heavy", [64, 300, 4096])
+def test_directed_power_law_small(K, heavy):
     el = graphgen.chung_lu(60_000, 900_000, 6.0, seed=4)
     g = K.Graph.from_edgelist(el)
+    g.set_option(K.KHOP_OPT_PULL_HEAVY, heavy)
     og = oracle.OracleGraph.from_edgelist(el)
     seeds = graphgen.draw_seeds(el, 40, seed=1)
     for mode in MODES:
         _set_mode(K, g, mode)
         for k in KS:
-            _say("chung-lu 60k", mode, k)
+            _say("chung-lu 60k", mode, k, "heavy", heavy)
             c, te = g.count(seeds, k, with_te=True)
             oc, ote = og.count(seeds, k)
+            assert np.array_equal(c, oc) and np.array_equal(te, ote), (mode, k)
+    g.free()
+
+
+@pytest.mark.parametrize("heavy", [64, 128])
+def test_g0_pull_heavy_chunks(K, g0, g0_oracle, heavy):
+    """Low chunk thresholds send many scale-10 vertices through the chunk kernel."""
+    el, seeds = g0
+    g = K.Graph.from_edgelist(el)
+    g.set_option(K.KHOP_OPT_PULL_HEAVY, heavy)
+    seeds_all = np.nonzero(g0_oracle.degrees() > 0)[0].astype(np.int32)
+    for mode in ("auto", "pull"):
+        _set_mode(K, g, mode)
+        for k in KS:
+            c, te = g.count(seeds_all, k, with_te=True)
+            oc, ote = g0_oracle.count(seeds_all, k)
             assert np.array_equal(c, oc) and np.array_equal(te, ote), (mode, k)
     g.free()
 
