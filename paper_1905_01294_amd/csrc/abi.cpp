@@ -22,8 +22,8 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line) {
 }
 
 const char *const kKernelNames[KK_COUNT_KINDS] = {
-    "plain_init", "plain_expand", "plain_count", "plain_finish", "plain_pull_heavy", "batch_init",
-    "batch_push", "batch_apply",  "batch_pull",    "batch_pull_heavy", "batch_count"};
+    "plain_init", "plain_hop", "plain_compact", "batch_init", "batch_push", "batch_apply", "batch_pull", "batch_pull_heavy",
+    "batch_count"};
 
 template <class F>
 static int guard(F &&f) {
@@ -378,6 +378,9 @@ int graph_load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, in
         HostCSR out_csr = build_csr(src, dst, num_edges, num_vertices, !directed);
         HostCSR in_csr;
         if (directed) in_csr = build_csr(dst, src, num_edges, num_vertices, false);
+        // per-hop counters pack a degree sum into 33 bits
+        if ((int64_t)out_csr.colidx.size() >= ((int64_t)1 << 33))
+            fail(KHOP_ERANGE, "more than 2^33 stored arcs");
         auto *g = new khop_graph();
         g->device = dev;
         g->n = num_vertices;
@@ -610,7 +613,7 @@ int khop_set_option(khop_graph *g, int32_t option, int64_t value) {
                 P.batch_push_div = (int)value;
                 break;
             case KHOP_OPT_PULL_HEAVY:
-                if (value < 64 || value > INT32_MAX) fail(KHOP_EINVAL, "pull heavy threshold out of range [64, 2^31)");
+                if (value < 1 || value > INT32_MAX) fail(KHOP_EINVAL, "pull heavy threshold out of range [1, 2^31)");
                 P.pull_heavy = (int)value;
                 break;
             default:

@@ -22,6 +22,14 @@ static const HeavyTable &build(khop_graph *g, HeavyTable &t, int threshold, int6
     free_table(t);
     std::vector<int32_t> vert;
     std::vector<int64_t> begin, end;
+    {
+        int64_t items = 0;
+        for (int64_t v = 0; v < g->n; ++v)
+            if (g->h_indeg[v] > threshold) items += (g->h_indeg[v] + chunk - 1) / chunk;
+        vert.reserve((size_t)items);
+        begin.reserve((size_t)items);
+        end.reserve((size_t)items);
+    }
     int64_t off = 0;
     for (int64_t v = 0; v < g->n; ++v) {
         const int64_t d = g->h_indeg[v];
@@ -50,7 +58,8 @@ static const HeavyTable &build(khop_graph *g, HeavyTable &t, int threshold, int6
     return t;
 }
 
-const HeavyTable &plain_heavy_table(khop_graph *g) { return build(g, g->plain_heavy, g->params.pull_heavy, 2048); }
+// 256-edge chunks: one round of 4 in-edges per lane of a wave
+const HeavyTable &plain_heavy_table(khop_graph *g) { return build(g, g->plain_heavy, g->params.pull_heavy, 256); }
 
 const HeavyTable &batch_heavy_table(khop_graph *g) { return build(g, g->batch_heavy, g->params.batch_heavy, 1024); }
 

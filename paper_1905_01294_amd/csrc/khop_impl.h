@@ -47,7 +47,8 @@ struct Params {
     int alpha = 14;        // push -> pull when mf * alpha > mu
     int beta = 24;         // pull -> push when nf * beta < n
     int pull_light = 32;   // plain bottom-up: lane-serial scan up to this degree
-    int pull_heavy = 4096; // plain bottom-up: edge chunks above this in-degree
+    int pull_heavy = 4096; // plain bottom-up: 256-edge chunks above this in-degree
+    int push_atomic_max = 65536;  // plain top-down: claim heads atomically up to this many frontier edges
     int batch_seeds = 1024;    // batched: seeds per launch (64 * words)
     int batch_heavy = 256;     // batched bottom-up: wave-per-vertex above this in-degree
     int batch_push_div = 64;   // batched: top-down level when frontier arcs * div < total arcs
@@ -75,10 +76,8 @@ struct CtxUse {
 
 enum KernelKind {
     KK_PLAIN_INIT = 0,
-    KK_PLAIN_EXPAND,
+    KK_PLAIN_HOP,
     KK_PLAIN_COMPACT,
-    KK_PLAIN_QUEUE,
-    KK_PLAIN_PULL_HEAVY,
     KK_BATCH_INIT,
     KK_BATCH_PUSH,
     KK_BATCH_APPLY,

@@ -1,32 +1,37 @@
 // Plain single-query k-hop count on gfx950.
 //
 // One hop is the masked boolean product of the paper's Section II: the next
-// frontier is (A^T f) AND NOT visited over the (OR, AND) semiring.  Each hop
-// runs as three launches, with every cross-block hand-off at a kernel boundary
-// (no intra-kernel fences, which on a multi-XCD part would write back L2):
-//   expand  top-down (push): edge-balanced sweep over the frontier queue that
-//           marks unvisited heads in a byte map (same-value races, no
-//           atomics); or bottom-up (pull): each unvisited vertex scans its
-//           in-neighbors against the frontier bitmap and stops at the first
-//           hit; one wave per 64-vertex word writes the next-frontier word
-//           straight from a ballot (single writer).  Vertices above the heavy
-//           threshold are split into edge chunks that many waves scan.
-//   count   per block of words: after a push, ballot(mark AND NOT visited)
-//           gives each next-frontier word and visited |= word; then the
-//           block's level popcount, queue length and frontier degree sums go
-//           to a per-block slot and, by one atomic per field, to the block's
-//           superblock total.
-//   finish  every block adds up the superblock totals (identical in every
-//           block, so the direction choice needs no broadcast) and its own
-//           prefix; block 0 advances the level state; when the next hop is a
-//           push each block writes its part of the ascending frontier queue
-//           and the exclusive prefix of the queue's out-degrees (LDS prefix
-//           sums, no atomics).
-// The level state is double buffered by level parity so that blocks of a
-// finish launch never read what block 0 of the same launch writes.  No hop
-// needs a host round trip; the host only enqueues.
+// frontier is (A^T f) AND NOT visited over the (OR, AND) semiring.  A query is
+// init, per hop a hop kernel and a compaction kernel (which exits at once
+// unless the hop marked bytes), and a final kernel; every cross-block hand-off
+// happens at a kernel boundary (intra-kernel release fences would write back
+// L2 on this multi-XCD part).
+//
+// The frontier queue is split into regions of consecutive vertices; region r
+// owns queue slots [r*RC, (r+1)*RC) and one packed 64-bit counter
+// (count << 33 | out-degree sum), so that appending a batch reserves its slots
+// and its out-degree offsets with one atomic, and appends spread over many
+// addresses instead of serialising on one.
+//
+// Hop kernel, all blocks:
+//   1. read the previous hop's region counters, prefix their degree sums in
+//      LDS, and pick the direction with Beamer-style thresholds on the totals
+//      (every block computes the same choice);
+//   2. top-down (push): an edge-balanced sweep over the regions' queues.  With
+//      few frontier edges each unvisited head is claimed by an atomicOr on its
+//      visited word (the old value makes the discovery exactly-once) and
+//      appended at once; with many, heads are only marked in a byte map (no
+//      atomics) and the compaction kernel turns the marks into frontier words
+//      with ballots;
+//      bottom-up (pull): one wave per 64-vertex word, each unvisited vertex
+//      scans its in-neighbors against the frontier bitmap and stops at the
+//      first hit; the ballot of hits is the word's new frontier bits.
+//      In-edges of vertices above the heavy threshold are split into chunks
+//      that any wave may scan.
+// Block 0 keeps the running count and traversed-edge sum.  Hop records,
+// region counters and frontier bitmaps rotate over three slots (hop l writes
+// slot l, reads slot l-1 and clears slot l+1), queues over two.
 #include <algorithm>
-#include <cmath>
 
 #include "khop_impl.h"
 #include "wave.h"
@@ -39,25 +44,32 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kPart = 4;  // per-block partials: cnt, qcnt, mf, din
+constexpr int kMaxRegions = kBlock;  // one region per thread in the prefix
+constexpr int kSumBits = 33;         // packed (count << 33) | sum
+constexpr uint64_t kSumMask = (1ull << kSumBits) - 1;
 enum { DIR_PUSH = KHOP_DIR_PUSH, DIR_PULL = KHOP_DIR_PULL };
+enum { MODE_PULL = 0, MODE_PUSH_ATOMIC = 1, MODE_PUSH_BYTES = 2, MODE_IDLE = 3 };
 
-struct LevelState {
-    int64_t count;  // vertices at distance 1..level
-    int64_t te;     // out-degree sum of levels 0..min(level, k-1)
-    int64_t nf;     // frontier size (vertices at distance == level)
-    int64_t qlen;   // frontier vertices with out-degree > 0 (queue length)
-    int64_t mf;     // out-degree sum of the frontier
-    int64_t mu;     // in-degree sum of unvisited vertices
-    int32_t dir;    // direction of the next expansion
-    int32_t done;   // the count is final and written out
+struct RegRec {
+    uint64_t qpack;  // (queued vertices << 33) | their out-degree sum
+    uint64_t fpack;  // (discovered vertices << 33) | their in-degree sum
+};
+
+struct HopHdr {
+    int64_t mu_before;  // in-degree sum of the vertices unvisited before this hop
+    int32_t dir;        // direction this hop used
+    int32_t mode;       // MODE_*
 };
 
 struct PlainCtl {
-    LevelState st[2];  // state after level l lives in st[l & 1]
+    HopHdr hdr[3];      // hop l's header in hdr[l % 3]; hdr[0] describes the seed
+    int64_t count_acc;  // vertices discovered at hops 1..l-1 (kept by block 0 of hop l)
+    int64_t te_acc;     // out-degree sum of the frontiers of hops 0..l-1
     int64_t *out_count;
     int64_t *out_te;
+    int64_t push_atomic_max;  // frontier edges up to which a push claims heads atomically
     int32_t k, dir_mode, alpha, beta;
+    int32_t valid, pad;
 };
 
 struct Graph {
@@ -68,22 +80,19 @@ struct Graph {
     int64_t n;
     int64_t nw;  // 64-vertex words
     int directed;
-    int heavy;   // bottom-up: in-degree above which the chunk kernel takes a vertex
+    int heavy;   // bottom-up: in-degree above which the chunk table takes a vertex
 };
 
 struct State {
-    uint64_t *V;     // visited bitmap
-    uint64_t *F0;    // frontier bitmaps, double buffered by level parity
-    uint64_t *F1;
-    uint8_t *nextb;  // top-down mark bytes, all zero between hops
-    int32_t *q;      // frontier queue
-    int64_t *qoff;   // exclusive prefix of queue out-degrees, qoff[qlen] = mf
-    int64_t *part;   // per-block partials (nblk * kPart)
-    int64_t *sup;    // superblock totals, 2 * nsup * kPart (level parity)
-    int wpb;         // words per block of the count / finish kernels
-    int nblk;        // blocks of the count / finish kernels
-    int sb;          // blocks per superblock
-    int nsup;        // superblocks
+    uint64_t *V;       // visited bitmap
+    uint64_t *F[3];    // frontier bitmaps by hop % 3
+    uint8_t *nextb;    // top-down marks (byte mode), all zero between hops
+    int32_t *q[2];     // region queues by hop parity, nreg * rc slots
+    int64_t *qoff[2];  // out-degree prefix within each region's queue
+    RegRec *regs;      // 3 * nreg region counters
+    int nreg;          // regions
+    int rw;            // words per region
+    int64_t rc;        // slots per region (rw * 64)
 };
 
 struct HeavyChunks {
@@ -93,31 +102,100 @@ struct HeavyChunks {
     int64_t n;
 };
 
-__device__ __forceinline__ uint64_t *frontier(const State &s, int completed_levels) {
-    return (completed_levels & 1) ? s.F1 : s.F0;
-}
-
-__device__ int64_t block_sum(int64_t v) {
-    __shared__ int64_t s_v[kWavesPerBlock];
-    v = wave_sum(v);
-    if (lane_id() == 0) s_v[threadIdx.x / kWave] = v;
-    __syncthreads();
-    int64_t t = 0;
-    for (int i = 0; i < kWavesPerBlock; ++i) t += s_v[i];
-    __syncthreads();
-    return t;
-}
-
 __device__ __forceinline__ void unit_add(int64_t *units, int i, int64_t v) {
     if (units && v) atomicAdd((unsigned long long *)&units[i], (unsigned long long)v);
+}
+
+__device__ __forceinline__ int64_t pk_count(uint64_t p) { return (int64_t)(p >> kSumBits); }
+__device__ __forceinline__ int64_t pk_sum(uint64_t p) { return (int64_t)(p & kSumMask); }
+__device__ __forceinline__ uint64_t pk(int64_t count, int64_t sum) {
+    return ((uint64_t)count << kSumBits) + (uint64_t)sum;
+}
+
+// Appends one discovered vertex (a single lane).
+__device__ __forceinline__ void append_one(const State &s, RegRec *regs, int L, int32_t v, int64_t od, int64_t id) {
+    const int r = (int)(((int64_t)v >> 6) / s.rw);
+    if (od > 0) {
+        const uint64_t old = atomicAdd((unsigned long long *)&regs[r].qpack, (unsigned long long)pk(1, od));
+        const int64_t at = (int64_t)r * s.rc + pk_count(old);
+        s.q[L & 1][at] = v;
+        s.qoff[L & 1][at] = pk_sum(old);
+    }
+    atomicAdd((unsigned long long *)&regs[r].fpack, (unsigned long long)pk(1, id));
+}
+
+// Per-wave LDS buffer of discoveries in one region, flushed with one
+// returning atomic per region instead of one per word.
+constexpr int kBufCap = 512;
+struct WaveBuf {
+    int32_t *v;    // LDS, kBufCap vertices
+    int32_t *d;    // their out-degrees
+    int cnt;       // buffered entries (wave-uniform)
+    int reg;       // region of the buffered entries, -1 if none
+    int64_t nf;    // discovered in that region (all, wave-uniform)
+    int64_t din;   // their in-degree sum
+};
+
+__device__ void wb_flush(WaveBuf &b, const State &s, RegRec *regs, int L) {
+    if (b.reg < 0 || (b.cnt == 0 && b.nf == 0)) return;
+    const int lane = lane_id();
+    int64_t dsum = 0;
+    for (int i = lane; i < b.cnt; i += kWave) dsum += b.d[i];
+    dsum = wave_sum(dsum);
+    uint64_t old = 0;
+    if (lane == 0) {
+        if (b.cnt) old = atomicAdd((unsigned long long *)&regs[b.reg].qpack, (unsigned long long)pk(b.cnt, dsum));
+        if (b.nf) atomicAdd((unsigned long long *)&regs[b.reg].fpack, (unsigned long long)pk(b.nf, b.din));
+    }
+    old = (uint64_t)shfl64((int64_t)old, 0);
+    const int64_t base = (int64_t)b.reg * s.rc + pk_count(old);
+    int64_t dpos = pk_sum(old);
+    for (int i0 = 0; i0 < b.cnt; i0 += kWave) {
+        const int i = i0 + lane;
+        const int64_t d = i < b.cnt ? b.d[i] : 0;
+        const int64_t dx = wave_exclusive_sum(d);
+        if (i < b.cnt) {
+            s.q[L & 1][base + i] = b.v[i];
+            s.qoff[L & 1][base + i] = dpos + dx;
+        }
+        dpos += wave_sum(d);
+    }
+    b.cnt = 0;
+    b.nf = 0;
+    b.din = 0;
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Buffers the lanes of word w that have `found` (wave-uniform call).
+__device__ __forceinline__ void wb_word(WaveBuf &b, const State &s, RegRec *regs, int L, int64_t w, bool found,
+                                       int64_t od, int64_t id) {
+    const uint64_t fm = ballot(found);
+    if (!fm) return;
+    const int r = (int)(w / s.rw);
+    const bool qd = found && od > 0;
+    const uint64_t qm = ballot(qd);
+    const int nq = __popcll(qm);
+    if (r != b.reg || b.cnt + nq > kBufCap) {
+        wb_flush(b, s, regs, L);
+        b.reg = r;
+    }
+    if (qd) {
+        const int at = b.cnt + mask_rank(qm);
+        b.v[at] = (int32_t)(w * kWave + lane_id());
+        b.d[at] = (int32_t)od;
+    }
+    b.cnt += nq;
+    b.nf += __popcll(fm);
+    b.din += wave_sum(found ? id : 0);
+    __builtin_amdgcn_wave_barrier();
 }
 
 // ------------------------------------------------------------------ init
 
 __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph g, State s, const int32_t *seeds,
                                                            int64_t qi, int k, int dir_mode, int alpha, int beta,
-                                                           int64_t nnz_in, int64_t *out_count, int64_t *out_te,
-                                                           int64_t *units) {
+                                                           int64_t push_atomic_max, int64_t nnz_in,
+                                                           int64_t *out_count, int64_t *out_te, int64_t *units) {
     const int32_t seed = seeds[qi];
     const bool valid = seed >= 0 && (int64_t)seed < g.n;
     const int64_t sw = valid ? (seed >> 6) : -1;
@@ -125,246 +203,253 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
     for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock) {
         const uint64_t x = (w == sw) ? sbit : 0ull;
         s.V[w] = x;
-        s.F0[w] = x;
+        s.F[0][w] = x;
+        s.F[1][w] = 0;
     }
-    if (blockIdx.x == 0) {
-        // superblock totals of level 1 start at zero
-        int64_t *sup1 = s.sup + (int64_t)s.nsup * kPart;
-        for (int i = threadIdx.x; i < s.nsup * kPart; i += kBlock) sup1[i] = 0;
+    if (blockIdx.x != 0) return;
+    // region counters of hop 0 (the seed) and hop 1 start at zero
+    for (int i = threadIdx.x; i < 2 * s.nreg; i += kBlock) {
+        s.regs[i].qpack = 0;
+        s.regs[i].fpack = 0;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
         ctl->out_count = out_count + qi;
         ctl->out_te = out_te ? out_te + qi : nullptr;
         ctl->dir_mode = dir_mode;
         ctl->alpha = alpha;
         ctl->beta = beta;
         ctl->k = k;
-        LevelState &st = ctl->st[0];
-        st.count = 0;
-        // the other parity slot is read at hop 2; it must not keep the previous query's state
-        ctl->st[1].done = (!valid || k == 0) ? 1 : 0;
+        ctl->valid = valid;
+        ctl->push_atomic_max = push_atomic_max;
+        ctl->count_acc = 0;
+        ctl->te_acc = 0;
         if (!valid) {
-            st.done = 1;
             out_count[qi] = -1;
             if (out_te) out_te[qi] = -1;
             return;
         }
         const int64_t od = g.rowptr[seed + 1] - g.rowptr[seed];
         const int64_t id = g.in_rowptr[seed + 1] - g.in_rowptr[seed];
-        s.qoff[0] = 0;
+        const int r = (int)(sw / s.rw);
         if (od > 0) {
-            s.q[0] = seed;
-            s.qoff[1] = od;
+            s.regs[r].qpack = pk(1, od);
+            s.q[0][(int64_t)r * s.rc] = seed;
+            s.qoff[0][(int64_t)r * s.rc] = 0;
         }
-        st.qlen = od > 0 ? 1 : 0;
-        st.nf = 1;
-        st.mf = od;
-        st.mu = nnz_in - id;
-        st.te = k >= 1 ? od : 0;
-        st.dir = dir_mode == DIR_PULL ? DIR_PULL : DIR_PUSH;
-        st.done = (k == 0) ? 1 : 0;
-        if (k == 0) {
-            out_count[qi] = 0;
-            if (out_te) out_te[qi] = 0;
-        }
-        if (units) units[0] = 2 * 8 * g.nw;
+        s.regs[r].fpack = pk(1, id);
+        ctl->hdr[0].mu_before = nnz_in;
+        ctl->hdr[0].dir = dir_mode == DIR_PULL ? DIR_PULL : DIR_PUSH;
+        ctl->hdr[0].mode = MODE_IDLE;
+        if (units) units[0] = 3 * 8 * g.nw;
     }
 }
 
 // ------------------------------------------------------------------ top-down
 
 // Edge-balanced sweep: wave w owns edges [E*w/W, E*(w+1)/W) of the frontier's
-// concatenated adjacency lists.  Within a 64-edge window the owning queue
-// entry of each lane is base - 1 + (number of list starts at or before it).
-__device__ void push_expand(const LevelState &st, const Graph &g, const State &s, int64_t *units) {
+// concatenated adjacency lists, region after region.  Within a 64-edge window
+// of one region's queue, the owning entry of each lane is base - 1 + (number
+// of list starts at or before it).
+__device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const int32_t *qcnt, const Graph &g,
+                         const State &s, RegRec *cur, uint64_t *smask, int64_t *units) {
     const int lane = lane_id();
-    const int64_t qlen = st.qlen;
-    const int64_t E = st.mf;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t e0 = E * wid / nwaves, e1 = E * (wid + 1) / nwaves;
-    if (units && wid == 0 && lane == 0) unit_add(units, 0, 4 * E + 20 * qlen);
     if (e0 >= e1) return;
-    __shared__ uint64_t s_mask[kWavesPerBlock];
-    uint64_t *smask = &s_mask[threadIdx.x / kWave];
-    const int32_t *__restrict__ q = s.q;
-    const int64_t *__restrict__ qoff = s.qoff;
-
-    // base = #{ j < qlen : qoff[j] < e0 } by a 64-way search
-    int64_t lo = 0, hi = qlen;
-    while (hi - lo > kWave) {
-        const int64_t step = (hi - lo + kWave - 1) / kWave;
-        const int64_t p = lo + (int64_t)lane * step;
-        const bool less = p < hi && qoff[p] < e0;
-        const int t = __popcll(ballot(less));
-        const int64_t nlo = t ? lo + (int64_t)(t - 1) * step + 1 : lo;
-        hi = std::min(hi, lo + (int64_t)t * step);
-        lo = nlo;
-    }
+    uint64_t *Fn = s.F[L % 3];
+    // first region whose edges reach past e0
+    int r = 0;
     {
-        const int64_t p = lo + lane;
-        const bool less = p < hi && qoff[p] < e0;
-        lo += __popcll(ballot(less));
-    }
-    int64_t base = lo;
-    int64_t carry_beg = 0, carry_off = 0;
-    if (base > 0) {
-        carry_beg = g.rowptr[q[base - 1]];
-        carry_off = qoff[base - 1];
-    }
-    const uint64_t *__restrict__ V = s.V;
-    uint8_t *__restrict__ nextb = s.nextb;
-    for (int64_t b = e0; b < e1; b += kWave) {
-        const int64_t j = base + lane;
-        bool inwin = false;
-        int64_t offj = 0, begj = 0;
-        if (j < qlen) {
-            offj = qoff[j];
-            inwin = offj < b + kWave;
+        int lo = 0, hi = s.nreg - 1;  // largest r with epre[r] <= e0
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (epre[mid] <= e0) lo = mid;
+            else hi = mid - 1;
         }
-        if (inwin) begj = g.rowptr[q[j]];
-        if (lane == 0) *smask = 0;
-        __builtin_amdgcn_wave_barrier();
-        if (inwin) atomicOr((unsigned long long *)smask, 1ull << (offj - b));
-        __builtin_amdgcn_wave_barrier();
-        const uint64_t starts = *smask;
-        const int ns = __popcll(ballot(inwin));
-        const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
-        const int c = __popcll(starts & le);
-        const int src = c > 0 ? c - 1 : 0;
-        const int64_t sb = shfl64(begj, src), so = shfl64(offj, src);
-        const int64_t e = b + lane;
-        if (e < e1) {
-            const int64_t beg = c ? sb : carry_beg;
-            const int64_t off = c ? so : carry_off;
-            const int32_t v = g.colidx[beg + (e - off)];
-            if (!test_bit(V, v)) nextb[v] = 1;
-        }
-        if (ns > 0) {
-            carry_beg = shfl64(begj, ns - 1);
-            carry_off = shfl64(offj, ns - 1);
-        }
-        base += ns;
-        __builtin_amdgcn_wave_barrier();
+        r = lo;
     }
+    int64_t starts_seen = 0;  // queue entries whose lists start in this wave's range
+    for (; r < s.nreg && epre[r] < e1; ++r) {
+        const int64_t rb = epre[r], re = epre[r + 1];
+        const int64_t a0 = std::max(e0, rb) - rb, a1 = std::min(e1, re) - rb;  // local edge range
+        if (a0 >= a1) continue;
+        const int64_t qlen = qcnt[r];
+        const int32_t *__restrict__ q = s.q[(L - 1) & 1] + (int64_t)r * s.rc;
+        const int64_t *__restrict__ qoff = s.qoff[(L - 1) & 1] + (int64_t)r * s.rc;
+        // base = #{ j < qlen : qoff[j] < a0 } by a 64-way search
+        int64_t lo = 0, hi = qlen;
+        while (hi - lo > kWave) {
+            const int64_t step = (hi - lo + kWave - 1) / kWave;
+            const int64_t p = lo + (int64_t)lane * step;
+            const bool less = p < hi && qoff[p] < a0;
+            const int t = __popcll(ballot(less));
+            const int64_t nlo = t ? lo + (int64_t)(t - 1) * step + 1 : lo;
+            hi = std::min(hi, lo + (int64_t)t * step);
+            lo = nlo;
+        }
+        {
+            const int64_t p = lo + lane;
+            const bool less = p < hi && qoff[p] < a0;
+            lo += __popcll(ballot(less));
+        }
+        int64_t base = lo;
+        int64_t carry_beg = 0, carry_off = 0;
+        if (base > 0) {
+            carry_beg = g.rowptr[q[base - 1]];
+            carry_off = qoff[base - 1];
+        }
+        for (int64_t b = a0; b < a1; b += kWave) {
+            const int64_t j = base + lane;
+            bool inwin = false;
+            int64_t offj = 0, begj = 0;
+            if (j < qlen) {
+                offj = qoff[j];
+                inwin = offj < b + kWave;
+            }
+            if (inwin) begj = g.rowptr[q[j]];
+            if (lane == 0) *smask = 0;
+            __builtin_amdgcn_wave_barrier();
+            if (inwin) atomicOr((unsigned long long *)smask, 1ull << (offj - b));
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t starts = *smask;
+            const int ns = __popcll(ballot(inwin));
+            const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+            const int c = __popcll(starts & le);
+            const int src = c > 0 ? c - 1 : 0;
+            const int64_t sb = shfl64(begj, src), so = shfl64(offj, src);
+            const int64_t e = b + lane;
+            if (e < a1) {
+                const int64_t beg = c ? sb : carry_beg;
+                const int64_t off = c ? so : carry_off;
+                const int32_t v = g.colidx[beg + (e - off)];
+                const uint64_t bit = 1ull << (v & 63);
+                if (!(s.V[v >> 6] & bit)) {
+                    if (mode == MODE_PUSH_BYTES) {
+                        s.nextb[v] = 1;
+                    } else {
+                        const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
+                        if (!(old & bit)) {
+                            atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                            const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
+                            const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+                            append_one(s, cur, L, v, od, id);
+                        }
+                    }
+                }
+            }
+            if (ns > 0) {
+                carry_beg = shfl64(begj, ns - 1);
+                carry_off = shfl64(offj, ns - 1);
+            }
+            base += ns;
+            starts_seen += ns;
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    // 4 B per frontier edge, 20 B (row pointer, queue entry, offset) per frontier vertex
+    if (units && lane == 0) unit_add(units, 0, 4 * (e1 - e0) + 20 * starts_seen);
 }
 
 // ------------------------------------------------------------------ bottom-up
 
 // Each wave takes 64-vertex words in turn.  Unvisited vertices of in-degree up
 // to `light` scan alone (4 in-edges per round); heavier ones up to g.heavy are
-// scanned by the whole wave, 256 in-edges per round; heavier still are left
-// for the chunk kernel.
-__device__ void pull_expand(int L, const Graph &g, const State &s, int light, int64_t *units) {
+// scanned by the whole wave, 256 in-edges per round; heavier still come from
+// the chunk table after the words.
+__device__ void pull_hop(int L, const Graph &g, const State &s, int light, const HeavyChunks &hc, RegRec *cur,
+                         WaveBuf &wb, int64_t *units) {
     const int lane = lane_id();
-    const uint64_t *__restrict__ Fc = frontier(s, L - 1);
-    uint64_t *__restrict__ Fn = frontier(s, L);
+    light = std::min(light, g.heavy);  // the chunk table alone takes vertices above g.heavy
+    const uint64_t *__restrict__ Fc = s.F[(L - 1) % 3];
+    uint64_t *Fn = s.F[L % 3];
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     int64_t c_pe = 0, c_pv = 0;
-    for (int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < g.nw; w += nwaves) {
+    // a contiguous run of words per wave keeps its discoveries in one or two regions
+    const int64_t wpw = (g.nw + nwaves - 1) / nwaves;
+    const int64_t wb0 = std::min(wid * wpw, g.nw), wb1 = std::min(wb0 + wpw, g.nw);
+    for (int64_t w = wb0; w < wb1; ++w) {
         const uint64_t vis = s.V[w];
         const int64_t v = w * kWave + lane;
         const bool unv = v < g.n && !((vis >> lane) & 1ull);
-        uint64_t found_mask = 0;
-        if (ballot(unv)) {
-            int64_t b = 0, e = 0;
-            if (unv) {
-                b = g.in_rowptr[v];
-                e = g.in_rowptr[v + 1];
+        if (!ballot(unv)) continue;
+        int64_t b = 0, e = 0;
+        if (unv) {
+            b = g.in_rowptr[v];
+            e = g.in_rowptr[v + 1];
+        }
+        const int64_t d = e - b;
+        bool found = false;
+        int64_t examined = 0;
+        if (unv && d <= light) {
+            int64_t x = b;
+            for (; x + 4 <= e; x += 4) {
+                const int32_t u0 = g.in_colidx[x], u1 = g.in_colidx[x + 1];
+                const int32_t u2 = g.in_colidx[x + 2], u3 = g.in_colidx[x + 3];
+                const bool h0 = test_bit(Fc, u0), h1 = test_bit(Fc, u1);
+                const bool h2 = test_bit(Fc, u2), h3 = test_bit(Fc, u3);
+                if (h0 | h1 | h2 | h3) {
+                    examined += h0 ? 1 : h1 ? 2 : h2 ? 3 : 4;
+                    found = true;
+                    break;
+                }
+                examined += 4;
             }
-            const int64_t d = e - b;
-            bool found = false;
-            int64_t examined = 0;
-            if (unv && d <= light) {
-                int64_t x = b;
-                for (; x + 4 <= e; x += 4) {
-                    const int32_t u0 = g.in_colidx[x], u1 = g.in_colidx[x + 1];
-                    const int32_t u2 = g.in_colidx[x + 2], u3 = g.in_colidx[x + 3];
-                    const bool h0 = test_bit(Fc, u0), h1 = test_bit(Fc, u1);
-                    const bool h2 = test_bit(Fc, u2), h3 = test_bit(Fc, u3);
-                    if (h0 | h1 | h2 | h3) {
-                        examined += h0 ? 1 : h1 ? 2 : h2 ? 3 : 4;
+            if (!found) {
+                for (; x < e; ++x) {
+                    ++examined;
+                    if (test_bit(Fc, g.in_colidx[x])) {
                         found = true;
                         break;
                     }
-                    examined += 4;
-                }
-                if (!found) {
-                    for (; x < e; ++x) {
-                        ++examined;
-                        if (test_bit(Fc, g.in_colidx[x])) {
-                            found = true;
-                            break;
-                        }
-                    }
                 }
             }
-            uint64_t medium = ballot(unv && d > light && d <= g.heavy);
-            while (medium) {
-                const int h = __builtin_ctzll(medium);
-                medium &= medium - 1;
-                const int64_t hb = shfl64(b, h), he = shfl64(e, h);
-                bool hit = false;
-                int64_t scanned = 0;
-                for (int64_t x0 = hb; x0 < he; x0 += 4 * kWave) {
-                    bool any = false;
+        }
+        uint64_t medium = ballot(unv && d > light && d <= g.heavy);
+        while (medium) {
+            const int h = __builtin_ctzll(medium);
+            medium &= medium - 1;
+            const int64_t hb = shfl64(b, h), he = shfl64(e, h);
+            bool hit = false;
+            int64_t scanned = 0;
+            for (int64_t x0 = hb; x0 < he; x0 += 4 * kWave) {
+                bool any = false;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t x = x0 + r * kWave + lane;
-                        if (x < he) any |= test_bit(Fc, g.in_colidx[x]);
-                    }
-                    scanned += std::min<int64_t>(4 * kWave, he - x0);
-                    if (ballot(any)) {
-                        hit = true;
-                        break;
-                    }
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t x = x0 + r * kWave + lane;
+                    if (x < he) any |= test_bit(Fc, g.in_colidx[x]);
                 }
-                if (lane == h) {
-                    found = hit;
-                    examined = scanned;
+                scanned += std::min<int64_t>(4 * kWave, he - x0);
+                if (ballot(any)) {
+                    hit = true;
+                    break;
                 }
             }
-            found_mask = ballot(found);
-            if (units) {
-                c_pe += wave_sum(examined);
-                c_pv += __popcll(ballot(unv && d <= g.heavy));
+            if (lane == h) {
+                found = hit;
+                examined = scanned;
             }
         }
-        if (lane == 0) {
-            Fn[w] = found_mask;
-            if (found_mask) s.V[w] = vis | found_mask;
+        const uint64_t fm = ballot(found);
+        if (fm && lane == 0) {
+            // chunk waves may set heavy bits of the same words concurrently
+            atomicOr((unsigned long long *)&s.V[w], (unsigned long long)fm);
+            atomicOr((unsigned long long *)&Fn[w], (unsigned long long)fm);
+        }
+        int64_t od = 0;
+        if (found) od = g.directed ? g.rowptr[v + 1] - g.rowptr[v] : d;
+        wb_word(wb, s, cur, L, w, found, od, d);
+        if (units) {
+            c_pe += wave_sum(examined);
+            c_pv += __popcll(ballot(unv && d <= g.heavy));
         }
     }
-    if (units && lane == 0) {
-        // 4 B per examined in-edge, 16 B of row pointers per scanned vertex
-        unit_add(units, 0, 4 * c_pe + 16 * c_pv);
-        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, 2 * ((g.n + 7) / 8));
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) plain_expand_kernel(const PlainCtl *ctl, int L, Graph g, State s, int light,
-                                                             int64_t *units) {
-    const LevelState &st = ctl->st[(L - 1) & 1];
-    if (st.done) return;
-    if (st.dir == DIR_PUSH) {
-        push_expand(st, g, s, units);
-    } else {
-        pull_expand(L, g, s, light, units);
-    }
-}
-
-// Bottom-up chunks of heavy vertices: a wave scans one chunk of in-edges of a
-// still-unvisited vertex; a hit sets its frontier and visited bits atomically.
-__global__ void __launch_bounds__(kBlock) plain_pull_heavy_kernel(const PlainCtl *ctl, int L, Graph g, State s,
-                                                                 HeavyChunks hc, int64_t *units) {
-    const LevelState &st = ctl->st[(L - 1) & 1];
-    if (st.done || st.dir != DIR_PULL) return;
-    const int lane = lane_id();
-    const uint64_t *__restrict__ Fc = frontier(s, L - 1);
-    uint64_t *Fn = frontier(s, L);
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    int64_t examined = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; i < hc.n; i += nwaves) {
+    wb_flush(wb, s, cur, L);
+    // edge chunks of heavy vertices
+    int64_t h_ex = 0;
+    for (int64_t i = wid; i < hc.n; i += nwaves) {
         const int32_t v = hc.vert[i];
         const uint64_t bit = 1ull << (v & 63);
         // visited before this hop, or already found by another chunk
@@ -378,190 +463,165 @@ __global__ void __launch_bounds__(kBlock) plain_pull_heavy_kernel(const PlainCtl
                 const int64_t x = x0 + r * kWave + lane;
                 if (x < e) any |= test_bit(Fc, g.in_colidx[x]);
             }
-            examined += std::min<int64_t>(4 * kWave, e - x0);
+            h_ex += std::min<int64_t>(4 * kWave, e - x0);
             if (ballot(any)) {
                 hit = true;
                 break;
             }
         }
         if (hit && lane == 0) {
-            atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-            atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
-        }
-    }
-    if (units && lane == 0) unit_add(units, 0, 4 * examined);
-}
-
-// ------------------------------------------------------------------ count
-
-__global__ void __launch_bounds__(kBlock) plain_count_kernel(const PlainCtl *ctl, int L, Graph g, State s,
-                                                            int64_t *units) {
-    const LevelState &st = ctl->st[(L - 1) & 1];
-    if (st.done) return;
-    const bool pushed = st.dir == DIR_PUSH;
-    const int lane = lane_id();
-    const int wv = threadIdx.x / kWave;
-    uint64_t *__restrict__ Fn = frontier(s, L);
-    const int64_t w0 = (int64_t)blockIdx.x * s.wpb;
-    const int64_t w1 = std::min<int64_t>(w0 + s.wpb, g.nw);
-    int64_t c_cnt = 0, c_q = 0, c_mf = 0, c_din = 0;
-    for (int64_t w = w0 + wv; w < w1; w += kWavesPerBlock) {
-        const int64_t v = w * kWave + lane;
-        uint64_t m;
-        if (pushed) {
-            const uint8_t nb = v < g.n ? s.nextb[v] : 0;
-            const uint64_t vis = s.V[w];
-            m = ballot(nb && !((vis >> lane) & 1ull));
-            if (nb) s.nextb[v] = 0;
-            if (lane == 0) {
-                Fn[w] = m;
-                if (m) s.V[w] = vis | m;
+            const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
+            if (!(old & bit)) {
+                atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
+                const int64_t id = g.in_rowptr[v + 1] - g.in_rowptr[v];
+                append_one(s, cur, L, v, od, id);
             }
-        } else {
-            m = Fn[w];
-        }
-        if (m) {
-            const bool fresh = (m >> lane) & 1ull;
-            int64_t od = 0, din = 0;
-            if (fresh) {
-                od = g.rowptr[v + 1] - g.rowptr[v];
-                din = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
-            }
-            c_cnt += __popcll(m);
-            c_q += __popcll(ballot(fresh && od > 0));
-            c_mf += wave_sum(od);
-            c_din += wave_sum(din);
         }
     }
-    const bool l0 = lane == 0;
-    const int64_t t_cnt = block_sum(l0 ? c_cnt : 0), t_q = block_sum(l0 ? c_q : 0);
-    const int64_t t_mf = block_sum(l0 ? c_mf : 0), t_din = block_sum(l0 ? c_din : 0);
-    if (threadIdx.x < kPart) {
-        const int64_t val = threadIdx.x == 0 ? t_cnt : threadIdx.x == 1 ? t_q : threadIdx.x == 2 ? t_mf : t_din;
-        s.part[(int64_t)blockIdx.x * kPart + threadIdx.x] = val;
-        int64_t *sup = s.sup + ((int64_t)(L & 1) * s.nsup + blockIdx.x / s.sb) * kPart;
-        if (val) atomicAdd((unsigned long long *)&sup[threadIdx.x], (unsigned long long)val);
-    }
-    if (units && threadIdx.x == 0) {
-        if (blockIdx.x == 0) unit_add(units, 0, pushed ? g.n + 2 * ((g.n + 7) / 8) : (g.n + 7) / 8);
-        unit_add(units, 0, 16 * t_cnt);
+    if (units && lane == 0) {
+        // 4 B per examined in-edge, 16 B of row pointers per scanned vertex
+        unit_add(units, 0, 4 * (c_pe + h_ex) + 16 * c_pv);
+        if (wid == 0) unit_add(units, 0, 2 * ((g.n + 7) / 8));
     }
 }
 
-// ------------------------------------------------------------------ finish
-
-__global__ void __launch_bounds__(kBlock) plain_finish_kernel(PlainCtl *ctl, int L, Graph g, State s,
-                                                             int64_t *units) {
-    const LevelState &st = ctl->st[(L - 1) & 1];
-    if (st.done) return;
-    const int lane = lane_id();
-    const int wv = threadIdx.x / kWave;
-    const int64_t *sup = s.sup + (int64_t)(L & 1) * s.nsup * kPart;
-    // level totals and this block's exclusive queue / degree offsets
-    const int my_sup = blockIdx.x / s.sb;
-    int64_t t_cnt = 0, t_q = 0, t_mf = 0, t_din = 0, o_q = 0, o_mf = 0;
-    for (int i = threadIdx.x; i < s.nsup; i += kBlock) {
-        const int64_t *p = sup + (int64_t)i * kPart;
-        t_cnt += p[0];
-        t_q += p[1];
-        t_mf += p[2];
-        t_din += p[3];
-        if (i < my_sup) {
-            o_q += p[1];
-            o_mf += p[2];
-        }
+__global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L, Graph g, State s, int light,
+                                                          HeavyChunks hc, int64_t *units) {
+    if (!ctl->valid) return;
+    __shared__ int64_t s_epre[kMaxRegions + 1];
+    __shared__ int32_t s_qcnt[kMaxRegions];
+    __shared__ int64_t s_tot[2][kWavesPerBlock];
+    __shared__ uint64_t s_mask[kWavesPerBlock];
+    const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
+    // previous hop's region counters: prefix of degree sums, totals
+    const RegRec *prev = s.regs + (int64_t)((L - 1) % 3) * s.nreg;
+    int64_t qd = 0, fc = 0, fd = 0;
+    if (t < s.nreg) {
+        const RegRec rr = prev[t];
+        qd = pk_sum(rr.qpack);
+        fc = pk_count(rr.fpack);
+        fd = pk_sum(rr.fpack);
+        s_qcnt[t] = (int32_t)pk_count(rr.qpack);
     }
-    for (int b = my_sup * s.sb + threadIdx.x; b < blockIdx.x; b += kBlock) {
-        o_q += s.part[(int64_t)b * kPart + 1];
-        o_mf += s.part[(int64_t)b * kPart + 2];
+    const int64_t xq = wave_exclusive_sum(qd);
+    const int64_t wq = wave_sum(qd), wf = wave_sum(fc), wd = wave_sum(fd);
+    if (lane == 0) {
+        s_tot[0][wv] = wq;
+        s_tot[1][wv] = wf;
     }
-    t_cnt = block_sum(t_cnt);
-    t_q = block_sum(t_q);
-    t_mf = block_sum(t_mf);
-    t_din = block_sum(t_din);
-    o_q = block_sum(o_q);
-    o_mf = block_sum(o_mf);
-    // next state (every block computes the same)
-    const int64_t mu = st.mu - t_din;
-    const int done = (t_cnt == 0) || (L >= ctl->k);
-    int dir = st.dir;
+    __syncthreads();
+    int64_t E = 0, nf = 0, pre = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+        if (i < wv) pre += s_tot[0][i];
+        E += s_tot[0][i];
+        nf += s_tot[1][i];
+    }
+    if (t < s.nreg) s_epre[t] = pre + xq;
+    if (t == 0) s_epre[s.nreg] = E;
+    __syncthreads();
+    if (lane == 0) s_tot[0][wv] = wd;
+    __syncthreads();
+    int64_t din = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) din += s_tot[0][i];
+    const HopHdr hp = ctl->hdr[(L - 1) % 3];
+    const int64_t mu = hp.mu_before - din;
+    int dir = hp.dir;
     if (ctl->dir_mode == DIR_PUSH) {
         dir = DIR_PUSH;
     } else if (ctl->dir_mode == DIR_PULL) {
         dir = DIR_PULL;
     } else if (dir == DIR_PUSH) {
-        if (t_mf * (int64_t)ctl->alpha > mu) dir = DIR_PULL;
+        if (E * (int64_t)ctl->alpha > mu) dir = DIR_PULL;
     } else {
-        if (t_cnt * (int64_t)ctl->beta < g.n) dir = DIR_PUSH;
+        if (nf * (int64_t)ctl->beta < g.n) dir = DIR_PUSH;
     }
-    if (blockIdx.x == 0) {
-        int64_t *nsup = s.sup + (int64_t)((L + 1) & 1) * s.nsup * kPart;
-        if (!done)
-            for (int i = threadIdx.x; i < s.nsup * kPart; i += kBlock) nsup[i] = 0;
-        if (threadIdx.x == 0) {
-            LevelState &nx = ctl->st[L & 1];
-            nx.count = st.count + t_cnt;
-            nx.te = st.te + (L < ctl->k ? t_mf : 0);
-            nx.nf = t_cnt;
-            nx.qlen = t_q;
-            nx.mf = t_mf;
-            nx.mu = mu;
-            nx.dir = dir;
-            nx.done = done;
-            if (done) {
-                // later hops read either parity slot; both must say done
-                ctl->st[(L + 1) & 1].done = 1;
-                *ctl->out_count = nx.count;
-                if (ctl->out_te) *ctl->out_te = nx.te;
-            } else if (dir == DIR_PUSH) {
-                s.qoff[t_q] = t_mf;
-            }
-            if (units && !done && dir == DIR_PUSH) unit_add(units, 0, (g.n + 7) / 8 + 28 * t_q);
-        }
+    const int mode = nf == 0 ? MODE_IDLE
+                             : dir == DIR_PULL ? MODE_PULL
+                                               : (E <= ctl->push_atomic_max ? MODE_PUSH_ATOMIC : MODE_PUSH_BYTES);
+    if (blockIdx.x == 0 && t == 0) {
+        ctl->hdr[L % 3].mu_before = mu;
+        ctl->hdr[L % 3].dir = dir;
+        ctl->hdr[L % 3].mode = mode;
+        if (L >= 2) ctl->count_acc += nf;
+        ctl->te_acc += E;
+        if (units) unit_add(units, 0, 16 * s.nreg);
     }
-    if (done || dir != DIR_PUSH) return;
-    // ascending queue: each wave takes a contiguous quarter of the block's words
-    const uint64_t *__restrict__ Fn = frontier(s, L);
-    const int64_t w0 = (int64_t)blockIdx.x * s.wpb;
-    const int per = (s.wpb + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t a0 = std::min<int64_t>(w0 + (int64_t)wv * per, g.nw);
-    const int64_t a1 = std::min<int64_t>(std::min<int64_t>(a0 + per, w0 + s.wpb), g.nw);
-    __shared__ int64_t s_q[kWavesPerBlock], s_d[kWavesPerBlock];
-    int64_t tq = 0, td = 0;
-    for (int64_t w = a0; w < a1; ++w) {
-        const uint64_t m = Fn[w];
-        if (!m) continue;
+    // the slots hop l+1 writes start clear
+    RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < s.nreg; i += (int64_t)gridDim.x * kBlock) {
+        nx[i].qpack = 0;
+        nx[i].fpack = 0;
+    }
+    uint64_t *Fz = s.F[(L + 1) % 3];
+    for (int64_t w = (int64_t)blockIdx.x * kBlock + t; w < g.nw; w += (int64_t)gridDim.x * kBlock) Fz[w] = 0;
+    if (mode == MODE_IDLE) return;  // empty frontier: nothing left to find
+    RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
+    if (mode == MODE_PULL) {
+        __shared__ int32_t s_bv[kWavesPerBlock][kBufCap];
+        __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
+        WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
+        pull_hop(L, g, s, light, hc, cur, wb, units);
+    } else {
+        push_hop(L, mode, E, s_epre, s_qcnt, g, s, cur, &s_mask[wv], units);
+    }
+}
+
+// After a byte-mode push: ballot(mark AND NOT visited) per 64-vertex word is
+// the word's new frontier bits; visited |= them, marks cleared, and the word's
+// discoveries appended to its region's queue.
+__global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *ctl, int L, Graph g, State s,
+                                                              int64_t *units) {
+    if (!ctl->valid || ctl->hdr[L % 3].mode != MODE_PUSH_BYTES) return;
+    const int lane = lane_id();
+    uint64_t *Fn = s.F[L % 3];
+    RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (units && wid == 0 && lane == 0) unit_add(units, 0, g.n + 2 * ((g.n + 7) / 8));
+    __shared__ int32_t s_bv[kWavesPerBlock][kBufCap];
+    __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
+    const int wv = threadIdx.x / kWave;
+    WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
+    const int64_t wpw = (g.nw + nwaves - 1) / nwaves;
+    const int64_t wb0 = std::min(wid * wpw, g.nw), wb1 = std::min(wb0 + wpw, g.nw);
+    for (int64_t w = wb0; w < wb1; ++w) {
         const int64_t v = w * kWave + lane;
-        int64_t od = 0;
-        if ((m >> lane) & 1ull) od = g.rowptr[v + 1] - g.rowptr[v];
-        tq += __popcll(ballot(od > 0));
-        td += wave_sum(od);
+        const uint8_t nb = v < g.n ? s.nextb[v] : 0;
+        if (!ballot(nb)) continue;
+        const uint64_t vis = s.V[w];
+        const bool fresh = nb && !((vis >> lane) & 1ull);
+        const uint64_t m = ballot(fresh);
+        if (nb) s.nextb[v] = 0;
+        if (lane == 0 && m) {
+            s.V[w] = vis | m;
+            Fn[w] = m;
+        }
+        int64_t od = 0, id = 0;
+        if (fresh) {
+            od = g.rowptr[v + 1] - g.rowptr[v];
+            id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+        }
+        wb_word(wb, s, cur, L, w, fresh, od, id);
+        if (units && lane == 0) unit_add(units, 0, 16 * __popcll(m));
     }
-    if (lane == 0) {
-        s_q[wv] = tq;
-        s_d[wv] = td;
-    }
+    wb_flush(wb, s, cur, L);
+}
+
+__global__ void __launch_bounds__(kBlock) plain_final_kernel(PlainCtl *ctl, int k, State s) {
+    if (!ctl->valid) return;
+    const RegRec *last = s.regs + (int64_t)(k % 3) * s.nreg;
+    __shared__ int64_t s_t[kWavesPerBlock];
+    int64_t c = 0;
+    for (int i = threadIdx.x; i < s.nreg; i += kBlock) c += pk_count(last[i].fpack);
+    c = wave_sum(c);
+    if (lane_id() == 0) s_t[threadIdx.x / kWave] = c;
     __syncthreads();
-    int64_t qpos = o_q, dpos = o_mf;
-    for (int i = 0; i < wv; ++i) {
-        qpos += s_q[i];
-        dpos += s_d[i];
-    }
-    for (int64_t w = a0; w < a1; ++w) {
-        const uint64_t m = Fn[w];
-        if (!m) continue;
-        const int64_t v = w * kWave + lane;
-        int64_t od = 0;
-        if ((m >> lane) & 1ull) od = g.rowptr[v + 1] - g.rowptr[v];
-        const uint64_t qm = ballot(od > 0);
-        const int64_t dx = wave_exclusive_sum(od);
-        if (od > 0) {
-            const int64_t at = qpos + mask_rank(qm);
-            s.q[at] = (int32_t)v;
-            s.qoff[at] = dpos + dx;
-        }
-        qpos += __popcll(qm);
-        dpos += wave_sum(od);
+    if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) tot += s_t[i];
+        *ctl->out_count = ctl->count_acc + tot;
+        if (ctl->out_te) *ctl->out_te = ctl->te_acc;
     }
 }
 
@@ -578,7 +638,9 @@ struct PlainCtx {
     khop_graph *g = nullptr;
     PlainCtl *ctl = nullptr;
     State s{};
-    int expand_grid = 1;
+    int hop_grid = 1;
+    int init_grid = 1;
+    int compact_grid = 1;
     void *arena = nullptr;
 };
 
@@ -586,32 +648,32 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     PlainCtx *c = new PlainCtx();
     c->g = g;
     const int64_t n = g->n, nw = (n + 63) / 64;
-    // word ranges for count / finish: at most about 4096 blocks
-    int wpb = (int)std::max<int64_t>(16, (nw + 4095) / 4096);
-    wpb = (wpb + 3) & ~3;
-    const int nblk = (int)((nw + wpb - 1) / wpb);
-    const int sb = std::max(8, (int)std::ceil(std::sqrt((double)nblk)));
-    const int nsup = (nblk + sb - 1) / sb;
+    const int nreg = (int)std::min<int64_t>(kMaxRegions, nw);
+    const int rw = (int)((nw + nreg - 1) / nreg);
+    const int64_t rc = (int64_t)rw * kWave;
+    const int64_t slots = (int64_t)nreg * rc;  // >= n
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
     const size_t o_ctl = off;
     off += al(sizeof(PlainCtl));
     const size_t o_V = off;
     off += al(nw * 8);
-    const size_t o_F0 = off;
-    off += al(nw * 8);
-    const size_t o_F1 = off;
-    off += al(nw * 8);
+    size_t o_F[3];
+    for (int i = 0; i < 3; ++i) {
+        o_F[i] = off;
+        off += al(nw * 8);
+    }
     const size_t o_nb = off;
     off += al(n);
-    const size_t o_q = off;
-    off += al(n * 4);
-    const size_t o_qoff = off;
-    off += al((n + 1) * 8);
-    const size_t o_part = off;
-    off += al((size_t)nblk * kPart * 8);
-    const size_t o_sup = off;
-    off += al((size_t)2 * nsup * kPart * 8);
+    size_t o_q[2], o_qoff[2];
+    for (int i = 0; i < 2; ++i) {
+        o_q[i] = off;
+        off += al(slots * 4);
+        o_qoff[i] = off;
+        off += al(slots * 8);
+    }
+    const size_t o_regs = off;
+    off += al((size_t)3 * nreg * sizeof(RegRec));
     hipError_t e = hipMalloc(&c->arena, off);
     if (e != hipSuccess) {
         delete c;
@@ -621,18 +683,19 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     char *base = (char *)c->arena;
     c->ctl = (PlainCtl *)(base + o_ctl);
     c->s.V = (uint64_t *)(base + o_V);
-    c->s.F0 = (uint64_t *)(base + o_F0);
-    c->s.F1 = (uint64_t *)(base + o_F1);
+    for (int i = 0; i < 3; ++i) c->s.F[i] = (uint64_t *)(base + o_F[i]);
     c->s.nextb = (uint8_t *)(base + o_nb);
-    c->s.q = (int32_t *)(base + o_q);
-    c->s.qoff = (int64_t *)(base + o_qoff);
-    c->s.part = (int64_t *)(base + o_part);
-    c->s.sup = (int64_t *)(base + o_sup);
-    c->s.wpb = wpb;
-    c->s.nblk = nblk;
-    c->s.sb = sb;
-    c->s.nsup = nsup;
-    c->expand_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 15) / 16, (int64_t)g->cu_count * 8));
+    for (int i = 0; i < 2; ++i) {
+        c->s.q[i] = (int32_t *)(base + o_q[i]);
+        c->s.qoff[i] = (int64_t *)(base + o_qoff[i]);
+    }
+    c->s.regs = (RegRec *)(base + o_regs);
+    c->s.nreg = nreg;
+    c->s.rw = rw;
+    c->s.rc = rc;
+    c->hop_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 7) / 8, (int64_t)g->cu_count * 4));
+    c->init_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kBlock - 1) / kBlock, 512));
+    c->compact_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 15) / 16, (int64_t)g->cu_count * 4));
     KHOP_HIP(hipMemset(c->arena, 0, off));
     KHOP_HIP(hipDeviceSynchronize());
     return c;
@@ -663,44 +726,30 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
              ht.threshold};
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
-    const int nblk = c->s.nblk;
-    const int init_grid = (int)std::max<int64_t>(1, std::min<int64_t>((gr.nw + kBlock - 1) / kBlock, 256));
-    const int heavy_grid =
-        (int)std::max<int64_t>(1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, g->cu_count * 8));
     const int64_t nnz_in = g->nnz;
     for (int64_t i = 0; i < num_seeds; ++i) {
         {
             ProfScope ps(g, KK_PLAIN_INIT, st);
-            hipLaunchKernelGGL(plain_init_kernel, dim3(init_grid), dim3(kBlock), 0, st, c->ctl, gr, c->s, d_seeds, i,
-                               (int)k, P.dir_mode, P.alpha, P.beta, nnz_in, d_counts, d_te, ps.units());
+            hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, c->ctl, gr, c->s, d_seeds,
+                               i, (int)k, P.dir_mode, P.alpha, P.beta, (int64_t)P.push_atomic_max, nnz_in, d_counts,
+                               d_te, ps.units());
             ps.end(0, 1);
         }
         for (int L = 1; L <= k; ++L) {
             {
-                ProfScope ps(g, KK_PLAIN_EXPAND, st);
-                hipLaunchKernelGGL(plain_expand_kernel, dim3(c->expand_grid), dim3(kBlock), 0, st, c->ctl, L, gr,
-                                   c->s, P.pull_light, ps.units());
-                ps.end(0, 1);
-            }
-            if (ht.n > 0 && P.dir_mode != KHOP_DIR_PUSH) {
-                ProfScope ps(g, KK_PLAIN_PULL_HEAVY, st);
-                hipLaunchKernelGGL(plain_pull_heavy_kernel, dim3(heavy_grid), dim3(kBlock), 0, st, c->ctl, L, gr,
-                                   c->s, hc, ps.units());
+                ProfScope ps(g, KK_PLAIN_HOP, st);
+                hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
+                                   P.pull_light, hc, ps.units());
                 ps.end(0, 1);
             }
             {
                 ProfScope ps(g, KK_PLAIN_COMPACT, st);
-                hipLaunchKernelGGL(plain_count_kernel, dim3(nblk), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
-                                   ps.units());
-                ps.end(0, 1);
-            }
-            {
-                ProfScope ps(g, KK_PLAIN_QUEUE, st);
-                hipLaunchKernelGGL(plain_finish_kernel, dim3(nblk), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
-                                   ps.units());
+                hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, c->ctl, L, gr,
+                                   c->s, ps.units());
                 ps.end(0, 1);
             }
         }
+        hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kBlock), 0, st, c->ctl, (int)k, c->s);
     }
     KHOP_HIP(hipGetLastError());
 }

@@ -187,7 +187,7 @@ def test_repeat_runs_bit_identical(K, g0_gpu, g0):
             assert np.array_equal(g0_gpu.count(seeds, k), ref)
 
 
-@pytest.mark.parametrize("heavy", [64, 300, 4096])
+@pytest.mark.parametrize("heavy", [8, 32, 300, 4096])
 def test_directed_power_law_small(K, heavy):
     el = graphgen.chung_lu(60_000, 900_000, 6.0, seed=4)
     g = K.Graph.from_edgelist(el)
@@ -204,7 +204,7 @@ def test_directed_power_law_small(K, heavy):
     g.free()
 
 
-@pytest.mark.parametrize("heavy", [64, 128])
+@pytest.mark.parametrize("heavy", [1, 4, 64, 128])
 def test_g0_pull_heavy_chunks(K, g0, g0_oracle, heavy):
     """Low chunk thresholds send many scale-10 vertices through the chunk kernel."""
     el, seeds = g0
