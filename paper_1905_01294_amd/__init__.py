@@ -343,3 +343,42 @@ class Graph:
 
     def profile_read(self):
         return khop_profile_read(self._h)
+
+
+class Server:
+    """Continuous-batching k-hop server over resident graphs (see khop_server_* in include/khop.h)."""
+
+    def __init__(self, mem_budget_bytes: int, max_batch_seeds: int = 1024):
+        self._h = khop_server_create(mem_budget_bytes, max_batch_seeds)
+        self._graphs = []
+
+    def add_graph(self, graph: "Graph") -> int:
+        gid = khop_server_add_graph(self._h, graph.handle)
+        self._graphs.append(graph)  # keep the graph alive while served
+        return gid
+
+    def submit(self, graph_id: int, seed: int, k: int, deadline_ns: int = 0) -> int:
+        return khop_server_submit(self._h, graph_id, seed, k, deadline_ns)
+
+    def poll(self, max_results: int = 4096):
+        return khop_server_poll(self._h, max_results)
+
+    def drain(self, timeout_ms: int = 60000):
+        khop_server_drain(self._h, timeout_ms)
+
+    def close(self):
+        if self._h is not None:
+            khop_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def monotonic_ns() -> int:
+    """CLOCK_MONOTONIC in nanoseconds, the clock of the server's time stamps and deadlines."""
+    import time
+    return time.clock_gettime_ns(time.CLOCK_MONOTONIC)

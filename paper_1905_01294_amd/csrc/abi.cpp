@@ -14,6 +14,8 @@ static thread_local std::string t_err;
 
 void fail(int status, const std::string &msg) { throw Error{status, msg}; }
 
+void set_last_error(const std::string &msg) { t_err = msg; }
+
 void hip_fail(hipError_t e, const char *what, const char *file, int line) {
     const char *base = std::strrchr(file, '/');
     std::string m = std::string("HIP error ") + hipGetErrorName(e) + " (" + hipGetErrorString(e) + ") in " + what +

@@ -266,6 +266,82 @@ __global__ void batch_output_kernel(const int64_t *counts_acc, const int32_t *pe
     if (j < nslots) out[perm[j]] = counts_acc[j] - 1;
 }
 
+// Serving: counts of the finished seed bits of the words in `fin` (word w's
+// finished bits fin[w]), then those bits cleared from V, F and N so their slots
+// can take new seeds.  counts_acc[w*64 + bit] accumulates vertex counts.
+__global__ void __launch_bounds__(kBlock) serve_harvest_kernel(uint64_t *V, uint64_t *F, uint64_t *N, int64_t n, int W,
+                                                              const uint64_t *fin, int64_t *counts_acc) {
+    const int w = blockIdx.y;
+    const uint64_t fm = fin[w];
+    if (!fm) return;
+    const int lane = lane_id();
+    __shared__ int64_t s_acc[kWavesPerBlock][kWave];
+    int64_t acc = 0;
+    const int64_t nchunks = (n + kWave - 1) / kWave;
+    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c < nchunks;
+         c += (int64_t)gridDim.x * kWavesPerBlock) {
+        const int64_t v = c * kWave + lane;
+        const int64_t at = v * W + w;
+        const uint64_t x = v < n ? V[at] : 0ull;
+        const uint64_t xf = x & fm;
+        if (ballot(xf != 0)) {
+#pragma unroll 8
+            for (int bit = 0; bit < kWave; ++bit) {
+                if (!((fm >> bit) & 1ull)) continue;  // uniform
+                const int cnt = __popcll(ballot((xf >> bit) & 1ull));
+                if (lane == bit) acc += cnt;
+            }
+        }
+        if (v < n) {
+            if (xf) V[at] = x & ~fm;
+            if (F[at] & fm) F[at] &= ~fm;
+            if (N[at] & fm) N[at] &= ~fm;
+        }
+    }
+    s_acc[threadIdx.x / kWave][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        int64_t t = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) t += s_acc[i][threadIdx.x];
+        if (t) atomicAdd((unsigned long long *)&counts_acc[w * kWave + threadIdx.x], (unsigned long long)t);
+    }
+}
+
+// Serving: slot slots[i] gets seed seeds[i] (bit set in V and F).
+__global__ void serve_admit_kernel(uint64_t *V, uint64_t *F, int W, const int32_t *slots, const int32_t *seeds,
+                                   int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int j = slots[i];
+    const int64_t at = (int64_t)seeds[i] * W + (j >> 6);
+    const unsigned long long bit = 1ull << (j & 63);
+    atomicOr((unsigned long long *)&V[at], bit);
+    atomicOr((unsigned long long *)&F[at], bit);
+}
+
+// Serving: first hop of newly admitted slots, pushed from their seeds into the
+// next frontier Fn and V (after the bottom-up pass has written Fn).
+__global__ void __launch_bounds__(kBlock) serve_push_kernel(const int64_t *__restrict__ rowptr,
+                                                           const int32_t *__restrict__ colidx, int W,
+                                                           const int32_t *slots, const int32_t *seeds, int count,
+                                                           uint64_t *Fn, uint64_t *V) {
+    for (int i = blockIdx.x; i < count; i += gridDim.x) {
+        const int j = slots[i];
+        const int32_t s = seeds[i];
+        const int64_t b = rowptr[s], e = rowptr[s + 1];
+        const unsigned long long bit = 1ull << (j & 63);
+        for (int64_t x = b + threadIdx.x; x < e; x += kBlock) {
+            const int64_t at = (int64_t)colidx[x] * W + (j >> 6);
+            atomicOr((unsigned long long *)&Fn[at], bit);
+            atomicOr((unsigned long long *)&V[at], bit);
+        }
+    }
+}
+
+__global__ void fill_zero_i64(int64_t *a, int64_t n) {
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a[i] = 0;
+}
+
 }  // namespace
 
 struct BatchCtx {
@@ -463,6 +539,163 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     }
     hipLaunchKernelGGL(batch_output_kernel, dim3((nslots + 255) / 256), dim3(256), 0, st, c->acc, c->perm, nslots,
                        d_counts);
+    KHOP_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- serving
+
+struct ServeCtx {
+    khop_graph *g = nullptr;
+    int W = 0;
+    uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
+    int64_t *acc = nullptr;     // 64 * W counters
+    uint64_t *d_act = nullptr;  // W active masks of the bottom-up pass
+    uint64_t *d_fin = nullptr;  // W finished masks
+    int32_t *d_slots = nullptr, *d_seeds = nullptr;  // admitted (slot, seed) pairs
+    int32_t *d_one = nullptr;   // a flag that is always 1, d_one[1] a scratch flag
+    void *arena = nullptr;
+    // pinned staging
+    uint64_t *h_act = nullptr, *h_fin = nullptr;
+    int32_t *h_slots = nullptr, *h_seeds = nullptr;
+    int64_t *h_counts = nullptr;
+    void *h_arena = nullptr;
+};
+
+size_t serve_ctx_bytes(int64_t n, int words) { return (size_t)3 * 8 * (size_t)n * words; }
+
+ServeCtx *serve_ctx_create(khop_graph *g, int words) {
+    ServeCtx *c = new ServeCtx();
+    c->g = g;
+    c->W = words;
+    const int64_t n = g->n;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t bits = al((size_t)n * words * 8);
+    const int slots = 64 * words;
+    size_t off = 0;
+    const size_t oV = off;
+    off += bits;
+    const size_t oF = off;
+    off += bits;
+    const size_t oN = off;
+    off += bits;
+    const size_t oacc = off;
+    off += al(slots * 8);
+    const size_t oact = off;
+    off += al(words * 8);
+    const size_t ofin = off;
+    off += al(words * 8);
+    const size_t osl = off;
+    off += al(slots * 4);
+    const size_t ose = off;
+    off += al(slots * 4);
+    const size_t oone = off;
+    off += al(16);
+    if (hipMalloc(&c->arena, off) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        fail(KHOP_ENOMEM, "device allocation for a serving batch failed");
+    }
+    char *b = (char *)c->arena;
+    c->V = (uint64_t *)(b + oV);
+    c->F = (uint64_t *)(b + oF);
+    c->N = (uint64_t *)(b + oN);
+    c->acc = (int64_t *)(b + oacc);
+    c->d_act = (uint64_t *)(b + oact);
+    c->d_fin = (uint64_t *)(b + ofin);
+    c->d_slots = (int32_t *)(b + osl);
+    c->d_seeds = (int32_t *)(b + ose);
+    c->d_one = (int32_t *)(b + oone);
+    const size_t hb = 2 * words * 8 + 2 * slots * 4 + slots * 8;
+    if (hipHostMalloc(&c->h_arena, hb, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(c->arena);
+        delete c;
+        fail(KHOP_ENOMEM, "pinned allocation for a serving batch failed");
+    }
+    char *h = (char *)c->h_arena;
+    c->h_act = (uint64_t *)h;
+    c->h_fin = c->h_act + words;
+    c->h_counts = (int64_t *)(c->h_fin + words);
+    c->h_slots = (int32_t *)(c->h_counts + slots);
+    c->h_seeds = c->h_slots + slots;
+    KHOP_HIP(hipMemset(c->arena, 0, off));
+    const int32_t one = 1;
+    KHOP_HIP(hipMemcpy(c->d_one, &one, 4, hipMemcpyHostToDevice));
+    KHOP_HIP(hipDeviceSynchronize());
+    return c;
+}
+
+void serve_ctx_destroy(ServeCtx *c) {
+    if (!c) return;
+    if (c->h_arena) (void)hipHostFree(c->h_arena);
+    if (c->arena) (void)hipFree(c->arena);
+    delete c;
+}
+
+int serve_ctx_words(const ServeCtx *c) { return c->W; }
+int64_t *serve_ctx_counts(ServeCtx *c) { return c->h_counts; }
+
+template <int G>
+static void serve_pull(ServeCtx *c, hipStream_t st) {
+    khop_graph *g = c->g;
+    const int64_t n = g->n;
+    const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
+                                                                 (int64_t)g->cu_count * 16));
+    const HeavyTable &ht = batch_heavy_table(g);
+    hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
+                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, c->d_one, c->d_one + 1, nullptr);
+    if (ht.n > 0) {
+        const int hgrid = (int)std::max<int64_t>(
+            1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
+        hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
+                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, c->d_one, c->d_one + 1,
+                           nullptr);
+    }
+}
+
+void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
+                     const int32_t *seeds, int n_new, hipStream_t st) {
+    khop_graph *g = c->g;
+    const int W = c->W;
+    const int64_t n = g->n;
+    bool any_fin = false;
+    for (int w = 0; w < W; ++w) any_fin |= fin[w] != 0;
+    if (any_fin) {
+        std::copy(fin, fin + W, c->h_fin);
+        KHOP_HIP(hipMemcpyAsync(c->d_fin, c->h_fin, W * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(fill_zero_i64, dim3(1), dim3(256), 0, st, c->acc, (int64_t)64 * W);
+        const int cgx = (int)std::max<int64_t>(
+            1, std::min<int64_t>((n + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock), (int64_t)g->cu_count * 2));
+        hipLaunchKernelGGL(serve_harvest_kernel, dim3(cgx, W), dim3(kBlock), 0, st, c->V, c->F, c->N, n, W, c->d_fin,
+                           c->acc);
+        KHOP_HIP(hipMemcpyAsync(c->h_counts, c->acc, (size_t)64 * W * 8, hipMemcpyDeviceToHost, st));
+    }
+    if (n_new > 0) {
+        std::copy(slots, slots + n_new, c->h_slots);
+        std::copy(seeds, seeds + n_new, c->h_seeds);
+        KHOP_HIP(hipMemcpyAsync(c->d_slots, c->h_slots, (size_t)n_new * 4, hipMemcpyHostToDevice, st));
+        KHOP_HIP(hipMemcpyAsync(c->d_seeds, c->h_seeds, (size_t)n_new * 4, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(serve_admit_kernel, dim3((n_new + 255) / 256), dim3(256), 0, st, c->V, c->F, W, c->d_slots,
+                           c->d_seeds, n_new);
+    }
+    if (any_old || n_new > 0) {
+        // bottom-up pass for the running slots (it rewrites every word of N) ...
+        std::copy(act_old, act_old + W, c->h_act);
+        KHOP_HIP(hipMemcpyAsync(c->d_act, c->h_act, W * 8, hipMemcpyHostToDevice, st));
+        switch (W) {
+            case 1: serve_pull<1>(c, st); break;
+            case 2: serve_pull<2>(c, st); break;
+            case 4: serve_pull<4>(c, st); break;
+            case 8: serve_pull<8>(c, st); break;
+            default: serve_pull<16>(c, st); break;
+        }
+        // ... then the first hop of the new slots, pushed from their seeds
+        if (n_new > 0)
+            hipLaunchKernelGGL(serve_push_kernel, dim3(std::min(n_new, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
+                               g->d_colidx, W, c->d_slots, c->d_seeds, n_new, c->N, c->V);
+        std::swap(c->F, c->N);
+    }
     KHOP_HIP(hipGetLastError());
 }
 

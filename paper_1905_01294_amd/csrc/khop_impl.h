@@ -20,6 +20,7 @@ struct Error {
 };
 
 [[noreturn]] void fail(int status, const std::string &msg);
+void set_last_error(const std::string &msg);  // khop_last_error() of the calling thread
 [[noreturn]] void hip_fail(hipError_t e, const char *what, const char *file, int line);
 
 #define KHOP_HIP(call)                                                  \
@@ -173,6 +174,19 @@ int batch_ctx_words(const BatchCtx *c);
 // at depth h_ks_sorted[j] (non-increasing in j); its count goes to d_counts[h_perm[j]].
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
                const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st);
+
+// Serving batches (batched.hip): one per resident graph, W words of seed slots.
+struct ServeCtx;
+size_t serve_ctx_bytes(int64_t n, int words);
+ServeCtx *serve_ctx_create(khop_graph *g, int words);
+void serve_ctx_destroy(ServeCtx *c);
+int serve_ctx_words(const ServeCtx *c);
+int64_t *serve_ctx_counts(ServeCtx *c);  // pinned; counts of the last harvest, valid after its stream work
+// One scheduler iteration on stream st: harvest (count + clear) the finished
+// bits fin[W]; admit n_new seeds into slots; one hop for the running slots
+// act_old[W] (bottom-up) and the new slots (top-down from their seeds).
+void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
+                     const int32_t *seeds, int n_new, hipStream_t st);
 
 // heavy.cpp: (re)built when the threshold option changes; valid until the next change.
 const HeavyTable &plain_heavy_table(khop_graph *g);

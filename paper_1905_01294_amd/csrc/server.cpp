@@ -1,11 +1,362 @@
-// Serving scheduler (placeholder until the scheduler is in place).
+// Continuous-batching server for k-hop queries.
+//
+// The paper serves many concurrent queries from a worker pool, one query per
+// worker, arguing that throughput under concurrency matters more than the
+// latency of one query on all cores (Section II).  Here the GPU analog: every
+// resident graph has one running batched traversal whose 64*W seed-bit slots
+// are refilled as queries finish.  A scheduler thread, per graph:
+//   - when the graph's previous iteration has completed on its stream, turns
+//     the counts it harvested into results;
+//   - harvests slots whose query reached its k (bit-column popcount, bits
+//     cleared), admits queued queries (FIFO) into free slots, and enqueues one
+//     hop for every running slot -- new seeds go top-down from their seed,
+//     running ones bottom-up in the shared bitset product;
+//   - allocates a graph's batch only while it has work, sized by what the
+//     memory budget still allows (3 bitsets of n words per 64 slots), so
+//     queries wait rather than fail when memory is short.
+// Graphs have their own HIP streams, so their iterations overlap on the device.
+#include <time.h>
+
+#include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+
 #include "khop_impl.h"
 
-extern "C" {
-int khop_server_create(int64_t, int32_t, khop_server **) { return KHOP_EINTERNAL; }
-int khop_server_add_graph(khop_server *, khop_graph *, int32_t *) { return KHOP_EINTERNAL; }
-int khop_server_submit(khop_server *, int32_t, int32_t, int32_t, int64_t, uint64_t *) { return KHOP_EINTERNAL; }
-int khop_server_poll(khop_server *, khop_result *, int64_t, int64_t *) { return KHOP_EINTERNAL; }
-int khop_server_drain(khop_server *, int64_t) { return KHOP_EINTERNAL; }
-int khop_server_destroy(khop_server *) { return KHOP_OK; }
+namespace {
+
+int64_t mono_ns() {
+    timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
 }
+
+struct Request {
+    uint64_t ticket;
+    int32_t graph_id, seed, k;
+    int64_t t_submit, deadline;
+};
+
+struct Slot {
+    bool used = false;
+    int level = 0;
+    Request req{};
+    int64_t t_admit = 0;
+};
+
+struct GraphServe {
+    khop_graph *g = nullptr;
+    int id = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev = nullptr;
+    khop::ServeCtx *ctx = nullptr;
+    size_t ctx_bytes = 0;
+    std::deque<Request> queue;
+    std::vector<Slot> slots;
+    bool inflight = false;
+    std::vector<std::pair<int, Slot>> harvesting;  // slots whose counts the in-flight iteration produces
+};
+
+constexpr size_t kMaxQueued = 1 << 22;
+
+}  // namespace
+
+struct khop_server {
+    int64_t budget = 0;
+    int64_t used = 0;
+    int max_words = 16;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::vector<GraphServe *> graphs;
+    std::deque<Request> incoming;
+    std::deque<khop_result> done;
+    uint64_t next_ticket = 1;
+    int64_t submitted = 0, completed = 0;
+    bool stop = false;
+    int device = 0;
+    std::thread th;
+    std::string thread_error;
+};
+
+namespace {
+
+void finish(khop_server *s, const Request &r, int status, int64_t count, int64_t t_admit) {
+    khop_result res{};
+    res.ticket = r.ticket;
+    res.status = status;
+    res.graph_id = r.graph_id;
+    res.seed = r.seed;
+    res.k = r.k;
+    res.count = count;
+    res.t_submit_ns = r.t_submit;
+    res.t_admit_ns = t_admit;
+    res.t_done_ns = mono_ns();
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->done.push_back(res);
+    s->completed += 1;
+    s->cv_done.notify_all();
+}
+
+// Results of the iteration that just completed on gs's stream.
+void complete_iteration(khop_server *s, GraphServe &gs) {
+    if (gs.harvesting.empty()) return;
+    const int64_t *counts = khop::serve_ctx_counts(gs.ctx);
+    for (auto &h : gs.harvesting) finish(s, h.second.req, KHOP_OK, counts[h.first] - 1, h.second.t_admit);
+    gs.harvesting.clear();
+}
+
+bool ensure_ctx(khop_server *s, GraphServe &gs) {
+    if (gs.ctx) return true;
+    const int64_t per_word = (int64_t)khop::serve_ctx_bytes(gs.g->n, 1);
+    int64_t afford = (s->budget - s->used) / std::max<int64_t>(per_word, 1);
+    int words = 1;
+    while (words * 2 <= std::min<int64_t>(afford, s->max_words)) words *= 2;
+    if (afford < 1) return false;
+    gs.ctx = khop::serve_ctx_create(gs.g, words);
+    gs.ctx_bytes = khop::serve_ctx_bytes(gs.g->n, words);
+    s->used += (int64_t)gs.ctx_bytes;
+    gs.slots.assign((size_t)64 * words, Slot{});
+    return true;
+}
+
+void release_ctx(khop_server *s, GraphServe &gs) {
+    if (!gs.ctx) return;
+    KHOP_HIP(hipStreamSynchronize(gs.stream));
+    khop::serve_ctx_destroy(gs.ctx);
+    gs.ctx = nullptr;
+    s->used -= (int64_t)gs.ctx_bytes;
+    gs.ctx_bytes = 0;
+    gs.slots.clear();
+}
+
+// Plans and enqueues one iteration; returns true if work was enqueued.
+bool plan(khop_server *s, GraphServe &gs, int64_t now) {
+    // queued requests past their deadline time out; k == 0 needs no traversal
+    for (auto it = gs.queue.begin(); it != gs.queue.end();) {
+        if (it->deadline > 0 && now > it->deadline) {
+            finish(s, *it, KHOP_ETIMEDOUT, -1, 0);
+            it = gs.queue.erase(it);
+        } else if (it->k == 0) {
+            finish(s, *it, KHOP_OK, 0, now);
+            it = gs.queue.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    bool running = false;
+    for (auto &sl : gs.slots) running |= sl.used;
+    if (!running && gs.queue.empty()) {
+        release_ctx(s, gs);  // idle: give the memory back
+        return false;
+    }
+    if (!ensure_ctx(s, gs)) return false;  // waits for budget
+    const int W = khop::serve_ctx_words(gs.ctx);
+    std::vector<uint64_t> fin((size_t)W, 0), act((size_t)W, 0);
+    std::vector<int32_t> new_slots, new_seeds;
+    bool any_old = false;
+    for (int j = 0; j < 64 * W; ++j) {
+        Slot &sl = gs.slots[j];
+        if (!sl.used) continue;
+        if (sl.level >= sl.req.k) {
+            fin[j >> 6] |= 1ull << (j & 63);
+            gs.harvesting.push_back({j, sl});
+            sl.used = false;
+        } else {
+            act[j >> 6] |= 1ull << (j & 63);
+            any_old = true;
+        }
+    }
+    for (int j = 0; j < 64 * W && !gs.queue.empty(); ++j) {
+        Slot &sl = gs.slots[j];
+        if (sl.used) continue;
+        // a slot being harvested this iteration is cleared before the admission (stream order)
+        sl.used = true;
+        sl.level = 0;
+        sl.req = gs.queue.front();
+        sl.t_admit = now;
+        gs.queue.pop_front();
+        new_slots.push_back(j);
+        new_seeds.push_back(sl.req.seed);
+    }
+    if (gs.harvesting.empty() && !any_old && new_slots.empty()) return false;
+    khop::serve_iteration(gs.ctx, fin.data(), act.data(), any_old, new_slots.data(), new_seeds.data(),
+                          (int)new_slots.size(), gs.stream);
+    for (auto &sl : gs.slots)
+        if (sl.used) sl.level += 1;
+    KHOP_HIP(hipEventRecord(gs.ev, gs.stream));
+    gs.inflight = true;
+    return true;
+}
+
+void scheduler(khop_server *s) {
+    try {
+        bool device_set = false;
+        while (true) {
+            std::vector<GraphServe *> graphs;
+            {
+                std::unique_lock<std::mutex> lk(s->mu);
+                if (s->stop) break;
+                graphs = s->graphs;
+                while (!s->incoming.empty()) {
+                    Request r = s->incoming.front();
+                    s->incoming.pop_front();
+                    s->graphs[r.graph_id]->queue.push_back(r);
+                }
+            }
+            const int64_t now = mono_ns();
+            bool busy = false;
+            if (!graphs.empty() && !device_set) {
+                KHOP_HIP(hipSetDevice(graphs[0]->g->device));
+                device_set = true;
+            }
+            for (GraphServe *gs : graphs) {
+                if (gs->inflight) {
+                    if (hipEventQuery(gs->ev) != hipSuccess) {
+                        busy = true;
+                        continue;
+                    }
+                    gs->inflight = false;
+                    complete_iteration(s, *gs);
+                }
+                busy |= plan(s, *gs, now);
+                busy |= !gs->queue.empty();
+            }
+            if (!busy) {
+                std::unique_lock<std::mutex> lk(s->mu);
+                if (!s->stop && s->incoming.empty())
+                    s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+            } else {
+                std::this_thread::sleep_for(std::chrono::microseconds(5));
+            }
+        }
+    } catch (const khop::Error &e) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->thread_error = e.msg;
+        s->stop = true;
+        s->cv_done.notify_all();
+    } catch (...) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->thread_error = "scheduler failed";
+        s->stop = true;
+        s->cv_done.notify_all();
+    }
+}
+
+template <class F>
+int sguard(F &&f) {
+    try {
+        f();
+        return KHOP_OK;
+    } catch (const khop::Error &e) {
+        khop::set_last_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        khop::set_last_error("host allocation failed");
+        return KHOP_ENOMEM;
+    } catch (...) {
+        khop::set_last_error("internal error");
+        return KHOP_EINTERNAL;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int khop_server_create(int64_t mem_budget_bytes, int32_t max_batch_seeds, khop_server **out) {
+    return sguard([&] {
+        if (!out) khop::fail(KHOP_EINVAL, "out is NULL");
+        if (mem_budget_bytes <= 0) khop::fail(KHOP_EINVAL, "mem_budget_bytes must be positive");
+        if (max_batch_seeds < 64 || max_batch_seeds > 1024 || max_batch_seeds % 64)
+            khop::fail(KHOP_EINVAL, "max_batch_seeds must be a multiple of 64 in [64, 1024]");
+        auto *s = new khop_server();
+        s->budget = mem_budget_bytes;
+        s->max_words = max_batch_seeds / 64;
+        s->th = std::thread(scheduler, s);
+        *out = s;
+    });
+}
+
+int khop_server_add_graph(khop_server *s, khop_graph *g, int32_t *graph_id) {
+    return sguard([&] {
+        if (!s || !g || !graph_id) khop::fail(KHOP_EINVAL, "server, graph or graph_id is NULL");
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) khop::fail(KHOP_EINTERNAL, "server stopped: " + s->thread_error);
+        if (!s->graphs.empty() && s->graphs[0]->g->device != g->device)
+            khop::fail(KHOP_EINVAL, "all graphs of a server must live on one device");
+        KHOP_HIP(hipSetDevice(g->device));
+        auto *gs = new GraphServe();
+        gs->g = g;
+        gs->id = (int)s->graphs.size();
+        KHOP_HIP(hipStreamCreateWithFlags(&gs->stream, hipStreamNonBlocking));
+        KHOP_HIP(hipEventCreateWithFlags(&gs->ev, hipEventDisableTiming));
+        s->device = g->device;
+        s->graphs.push_back(gs);
+        *graph_id = gs->id;
+    });
+}
+
+int khop_server_submit(khop_server *s, int32_t graph_id, int32_t seed, int32_t k, int64_t deadline_ns,
+                       uint64_t *ticket) {
+    return sguard([&] {
+        if (!s || !ticket) khop::fail(KHOP_EINVAL, "server or ticket is NULL");
+        if (k < 0) khop::fail(KHOP_EINVAL, "k < 0");
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) khop::fail(KHOP_EINTERNAL, "server stopped: " + s->thread_error);
+        if (graph_id < 0 || graph_id >= (int32_t)s->graphs.size()) khop::fail(KHOP_EINVAL, "unknown graph_id");
+        if (seed < 0 || (int64_t)seed >= s->graphs[graph_id]->g->n) khop::fail(KHOP_EINVAL, "seed out of range");
+        if (s->incoming.size() >= kMaxQueued) khop::fail(KHOP_EBUSY, "request queue full");
+        Request r{s->next_ticket++, graph_id, seed, k, mono_ns(), deadline_ns};
+        s->incoming.push_back(r);
+        s->submitted += 1;
+        *ticket = r.ticket;
+        s->cv_work.notify_one();
+    });
+}
+
+int khop_server_poll(khop_server *s, khop_result *out, int64_t max, int64_t *n_out) {
+    return sguard([&] {
+        if (!s || !n_out || (max > 0 && !out)) khop::fail(KHOP_EINVAL, "server, out or n_out is NULL");
+        std::lock_guard<std::mutex> lk(s->mu);
+        int64_t n = 0;
+        while (n < max && !s->done.empty()) {
+            out[n++] = s->done.front();
+            s->done.pop_front();
+        }
+        *n_out = n;
+    });
+}
+
+int khop_server_drain(khop_server *s, int64_t timeout_ms) {
+    return sguard([&] {
+        if (!s) khop::fail(KHOP_EINVAL, "server is NULL");
+        std::unique_lock<std::mutex> lk(s->mu);
+        const bool ok = s->cv_done.wait_for(lk, std::chrono::milliseconds(std::max<int64_t>(timeout_ms, 0)),
+                                            [&] { return s->completed >= s->submitted || s->stop; });
+        if (s->stop && s->completed < s->submitted) khop::fail(KHOP_EINTERNAL, "server stopped: " + s->thread_error);
+        if (!ok) khop::fail(KHOP_ETIMEDOUT, "requests still pending after the timeout");
+    });
+}
+
+int khop_server_destroy(khop_server *s) {
+    return sguard([&] {
+        if (!s) return;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stop = true;
+            s->cv_work.notify_all();
+        }
+        if (s->th.joinable()) s->th.join();
+        for (GraphServe *gs : s->graphs) {
+            if (gs->stream) (void)hipStreamSynchronize(gs->stream);
+            if (gs->ctx) khop::serve_ctx_destroy(gs->ctx);
+            if (gs->ev) (void)hipEventDestroy(gs->ev);
+            if (gs->stream) (void)hipStreamDestroy(gs->stream);
+            delete gs;
+        }
+        delete s;
+    });
+}
+
+}  // extern "C"

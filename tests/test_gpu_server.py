@@ -1,0 +1,161 @@
+"""GPU tests of the continuous-batching server: every served count equals the
+oracle's (tolerance 0: counts are integers), alone and in a mix of seeds, k and
+graphs, with admissions while other queries are in flight, under tight memory
+budgets and with deadlines."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-server]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def K():
+    import paper_1905_01294_amd as K
+    return K
+
+
+@pytest.fixture(scope="module")
+def graphs(K, g0):
+    el0, _ = g0
+    el1 = graphgen.chung_lu(20_000, 200_000, 4.0, seed=3)
+    g = [K.Graph.from_edgelist(el0), K.Graph.from_edgelist(el1)]
+    o = [oracle.OracleGraph.from_edgelist(el0), oracle.OracleGraph.from_edgelist(el1)]
+    yield (el0, el1), g, o
+    for x in g:
+        x.free()
+
+
+def _collect(srv, expect_n, timeout=60.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < expect_n:
+        for r in srv.poll():
+            got[r.ticket] = r
+        if time.time() - t0 > timeout:
+            raise AssertionError(f"only {len(got)} of {expect_n} results")
+        time.sleep(0.001)
+    return got
+
+
+def test_mixed_batch_matches_oracle(K, graphs):
+    (el0, el1), g, o = graphs
+    srv = K.Server(1 << 30, 1024)
+    ids = [srv.add_graph(x) for x in g]
+    rng = np.random.default_rng(1)
+    reqs = []
+    for i in range(1500):
+        gi = int(rng.integers(0, 2))
+        el = (el0, el1)[gi]
+        s = int(rng.integers(0, el.n))
+        k = int(rng.choice([0, 1, 2, 3, 6]))
+        reqs.append((srv.submit(ids[gi], s, k), gi, s, k))
+    srv.drain(120000)
+    got = _collect(srv, len(reqs))
+    for t, gi, s, k in reqs:
+        r = got[t]
+        assert r.status == K.KHOP_OK
+        assert (r.graph_id, r.seed, r.k) == (ids[gi], s, k)
+        assert r.count == o[gi].khop(s, k)[0], (gi, s, k)
+        assert r.t_submit_ns <= r.t_done_ns
+    srv.close()
+
+
+def test_alone_equals_in_mix(K, graphs):
+    (el0, el1), g, o = graphs
+    srv = K.Server(1 << 30, 256)
+    gid = srv.add_graph(g[1])
+    seeds = graphgen.draw_seeds(el1, 40, seed=9)
+    alone = {}
+    for s in seeds[:10]:
+        t = srv.submit(gid, int(s), 3)
+        srv.drain(30000)
+        alone[int(s)] = _collect(srv, 1)[t].count
+    ticks = [(srv.submit(gid, int(s), 3), int(s)) for s in seeds]
+    srv.drain(30000)
+    mix = _collect(srv, len(ticks))
+    for t, s in ticks:
+        if s in alone:
+            assert mix[t].count == alone[s]
+        assert mix[t].count == o[1].khop(s, 3)[0]
+    srv.close()
+
+
+def test_open_loop_arrivals_while_running(K, graphs):
+    """Requests arrive from another thread while batches run; all are admitted and correct."""
+    (el0, el1), g, o = graphs
+    srv = K.Server(1 << 30, 128)
+    ids = [srv.add_graph(x) for x in g]
+    rng = np.random.default_rng(5)
+    plan = [(int(rng.integers(0, 2)), int(rng.choice([1, 2, 3, 6]))) for _ in range(600)]
+    plan = [(gi, int(rng.integers(0, (el0, el1)[gi].n)), k) for gi, k in plan]
+    gaps = rng.exponential(50e-6, size=len(plan))
+    tickets = []
+
+    def producer():
+        for (gi, s, k), gap in zip(plan, gaps):
+            tickets.append((srv.submit(ids[gi], s, k), gi, s, k))
+            time.sleep(gap)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    srv.drain(60000)
+    got = _collect(srv, len(tickets))
+    admitted_late = 0
+    for t, gi, s, k in tickets:
+        r = got[t]
+        assert r.status == K.KHOP_OK
+        assert r.count == o[gi].khop(s, k)[0]
+        admitted_late += r.t_admit_ns > r.t_submit_ns
+    assert admitted_late > 0
+    srv.close()
+
+
+def test_small_budget_one_word(K, graphs):
+    (el0, _), g, o = graphs
+    budget = 3 * 8 * el0.n  # exactly one 64-slot word for the scale-10 graph
+    srv = K.Server(budget, 1024)
+    gid = srv.add_graph(g[0])
+    seeds = np.nonzero(o[0].degrees() > 0)[0][:300]
+    ticks = [(srv.submit(gid, int(s), 2), int(s)) for s in seeds]
+    srv.drain(60000)
+    got = _collect(srv, len(ticks))
+    for t, s in ticks:
+        assert got[t].count == o[0].khop(s, 2)[0]
+    srv.close()
+
+
+def test_deadlines_when_no_memory(K, graphs):
+    (el0, _), g, o = graphs
+    srv = K.Server(1024, 64)  # too small for any batch: requests wait, then time out
+    gid = srv.add_graph(g[0])
+    t = srv.submit(gid, 1, 2, deadline_ns=K.monotonic_ns() + 20_000_000)
+    srv.drain(5000)
+    r = _collect(srv, 1)[t]
+    assert r.status == K.KHOP_ETIMEDOUT
+    srv.close()
+
+
+def test_k0_and_invalid(K, graphs):
+    (el0, _), g, o = graphs
+    srv = K.Server(1 << 28, 64)
+    gid = srv.add_graph(g[0])
+    t = srv.submit(gid, 3, 0)
+    srv.drain(5000)
+    r = _collect(srv, 1)[t]
+    assert r.status == K.KHOP_OK and r.count == 0
+    with pytest.raises(K.KhopError):
+        srv.submit(gid, el0.n, 1)
+    with pytest.raises(K.KhopError):
+        srv.submit(gid, 0, -1)
+    srv.close()
