@@ -64,7 +64,23 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the batched seeds-per-launch sweep")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--twitter", action="store_true",
+                    help="also load the 41.6M-vertex power-law graph and serve both graphs")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per offered-load level")
+    ap.add_argument("--autotune", action="store_true", help="autotune the graph before timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device buffers (the known-size kernel that scales PMC byte counters)")
+    ap.add_argument("--pmc-summary", metavar="DIR",
+                    help="summarise rocprofv3 --pmc FETCH_SIZE/WRITE_SIZE CSVs (bench_* and copy_*) in DIR as JSON")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(args.pmc_summary), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design is "
               "described but not built", file=sys.stderr)
@@ -82,6 +98,10 @@ def main():
     t0 = time.time()
     g = K.Graph.from_edgelist(el)
     log(f"device graph: n={g.n} arcs={g.num_arcs} in {time.time() - t0:.1f}s")
+    if args.autotune:
+        t0 = time.time()
+        g.autotune(0)
+        log(f"autotuned in {time.time() - t0:.1f}s")
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
@@ -154,8 +174,10 @@ def main():
         g.profile(False)
         dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
         achieved = dom["algorithmic_bytes"] / (dom["total_ms"] / 1000.0) / 1e9 if dom["total_ms"] > 0 else 0.0
+        tr = traffic_per_launch(dom_name)
         roofline = {"kernel": dom_name, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": round(tr, 1) if tr is not None else None, "traffic_unit": "bytes per launch",
                     "launches": dom["launches"], "avg_launch_us": round(1000.0 * dom["total_ms"] / dom["launches"], 3),
                     "algorithmic_bytes_per_launch": round(dom["algorithmic_bytes"] / dom["launches"], 1)}
         for name, kv in kernels.items():
@@ -174,6 +196,21 @@ def main():
                 lat.append((time.perf_counter() - t) * 1000.0)
             latency[f"k{k}"] = {"mean_ms": round(float(np.mean(lat)), 4), "p50_ms": round(pct(lat, 50), 4),
                                 "p99_ms": round(pct(lat, 99), 4), "n": len(lat)}
+
+    sweep = None if args.no_sweep else batched_sweep(g, el, K, torch)
+    serving = None
+    if not args.no_serving:
+        graphs = [("rmat21", g, el)]
+        g2 = None
+        if args.twitter:
+            t0 = time.time()
+            el2 = graphgen.twitter_like(seed=1)
+            g2 = K.Graph.from_edgelist(el2)
+            log(f"power-law graph: n={g2.n} arcs={g2.num_arcs} in {time.time() - t0:.1f}s")
+            graphs.append(("chunglu41.6M", g2, el2))
+        serving = serving_bench(K, graphs, args.serve_seconds)
+        if g2 is not None:
+            g2.free()
 
     # ---- CPU oracle baseline (host cores, same queries)
     cpu = None
@@ -221,12 +258,210 @@ def main():
                     "ms_per_pass": round(b_ms, 3), "seeds_per_launch": g.get_option(K.KHOP_OPT_BATCH_SEEDS)},
         "batched_vs_plain_qps": round(p_ms / b_ms, 3),
         "latency_host_api": latency,
+        "batched_sweep": sweep,
+        "serving": serving,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     g.free()
+
+
+KERNEL_SOURCES = {"plain": "paper_1905_01294_amd/csrc/plain.hip", "batch": "paper_1905_01294_amd/csrc/batched.hip"}
+
+
+def _source_sha(kernel):
+    import hashlib
+    path = os.path.join(ROOT, KERNEL_SOURCES[kernel.split("_")[0]])
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def pmc_summary(d, copy_bytes=256 << 20):
+    """Mean FETCH_SIZE / WRITE_SIZE (KiB per dispatch) per library kernel, with the
+    factors that make the counters read a 256 MiB copy as 256 MiB each way."""
+    import csv
+    import re
+    out = {"fetch_scale": None, "write_scale": None, "kernels": {}}
+    for c, key in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(os.path.join(d, f"copy_{c}_counter_collection.csv")))
+                if "copyBuffer" in r["Kernel_Name"]]
+        out[f"{key}_scale"] = round(copy_bytes / 1024.0 / (sum(vals) / len(vals)), 4)
+        acc = {}
+        for r in csv.DictReader(open(os.path.join(d, f"bench_{c}_counter_collection.csv"))):
+            m = re.search(r"(plain_[a-z]+|batch_[a-z_]+?)_kernel", r["Kernel_Name"])
+            if m:
+                acc.setdefault(m.group(1), []).append(float(r["Counter_Value"]))
+        for k, v in acc.items():
+            e = out["kernels"].setdefault(k, {"source_sha256_16": _source_sha(k)})
+            e[f"{key}_kib_per_dispatch"] = round(sum(v) / len(v), 1)
+            e["dispatches"] = len(v)
+    return out
+
+
+def traffic_per_launch(kernel):
+    """HBM bytes per launch of `kernel` from profiles/pmc_traffic.md, or None when absent or
+    when the kernel's source changed after the counters were taken."""
+    import re
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)```", open(path).read(), re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    e = d["kernels"].get(kernel)
+    if not e or e.get("source_sha256_16") != _source_sha(kernel):
+        return None
+    return 1024.0 * (e["fetch_kib_per_dispatch"] * d["fetch_scale"] + e["write_kib_per_dispatch"] * d["write_scale"])
+
+
+def copy_calibration(nbytes=256 << 20, reps=5):
+    """Device-to-device copies of a known size: under rocprofv3 --pmc their FETCH_SIZE and
+    WRITE_SIZE per dispatch give the factor between the counters and bytes moved."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": nbytes, "dispatches": reps}), flush=True)
+
+
+def batched_sweep(g, el, K, torch):
+    """Seeds per batched launch 64 / 256 / 1024 (prefixes of one 1024-seed draw) at k = 3 and 6."""
+    import graphgen
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    s1024 = graphgen.draw_seeds(el, 1024, seed=11)
+    d_s = torch.from_numpy(s1024).to(dev)
+    d_te = torch.empty(1024, dtype=torch.int64, device=dev)
+    d_c = torch.empty(1024, dtype=torch.int64, device=dev)
+    saved = g.get_option(K.KHOP_OPT_BATCH_SEEDS)
+    out = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for k in (3, 6):
+        g.count_dev(d_s, k, d_c, d_te, stream=stream)  # plain path: per-seed traversed edges
+        torch.cuda.synchronize()
+        te = d_te.cpu().numpy()
+        plain_counts = d_c.cpu().numpy()
+        e0.record(stream)
+        g.count_dev(d_s[:64], k, d_c[:64], stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        plain_ms = e0.elapsed_time(e1)
+        out[f"plain_k{k}"] = {"seeds": 64, "ms": round(plain_ms, 3), "qps": round(64 / (plain_ms / 1e3), 1),
+                              "gteps": round(float(te[:64].sum()) / (plain_ms / 1e3) / 1e9, 2)}
+        for per in (64, 256, 1024):
+            g.set_option(K.KHOP_OPT_BATCH_SEEDS, per)
+            d_k = torch.full((per,), k, dtype=torch.int32, device=dev)
+            d_b = torch.empty(per, dtype=torch.int64, device=dev)
+            g.count_batched_dev(d_s[:per], d_k, d_b, stream=stream)
+            torch.cuda.synchronize()
+            if not np.array_equal(d_b.cpu().numpy(), plain_counts[:per]):
+                raise SystemExit(f"batched counts differ from plain ({per} seeds, k={k})")
+            reps = 3
+            e0.record(stream)
+            for _ in range(reps):
+                g.count_batched_dev(d_s[:per], d_k, d_b, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            out[f"batch{per}_k{k}"] = {"seeds": per, "ms": round(ms, 3), "qps": round(per / (ms / 1e3), 1),
+                                       "gteps": round(float(te[:per].sum()) / (ms / 1e3) / 1e9, 2)}
+    g.set_option(K.KHOP_OPT_BATCH_SEEDS, saved)
+    log("batched sweep: " + ", ".join(f"{k}={v['qps']} q/s" for k, v in out.items()))
+    return out
+
+
+def serving_bench(K, graphs, seconds):
+    """Open-loop Poisson arrivals at 0.25, 0.5 and 0.8 of the closed-loop saturation rate.
+
+    Queries: k in {1, 2, 3, 6} with weights 0.4/0.3/0.2/0.1, seeds uniform over
+    non-isolated vertices, graph uniform over the resident graphs.  Latency is
+    completion minus scheduled arrival (CLOCK_MONOTONIC).
+    """
+    import threading
+
+    import graphgen
+    rng = np.random.default_rng(2024)
+    pools = [graphgen.draw_seeds(el, 50000, seed=21) for _, _, el in graphs]
+    srv = K.Server(96 << 30, 1024)
+    ids = [srv.add_graph(g) for _, g, _ in graphs]
+
+    def make(n):
+        gi = rng.integers(0, len(graphs), size=n)
+        ks = rng.choice(np.array([1, 2, 3, 6]), size=n, p=[0.4, 0.3, 0.2, 0.1])
+        si = rng.integers(0, 50000, size=n)
+        return [(int(a), int(pools[a][b]), int(c)) for a, b, c in zip(gi, si, ks)]
+
+    def collect(n, deadline_s=120.0):
+        got = {}
+        t_end = time.time() + deadline_s
+        while len(got) < n and time.time() < t_end:
+            for r in srv.poll(8192):
+                got[r.ticket] = r
+            time.sleep(0.0005)
+        return got
+
+    # warm-up and closed-loop saturation
+    for gi, s, k in make(2000):
+        srv.submit(ids[gi], s, k)
+    collect(2000)
+    n_sat = 20000
+    qs = make(n_sat)
+    t0 = time.perf_counter()
+    for gi, s, k in qs:
+        srv.submit(ids[gi], s, k)
+    got = collect(n_sat)
+    sat = len(got) / (time.perf_counter() - t0)
+    log(f"serving: closed-loop {sat:.0f} queries/s")
+    levels = []
+    check = []
+    for frac in (0.25, 0.5, 0.8):
+        qps = frac * sat
+        n = int(min(max(qps * seconds, 200), 60000))
+        qs = make(n)
+        gaps = rng.exponential(1.0 / qps, size=n)
+        sched = np.cumsum(gaps)
+        tick = {}
+        t_base = K.monotonic_ns() + 2_000_000
+
+        def producer():
+            for i, (gi, s, k) in enumerate(qs):
+                due = t_base + int(sched[i] * 1e9)
+                while K.monotonic_ns() < due:
+                    pass
+                tick[srv.submit(ids[gi], s, k)] = (due, i)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        got = collect(n)
+        lat = []
+        done_last = 0
+        for t, (due, i) in tick.items():
+            r = got.get(t)
+            if r is None or r.status != K.KHOP_OK:
+                continue
+            lat.append((r.t_done_ns - due) / 1e6)
+            done_last = max(done_last, r.t_done_ns)
+            if len(check) < 400 and i % 25 == 0:
+                check.append((qs[i], r.count))
+        span = (done_last - t_base) / 1e9 if done_last else float("nan")
+        levels.append({"offered_qps": round(qps, 1), "achieved_qps": round(len(lat) / span, 1), "n": n,
+                       "completed": len(lat), "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
+                       "mean_ms": round(float(np.mean(lat)), 3)})
+        log(f"serving at {qps:.0f} q/s offered: p50 {levels[-1]['p50_ms']} ms, p99 {levels[-1]['p99_ms']} ms")
+    srv.close()
+    # served counts against the plain path, query by query
+    ok = 0
+    for (gi, s, k), c in check:
+        ok += int(graphs[gi][1].count(np.array([s], np.int32), k)[0] == c)
+    return {"graphs": [name for name, _, _ in graphs], "k_weights": {"1": 0.4, "2": 0.3, "3": 0.2, "6": 0.1},
+            "max_batch_seeds": 1024, "saturation_qps": round(sat, 1), "levels": levels,
+            "checked_against_plain": len(check), "equal": ok}
 
 
 def _cpu_model():

@@ -14,7 +14,7 @@ OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkhop.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["graph.cpp", "heavy.cpp", "abi.cpp", "tune.cpp", "server.cpp", "plain.hip", "batched.hip"]
+SOURCES = ["graph.cpp", "heavy.cpp", "abi.cpp", "tune.cpp", "server.cpp", "plain.hip", "batched.hip", "prof.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + INCLUDE, "-I" + CSRC]

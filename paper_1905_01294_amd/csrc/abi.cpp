@@ -79,11 +79,13 @@ ProfScope::ProfScope(khop_graph *g, int kind, hipStream_t st) : g_(g), kind_(kin
     units_ = P.d_units + 4 * slot_;
     if (P.events.empty()) {
         hipEvent_t e;
-        KHOP_HIP(hipEventCreate(&e));
+        // timing-only events: no system-scope fence, so no cache writeback in the interval
+        KHOP_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         P.events.push_back(e);
     }
     e0_ = P.events.back();
     P.events.pop_back();
+    prof_delay(st_);
     KHOP_HIP(hipEventRecord(e0_, st_));
 }
 
@@ -93,7 +95,8 @@ void ProfScope::end(double fixed_bytes, double w0, double w1, double w2, double 
     std::lock_guard<std::mutex> lk(g_->prof_mu);
     if (P.events.empty()) {
         hipEvent_t e;
-        KHOP_HIP(hipEventCreate(&e));
+        // timing-only events: no system-scope fence, so no cache writeback in the interval
+        KHOP_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         P.events.push_back(e);
     }
     hipEvent_t e1 = P.events.back();
@@ -311,7 +314,7 @@ static void validate_seeds(const khop_graph *g, const int32_t *seeds, int64_t nu
 }
 
 // Runs a sorted batch plan: slots grouped in launches of at most `per` seeds.
-static void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int64_t num,
+void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int64_t num,
                         int64_t *d_counts, hipStream_t st) {
     std::vector<int32_t> order((size_t)num);
     std::iota(order.begin(), order.end(), 0);

@@ -129,7 +129,8 @@ class ProfScope {
     int64_t *units_ = nullptr;
 };
 
-void prof_collect(khop_graph *g);  // caller holds g->mu
+void prof_collect(khop_graph *g);  // caller holds g->prof_mu
+void prof_delay(hipStream_t st);    // prof.hip
 
 }  // namespace khop
 
@@ -165,6 +166,10 @@ void plain_ctx_destroy(PlainCtx *c);
 void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k,
                int64_t *d_counts, int64_t *d_te, hipStream_t st);
 void plain_fill_zero_outputs(int64_t *d_counts, int64_t *d_te, int64_t n, hipStream_t st);
+
+// abi.cpp: batched launches of a seed set (seeds on the device, ks on the host), pooled contexts
+void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int64_t num, int64_t *d_counts,
+                 hipStream_t st);
 
 // batched.hip
 BatchCtx *batch_ctx_create(khop_graph *g, int words);
