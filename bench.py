@@ -69,7 +69,7 @@ def main():
     ap.add_argument("--twitter", action="store_true",
                     help="also load the 41.6M-vertex power-law graph and serve both graphs")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per offered-load level")
-    ap.add_argument("--autotune", action="store_true", help="autotune the graph before timing")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default settings instead of tuned ones")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device buffers (the known-size kernel that scales PMC byte counters)")
     ap.add_argument("--pmc-summary", metavar="DIR",
@@ -86,6 +86,9 @@ def main():
               "described but not built", file=sys.stderr)
         sys.exit(2)
 
+    # tuned settings are cached per (architecture, graph content); the package ships the
+    # cache that khop_autotune wrote for the bench graphs on an MI355X
+    os.environ.setdefault("KHOP_TUNE_CACHE", os.path.join(ROOT, "paper_1905_01294_amd", "tuned.txt"))
     import torch
 
     import graphgen
@@ -98,10 +101,15 @@ def main():
     t0 = time.time()
     g = K.Graph.from_edgelist(el)
     log(f"device graph: n={g.n} arcs={g.num_arcs} in {time.time() - t0:.1f}s")
-    if args.autotune:
+    if not args.no_autotune:
         t0 = time.time()
         g.autotune(0)
-        log(f"autotuned in {time.time() - t0:.1f}s")
+        log(f"autotuned in {time.time() - t0:.1f}s: " + ", ".join(
+            f"{name}={g.get_option(opt)}" for name, opt in (
+                ("alpha", K.KHOP_OPT_ALPHA), ("beta", K.KHOP_OPT_BETA), ("pull_light", K.KHOP_OPT_PULL_LIGHT),
+                ("pull_heavy", K.KHOP_OPT_PULL_HEAVY), ("push_atomic", K.KHOP_OPT_PUSH_ATOMIC),
+                ("batch_seeds", K.KHOP_OPT_BATCH_SEEDS),
+                ("batch_heavy", K.KHOP_OPT_BATCH_HEAVY))))
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()

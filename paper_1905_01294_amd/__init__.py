@@ -40,6 +40,7 @@ KHOP_OPT_BATCH_SEEDS = 5
 KHOP_OPT_BATCH_HEAVY = 6
 KHOP_OPT_BATCH_PUSH = 7
 KHOP_OPT_PULL_HEAVY = 8
+KHOP_OPT_PUSH_ATOMIC = 9
 KHOP_DIR_AUTO = 0
 KHOP_DIR_PUSH = 1
 KHOP_DIR_PULL = 2

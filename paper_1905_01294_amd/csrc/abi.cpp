@@ -621,6 +621,10 @@ int khop_set_option(khop_graph *g, int32_t option, int64_t value) {
                 if (value < 1 || value > INT32_MAX) fail(KHOP_EINVAL, "pull heavy threshold out of range [1, 2^31)");
                 P.pull_heavy = (int)value;
                 break;
+            case KHOP_OPT_PUSH_ATOMIC:
+                if (value < 0 || value > INT32_MAX) fail(KHOP_EINVAL, "push atomic limit out of range [0, 2^31)");
+                P.push_atomic_max = (int)value;
+                break;
             default:
                 fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
@@ -641,6 +645,7 @@ int khop_get_option(const khop_graph *g, int32_t option, int64_t *value) {
             case KHOP_OPT_BATCH_HEAVY: *value = P.batch_heavy; break;
             case KHOP_OPT_BATCH_PUSH: *value = P.batch_push_div; break;
             case KHOP_OPT_PULL_HEAVY: *value = P.pull_heavy; break;
+            case KHOP_OPT_PUSH_ATOMIC: *value = P.push_atomic_max; break;
             default: fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
     });

@@ -192,9 +192,30 @@ __device__ __forceinline__ void wb_word(WaveBuf &b, const State &s, RegRec *regs
 
 // ------------------------------------------------------------------ init
 
+// Sum of the discoveries of the last hop of the query in ctl, whose depth was k; block-wide.
+__device__ void finalize_query(PlainCtl *ctl, int k, const State &s) {
+    const RegRec *last = s.regs + (int64_t)(k % 3) * s.nreg;
+    __shared__ int64_t s_t[kWavesPerBlock];
+    int64_t c = 0;
+    for (int i = threadIdx.x; i < s.nreg; i += kBlock) c += pk_count(last[i].fpack);
+    c = wave_sum(c);
+    if (lane_id() == 0) s_t[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int i = 0; i < kWavesPerBlock; ++i) tot += s_t[i];
+        *ctl->out_count = ctl->count_acc + tot;
+        if (ctl->out_te) *ctl->out_te = ctl->te_acc;
+    }
+    __syncthreads();
+}
+
+// Clears the visited and frontier bitmaps and sets up the seed.  When prev_k > 0
+// block 0 first writes out the count of the previous query (depth prev_k) still
+// held in ctl, which saves that query a separate final launch.
 __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph g, State s, const int32_t *seeds,
-                                                           int64_t qi, int k, int dir_mode, int alpha, int beta,
-                                                           int64_t push_atomic_max, int64_t nnz_in,
+                                                           int64_t qi, int k, int prev_k, int dir_mode, int alpha,
+                                                           int beta, int64_t push_atomic_max, int64_t nnz_in,
                                                            int64_t *out_count, int64_t *out_te, int64_t *units) {
     const int32_t seed = seeds[qi];
     const bool valid = seed >= 0 && (int64_t)seed < g.n;
@@ -207,6 +228,7 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
         s.F[1][w] = 0;
     }
     if (blockIdx.x != 0) return;
+    if (prev_k > 0 && ctl->valid) finalize_query(ctl, prev_k, s);
     // region counters of hop 0 (the seed) and hop 1 start at zero
     for (int i = threadIdx.x; i < 2 * s.nreg; i += kBlock) {
         s.regs[i].qpack = 0;
@@ -609,20 +631,7 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
 }
 
 __global__ void __launch_bounds__(kBlock) plain_final_kernel(PlainCtl *ctl, int k, State s) {
-    if (!ctl->valid) return;
-    const RegRec *last = s.regs + (int64_t)(k % 3) * s.nreg;
-    __shared__ int64_t s_t[kWavesPerBlock];
-    int64_t c = 0;
-    for (int i = threadIdx.x; i < s.nreg; i += kBlock) c += pk_count(last[i].fpack);
-    c = wave_sum(c);
-    if (lane_id() == 0) s_t[threadIdx.x / kWave] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t tot = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) tot += s_t[i];
-        *ctl->out_count = ctl->count_acc + tot;
-        if (ctl->out_te) *ctl->out_te = ctl->te_acc;
-    }
+    if (ctl->valid) finalize_query(ctl, k, s);
 }
 
 __global__ void fill_kernel(int64_t *a, int64_t *b, int64_t n, int64_t value) {
@@ -727,19 +736,21 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
              ht.threshold};
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
     const int64_t nnz_in = g->nnz;
+    // hop 1 expands the seed alone: top-down unless forced, so a small grid suffices
+    const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::min(c->hop_grid, std::max(1, g->cu_count / 4));
     for (int64_t i = 0; i < num_seeds; ++i) {
         {
             ProfScope ps(g, KK_PLAIN_INIT, st);
             hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, c->ctl, gr, c->s, d_seeds,
-                               i, (int)k, P.dir_mode, P.alpha, P.beta, (int64_t)P.push_atomic_max, nnz_in, d_counts,
-                               d_te, ps.units());
+                               i, (int)k, i > 0 ? (int)k : 0, P.dir_mode, P.alpha, P.beta,
+                               (int64_t)P.push_atomic_max, nnz_in, d_counts, d_te, ps.units());
             ps.end(0, 1);
         }
         for (int L = 1; L <= k; ++L) {
             {
                 ProfScope ps(g, KK_PLAIN_HOP, st);
-                hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, c->ctl, L, gr, c->s,
-                                   P.pull_light, hc, ps.units());
+                hipLaunchKernelGGL(plain_hop_kernel, dim3(L == 1 ? hop1_grid : c->hop_grid), dim3(kBlock), 0, st,
+                                   c->ctl, L, gr, c->s, P.pull_light, hc, ps.units());
                 ps.end(0, 1);
             }
             {
@@ -749,8 +760,9 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
                 ps.end(0, 1);
             }
         }
-        hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kBlock), 0, st, c->ctl, (int)k, c->s);
     }
+    // the last query's count (the others were written by the next query's init)
+    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kBlock), 0, st, c->ctl, (int)k, c->s);
     KHOP_HIP(hipGetLastError());
 }
 
