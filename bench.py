@@ -14,8 +14,8 @@ value = traversed edges credited to every answered query / step time (GTEPS),
 where a query's credit is the out-degree sum of the vertices at distance
 0..k-1 (the edges a top-down search inspects).
 
-After the timed steps, the same steps run once more with per-kernel HIP-event
-profiling for the roofline figure, per-query latencies are taken through the
+After the timed steps, three more steps run with per-kernel HIP-event profiling
+for the roofline figure, per-query latencies are taken through the
 host entry point, and (N = 1 only) the CPU oracle answers the query set on the
 host for the baseline; its counts are also compared with the GPU's.
 """
@@ -175,7 +175,7 @@ def main():
     kernels = None
     if not args.no_profile:
         g.profile(True)
-        for _ in range(args.steps):
+        for _ in range(min(args.steps, 3)):
             step()
         torch.cuda.synchronize()
         kernels = g.profile_read()

@@ -76,7 +76,7 @@ ProfScope::ProfScope(khop_graph *g, int kind, hipStream_t st) : g_(g), kind_(kin
     if (!P.on) return;
     if (P.next_slot >= P.cap) prof_collect(g);
     slot_ = P.next_slot++;
-    units_ = P.d_units + 4 * slot_;
+    units_ = P.d_units + 4 * 64 * slot_;
     if (P.events.empty()) {
         hipEvent_t e;
         // timing-only events: no system-scope fence, so no cache writeback in the interval
@@ -110,7 +110,8 @@ void ProfScope::end(double fixed_bytes, double w0, double w1, double w2, double 
 void prof_collect(khop_graph *g) {
     Profiler &P = g->prof;
     if (P.pending.empty()) return;
-    std::vector<int64_t> units((size_t)P.next_slot * 4, 0);
+    constexpr int kLanes = 64;  // per-field lanes the kernels spread their counter atomics over
+    std::vector<int64_t> units((size_t)P.next_slot * 4 * kLanes, 0);
     KHOP_HIP(hipEventSynchronize(P.pending.back().e1));
     for (auto &p : P.pending) KHOP_HIP(hipEventSynchronize(p.e1));
     if (P.next_slot > 0)
@@ -120,7 +121,11 @@ void prof_collect(khop_graph *g) {
         KHOP_HIP(hipEventElapsedTime(&ms, p.e0, p.e1));
         double bytes = p.fixed_bytes;
         if (p.slot >= 0)
-            for (int i = 0; i < 4; ++i) bytes += p.w[i] * (double)units[(size_t)p.slot * 4 + i];
+            for (int i = 0; i < 4; ++i) {
+                int64_t f = 0;
+                for (int l = 0; l < kLanes; ++l) f += units[((size_t)p.slot * 4 + i) * kLanes + l];
+                bytes += p.w[i] * (double)f;
+            }
         P.launches[p.kind] += 1;
         P.ms[p.kind] += ms;
         P.bytes[p.kind] += bytes;
@@ -128,7 +133,7 @@ void prof_collect(khop_graph *g) {
         P.events.push_back(p.e1);
     }
     P.pending.clear();
-    if (P.next_slot > 0) KHOP_HIP(hipMemset(P.d_units, 0, (size_t)P.next_slot * 4 * 8));
+    if (P.next_slot > 0) KHOP_HIP(hipMemset(P.d_units, 0, (size_t)P.next_slot * 4 * kLanes * 8));
     P.next_slot = 0;
 }
 
@@ -322,8 +327,7 @@ void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int
     const int per = std::max(64, std::min(1024, g->params.batch_seeds));
     for (int64_t at = 0; at < num; at += per) {
         const int64_t cnt = std::min<int64_t>(per, num - at);
-        int words = 1;
-        while (words * 64 < cnt) words <<= 1;
+        const int words = (int)((cnt + 63) / 64);  // exact: unused words would only widen every gather
         std::vector<int32_t> ks((size_t)cnt);
         for (int64_t j = 0; j < cnt; ++j) ks[j] = h_ks[order[at + j]];
         BatchSlot s = take_batch(g, words, st);
@@ -659,15 +663,15 @@ int khop_profile(khop_graph *g, int32_t enable) {
         Profiler &P = g->prof;
         if (enable) {
             if (!P.d_units) {
-                P.cap = 1 << 18;
-                if (hipMalloc(&P.d_units, (size_t)P.cap * 4 * 8) != hipSuccess) {
+                P.cap = 1 << 15;  // launches per collection; 2 KiB of counters each
+                if (hipMalloc(&P.d_units, (size_t)P.cap * 4 * 64 * 8) != hipSuccess) {
                     (void)hipGetLastError();
                     P.d_units = nullptr;
                     fail(KHOP_ENOMEM, "device allocation for profiling counters failed");
                 }
             }
             prof_collect(g);
-            KHOP_HIP(hipMemset(P.d_units, 0, (size_t)P.cap * 4 * 8));
+            KHOP_HIP(hipMemset(P.d_units, 0, (size_t)P.cap * 4 * 64 * 8));
             KHOP_HIP(hipDeviceSynchronize());
             P.next_slot = 0;
             std::fill(std::begin(P.launches), std::end(P.launches), 0);

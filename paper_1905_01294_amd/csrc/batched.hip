@@ -1,6 +1,6 @@
 // Batched multi-source k-hop count on gfx950.
 //
-// Up to 64*W seeds share one traversal: each vertex carries W 64-bit words
+// Up to 64*W seeds share one traversal (W = 1..16): each vertex carries W 64-bit words
 // of seed bits (vertex-major, word w of vertex v at v*W + w).  A hop is then
 // the boolean product of the paper's Section II with a dense bit matrix in
 // place of the frontier vector,
@@ -168,9 +168,9 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
     if (ballot(any) && lane == 0) atomicOr(flag, 1);
     if (units) {
         const int64_t ex = wave_sum(examined), sc = wave_sum(scanned);
-        if (lane == 0 && (ex | sc)) {
-            atomicAdd((unsigned long long *)&units[1], (unsigned long long)ex);
-            atomicAdd((unsigned long long *)&units[2], (unsigned long long)sc);
+        if (lane == 0) {
+            unit_add(units, 1, ex);
+            unit_add(units, 2, sc);
         }
     }
 }
@@ -228,9 +228,7 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
         }
     }
     if (ballot(any) && lane == 0) atomicOr(flag, 1);
-    if (units && lane == 0 && examined) {
-        atomicAdd((unsigned long long *)&units[1], (unsigned long long)examined);
-    }
+    if (lane == 0) unit_add(units, 1, examined);
 }
 
 // counts_acc[w*64 + bit] += number of vertices whose word w has that bit.
@@ -245,9 +243,10 @@ __global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__r
          c += (int64_t)gridDim.x * kWavesPerBlock) {
         const int64_t v = c * kWave + lane;
         const uint64_t x = v < n ? V[v * W + w] : 0ull;
-        if (!ballot(x != 0)) continue;
-#pragma unroll 8
-        for (int bit = 0; bit < kWave; ++bit) {
+        uint64_t any = wave_or(x);  // only bits set somewhere in these 64 words
+        while (any) {
+            const int bit = __builtin_ctzll(any);
+            any &= any - 1;
             const int cnt = __popcll(ballot((x >> bit) & 1ull));
             if (lane == bit) acc += cnt;
         }
@@ -346,7 +345,7 @@ __global__ void fill_zero_i64(int64_t *a, int64_t n) {
 
 struct BatchCtx {
     khop_graph *g = nullptr;
-    int W = 0;  // words per vertex (power of two)
+    int W = 0;  // words per vertex (1..16)
     uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
     int64_t *acc = nullptr;    // 64 * W counters
     uint64_t *act = nullptr;   // kMaxLevels * W active masks

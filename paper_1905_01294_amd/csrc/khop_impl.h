@@ -90,11 +90,12 @@ enum KernelKind {
 extern const char *const kKernelNames[KK_COUNT_KINDS];
 
 // Per-kernel profiling with HIP events.  Each profiled launch may also own a
-// slot of 4 int64 device counters that the kernel fills with the sizes its
-// traffic depends on (edges examined, frontier size, ...).
+// slot of 4 device counter fields (64 int64 lanes each, summed on the host)
+// that the kernel fills with the sizes its traffic depends on (edges examined,
+// frontier size, ...).
 struct Profiler {
     bool on = false;
-    int64_t *d_units = nullptr;  // cap * 4
+    int64_t *d_units = nullptr;  // cap * 4 * 64
     int64_t cap = 0;
     int64_t next_slot = 0;
     struct Pending {

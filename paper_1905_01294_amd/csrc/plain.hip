@@ -102,9 +102,6 @@ struct HeavyChunks {
     int64_t n;
 };
 
-__device__ __forceinline__ void unit_add(int64_t *units, int i, int64_t v) {
-    if (units && v) atomicAdd((unsigned long long *)&units[i], (unsigned long long)v);
-}
 
 __device__ __forceinline__ int64_t pk_count(uint64_t p) { return (int64_t)(p >> kSumBits); }
 __device__ __forceinline__ int64_t pk_sum(uint64_t p) { return (int64_t)(p & kSumMask); }
@@ -263,7 +260,7 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
         ctl->hdr[0].mu_before = nnz_in;
         ctl->hdr[0].dir = dir_mode == DIR_PULL ? DIR_PULL : DIR_PUSH;
         ctl->hdr[0].mode = MODE_IDLE;
-        if (units) units[0] = 3 * 8 * g.nw;
+        unit_add(units, 0, 3 * 8 * g.nw);
     }
 }
 
@@ -273,8 +270,11 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
 // concatenated adjacency lists, region after region.  Within a 64-edge window
 // of one region's queue, the owning entry of each lane is base - 1 + (number
 // of list starts at or before it).
-__device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const int32_t *qcnt, const Graph &g,
-                         const State &s, RegRec *cur, uint64_t *smask, int64_t *units) {
+// With `last` set (the query's final hop) discoveries are only counted into
+// *found: no frontier word, queue entry or degree is needed afterwards.
+__device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *epre, const int32_t *qcnt,
+                         const Graph &g, const State &s, RegRec *cur, uint64_t *smask, int64_t *found,
+                         int64_t *units) {
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
@@ -353,10 +353,14 @@ __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const 
                     } else {
                         const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
                         if (!(old & bit)) {
-                            atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-                            const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
-                            const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
-                            append_one(s, cur, L, v, od, id);
+                            if (last) {
+                                *found += 1;
+                            } else {
+                                atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                                const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
+                                const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+                                append_one(s, cur, L, v, od, id);
+                            }
                         }
                     }
                 }
@@ -380,8 +384,8 @@ __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const 
 // to `light` scan alone (4 in-edges per round); heavier ones up to g.heavy are
 // scanned by the whole wave, 256 in-edges per round; heavier still come from
 // the chunk table after the words.
-__device__ void pull_hop(int L, const Graph &g, const State &s, int light, const HeavyChunks &hc, RegRec *cur,
-                         WaveBuf &wb, int64_t *units) {
+__device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int light, const HeavyChunks &hc,
+                         RegRec *cur, WaveBuf &wb, int64_t *found_out, int64_t *units) {
     const int lane = lane_id();
     light = std::min(light, g.heavy);  // the chunk table alone takes vertices above g.heavy
     const uint64_t *__restrict__ Fc = s.F[(L - 1) % 3];
@@ -455,14 +459,19 @@ __device__ void pull_hop(int L, const Graph &g, const State &s, int light, const
             }
         }
         const uint64_t fm = ballot(found);
-        if (fm && lane == 0) {
-            // chunk waves may set heavy bits of the same words concurrently
-            atomicOr((unsigned long long *)&s.V[w], (unsigned long long)fm);
-            atomicOr((unsigned long long *)&Fn[w], (unsigned long long)fm);
+        if (last) {
+            // final hop: only the count matters (chunk vertices are counted below)
+            if (lane == 0) *found_out += __popcll(fm);
+        } else {
+            if (fm && lane == 0) {
+                // chunk waves may set heavy bits of the same words concurrently
+                atomicOr((unsigned long long *)&s.V[w], (unsigned long long)fm);
+                atomicOr((unsigned long long *)&Fn[w], (unsigned long long)fm);
+            }
+            int64_t od = 0;
+            if (found) od = g.directed ? g.rowptr[v + 1] - g.rowptr[v] : d;
+            wb_word(wb, s, cur, L, w, found, od, d);
         }
-        int64_t od = 0;
-        if (found) od = g.directed ? g.rowptr[v + 1] - g.rowptr[v] : d;
-        wb_word(wb, s, cur, L, w, found, od, d);
         if (units) {
             c_pe += wave_sum(examined);
             c_pv += __popcll(ballot(unv && d <= g.heavy));
@@ -494,10 +503,14 @@ __device__ void pull_hop(int L, const Graph &g, const State &s, int light, const
         if (hit && lane == 0) {
             const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
             if (!(old & bit)) {
-                atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-                const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
-                const int64_t id = g.in_rowptr[v + 1] - g.in_rowptr[v];
-                append_one(s, cur, L, v, od, id);
+                if (last) {
+                    *found_out += 1;
+                } else {
+                    atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                    const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
+                    const int64_t id = g.in_rowptr[v + 1] - g.in_rowptr[v];
+                    append_one(s, cur, L, v, od, id);
+                }
             }
         }
     }
@@ -569,23 +582,33 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
         ctl->te_acc += E;
         if (units) unit_add(units, 0, 16 * s.nreg);
     }
-    // the slots hop l+1 writes start clear
-    RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < s.nreg; i += (int64_t)gridDim.x * kBlock) {
-        nx[i].qpack = 0;
-        nx[i].fpack = 0;
+    const bool last = L >= ctl->k;  // the final hop only counts
+    if (!last) {
+        // the slots hop l+1 writes start clear
+        RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < s.nreg; i += (int64_t)gridDim.x * kBlock) {
+            nx[i].qpack = 0;
+            nx[i].fpack = 0;
+        }
+        uint64_t *Fz = s.F[(L + 1) % 3];
+        for (int64_t w = (int64_t)blockIdx.x * kBlock + t; w < g.nw; w += (int64_t)gridDim.x * kBlock) Fz[w] = 0;
     }
-    uint64_t *Fz = s.F[(L + 1) % 3];
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + t; w < g.nw; w += (int64_t)gridDim.x * kBlock) Fz[w] = 0;
     if (mode == MODE_IDLE) return;  // empty frontier: nothing left to find
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
+    int64_t found = 0;  // final hop: discoveries of this lane (push) or wave (pull)
     if (mode == MODE_PULL) {
         __shared__ int32_t s_bv[kWavesPerBlock][kBufCap];
         __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
         WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
-        pull_hop(L, g, s, light, hc, cur, wb, units);
+        pull_hop(L, last, g, s, light, hc, cur, wb, &found, units);
+        found = shfl64(found, 0);
     } else {
-        push_hop(L, mode, E, s_epre, s_qcnt, g, s, cur, &s_mask[wv], units);
+        push_hop(L, mode, last, E, s_epre, s_qcnt, g, s, cur, &s_mask[wv], &found, units);
+        found = wave_sum(found);
+    }
+    if (last && lane == 0 && found) {
+        const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+        atomicAdd((unsigned long long *)&cur[wid % s.nreg].fpack, (unsigned long long)pk(found, 0));
     }
 }
 
@@ -595,6 +618,7 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
 __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *ctl, int L, Graph g, State s,
                                                               int64_t *units) {
     if (!ctl->valid || ctl->hdr[L % 3].mode != MODE_PUSH_BYTES) return;
+    const bool last = L >= ctl->k;
     const int lane = lane_id();
     uint64_t *Fn = s.F[L % 3];
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
@@ -607,27 +631,47 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
     WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
     const int64_t wpw = (g.nw + nwaves - 1) / nwaves;
     const int64_t wb0 = std::min(wid * wpw, g.nw), wb1 = std::min(wb0 + wpw, g.nw);
-    for (int64_t w = wb0; w < wb1; ++w) {
-        const int64_t v = w * kWave + lane;
-        const uint8_t nb = v < g.n ? s.nextb[v] : 0;
-        if (!ballot(nb)) continue;
-        const uint64_t vis = s.V[w];
-        const bool fresh = nb && !((vis >> lane) & 1ull);
-        const uint64_t m = ballot(fresh);
-        if (nb) s.nextb[v] = 0;
-        if (lane == 0 && m) {
-            s.V[w] = vis | m;
-            Fn[w] = m;
+    int64_t found_total = 0;
+    // four words per round: their marks and visited words are loaded before any is used
+    for (int64_t w0 = wb0; w0 < wb1; w0 += 4) {
+        uint8_t nb[4];
+        uint64_t vis[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t v = (w0 + i) * kWave + lane;
+            nb[i] = (w0 + i < wb1 && v < g.n) ? s.nextb[v] : 0;
         }
-        int64_t od = 0, id = 0;
-        if (fresh) {
-            od = g.rowptr[v + 1] - g.rowptr[v];
-            id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vis[i] = ballot(nb[i]) ? s.V[w0 + i] : 0ull;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t w = w0 + i;
+            if (!ballot(nb[i])) continue;
+            const int64_t v = w * kWave + lane;
+            const bool fresh = nb[i] && !((vis[i] >> lane) & 1ull);
+            const uint64_t m = ballot(fresh);
+            if (nb[i]) s.nextb[v] = 0;
+            if (last) {  // final hop: count only
+                found_total += __popcll(m);
+                continue;
+            }
+            if (lane == 0 && m) {
+                s.V[w] = vis[i] | m;
+                Fn[w] = m;
+            }
+            int64_t od = 0, id = 0;
+            if (fresh) {
+                od = g.rowptr[v + 1] - g.rowptr[v];
+                id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+            }
+            wb_word(wb, s, cur, L, w, fresh, od, id);
+            found_total += __popcll(m);
         }
-        wb_word(wb, s, cur, L, w, fresh, od, id);
-        if (units && lane == 0) unit_add(units, 0, 16 * __popcll(m));
     }
     wb_flush(wb, s, cur, L);
+    if (last && lane == 0 && found_total)
+        atomicAdd((unsigned long long *)&cur[wid % s.nreg].fpack, (unsigned long long)pk(found_total, 0));
+    if (lane == 0) unit_add(units, 0, 16 * found_total);
 }
 
 __global__ void __launch_bounds__(kBlock) plain_final_kernel(PlainCtl *ctl, int k, State s) {

@@ -10,7 +10,7 @@ namespace {
 __global__ void prof_delay_kernel(uint64_t ticks) {
     // wall clock at 100 MHz; the iteration cap bounds the wait whatever the clock does
     const uint64_t t0 = wall_clock64();
-    for (int i = 0; i < (1 << 20); ++i) {
+    for (int i = 0; i < (1 << 22); ++i) {
         if (wall_clock64() - t0 >= ticks) break;
         __builtin_amdgcn_s_sleep(2);
     }
@@ -19,7 +19,8 @@ __global__ void prof_delay_kernel(uint64_t ticks) {
 }  // namespace
 
 void prof_delay(hipStream_t st) {
-    hipLaunchKernelGGL(prof_delay_kernel, dim3(1), dim3(64), 0, st, (uint64_t)3000);  // about 30 us
+    // about 200 us: longer than the host needs to enqueue the events and the kernel
+    hipLaunchKernelGGL(prof_delay_kernel, dim3(1), dim3(64), 0, st, (uint64_t)20000);
 }
 
 }  // namespace khop

@@ -49,5 +49,14 @@ __device__ __forceinline__ bool test_bit(const uint64_t *__restrict__ bm, int32_
     return (bm[(uint32_t)v >> 6] >> ((uint32_t)v & 63u)) & 1ull;
 }
 
+// Profiling counters of one launch: 4 fields x 64 lanes; each block adds to the
+// lane of its index mod 64 so that no single address serialises the atomics.
+constexpr int kUnitLanes = 64;
+__device__ __forceinline__ void unit_add(int64_t *units, int field, int64_t v) {
+    if (units && v)
+        atomicAdd((unsigned long long *)&units[field * kUnitLanes + (blockIdx.x & (kUnitLanes - 1))],
+                  (unsigned long long)v);
+}
+
 }  // namespace dev
 }  // namespace khop
