@@ -24,7 +24,7 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line) {
 }
 
 const char *const kKernelNames[KK_COUNT_KINDS] = {
-    "plain_init", "plain_hop", "plain_compact", "batch_init", "batch_push", "batch_apply", "batch_pull", "batch_pull_heavy",
+    "plain_init", "plain_hop", "plain_compact", "batch_init", "batch_push", "batch_pull", "batch_pull_heavy",
     "batch_count"};
 
 template <class F>

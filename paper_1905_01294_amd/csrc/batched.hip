@@ -8,13 +8,18 @@
 // where active_l keeps the seeds whose own k is at least l (mixed k in one
 // batch), followed by V |= N, F <- N.
 //   hop 1     top-down from the seeds: a block per seed ORs its bit into the
-//             out-neighbors' words (atomicOr), then `apply` masks by NOT V;
+//             out-neighbors' F and V words (atomicOr).  No mask is needed:
+//             before hop 1 seed j's bit is set only at seed j, which has no
+//             self-loop, so every bit pushed is new;
 //   hop >= 2  bottom-up: a group of G lanes (one per active word) per vertex
-//             gathers F[u] over the in-neighbors, stopping as soon as every
-//             still-needed bit of the vertex is found; vertices above the
-//             heavy threshold get a whole wave each (64/G edge streams);
-//   count     per seed column: 64 ballots per 64 vertex words, one lane per
-//             bit accumulating popcounts, minus the seed itself.
+//             scans the in-neighbors G at a time against a frontier bitmap
+//             (one bit per vertex, L2-resident) and gathers the words F[u] of
+//             the hits only, stopping as soon as every still-needed bit of
+//             the vertex is found; vertices above the heavy threshold are
+//             split into edge chunks of a whole wave each;
+//   count     per seed column: each 64x64 bit block of V (64 vertices, one
+//             word) is transposed across the wave with six butterfly
+//             exchanges, so lane j's popcount is column j's count.
 // Seeds arrive sorted by k (largest first), so at hop l only the leading
 // words still hold active seeds and the lane groups shrink with them.
 #include <algorithm>
@@ -31,97 +36,113 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
-__global__ void __launch_bounds__(kBlock) batch_zero_kernel(uint64_t *a, uint64_t *b, uint64_t *c, int64_t words,
-                                                           int64_t *acc, int64_t nacc, int32_t *flags, int nflags) {
+__global__ void __launch_bounds__(kBlock) batch_zero_kernel(uint64_t *a, uint64_t *b, int64_t words, uint64_t *fb,
+                                                           int64_t fb_words, int64_t *acc, int64_t nacc,
+                                                           int32_t *flags, int nflags) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride) {
         a[i] = 0;
         b[i] = 0;
-        c[i] = 0;
     }
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < fb_words; i += stride) fb[i] = 0;
     if (blockIdx.x == 0) {
         for (int64_t i = threadIdx.x; i < nacc; i += kBlock) acc[i] = 0;
         for (int i = threadIdx.x; i < nflags; i += kBlock) flags[i] = 0;
     }
 }
 
-// V and F get bit j at seed j.
-__global__ void __launch_bounds__(kBlock) batch_seed_kernel(uint64_t *V, uint64_t *F, const int32_t *seeds,
-                                                           const int32_t *perm, int nslots, int W) {
+// V gets bit j at seed j.
+__global__ void __launch_bounds__(kBlock) batch_seed_kernel(uint64_t *V, const int32_t *seeds, const int32_t *perm,
+                                                           int nslots, int W) {
     const int j = blockIdx.x * kBlock + threadIdx.x;
     if (j >= nslots) return;
     const int32_t s = seeds[perm[j]];
     const int64_t at = (int64_t)s * W + (j >> 6);
-    const unsigned long long bit = 1ull << (j & 63);
-    atomicOr((unsigned long long *)&V[at], bit);
-    atomicOr((unsigned long long *)&F[at], bit);
+    atomicOr((unsigned long long *)&V[at], 1ull << (j & 63));
 }
 
-// Hop 1: one block per seed slot with k >= 1 ORs its bit into N of each out-neighbor.
+// Sets bit v of a frontier bitmap; the plain read skips most repeats on hubs.
+__device__ __forceinline__ void fb_set(uint64_t *fb, int32_t v) {
+    const uint64_t bit = 1ull << (v & 63);
+    if (!(fb[v >> 6] & bit)) atomicOr((unsigned long long *)&fb[v >> 6], (unsigned long long)bit);
+}
+
+// Hop 1: one block per seed slot with k >= 1 ORs its bit into F and V of each
+// out-neighbor and marks the neighbor in the frontier bitmap.
 __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t *__restrict__ rowptr,
                                                                  const int32_t *__restrict__ colidx,
                                                                  const int32_t *seeds, const int32_t *perm,
                                                                  const int32_t *ks_sorted, int nslots, int W,
-                                                                 uint64_t *N) {
+                                                                 uint64_t *F, uint64_t *V, uint64_t *fb,
+                                                                 int32_t *flag) {
     for (int j = blockIdx.x; j < nslots; j += gridDim.x) {
         if (ks_sorted[j] < 1) continue;
         const int32_t s = seeds[perm[j]];
         const int64_t b = rowptr[s], e = rowptr[s + 1];
         const unsigned long long bit = 1ull << (j & 63);
         const int w = j >> 6;
+        if (e > b && threadIdx.x == 0) atomicOr(flag, 1);
         for (int64_t x = b + threadIdx.x; x < e; x += kBlock) {
             const int32_t v = colidx[x];
-            atomicOr((unsigned long long *)&N[(int64_t)v * W + w], bit);
+            atomicOr((unsigned long long *)&F[(int64_t)v * W + w], bit);
+            atomicOr((unsigned long long *)&V[(int64_t)v * W + w], bit);
+            fb_set(fb, v);
         }
     }
 }
 
-// After hop 1: x = N AND NOT V AND active; V |= x; F = x; N = 0.
-__global__ void __launch_bounds__(kBlock) batch_apply_kernel(uint64_t *V, uint64_t *F, uint64_t *N, int64_t n,
-                                                            int W, const uint64_t *act, int32_t *flag) {
-    const int64_t total = n * W;
-    bool any = false;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
-        const uint64_t nv = N[i];
-        const uint64_t x = nv & ~V[i] & act[i % W];
-        if (x) {
-            V[i] |= x;
-            any = true;
-        }
-        F[i] = x;
-        if (nv) N[i] = 0;
+// Bits of the groups of G lanes that have any bit of m: bit g for group g.
+template <int G>
+__device__ __forceinline__ uint64_t group_any(uint64_t m) {
+    if constexpr (G == 1) {
+        return m;
+    } else {
+        constexpr uint64_t gm = (1ull << G) - 1;
+        uint64_t r = 0;
+#pragma unroll
+        for (int g = 0; g < kWave / G; ++g)
+            if ((m >> (g * G)) & gm) r |= 1ull << g;
+        return r;
     }
-    if (ballot(any) && lane_id() == 0) atomicOr(flag, 1);
 }
 
-// Hop >= 2, light vertices: G lanes per vertex (lane word = lane % G).
+// Hop >= 2, light vertices: G lanes per vertex (lane word = lane % G).  Each
+// step the group's lanes read R rounds of G consecutive in-edges and test them
+// against the frontier bitmap Fbc; for every hit the G lanes gather their
+// words of F[u].  Vertices with a new bit are marked in Fbn; Fbz (the bitmap
+// of the hop after this one) is cleared on the way.
 template <int G>
 __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__restrict__ in_rowptr,
                                                            const int32_t *__restrict__ in_colidx,
                                                            uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
                                                            uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
                                                            const uint64_t *__restrict__ act, int heavy,
-                                                           const int32_t *prev_flag, int32_t *flag,
+                                                           const uint64_t *__restrict__ Fbc, uint64_t *Fbn,
+                                                           uint64_t *Fbz, const int32_t *prev_flag, int32_t *flag,
                                                            int64_t *units) {
     if (*prev_flag == 0) return;  // empty frontier: nothing left to find
-    constexpr int VPW = kWave / G;  // vertices per wave
+    {
+        const int64_t nw = (n + kWave - 1) / kWave;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBlock)
+            Fbz[i] = 0;
+    }
+    constexpr int VPW = kWave / G;                          // vertices per wave
+    constexpr int R = G == 1 ? 4 : (G >= 16 ? 1 : 16 / G);  // rounds of G in-edges per step
     const int lane = lane_id();
     const int grp = lane / G;
     const int wi = lane % G;
-    const uint64_t grp_bits = (G == 64) ? ~0ull : (((1ull << G) - 1) << (grp * G));
+    const uint64_t grp_bits = ((G == 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G);
     const uint64_t actw = wi < wact ? act[wi] : 0ull;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     bool any = false;
-    int64_t examined = 0, scanned = 0;
+    int64_t examined = 0, scanned = 0, gathered = 0;
     for (int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; wv * VPW < n; wv += nwaves) {
         const int64_t v = wv * VPW + grp;
         const bool valid = v < n && wi < wact;
         const int64_t at = v * W + wi;
         uint64_t need = 0;
         int64_t b = 0, e = 0;
-        if (valid) {
-            need = ~V[at] & actw;
-        }
+        if (valid) need = ~V[at] & actw;
         // the group works on v only if some lane still needs a bit
         const bool grp_need = (ballot(need != 0) & grp_bits) != 0;
         if (grp_need && v < n) {
@@ -131,31 +152,52 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
         }
         uint64_t acc = 0;
         bool active = grp_need && (e > b);
-        if (grp_need && e - b > 0) scanned += (wi == 0);
-        int64_t x = b;
-        while (true) {
-            const bool done_lane = (acc & need) == need;
-            const uint64_t dm = ballot(!active || done_lane);
-            if ((dm & grp_bits) == grp_bits) active = false;
-            if (!ballot(active)) break;
-            if (active) {
-                // up to 4 in-neighbors per round
-                const int64_t r = std::min<int64_t>(4, e - x);
-                const int32_t u0 = in_colidx[x];
-                const int32_t u1 = r > 1 ? in_colidx[x + 1] : u0;
-                const int32_t u2 = r > 2 ? in_colidx[x + 2] : u0;
-                const int32_t u3 = r > 3 ? in_colidx[x + 3] : u0;
-                if (wi < wact) {
-                    acc |= F[(int64_t)u0 * W + wi] | F[(int64_t)u1 * W + wi] | F[(int64_t)u2 * W + wi] |
-                           F[(int64_t)u3 * W + wi];
-                }
-                if (wi == 0) examined += r;
-                x += r;
-                if (x >= e) active = false;
+        if (active) scanned += (wi == 0);
+        int64_t x0 = b;
+        while (ballot(active)) {
+            int32_t u[R];
+            bool hit[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t x = x0 + (int64_t)r * G + wi;
+                u[r] = (active && x < e) ? in_colidx[x] : -1;
             }
+#pragma unroll
+            for (int r = 0; r < R; ++r) hit[r] = u[r] >= 0 && test_bit(Fbc, u[r]);
+            if constexpr (G == 1) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (hit[r]) {
+                        acc |= F[(int64_t)u[r] * W];
+                        ++gathered;
+                    }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    uint64_t mine = ballot(hit[r]) & grp_bits;
+                    while (ballot(mine != 0)) {
+                        const int h = mine ? __builtin_ctzll(mine) : lane;
+                        const int32_t uh = __shfl(u[r], h, kWave);
+                        if (mine) {
+                            if (wi < wact) acc |= F[(int64_t)uh * W + wi];
+                            gathered += (wi == 0);
+                            mine &= mine - 1;
+                        }
+                    }
+                }
+            }
+            if (active) {
+                if (wi == 0) examined += std::min<int64_t>((int64_t)R * G, e - x0);
+                x0 += (int64_t)R * G;
+                if (x0 >= e) active = false;
+            }
+            // the group stops once every lane holds all of its needed bits
+            const bool ok = (acc & need) == need;
+            if ((ballot(!ok) & grp_bits) == 0) active = false;
         }
+        uint64_t nx = 0;
         if (valid && grp_need) {
-            const uint64_t nx = acc & need;
+            nx = acc & need;
             Fn[at] = nx;
             if (nx) {
                 V[at] |= nx;
@@ -164,13 +206,19 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
         } else if (valid) {
             Fn[at] = 0;
         }
+        const uint64_t gm = group_any<G>(ballot(nx != 0));
+        if (gm && lane == 0) {
+            const int64_t v0 = wv * VPW;  // VPW divides 64: the wave's vertices share one bitmap word
+            atomicOr((unsigned long long *)&Fbn[v0 >> 6], (unsigned long long)(gm << (v0 & 63)));
+        }
     }
     if (ballot(any) && lane == 0) atomicOr(flag, 1);
     if (units) {
-        const int64_t ex = wave_sum(examined), sc = wave_sum(scanned);
+        const int64_t ex = wave_sum(examined), sc = wave_sum(scanned), ga = wave_sum(gathered);
         if (lane == 0) {
             unit_add(units, 1, ex);
             unit_add(units, 2, sc);
+            unit_add(units, 3, ga);
         }
     }
 }
@@ -182,24 +230,29 @@ __device__ __forceinline__ uint64_t subgroup_or(uint64_t v) {
     return v;
 }
 
-// Hop >= 2, heavy vertices: one wave per edge chunk of a heavy vertex, 64/G
-// interleaved edge streams; the chunk's findings are ORed into the vertex's
-// next-frontier and visited words atomically (the light kernel left zeros).
+// Hop >= 2, heavy vertices: one wave per edge chunk of a heavy vertex.  The
+// wave tests 64 in-edges per round against the frontier bitmap, packs the hits
+// of four rounds in LDS and gathers their words with 64/G streams of G lanes;
+// the chunk's findings are ORed into the vertex's next-frontier and visited
+// words atomically (the light kernel left zeros).
 template <int G>
 __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     const int32_t *__restrict__ in_colidx, uint64_t *V, const uint64_t *__restrict__ F, uint64_t *Fn, int W, int wact,
     const uint64_t *__restrict__ act, const int32_t *__restrict__ hvert, const int64_t *__restrict__ hbegin,
-    const int64_t *__restrict__ hend, int64_t n_items, const int32_t *prev_flag, int32_t *flag, int64_t *units) {
+    const int64_t *__restrict__ hend, int64_t n_items, const uint64_t *__restrict__ Fbc, uint64_t *Fbn,
+    const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;
-    constexpr int S = kWave / G;  // edge streams
+    constexpr int S = kWave / G;  // gather streams
+    __shared__ int32_t s_hit[kWavesPerBlock][4 * kWave];
     const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
     const int wi = lane % G;
     const int sg = lane / G;
     const uint64_t actw = wi < wact ? act[wi] : 0ull;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     bool any = false;
-    int64_t examined = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; i < n_items; i += nwaves) {
+    int64_t examined = 0, gathered = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wv; i < n_items; i += nwaves) {
         const int64_t v = hvert[i];
         const int64_t at = v * W + wi;
         uint64_t need = 0;
@@ -207,28 +260,71 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
         if (!ballot(need != 0)) continue;
         const int64_t b = hbegin[i], e = hend[i];
         uint64_t acc = 0;
-        for (int64_t x0 = b; x0 < e; x0 += 4 * S) {
+        for (int64_t x0 = b; x0 < e; x0 += 4 * kWave) {
+            int32_t u[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t x = x0 + r * S + sg;
-                if (x < e && wi < wact) acc |= F[(int64_t)in_colidx[x] * W + wi];
+                const int64_t x = x0 + r * kWave + lane;
+                u[r] = x < e ? in_colidx[x] : -1;
             }
-            examined += std::min<int64_t>(4 * S, e - x0);
+            bool hit[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) hit[r] = u[r] >= 0 && test_bit(Fbc, u[r]);
+            // pack the hits of the four rounds, in order, into the wave's LDS row
+            int nh = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t hm = ballot(hit[r]);
+                if (hit[r]) s_hit[wv][nh + mask_rank(hm)] = u[r];
+                nh += __popcll(hm);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if (wi < wact)
+                for (int j = sg; j < nh; j += S) acc |= F[(int64_t)s_hit[wv][j] * W + wi];
+            gathered += nh;
+            examined += std::min<int64_t>(4 * kWave, e - x0);
+            // the row is rewritten next round only after every lane has read it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             const uint64_t full = subgroup_or<G>(acc);
             if (!ballot((full & need) != need)) break;
         }
         acc = subgroup_or<G>(acc);
-        if (sg == 0 && wi < wact) {
-            const uint64_t nx = acc & need;
-            if (nx) {
-                atomicOr((unsigned long long *)&Fn[at], (unsigned long long)nx);
-                atomicOr((unsigned long long *)&V[at], (unsigned long long)nx);
-                any = true;
-            }
+        const uint64_t nx = (sg == 0 && wi < wact) ? (acc & need) : 0ull;
+        if (nx) {
+            atomicOr((unsigned long long *)&Fn[at], (unsigned long long)nx);
+            atomicOr((unsigned long long *)&V[at], (unsigned long long)nx);
+            any = true;
         }
+        if (ballot(nx != 0) && lane == 0) fb_set(Fbn, (int32_t)v);
     }
     if (ballot(any) && lane == 0) atomicOr(flag, 1);
-    if (lane == 0) unit_add(units, 1, examined);
+    if (units && lane == 0) {
+        unit_add(units, 1, examined);
+        unit_add(units, 3, gathered);
+    }
+}
+
+// One butterfly stage of a 64x64 bit transpose held one row per lane: the
+// block of columns with bit s clear in the rows with bit s set trades places
+// with the block of columns with bit s set in the rows with bit s clear.
+__device__ __forceinline__ uint64_t transpose_stage(uint64_t x, int s, uint64_t lo) {
+    const uint64_t y = (uint64_t)__shfl_xor((long long)x, s, kWave);
+    return (lane_id() & s) ? ((x & ~lo) | ((y & ~lo) >> s)) : ((x & lo) | ((y & lo) << s));
+}
+
+// Lane i holds row i on entry; lane j holds column j (bit i = row i's bit j) on return.
+__device__ __forceinline__ uint64_t transpose64(uint64_t x) {
+    x = transpose_stage(x, 32, 0x00000000FFFFFFFFull);
+    x = transpose_stage(x, 16, 0x0000FFFF0000FFFFull);
+    x = transpose_stage(x, 8, 0x00FF00FF00FF00FFull);
+    x = transpose_stage(x, 4, 0x0F0F0F0F0F0F0F0Full);
+    x = transpose_stage(x, 2, 0x3333333333333333ull);
+    x = transpose_stage(x, 1, 0x5555555555555555ull);
+    return x;
 }
 
 // counts_acc[w*64 + bit] += number of vertices whose word w has that bit.
@@ -243,13 +339,8 @@ __global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__r
          c += (int64_t)gridDim.x * kWavesPerBlock) {
         const int64_t v = c * kWave + lane;
         const uint64_t x = v < n ? V[v * W + w] : 0ull;
-        uint64_t any = wave_or(x);  // only bits set somewhere in these 64 words
-        while (any) {
-            const int bit = __builtin_ctzll(any);
-            any &= any - 1;
-            const int cnt = __popcll(ballot((x >> bit) & 1ull));
-            if (lane == bit) acc += cnt;
-        }
+        if (!ballot(x != 0)) continue;
+        acc += __popcll(transpose64(x));
     }
     s_acc[threadIdx.x / kWave][lane] = acc;
     __syncthreads();
@@ -283,14 +374,7 @@ __global__ void __launch_bounds__(kBlock) serve_harvest_kernel(uint64_t *V, uint
         const int64_t at = v * W + w;
         const uint64_t x = v < n ? V[at] : 0ull;
         const uint64_t xf = x & fm;
-        if (ballot(xf != 0)) {
-#pragma unroll 8
-            for (int bit = 0; bit < kWave; ++bit) {
-                if (!((fm >> bit) & 1ull)) continue;  // uniform
-                const int cnt = __popcll(ballot((xf >> bit) & 1ull));
-                if (lane == bit) acc += cnt;
-            }
-        }
+        if (ballot(xf != 0)) acc += __popcll(transpose64(xf));
         if (v < n) {
             if (xf) V[at] = x & ~fm;
             if (F[at] & fm) F[at] &= ~fm;
@@ -319,20 +403,23 @@ __global__ void serve_admit_kernel(uint64_t *V, uint64_t *F, int W, const int32_
 }
 
 // Serving: first hop of newly admitted slots, pushed from their seeds into the
-// next frontier Fn and V (after the bottom-up pass has written Fn).
+// next frontier Fn, V and the next frontier bitmap (after the bottom-up pass
+// has written Fn).
 __global__ void __launch_bounds__(kBlock) serve_push_kernel(const int64_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ colidx, int W,
                                                            const int32_t *slots, const int32_t *seeds, int count,
-                                                           uint64_t *Fn, uint64_t *V) {
+                                                           uint64_t *Fn, uint64_t *V, uint64_t *Fbn) {
     for (int i = blockIdx.x; i < count; i += gridDim.x) {
         const int j = slots[i];
         const int32_t s = seeds[i];
         const int64_t b = rowptr[s], e = rowptr[s + 1];
         const unsigned long long bit = 1ull << (j & 63);
         for (int64_t x = b + threadIdx.x; x < e; x += kBlock) {
-            const int64_t at = (int64_t)colidx[x] * W + (j >> 6);
+            const int32_t v = colidx[x];
+            const int64_t at = (int64_t)v * W + (j >> 6);
             atomicOr((unsigned long long *)&Fn[at], bit);
             atomicOr((unsigned long long *)&V[at], bit);
+            fb_set(Fbn, v);
         }
     }
 }
@@ -347,6 +434,7 @@ struct BatchCtx {
     khop_graph *g = nullptr;
     int W = 0;  // words per vertex (1..16)
     uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
+    uint64_t *Fb = nullptr;    // three frontier bitmaps of nw words each (hop l uses slot l % 3)
     int64_t *acc = nullptr;    // 64 * W counters
     uint64_t *act = nullptr;   // kMaxLevels * W active masks
     int32_t *flags = nullptr;  // kMaxLevels + 1 frontier-nonempty flags
@@ -376,6 +464,8 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     off += bits;
     const size_t oN = off;
     off += bits;
+    const size_t oFb = off;
+    off += al(3 * (size_t)((n + 63) / 64) * 8);
     const size_t oacc = off;
     off += al(64 * (size_t)words * 8);
     const size_t oact = off;
@@ -396,6 +486,7 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     c->V = (uint64_t *)(b + oV);
     c->F = (uint64_t *)(b + oF);
     c->N = (uint64_t *)(b + oN);
+    c->Fb = (uint64_t *)(b + oFb);
     c->acc = (int64_t *)(b + oacc);
     c->act = (uint64_t *)(b + oact);
     c->flags = (int32_t *)(b + oflags);
@@ -431,18 +522,21 @@ int batch_ctx_words(const BatchCtx *c) { return c->W; }
 
 template <int G>
 static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, hipStream_t st, uint64_t *F, uint64_t *Fn) {
-    const int64_t n = g->n;
+    const int64_t n = g->n, nw = (n + 63) / 64;
     const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
                                                                  (int64_t)g->cu_count * 16));
     const uint64_t *act = c->act + (int64_t)(L - 1) * c->W;
+    const uint64_t *Fbc = c->Fb + ((L - 1) % 3) * nw;
+    uint64_t *Fbn = c->Fb + (L % 3) * nw, *Fbz = c->Fb + ((L + 1) % 3) * nw;
     {
         ProfScope ps(g, KK_BATCH_PULL, st);
         hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx,
-                           c->V, F, Fn, n, c->W, wact, act, batch_heavy_table(g).threshold, c->flags + (L - 1),
-                           c->flags + L, ps.units());
-        // bytes: 4 per examined edge + 8 per gathered word, 16 per scanned vertex, V/F/Fn words
-        ps.end(3.0 * 8.0 * (double)n * wact, 0, 4.0 + 8.0 * wact, 16.0);
+                           c->V, F, Fn, n, c->W, wact, act, batch_heavy_table(g).threshold, Fbc, Fbn, Fbz,
+                           c->flags + (L - 1), c->flags + L, ps.units());
+        // bytes: V read and write-back and Fn write per active word, the frontier bitmap once,
+        // 4 per examined in-edge, 16 per scanned vertex, 8 per gathered word
+        ps.end(3.0 * 8.0 * (double)n * wact + 2.0 * 8.0 * nw, 0, 4.0, 16.0, 8.0 * wact);
     }
     const HeavyTable &ht = batch_heavy_table(g);
     if (ht.n > 0) {
@@ -450,9 +544,9 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, hipStream_t
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         ProfScope ps(g, KK_BATCH_PULL_HEAVY, st);
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, F,
-                           Fn, c->W, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, c->flags + (L - 1),
+                           Fn, c->W, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, Fbc, Fbn, c->flags + (L - 1),
                            c->flags + L, ps.units());
-        ps.end(16.0 * (double)ht.n, 0, 4.0 + 8.0 * wact);
+        ps.end(16.0 * (double)ht.n, 0, 4.0, 0, 8.0 * wact);
     }
 }
 
@@ -487,26 +581,19 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     const int zgrid = (int)std::min<int64_t>(((int64_t)n * W + kBlock - 1) / kBlock, (int64_t)g->cu_count * 8);
     {
         ProfScope ps(g, KK_BATCH_INIT, st);
-        hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, c->F, c->N,
-                           (int64_t)n * W, c->acc, (int64_t)64 * W, c->flags, levels + 1);
-        ps.end(3.0 * 8.0 * n * W);
+        hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, c->F,
+                           (int64_t)n * W, c->Fb, 3 * ((n + 63) / 64), c->acc, (int64_t)64 * W, c->flags, levels + 1);
+        ps.end(2.0 * 8.0 * n * W + 3.0 * 8.0 * ((n + 63) / 64));
     }
-    hipLaunchKernelGGL(batch_seed_kernel, dim3((nslots + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->V, c->F,
-                       d_seeds, c->perm, nslots, W);
+    hipLaunchKernelGGL(batch_seed_kernel, dim3((nslots + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->V, d_seeds,
+                       c->perm, nslots, W);
     uint64_t *F = c->F, *Nb = c->N;
     if (levels >= 1) {
-        {
-            ProfScope ps(g, KK_BATCH_PUSH, st);
-            hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots, 4096)), dim3(kBlock), 0, st,
-                               g->d_rowptr, g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, Nb);
-            ps.end(0);
-        }
-        {
-            ProfScope ps(g, KK_BATCH_APPLY, st);
-            hipLaunchKernelGGL(batch_apply_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, F, Nb, n,
-                               W, c->act, c->flags + 1);
-            ps.end(4.0 * 8.0 * n * W);
-        }
+        ProfScope ps(g, KK_BATCH_PUSH, st);
+        hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
+                           g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, F, c->V, c->Fb + (int64_t)((n + 63) / 64),
+                           c->flags + 1);
+        ps.end(0);
     }
     for (int L = 2; L <= levels; ++L) {
         const int wa = wact[L];
@@ -547,6 +634,8 @@ struct ServeCtx {
     khop_graph *g = nullptr;
     int W = 0;
     uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
+    uint64_t *Fb = nullptr;  // three frontier bitmaps of nw words; slot fbi holds F's
+    int fbi = 0;
     int64_t *acc = nullptr;     // 64 * W counters
     uint64_t *d_act = nullptr;  // W active masks of the bottom-up pass
     uint64_t *d_fin = nullptr;  // W finished masks
@@ -560,7 +649,9 @@ struct ServeCtx {
     void *h_arena = nullptr;
 };
 
-size_t serve_ctx_bytes(int64_t n, int words) { return (size_t)3 * 8 * (size_t)n * words; }
+size_t serve_ctx_bytes(int64_t n, int words) {
+    return (size_t)3 * 8 * (size_t)n * words + (size_t)3 * 8 * (size_t)((n + 63) / 64);
+}
 
 ServeCtx *serve_ctx_create(khop_graph *g, int words) {
     ServeCtx *c = new ServeCtx();
@@ -577,6 +668,8 @@ ServeCtx *serve_ctx_create(khop_graph *g, int words) {
     off += bits;
     const size_t oN = off;
     off += bits;
+    const size_t oFb = off;
+    off += al((size_t)3 * ((n + 63) / 64) * 8);
     const size_t oacc = off;
     off += al(slots * 8);
     const size_t oact = off;
@@ -598,6 +691,7 @@ ServeCtx *serve_ctx_create(khop_graph *g, int words) {
     c->V = (uint64_t *)(b + oV);
     c->F = (uint64_t *)(b + oF);
     c->N = (uint64_t *)(b + oN);
+    c->Fb = (uint64_t *)(b + oFb);
     c->acc = (int64_t *)(b + oacc);
     c->d_act = (uint64_t *)(b + oact);
     c->d_fin = (uint64_t *)(b + ofin);
@@ -642,14 +736,18 @@ static void serve_pull(ServeCtx *c, hipStream_t st) {
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
                                                                  (int64_t)g->cu_count * 16));
     const HeavyTable &ht = batch_heavy_table(g);
+    const int64_t nw = (n + 63) / 64;
+    const uint64_t *Fbc = c->Fb + c->fbi * nw;
+    uint64_t *Fbn = c->Fb + ((c->fbi + 1) % 3) * nw, *Fbz = c->Fb + ((c->fbi + 2) % 3) * nw;
     hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
-                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, c->d_one, c->d_one + 1, nullptr);
+                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, Fbc, Fbn, Fbz, c->d_one, c->d_one + 1,
+                       nullptr);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
-                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, c->d_one, c->d_one + 1,
-                           nullptr);
+                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, Fbc, Fbn, c->d_one,
+                           c->d_one + 1, nullptr);
     }
 }
 
@@ -692,8 +790,10 @@ void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, 
         // ... then the first hop of the new slots, pushed from their seeds
         if (n_new > 0)
             hipLaunchKernelGGL(serve_push_kernel, dim3(std::min(n_new, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
-                               g->d_colidx, W, c->d_slots, c->d_seeds, n_new, c->N, c->V);
+                               g->d_colidx, W, c->d_slots, c->d_seeds, n_new, c->N, c->V,
+                               c->Fb + ((c->fbi + 1) % 3) * ((n + 63) / 64));
         std::swap(c->F, c->N);
+        c->fbi = (c->fbi + 1) % 3;
     }
     KHOP_HIP(hipGetLastError());
 }

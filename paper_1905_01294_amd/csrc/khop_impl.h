@@ -81,7 +81,6 @@ enum KernelKind {
     KK_PLAIN_COMPACT,
     KK_BATCH_INIT,
     KK_BATCH_PUSH,
-    KK_BATCH_APPLY,
     KK_BATCH_PULL,
     KK_BATCH_PULL_HEAVY,
     KK_BATCH_COUNT,

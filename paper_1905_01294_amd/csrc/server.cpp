@@ -108,11 +108,10 @@ void complete_iteration(khop_server *s, GraphServe &gs) {
 
 bool ensure_ctx(khop_server *s, GraphServe &gs) {
     if (gs.ctx) return true;
-    const int64_t per_word = (int64_t)khop::serve_ctx_bytes(gs.g->n, 1);
-    int64_t afford = (s->budget - s->used) / std::max<int64_t>(per_word, 1);
+    const int64_t avail = s->budget - s->used;
+    if ((int64_t)khop::serve_ctx_bytes(gs.g->n, 1) > avail) return false;
     int words = 1;
-    while (words * 2 <= std::min<int64_t>(afford, s->max_words)) words *= 2;
-    if (afford < 1) return false;
+    while (words * 2 <= s->max_words && (int64_t)khop::serve_ctx_bytes(gs.g->n, words * 2) <= avail) words *= 2;
     gs.ctx = khop::serve_ctx_create(gs.g, words);
     gs.ctx_bytes = khop::serve_ctx_bytes(gs.g->n, words);
     s->used += (int64_t)gs.ctx_bytes;

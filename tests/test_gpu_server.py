@@ -123,7 +123,8 @@ def test_open_loop_arrivals_while_running(K, graphs):
 
 def test_small_budget_one_word(K, graphs):
     (el0, _), g, o = graphs
-    budget = 3 * 8 * el0.n  # exactly one 64-slot word for the scale-10 graph
+    # exactly one 64-slot word for the scale-10 graph: V, F, N words and three frontier bitmaps
+    budget = 3 * 8 * el0.n + 3 * 8 * ((el0.n + 63) // 64)
     srv = K.Server(budget, 1024)
     gid = srv.add_graph(g[0])
     seeds = np.nonzero(o[0].degrees() > 0)[0][:300]
