@@ -2,10 +2,12 @@
 //
 // One hop is the masked boolean product of the paper's Section II: the next
 // frontier is (A^T f) AND NOT visited over the (OR, AND) semiring.  A query is
-// init, per hop a hop kernel and a compaction kernel (which exits at once
-// unless the hop marked bytes), and a final kernel; every cross-block hand-off
-// happens at a kernel boundary (intra-kernel release fences would write back
-// L2 on this multi-XCD part).
+// an init kernel and one hop kernel per hop; a hop 2..k-1 is followed by a
+// compaction kernel (which exits at once unless the hop marked bytes).  Hop 1
+// never marks bytes, and the last hop's marks are counted by the next query's
+// init (or the run's tail), so neither needs a compaction launch.  Every
+// cross-block hand-off happens at a kernel boundary (intra-kernel release
+// fences would write back L2 on this multi-XCD part).
 //
 // The frontier queue is split into regions of consecutive vertices; region r
 // owns queue slots [r*RC, (r+1)*RC) and one packed 64-bit counter
@@ -69,7 +71,15 @@ struct PlainCtl {
     int64_t *out_te;
     int64_t push_atomic_max;  // frontier edges up to which a push claims heads atomically
     int32_t k, dir_mode, alpha, beta;
-    int32_t valid, pad;
+    int32_t valid;
+    int32_t last_bytes;  // the finished query's last hop left byte marks (set by its last hop)
+    // a count waiting for the marks of a byte-mode last hop: the next init adds
+    // the marks into tail[] (spread over 64 lanes), then hop 1 or the final
+    // kernel writes pend_count + sum(tail) to *pend_out
+    int64_t pend_count;
+    int64_t *pend_out;
+    int32_t pend, pad;
+    int64_t tail[64];
 };
 
 struct Graph {
@@ -190,6 +200,7 @@ __device__ __forceinline__ void wb_word(WaveBuf &b, const State &s, RegRec *regs
 // ------------------------------------------------------------------ init
 
 // Sum of the discoveries of the last hop of the query in ctl, whose depth was k; block-wide.
+// If that hop left byte marks, the count waits in ctl for their number.
 __device__ void finalize_query(PlainCtl *ctl, int k, const State &s) {
     const RegRec *last = s.regs + (int64_t)(k % 3) * s.nreg;
     __shared__ int64_t s_t[kWavesPerBlock];
@@ -201,31 +212,86 @@ __device__ void finalize_query(PlainCtl *ctl, int k, const State &s) {
     if (threadIdx.x == 0) {
         int64_t tot = 0;
         for (int i = 0; i < kWavesPerBlock; ++i) tot += s_t[i];
-        *ctl->out_count = ctl->count_acc + tot;
+        if (ctl->last_bytes) {
+            ctl->pend_count = ctl->count_acc + tot;
+            ctl->pend_out = ctl->out_count;
+            ctl->pend = 1;
+        } else {
+            *ctl->out_count = ctl->count_acc + tot;
+        }
         if (ctl->out_te) *ctl->out_te = ctl->te_acc;
     }
     __syncthreads();
 }
 
-// Clears the visited and frontier bitmaps and sets up the seed.  When prev_k > 0
-// block 0 first writes out the count of the previous query (depth prev_k) still
-// held in ctl, which saves that query a separate final launch.
+// Writes a waiting count once the marks are in tail[] (one wave).
+__device__ void settle_pending(PlainCtl *ctl) {
+    const int lane = lane_id();
+    if (ctl->pend) {
+        const int64_t t = wave_sum(ctl->tail[lane]);
+        ctl->tail[lane] = 0;
+        if (lane == 0) {
+            *ctl->pend_out = ctl->pend_count + t;
+            ctl->pend = 0;
+        }
+    }
+    if (lane == 0) ctl->last_bytes = 0;
+}
+
+// Lanes whose byte of x is nonzero, one bit per byte (16 bytes).
+__device__ __forceinline__ uint32_t nonzero_bytes(uint4 x) {
+    auto f = [](uint32_t w) -> uint32_t {
+        const uint32_t y = (((w & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | w) & 0x80808080u;
+        return ((y >> 7) & 1u) | ((y >> 14) & 2u) | ((y >> 21) & 4u) | ((y >> 28) & 8u);
+    };
+    return f(x.x) | (f(x.y) << 4) | (f(x.z) << 8) | (f(x.w) << 12);
+}
+
+// Clears the visited and frontier bitmaps and sets up the seed qi.  When
+// prev_k > 0 it first closes the previous query (depth prev_k) still held in
+// ctl: block 0 writes its count (or parks it, see PlainCtl), and if that
+// query's last hop marked bytes every block counts and clears the marks of its
+// words.  With qi < 0 (the tail of a run) it only closes the previous query.
 __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph g, State s, const int32_t *seeds,
                                                            int64_t qi, int k, int prev_k, int dir_mode, int alpha,
                                                            int beta, int64_t push_atomic_max, int64_t nnz_in,
                                                            int64_t *out_count, int64_t *out_te, int64_t *units) {
-    const int32_t seed = seeds[qi];
+    const bool close_marks = prev_k > 0 && ctl->last_bytes;  // written only by hop kernels
+    const int32_t seed = qi >= 0 ? seeds[qi] : -1;
     const bool valid = seed >= 0 && (int64_t)seed < g.n;
     const int64_t sw = valid ? (seed >> 6) : -1;
     const uint64_t sbit = valid ? (1ull << (seed & 63)) : 0;
+    int64_t fresh = 0;
     for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock) {
-        const uint64_t x = (w == sw) ? sbit : 0ull;
-        s.V[w] = x;
-        s.F[0][w] = x;
-        s.F[1][w] = 0;
+        if (close_marks) {
+            // the 64 mark bytes of word w (the byte map is padded to whole words)
+            uint4 *mb = (uint4 *)(s.nextb + w * kWave);
+            uint64_t m = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) m |= (uint64_t)nonzero_bytes(mb[j]) << (16 * j);
+            if (m) {
+                fresh += __popcll(m & ~s.V[w]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) mb[j] = make_uint4(0, 0, 0, 0);
+            }
+        }
+        if (qi >= 0) {
+            const uint64_t x = (w == sw) ? sbit : 0ull;
+            s.V[w] = x;
+            s.F[0][w] = x;
+            s.F[1][w] = 0;
+        }
+    }
+    if (close_marks) {
+        fresh = wave_sum(fresh);
+        if (lane_id() == 0 && fresh)
+            atomicAdd((unsigned long long *)&ctl->tail[blockIdx.x & 63], (unsigned long long)fresh);
+        // the mark bytes and the visited words
+        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.n + 8 * g.nw);
     }
     if (blockIdx.x != 0) return;
     if (prev_k > 0 && ctl->valid) finalize_query(ctl, prev_k, s);
+    if (qi < 0) return;
     // region counters of hop 0 (the seed) and hop 1 start at zero
     for (int i = threadIdx.x; i < 2 * s.nreg; i += kBlock) {
         s.regs[i].qpack = 0;
@@ -523,6 +589,8 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
 
 __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L, Graph g, State s, int light,
                                                           HeavyChunks hc, int64_t *units) {
+    // hop 1 also writes the previous query's count if it waited for its marks
+    if (L == 1 && blockIdx.x == 0 && threadIdx.x < kWave) settle_pending(ctl);
     if (!ctl->valid) return;
     __shared__ int64_t s_epre[kMaxRegions + 1];
     __shared__ int32_t s_qcnt[kMaxRegions];
@@ -571,18 +639,20 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
     } else {
         if (nf * (int64_t)ctl->beta < g.n) dir = DIR_PUSH;
     }
+    const bool last = L >= ctl->k;  // the final hop only counts
+    // hop 1 never marks bytes: no compaction launch follows it
     const int mode = nf == 0 ? MODE_IDLE
-                             : dir == DIR_PULL ? MODE_PULL
-                                               : (E <= ctl->push_atomic_max ? MODE_PUSH_ATOMIC : MODE_PUSH_BYTES);
+                     : dir == DIR_PULL ? MODE_PULL
+                     : (E <= ctl->push_atomic_max || L == 1 ? MODE_PUSH_ATOMIC : MODE_PUSH_BYTES);
     if (blockIdx.x == 0 && t == 0) {
         ctl->hdr[L % 3].mu_before = mu;
         ctl->hdr[L % 3].dir = dir;
         ctl->hdr[L % 3].mode = mode;
+        if (last) ctl->last_bytes = mode == MODE_PUSH_BYTES;
         if (L >= 2) ctl->count_acc += nf;
         ctl->te_acc += E;
         if (units) unit_add(units, 0, 16 * s.nreg);
     }
-    const bool last = L >= ctl->k;  // the final hop only counts
     if (!last) {
         // the slots hop l+1 writes start clear
         RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
@@ -618,7 +688,6 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
 __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *ctl, int L, Graph g, State s,
                                                               int64_t *units) {
     if (!ctl->valid || ctl->hdr[L % 3].mode != MODE_PUSH_BYTES) return;
-    const bool last = L >= ctl->k;
     const int lane = lane_id();
     uint64_t *Fn = s.F[L % 3];
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
@@ -651,10 +720,6 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
             const bool fresh = nb[i] && !((vis[i] >> lane) & 1ull);
             const uint64_t m = ballot(fresh);
             if (nb[i]) s.nextb[v] = 0;
-            if (last) {  // final hop: count only
-                found_total += __popcll(m);
-                continue;
-            }
             if (lane == 0 && m) {
                 s.V[w] = vis[i] | m;
                 Fn[w] = m;
@@ -669,14 +734,11 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
         }
     }
     wb_flush(wb, s, cur, L);
-    if (last && lane == 0 && found_total)
-        atomicAdd((unsigned long long *)&cur[wid % s.nreg].fpack, (unsigned long long)pk(found_total, 0));
     if (lane == 0) unit_add(units, 0, 16 * found_total);
 }
 
-__global__ void __launch_bounds__(kBlock) plain_final_kernel(PlainCtl *ctl, int k, State s) {
-    if (ctl->valid) finalize_query(ctl, k, s);
-}
+// End of a run: the last query's count, if it waited for its marks.
+__global__ void __launch_bounds__(kWave) plain_final_kernel(PlainCtl *ctl) { settle_pending(ctl); }
 
 __global__ void fill_kernel(int64_t *a, int64_t *b, int64_t n, int64_t value) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -797,7 +859,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
                                    c->ctl, L, gr, c->s, P.pull_light, hc, ps.units());
                 ps.end(0, 1);
             }
-            {
+            if (L >= 2 && L < k) {
                 ProfScope ps(g, KK_PLAIN_COMPACT, st);
                 hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, c->ctl, L, gr,
                                    c->s, ps.units());
@@ -805,8 +867,15 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
             }
         }
     }
-    // the last query's count (the others were written by the next query's init)
-    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kBlock), 0, st, c->ctl, (int)k, c->s);
+    // the last query's count (the others were closed by the next query's init)
+    {
+        ProfScope ps(g, KK_PLAIN_INIT, st);
+        hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, c->ctl, gr, c->s, d_seeds,
+                           (int64_t)-1, (int)k, (int)k, P.dir_mode, P.alpha, P.beta, (int64_t)P.push_atomic_max,
+                           nnz_in, d_counts, d_te, ps.units());
+        ps.end(0, 1);
+    }
+    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, c->ctl);
     KHOP_HIP(hipGetLastError());
 }
 
