@@ -73,6 +73,9 @@ struct PlainCtl {
     int32_t k, dir_mode, alpha, beta;
     int32_t valid;
     int32_t last_bytes;  // the finished query's last hop left byte marks (set by its last hop)
+    int64_t seed_beg;    // the seed's first out-edge, its out- and in-degree (hop 1 reads them)
+    int64_t seed_od;
+    int64_t seed_id;
     // a count waiting for the marks of a byte-mode last hop: the next init adds
     // the marks into tail[] (spread over 64 lanes), then hop 1 or the final
     // kernel writes pend_count + sum(tail) to *pend_out
@@ -314,8 +317,12 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
             if (out_te) out_te[qi] = -1;
             return;
         }
-        const int64_t od = g.rowptr[seed + 1] - g.rowptr[seed];
+        const int64_t beg = g.rowptr[seed];
+        const int64_t od = g.rowptr[seed + 1] - beg;
         const int64_t id = g.in_rowptr[seed + 1] - g.in_rowptr[seed];
+        ctl->seed_beg = beg;
+        ctl->seed_od = od;
+        ctl->seed_id = id;
         const int r = (int)(sw / s.rw);
         if (od > 0) {
             s.regs[r].qpack = pk(1, od);
@@ -587,16 +594,89 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
     }
 }
 
+// Top-down hop 1: the seed alone is the frontier, so its out-edges are read
+// straight from its adjacency list (64 per wave) with no region prefix or
+// queue search; heads are claimed with atomicOr on their visited words.
+__device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E, bool last, int64_t *units) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    RegRec *cur = s.regs + s.nreg;  // hop 1's slot
+    uint64_t *Fn = s.F[1];
+    int64_t found = 0, edges = 0;
+    for (int64_t e0 = wid * kWave; e0 < E; e0 += nwaves * kWave) {
+        const int64_t e = e0 + lane;
+        if (e < E) {
+            const int32_t v = g.colidx[beg + e];
+            const uint64_t bit = 1ull << (v & 63);
+            const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
+            if (!(old & bit)) {
+                if (last) {
+                    ++found;
+                } else {
+                    atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                    const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
+                    const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+                    append_one(s, cur, 1, v, od, id);
+                }
+            }
+        }
+        edges += std::min<int64_t>(kWave, E - e0);
+    }
+    if (last) {
+        found = wave_sum(found);
+        if (lane == 0 && found) atomicAdd((unsigned long long *)&cur[wid % s.nreg].fpack, (unsigned long long)pk(found, 0));
+    }
+    // 4 B per out-edge of the seed
+    if (units && lane == 0 && edges) unit_add(units, 0, 4 * edges);
+}
+
 __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L, Graph g, State s, int light,
                                                           HeavyChunks hc, int64_t *units) {
     // hop 1 also writes the previous query's count if it waited for its marks
     if (L == 1 && blockIdx.x == 0 && threadIdx.x < kWave) settle_pending(ctl);
-    if (!ctl->valid) return;
+    // No validity test: an invalid seed leaves every region counter at zero, so
+    // each of its hops sees an empty frontier.  The control words are read up
+    // front, beside the region counters, so their loads overlap.
+    const int32_t k = ctl->k, dir_mode = ctl->dir_mode, alpha = ctl->alpha, beta = ctl->beta;
+    const int64_t push_atomic_max = ctl->push_atomic_max;
+    const HopHdr hp = ctl->hdr[(L - 1) % 3];
+    const bool last = L >= k;  // the final hop only counts
+    const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
+    if (!last) {
+        // the slots hop l+1 writes start clear
+        RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < s.nreg; i += (int64_t)gridDim.x * kBlock) {
+            nx[i].qpack = 0;
+            nx[i].fpack = 0;
+        }
+        uint64_t *Fz = s.F[(L + 1) % 3];
+        for (int64_t w = (int64_t)blockIdx.x * kBlock + t; w < g.nw; w += (int64_t)gridDim.x * kBlock) Fz[w] = 0;
+    }
+    if (L == 1) {
+        // the same direction test as below, on the seed's degrees
+        const int64_t E = ctl->seed_od, beg = ctl->seed_beg;
+        const int64_t mu = hp.mu_before - ctl->seed_id;
+        const bool push = ctl->valid && (dir_mode == DIR_PUSH ||
+                                         (dir_mode != DIR_PULL && (hp.dir == DIR_PUSH ? E * (int64_t)alpha <= mu
+                                                                                       : (int64_t)beta < g.n)));
+        if (push) {
+            if (blockIdx.x == 0 && t == 0) {
+                ctl->hdr[1].mu_before = mu;
+                ctl->hdr[1].dir = DIR_PUSH;
+                ctl->hdr[1].mode = MODE_PUSH_ATOMIC;
+                if (last) ctl->last_bytes = 0;
+                ctl->te_acc += E;
+                if (units) unit_add(units, 0, 24);
+            }
+            hop1_push(g, s, beg, E, last, units);
+            return;
+        }
+    }
     __shared__ int64_t s_epre[kMaxRegions + 1];
     __shared__ int32_t s_qcnt[kMaxRegions];
     __shared__ int64_t s_tot[2][kWavesPerBlock];
     __shared__ uint64_t s_mask[kWavesPerBlock];
-    const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
     // previous hop's region counters: prefix of degree sums, totals
     const RegRec *prev = s.regs + (int64_t)((L - 1) % 3) * s.nreg;
     int64_t qd = 0, fc = 0, fd = 0;
@@ -627,23 +707,21 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
     __syncthreads();
     int64_t din = 0;
     for (int i = 0; i < kWavesPerBlock; ++i) din += s_tot[0][i];
-    const HopHdr hp = ctl->hdr[(L - 1) % 3];
     const int64_t mu = hp.mu_before - din;
     int dir = hp.dir;
-    if (ctl->dir_mode == DIR_PUSH) {
+    if (dir_mode == DIR_PUSH) {
         dir = DIR_PUSH;
-    } else if (ctl->dir_mode == DIR_PULL) {
+    } else if (dir_mode == DIR_PULL) {
         dir = DIR_PULL;
     } else if (dir == DIR_PUSH) {
-        if (E * (int64_t)ctl->alpha > mu) dir = DIR_PULL;
+        if (E * (int64_t)alpha > mu) dir = DIR_PULL;
     } else {
-        if (nf * (int64_t)ctl->beta < g.n) dir = DIR_PUSH;
+        if (nf * (int64_t)beta < g.n) dir = DIR_PUSH;
     }
-    const bool last = L >= ctl->k;  // the final hop only counts
     // hop 1 never marks bytes: no compaction launch follows it
     const int mode = nf == 0 ? MODE_IDLE
                      : dir == DIR_PULL ? MODE_PULL
-                     : (E <= ctl->push_atomic_max || L == 1 ? MODE_PUSH_ATOMIC : MODE_PUSH_BYTES);
+                     : (E <= push_atomic_max || L == 1 ? MODE_PUSH_ATOMIC : MODE_PUSH_BYTES);
     if (blockIdx.x == 0 && t == 0) {
         ctl->hdr[L % 3].mu_before = mu;
         ctl->hdr[L % 3].dir = dir;
@@ -652,16 +730,6 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
         if (L >= 2) ctl->count_acc += nf;
         ctl->te_acc += E;
         if (units) unit_add(units, 0, 16 * s.nreg);
-    }
-    if (!last) {
-        // the slots hop l+1 writes start clear
-        RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
-        for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < s.nreg; i += (int64_t)gridDim.x * kBlock) {
-            nx[i].qpack = 0;
-            nx[i].fpack = 0;
-        }
-        uint64_t *Fz = s.F[(L + 1) % 3];
-        for (int64_t w = (int64_t)blockIdx.x * kBlock + t; w < g.nw; w += (int64_t)gridDim.x * kBlock) Fz[w] = 0;
     }
     if (mode == MODE_IDLE) return;  // empty frontier: nothing left to find
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
