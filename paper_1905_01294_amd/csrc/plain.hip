@@ -100,7 +100,7 @@ struct State {
     uint64_t *V;       // visited bitmap
     uint64_t *F[3];    // frontier bitmaps by hop % 3
     uint8_t *nextb;    // top-down marks (byte mode), all zero between hops
-    int32_t *q[2];     // region queues by hop parity, nreg * rc slots
+    int64_t *qb[2];    // region queues by hop parity, nreg * rc slots: the row begin of each queued vertex
     int64_t *qoff[2];  // out-degree prefix within each region's queue
     RegRec *regs;      // 3 * nreg region counters
     int nreg;          // regions
@@ -122,13 +122,14 @@ __device__ __forceinline__ uint64_t pk(int64_t count, int64_t sum) {
     return ((uint64_t)count << kSumBits) + (uint64_t)sum;
 }
 
-// Appends one discovered vertex (a single lane).
-__device__ __forceinline__ void append_one(const State &s, RegRec *regs, int L, int32_t v, int64_t od, int64_t id) {
+// Appends one discovered vertex v, whose out-edges start at beg (a single lane).
+__device__ __forceinline__ void append_one(const State &s, RegRec *regs, int L, int32_t v, int64_t beg, int64_t od,
+                                           int64_t id) {
     const int r = (int)(((int64_t)v >> 6) / s.rw);
     if (od > 0) {
         const uint64_t old = atomicAdd((unsigned long long *)&regs[r].qpack, (unsigned long long)pk(1, od));
         const int64_t at = (int64_t)r * s.rc + pk_count(old);
-        s.q[L & 1][at] = v;
+        s.qb[L & 1][at] = beg;
         s.qoff[L & 1][at] = pk_sum(old);
     }
     atomicAdd((unsigned long long *)&regs[r].fpack, (unsigned long long)pk(1, id));
@@ -138,7 +139,7 @@ __device__ __forceinline__ void append_one(const State &s, RegRec *regs, int L, 
 // returning atomic per region instead of one per word.
 constexpr int kBufCap = 512;
 struct WaveBuf {
-    int32_t *v;    // LDS, kBufCap vertices
+    int64_t *v;    // LDS, kBufCap row begins of the buffered vertices
     int32_t *d;    // their out-degrees
     int cnt;       // buffered entries (wave-uniform)
     int reg;       // region of the buffered entries, -1 if none
@@ -165,7 +166,7 @@ __device__ void wb_flush(WaveBuf &b, const State &s, RegRec *regs, int L) {
         const int64_t d = i < b.cnt ? b.d[i] : 0;
         const int64_t dx = wave_exclusive_sum(d);
         if (i < b.cnt) {
-            s.q[L & 1][base + i] = b.v[i];
+            s.qb[L & 1][base + i] = b.v[i];
             s.qoff[L & 1][base + i] = dpos + dx;
         }
         dpos += wave_sum(d);
@@ -176,9 +177,9 @@ __device__ void wb_flush(WaveBuf &b, const State &s, RegRec *regs, int L) {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Buffers the lanes of word w that have `found` (wave-uniform call).
+// Buffers the lanes of word w that have `found`, with their row begins (wave-uniform call).
 __device__ __forceinline__ void wb_word(WaveBuf &b, const State &s, RegRec *regs, int L, int64_t w, bool found,
-                                       int64_t od, int64_t id) {
+                                       int64_t beg, int64_t od, int64_t id) {
     const uint64_t fm = ballot(found);
     if (!fm) return;
     const int r = (int)(w / s.rw);
@@ -191,7 +192,7 @@ __device__ __forceinline__ void wb_word(WaveBuf &b, const State &s, RegRec *regs
     }
     if (qd) {
         const int at = b.cnt + mask_rank(qm);
-        b.v[at] = (int32_t)(w * kWave + lane_id());
+        b.v[at] = beg;
         b.d[at] = (int32_t)od;
     }
     b.cnt += nq;
@@ -326,7 +327,7 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
         const int r = (int)(sw / s.rw);
         if (od > 0) {
             s.regs[r].qpack = pk(1, od);
-            s.q[0][(int64_t)r * s.rc] = seed;
+            s.qb[0][(int64_t)r * s.rc] = beg;
             s.qoff[0][(int64_t)r * s.rc] = 0;
         }
         s.regs[r].fpack = pk(1, id);
@@ -371,7 +372,7 @@ __device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *e
         const int64_t a0 = std::max(e0, rb) - rb, a1 = std::min(e1, re) - rb;  // local edge range
         if (a0 >= a1) continue;
         const int64_t qlen = qcnt[r];
-        const int32_t *__restrict__ q = s.q[(L - 1) & 1] + (int64_t)r * s.rc;
+        const int64_t *__restrict__ qb = s.qb[(L - 1) & 1] + (int64_t)r * s.rc;
         const int64_t *__restrict__ qoff = s.qoff[(L - 1) & 1] + (int64_t)r * s.rc;
         // base = #{ j < qlen : qoff[j] < a0 } by a 64-way search
         int64_t lo = 0, hi = qlen;
@@ -392,7 +393,7 @@ __device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *e
         int64_t base = lo;
         int64_t carry_beg = 0, carry_off = 0;
         if (base > 0) {
-            carry_beg = g.rowptr[q[base - 1]];
+            carry_beg = qb[base - 1];
             carry_off = qoff[base - 1];
         }
         for (int64_t b = a0; b < a1; b += kWave) {
@@ -401,9 +402,9 @@ __device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *e
             int64_t offj = 0, begj = 0;
             if (j < qlen) {
                 offj = qoff[j];
+                begj = qb[j];
                 inwin = offj < b + kWave;
             }
-            if (inwin) begj = g.rowptr[q[j]];
             if (lane == 0) *smask = 0;
             __builtin_amdgcn_wave_barrier();
             if (inwin) atomicOr((unsigned long long *)smask, 1ull << (offj - b));
@@ -430,9 +431,10 @@ __device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *e
                                 *found += 1;
                             } else {
                                 atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-                                const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
+                                const int64_t vb = g.rowptr[v];
+                                const int64_t od = g.rowptr[v + 1] - vb;
                                 const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
-                                append_one(s, cur, L, v, od, id);
+                                append_one(s, cur, L, v, vb, od, id);
                             }
                         }
                     }
@@ -453,10 +455,11 @@ __device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *e
 
 // ------------------------------------------------------------------ bottom-up
 
-// Each wave takes 64-vertex words in turn.  Unvisited vertices of in-degree up
-// to `light` scan alone (4 in-edges per round); heavier ones up to g.heavy are
-// scanned by the whole wave, 256 in-edges per round; heavier still come from
-// the chunk table after the words.
+// Each wave takes 64-vertex words in turn.  Every unvisited vertex of
+// in-degree up to g.heavy scans its first `light` in-edges alone (4 per
+// round); those with more edges and no hit yet have the rest scanned by the
+// whole wave, 256 in-edges per round; heavier vertices come from the chunk
+// table after the words.
 __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int light, const HeavyChunks &hc,
                          RegRec *cur, WaveBuf &wb, int64_t *found_out, int64_t *units) {
     const int lane = lane_id();
@@ -482,9 +485,12 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
         const int64_t d = e - b;
         bool found = false;
         int64_t examined = 0;
-        if (unv && d <= light) {
+        // every unvisited vertex first scans up to `light` in-edges alone: on a
+        // wide frontier most find a hit there, whatever their degree
+        const int64_t le = b + std::min<int64_t>(d, light);
+        if (unv && d <= g.heavy) {
             int64_t x = b;
-            for (; x + 4 <= e; x += 4) {
+            for (; x + 4 <= le; x += 4) {
                 const int32_t u0 = g.in_colidx[x], u1 = g.in_colidx[x + 1];
                 const int32_t u2 = g.in_colidx[x + 2], u3 = g.in_colidx[x + 3];
                 const bool h0 = test_bit(Fc, u0), h1 = test_bit(Fc, u1);
@@ -497,7 +503,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
                 examined += 4;
             }
             if (!found) {
-                for (; x < e; ++x) {
+                for (; x < le; ++x) {
                     ++examined;
                     if (test_bit(Fc, g.in_colidx[x])) {
                         found = true;
@@ -506,11 +512,12 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
                 }
             }
         }
-        uint64_t medium = ballot(unv && d > light && d <= g.heavy);
+        // the rest of the in-edges of vertices with no hit yet: the whole wave, 256 per round
+        uint64_t medium = ballot(unv && !found && d > light && d <= g.heavy);
         while (medium) {
             const int h = __builtin_ctzll(medium);
             medium &= medium - 1;
-            const int64_t hb = shfl64(b, h), he = shfl64(e, h);
+            const int64_t hb = shfl64(b, h) + light, he = shfl64(e, h);
             bool hit = false;
             int64_t scanned = 0;
             for (int64_t x0 = hb; x0 < he; x0 += 4 * kWave) {
@@ -528,7 +535,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
             }
             if (lane == h) {
                 found = hit;
-                examined = scanned;
+                examined += scanned;
             }
         }
         const uint64_t fm = ballot(found);
@@ -541,9 +548,14 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
                 atomicOr((unsigned long long *)&s.V[w], (unsigned long long)fm);
                 atomicOr((unsigned long long *)&Fn[w], (unsigned long long)fm);
             }
-            int64_t od = 0;
-            if (found) od = g.directed ? g.rowptr[v + 1] - g.rowptr[v] : d;
-            wb_word(wb, s, cur, L, w, found, od, d);
+            int64_t od = 0, vb = b;  // undirected: the in-row is the out-row
+            if (found && g.directed) {
+                vb = g.rowptr[v];
+                od = g.rowptr[v + 1] - vb;
+            } else if (found) {
+                od = d;
+            }
+            wb_word(wb, s, cur, L, w, found, vb, od, d);
         }
         if (units) {
             c_pe += wave_sum(examined);
@@ -580,9 +592,10 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
                     *found_out += 1;
                 } else {
                     atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-                    const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
+                    const int64_t vb = g.rowptr[v];
+                    const int64_t od = g.rowptr[v + 1] - vb;
                     const int64_t id = g.in_rowptr[v + 1] - g.in_rowptr[v];
-                    append_one(s, cur, L, v, od, id);
+                    append_one(s, cur, L, v, vb, od, id);
                 }
             }
         }
@@ -615,9 +628,10 @@ __device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E
                     ++found;
                 } else {
                     atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-                    const int64_t od = g.rowptr[v + 1] - g.rowptr[v];
+                    const int64_t vb = g.rowptr[v];
+                    const int64_t od = g.rowptr[v + 1] - vb;
                     const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
-                    append_one(s, cur, 1, v, od, id);
+                    append_one(s, cur, 1, v, vb, od, id);
                 }
             }
         }
@@ -735,7 +749,7 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
     int64_t found = 0;  // final hop: discoveries of this lane (push) or wave (pull)
     if (mode == MODE_PULL) {
-        __shared__ int32_t s_bv[kWavesPerBlock][kBufCap];
+        __shared__ int64_t s_bv[kWavesPerBlock][kBufCap];
         __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
         WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
         pull_hop(L, last, g, s, light, hc, cur, wb, &found, units);
@@ -762,7 +776,7 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (units && wid == 0 && lane == 0) unit_add(units, 0, g.n + 2 * ((g.n + 7) / 8));
-    __shared__ int32_t s_bv[kWavesPerBlock][kBufCap];
+    __shared__ int64_t s_bv[kWavesPerBlock][kBufCap];
     __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
     const int wv = threadIdx.x / kWave;
     WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
@@ -792,12 +806,13 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
                 s.V[w] = vis[i] | m;
                 Fn[w] = m;
             }
-            int64_t od = 0, id = 0;
+            int64_t vb = 0, od = 0, id = 0;
             if (fresh) {
-                od = g.rowptr[v + 1] - g.rowptr[v];
+                vb = g.rowptr[v];
+                od = g.rowptr[v + 1] - vb;
                 id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
             }
-            wb_word(wb, s, cur, L, w, fresh, od, id);
+            wb_word(wb, s, cur, L, w, fresh, vb, od, id);
             found_total += __popcll(m);
         }
     }
@@ -851,7 +866,7 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     size_t o_q[2], o_qoff[2];
     for (int i = 0; i < 2; ++i) {
         o_q[i] = off;
-        off += al(slots * 4);
+        off += al(slots * 8);
         o_qoff[i] = off;
         off += al(slots * 8);
     }
@@ -869,7 +884,7 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     for (int i = 0; i < 3; ++i) c->s.F[i] = (uint64_t *)(base + o_F[i]);
     c->s.nextb = (uint8_t *)(base + o_nb);
     for (int i = 0; i < 2; ++i) {
-        c->s.q[i] = (int32_t *)(base + o_q[i]);
+        c->s.qb[i] = (int64_t *)(base + o_q[i]);
         c->s.qoff[i] = (int64_t *)(base + o_qoff[i]);
     }
     c->s.regs = (RegRec *)(base + o_regs);
