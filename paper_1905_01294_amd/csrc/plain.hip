@@ -2,12 +2,15 @@
 //
 // One hop is the masked boolean product of the paper's Section II: the next
 // frontier is (A^T f) AND NOT visited over the (OR, AND) semiring.  A query is
-// an init kernel and one hop kernel per hop; a hop 2..k-1 is followed by a
-// compaction kernel (which exits at once unless the hop marked bytes).  Hop 1
-// never marks bytes, and the last hop's marks are counted by the next query's
-// init (or the run's tail), so neither needs a compaction launch.  Every
-// cross-block hand-off happens at a kernel boundary (intra-kernel release
-// fences would write back L2 on this multi-XCD part).
+// one hop kernel per hop; a hop 2..k-1 is followed by a compaction kernel
+// (which exits at once unless the hop marked bytes).  Hop 1 never marks
+// bytes, and the last hop only counts, so neither needs a compaction.
+// Consecutive queries alternate between two sets of bitmaps and region
+// counters: hop 1 of query i also counts the byte marks query i-1 left,
+// resets the other set for query i+1 and writes the count of query i-2, so a
+// query needs no launch of its own for set-up.  Control records rotate over
+// three slots.  Every cross-block hand-off happens at a kernel boundary
+// (intra-kernel release fences would write back L2 on this multi-XCD part).
 //
 // The frontier queue is split into regions of consecutive vertices; region r
 // owns queue slots [r*RC, (r+1)*RC) and one packed 64-bit counter
@@ -49,6 +52,7 @@ constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kMaxRegions = kBlock;  // one region per thread in the prefix
 constexpr int kSumBits = 33;         // packed (count << 33) | sum
 constexpr uint64_t kSumMask = (1ull << kSumBits) - 1;
+constexpr int kTail = 256;           // lanes of a query's last-hop counter
 enum { DIR_PUSH = KHOP_DIR_PUSH, DIR_PULL = KHOP_DIR_PULL };
 enum { MODE_PULL = 0, MODE_PUSH_ATOMIC = 1, MODE_PUSH_BYTES = 2, MODE_IDLE = 3 };
 
@@ -72,17 +76,11 @@ struct PlainCtl {
     int64_t push_atomic_max;  // frontier edges up to which a push claims heads atomically
     int32_t k, dir_mode, alpha, beta;
     int32_t valid;
-    int32_t last_bytes;  // the finished query's last hop left byte marks (set by its last hop)
+    int32_t last_bytes;  // the last hop left byte marks (counted by the next query's hop 1)
     int64_t seed_beg;    // the seed's first out-edge, its out- and in-degree (hop 1 reads them)
     int64_t seed_od;
     int64_t seed_id;
-    // a count waiting for the marks of a byte-mode last hop: the next init adds
-    // the marks into tail[] (spread over 64 lanes), then hop 1 or the final
-    // kernel writes pend_count + sum(tail) to *pend_out
-    int64_t pend_count;
-    int64_t *pend_out;
-    int32_t pend, pad;
-    int64_t tail[64];
+    int64_t tail[kTail];  // discoveries of the last hop, spread over many addresses
 };
 
 struct Graph {
@@ -96,6 +94,8 @@ struct Graph {
     int heavy;   // bottom-up: in-degree above which the chunk table takes a vertex
 };
 
+// The bitmaps and region counters of one query parity; the byte map and the
+// queues are shared by both.
 struct State {
     uint64_t *V;       // visited bitmap
     uint64_t *F[3];    // frontier bitmaps by hop % 3
@@ -201,46 +201,7 @@ __device__ __forceinline__ void wb_word(WaveBuf &b, const State &s, RegRec *regs
     __builtin_amdgcn_wave_barrier();
 }
 
-// ------------------------------------------------------------------ init
-
-// Sum of the discoveries of the last hop of the query in ctl, whose depth was k; block-wide.
-// If that hop left byte marks, the count waits in ctl for their number.
-__device__ void finalize_query(PlainCtl *ctl, int k, const State &s) {
-    const RegRec *last = s.regs + (int64_t)(k % 3) * s.nreg;
-    __shared__ int64_t s_t[kWavesPerBlock];
-    int64_t c = 0;
-    for (int i = threadIdx.x; i < s.nreg; i += kBlock) c += pk_count(last[i].fpack);
-    c = wave_sum(c);
-    if (lane_id() == 0) s_t[threadIdx.x / kWave] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t tot = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) tot += s_t[i];
-        if (ctl->last_bytes) {
-            ctl->pend_count = ctl->count_acc + tot;
-            ctl->pend_out = ctl->out_count;
-            ctl->pend = 1;
-        } else {
-            *ctl->out_count = ctl->count_acc + tot;
-        }
-        if (ctl->out_te) *ctl->out_te = ctl->te_acc;
-    }
-    __syncthreads();
-}
-
-// Writes a waiting count once the marks are in tail[] (one wave).
-__device__ void settle_pending(PlainCtl *ctl) {
-    const int lane = lane_id();
-    if (ctl->pend) {
-        const int64_t t = wave_sum(ctl->tail[lane]);
-        ctl->tail[lane] = 0;
-        if (lane == 0) {
-            *ctl->pend_out = ctl->pend_count + t;
-            ctl->pend = 0;
-        }
-    }
-    if (lane == 0) ctl->last_bytes = 0;
-}
+// ------------------------------------------------------------------ query set-up and close
 
 // Lanes whose byte of x is nonzero, one bit per byte (16 bytes).
 __device__ __forceinline__ uint32_t nonzero_bytes(uint4 x) {
@@ -251,92 +212,131 @@ __device__ __forceinline__ uint32_t nonzero_bytes(uint4 x) {
     return f(x.x) | (f(x.y) << 4) | (f(x.z) << 8) | (f(x.w) << 12);
 }
 
-// Clears the visited and frontier bitmaps and sets up the seed qi.  When
-// prev_k > 0 it first closes the previous query (depth prev_k) still held in
-// ctl: block 0 writes its count (or parks it, see PlainCtl), and if that
-// query's last hop marked bytes every block counts and clears the marks of its
-// words.  With qi < 0 (the tail of a run) it only closes the previous query.
-__global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph g, State s, const int32_t *seeds,
-                                                           int64_t qi, int k, int prev_k, int dir_mode, int alpha,
-                                                           int beta, int64_t push_atomic_max, int64_t nnz_in,
-                                                           int64_t *out_count, int64_t *out_te, int64_t *units) {
-    const bool close_marks = prev_k > 0 && ctl->last_bytes;  // written only by hop kernels
-    const int32_t seed = qi >= 0 ? seeds[qi] : -1;
+// The byte marks a byte-mode last hop left on the 64 vertices of word w that
+// were unvisited (visited word vis); the marks are cleared.  The byte map is
+// padded to whole words.
+__device__ __forceinline__ int64_t close_marks_word(const State &s, int64_t w, uint64_t vis) {
+    uint4 *mb = (uint4 *)(s.nextb + w * kWave);
+    uint64_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) m |= (uint64_t)nonzero_bytes(mb[j]) << (16 * j);
+    if (!m) return 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) mb[j] = make_uint4(0, 0, 0, 0);
+    return __popcll(m & ~vis);
+}
+
+// Adds a wave's share of a finished query's last-hop discoveries.
+__device__ __forceinline__ void add_tail(PlainCtl *ctl, int64_t wid, int64_t v) {
+    if (v) atomicAdd((unsigned long long *)&ctl->tail[wid & (kTail - 1)], (unsigned long long)v);
+}
+
+// Writes the count and traversed edges of a finished query (one wave).
+__device__ void finalize(PlainCtl *ctl) {
+    const int lane = lane_id();
+    int64_t t = 0;
+    for (int i = lane; i < kTail; i += kWave) {
+        t += ctl->tail[i];
+        ctl->tail[i] = 0;
+    }
+    t = wave_sum(t);
+    if (lane == 0 && ctl->valid) {
+        *ctl->out_count = ctl->count_acc + t;
+        if (ctl->out_te) *ctl->out_te = ctl->te_acc;
+    }
+}
+
+// Block 0: the control record of query qi (seed `seed`) and the region
+// counters of its hops 0 and 1 (hop 0 holds the seed).  Its bitmap words are
+// reset by the caller's grid.
+__device__ void setup_query(PlainCtl *ctl, const Graph &g, const State &s, int32_t seed, int64_t qi, int k,
+                            int dir_mode, int alpha, int beta, int64_t push_atomic_max, int64_t nnz_in,
+                            int64_t *out_count, int64_t *out_te, int64_t *units) {
     const bool valid = seed >= 0 && (int64_t)seed < g.n;
-    const int64_t sw = valid ? (seed >> 6) : -1;
-    const uint64_t sbit = valid ? (1ull << (seed & 63)) : 0;
-    int64_t fresh = 0;
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock) {
-        if (close_marks) {
-            // the 64 mark bytes of word w (the byte map is padded to whole words)
-            uint4 *mb = (uint4 *)(s.nextb + w * kWave);
-            uint64_t m = 0;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) m |= (uint64_t)nonzero_bytes(mb[j]) << (16 * j);
-            if (m) {
-                fresh += __popcll(m & ~s.V[w]);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) mb[j] = make_uint4(0, 0, 0, 0);
-            }
-        }
-        if (qi >= 0) {
-            const uint64_t x = (w == sw) ? sbit : 0ull;
-            s.V[w] = x;
-            s.F[0][w] = x;
-            s.F[1][w] = 0;
-        }
-    }
-    if (close_marks) {
-        fresh = wave_sum(fresh);
-        if (lane_id() == 0 && fresh)
-            atomicAdd((unsigned long long *)&ctl->tail[blockIdx.x & 63], (unsigned long long)fresh);
-        // the mark bytes and the visited words
-        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.n + 8 * g.nw);
-    }
-    if (blockIdx.x != 0) return;
-    if (prev_k > 0 && ctl->valid) finalize_query(ctl, prev_k, s);
-    if (qi < 0) return;
-    // region counters of hop 0 (the seed) and hop 1 start at zero
     for (int i = threadIdx.x; i < 2 * s.nreg; i += kBlock) {
         s.regs[i].qpack = 0;
         s.regs[i].fpack = 0;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        ctl->out_count = out_count + qi;
-        ctl->out_te = out_te ? out_te + qi : nullptr;
-        ctl->dir_mode = dir_mode;
-        ctl->alpha = alpha;
-        ctl->beta = beta;
-        ctl->k = k;
-        ctl->valid = valid;
-        ctl->push_atomic_max = push_atomic_max;
-        ctl->count_acc = 0;
-        ctl->te_acc = 0;
-        if (!valid) {
-            out_count[qi] = -1;
-            if (out_te) out_te[qi] = -1;
-            return;
-        }
-        const int64_t beg = g.rowptr[seed];
-        const int64_t od = g.rowptr[seed + 1] - beg;
-        const int64_t id = g.in_rowptr[seed + 1] - g.in_rowptr[seed];
-        ctl->seed_beg = beg;
-        ctl->seed_od = od;
-        ctl->seed_id = id;
-        const int r = (int)(sw / s.rw);
-        if (od > 0) {
-            s.regs[r].qpack = pk(1, od);
-            s.qb[0][(int64_t)r * s.rc] = beg;
-            s.qoff[0][(int64_t)r * s.rc] = 0;
-        }
-        s.regs[r].fpack = pk(1, id);
-        ctl->hdr[0].mu_before = nnz_in;
-        ctl->hdr[0].dir = dir_mode == DIR_PULL ? DIR_PULL : DIR_PUSH;
-        ctl->hdr[0].mode = MODE_IDLE;
-        unit_add(units, 0, 3 * 8 * g.nw);
+    if (threadIdx.x != 0) return;
+    ctl->out_count = out_count + qi;
+    ctl->out_te = out_te ? out_te + qi : nullptr;
+    ctl->dir_mode = dir_mode;
+    ctl->alpha = alpha;
+    ctl->beta = beta;
+    ctl->k = k;
+    ctl->valid = valid;
+    ctl->last_bytes = 0;
+    ctl->push_atomic_max = push_atomic_max;
+    ctl->count_acc = 0;
+    ctl->te_acc = 0;
+    ctl->seed_od = 0;
+    if (!valid) {
+        out_count[qi] = -1;
+        if (out_te) out_te[qi] = -1;
+        return;
     }
+    const int64_t beg = g.rowptr[seed];
+    const int64_t od = g.rowptr[seed + 1] - beg;
+    const int64_t id = g.in_rowptr[seed + 1] - g.in_rowptr[seed];
+    ctl->seed_beg = beg;
+    ctl->seed_od = od;
+    ctl->seed_id = id;
+    const int64_t sw = seed >> 6;
+    const int r = (int)(sw / s.rw);
+    // hop 0's counters describe the seed; no queue entry is needed, since a
+    // top-down hop 1 reads the seed's row from this record
+    if (od > 0) s.regs[r].qpack = pk(1, od);
+    s.regs[r].fpack = pk(1, id);
+    ctl->hdr[0].mu_before = nnz_in;
+    ctl->hdr[0].dir = dir_mode == DIR_PULL ? DIR_PULL : DIR_PUSH;
+    ctl->hdr[0].mode = MODE_IDLE;
+    unit_add(units, 0, 3 * 8 * g.nw);
 }
+
+// Word w of a query's visited and frontier bitmaps at its start: the seed's
+// bit only (sw = -1: no seed).
+__device__ __forceinline__ void reset_word(const State &s, int64_t w, int64_t sw, uint64_t sbit) {
+    const uint64_t x = (w == sw) ? sbit : 0ull;
+    s.V[w] = x;
+    s.F[0][w] = x;
+    s.F[1][w] = 0;
+}
+
+// Set-up of the first query of a run (later queries are set up by the hop 1
+// of the query before them).
+__global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph g, State s, const int32_t *seeds,
+                                                           int64_t qi, int k, int dir_mode, int alpha, int beta,
+                                                           int64_t push_atomic_max, int64_t nnz_in,
+                                                           int64_t *out_count, int64_t *out_te, int64_t *units) {
+    const int32_t seed = seeds[qi];
+    const bool valid = seed >= 0 && (int64_t)seed < g.n;
+    const int64_t sw = valid ? (seed >> 6) : -1;
+    const uint64_t sbit = valid ? (1ull << (seed & 63)) : 0;
+    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock)
+        reset_word(s, w, sw, sbit);
+    if (blockIdx.x == 0)
+        setup_query(ctl, g, s, seed, qi, k, dir_mode, alpha, beta, push_atomic_max, nnz_in, out_count, out_te,
+                    units);
+}
+
+// End of a run: the last query's byte marks (if its last hop left any), and
+// the count of the query before it.
+__global__ void __launch_bounds__(kBlock) plain_close_kernel(PlainCtl *ctl_last, PlainCtl *ctl_before,
+                                                            int fin_before, Graph g, State s_last, int64_t *units) {
+    if (ctl_last->last_bytes) {
+        int64_t fresh = 0;
+        for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock)
+            fresh += close_marks_word(s_last, w, s_last.V[w]);
+        fresh = wave_sum(fresh);
+        if (lane_id() == 0) add_tail(ctl_last, (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave, fresh);
+        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.n + 8 * g.nw);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kWave && fin_before) finalize(ctl_before);
+}
+
+// The last query's count.
+__global__ void __launch_bounds__(kWave) plain_final_kernel(PlainCtl *ctl) { finalize(ctl); }
 
 // ------------------------------------------------------------------ top-down
 
@@ -610,7 +610,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
 // Top-down hop 1: the seed alone is the frontier, so its out-edges are read
 // straight from its adjacency list (64 per wave) with no region prefix or
 // queue search; heads are claimed with atomicOr on their visited words.
-__device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E, bool last, int64_t *units) {
+__device__ int64_t hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E, bool last, int64_t *units) {
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
@@ -637,26 +637,23 @@ __device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E
         }
         edges += std::min<int64_t>(kWave, E - e0);
     }
-    if (last) {
-        found = wave_sum(found);
-        if (lane == 0 && found) atomicAdd((unsigned long long *)&cur[wid % s.nreg].fpack, (unsigned long long)pk(found, 0));
-    }
     // 4 B per out-edge of the seed
     if (units && lane == 0 && edges) unit_add(units, 0, 4 * edges);
+    return wave_sum(found);
 }
 
-__global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L, Graph g, State s, int light,
-                                                          HeavyChunks hc, int64_t *units) {
-    // hop 1 also writes the previous query's count if it waited for its marks
-    if (L == 1 && blockIdx.x == 0 && threadIdx.x < kWave) settle_pending(ctl);
-    // No validity test: an invalid seed leaves every region counter at zero, so
-    // each of its hops sees an empty frontier.  The control words are read up
-    // front, beside the region counters, so their loads overlap.
+// One hop of query ctl on its state s.  No validity test: an invalid seed
+// leaves every region counter at zero, so each of its hops sees an empty
+// frontier.  The control words are read up front, beside the region
+// counters, so their loads overlap.
+__device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, int light, const HeavyChunks &hc,
+                         int64_t *units) {
     const int32_t k = ctl->k, dir_mode = ctl->dir_mode, alpha = ctl->alpha, beta = ctl->beta;
     const int64_t push_atomic_max = ctl->push_atomic_max;
     const HopHdr hp = ctl->hdr[(L - 1) % 3];
     const bool last = L >= k;  // the final hop only counts
     const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
+    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     if (!last) {
         // the slots hop l+1 writes start clear
         RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
@@ -668,7 +665,8 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
         for (int64_t w = (int64_t)blockIdx.x * kBlock + t; w < g.nw; w += (int64_t)gridDim.x * kBlock) Fz[w] = 0;
     }
     if (L == 1) {
-        // the same direction test as below, on the seed's degrees
+        // the same direction test as below, on the seed's degrees; when it
+        // says bottom-up the general path below runs a pull
         const int64_t E = ctl->seed_od, beg = ctl->seed_beg;
         const int64_t mu = hp.mu_before - ctl->seed_id;
         const bool push = ctl->valid && (dir_mode == DIR_PUSH ||
@@ -679,11 +677,11 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
                 ctl->hdr[1].mu_before = mu;
                 ctl->hdr[1].dir = DIR_PUSH;
                 ctl->hdr[1].mode = MODE_PUSH_ATOMIC;
-                if (last) ctl->last_bytes = 0;
                 ctl->te_acc += E;
                 if (units) unit_add(units, 0, 24);
             }
-            hop1_push(g, s, beg, E, last, units);
+            const int64_t found = hop1_push(g, s, beg, E, last, units);
+            if (last && lane == 0) add_tail(ctl, wid, found);
             return;
         }
     }
@@ -723,7 +721,9 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
     for (int i = 0; i < kWavesPerBlock; ++i) din += s_tot[0][i];
     const int64_t mu = hp.mu_before - din;
     int dir = hp.dir;
-    if (dir_mode == DIR_PUSH) {
+    if (L == 1) {
+        dir = DIR_PULL;  // the same test on the seed's degrees chose bottom-up above
+    } else if (dir_mode == DIR_PUSH) {
         dir = DIR_PUSH;
     } else if (dir_mode == DIR_PULL) {
         dir = DIR_PULL;
@@ -758,10 +758,48 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
         push_hop(L, mode, last, E, s_epre, s_qcnt, g, s, cur, &s_mask[wv], &found, units);
         found = wave_sum(found);
     }
-    if (last && lane == 0 && found) {
-        const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wv;
-        atomicAdd((unsigned long long *)&cur[wid % s.nreg].fpack, (unsigned long long)pk(found, 0));
+    if (last && lane == 0) add_tail(ctl, wid, found);
+}
+
+// Hop 1 of query ctl (state s).  Before it: the byte marks the previous query
+// (ctl_prev, state sn) left are counted, sn is reset for the next query qn,
+// and the control slot ctl_next, which still holds the query two back, is
+// finalized and then set up for qn.
+__global__ void __launch_bounds__(kBlock) plain_hop1_kernel(PlainCtl *ctl, PlainCtl *ctl_prev, PlainCtl *ctl_next,
+                                                           int close_prev, int fin_next, Graph g, State s, State sn,
+                                                           const int32_t *seeds, int64_t qn, int k, int dir_mode,
+                                                           int alpha, int beta, int64_t push_atomic_max,
+                                                           int64_t nnz_in, int64_t *out_count, int64_t *out_te,
+                                                           int light, HeavyChunks hc, int64_t *units) {
+    const bool marks = close_prev && ctl_prev->last_bytes;  // ctl_prev is not written in this kernel
+    const int32_t nseed = qn >= 0 ? seeds[qn] : -1;
+    const bool nvalid = nseed >= 0 && (int64_t)nseed < g.n;
+    const int64_t nsw = nvalid ? (nseed >> 6) : -1;
+    const uint64_t nsbit = nvalid ? (1ull << (nseed & 63)) : 0;
+    int64_t fresh = 0;
+    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock) {
+        if (marks) fresh += close_marks_word(sn, w, sn.V[w]);
+        if (qn >= 0) reset_word(sn, w, nsw, nsbit);
     }
+    if (marks) {
+        fresh = wave_sum(fresh);
+        if (lane_id() == 0) add_tail(ctl_prev, (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave, fresh);
+        // the mark bytes and the visited words
+        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.n + 8 * g.nw);
+    }
+    if (blockIdx.x == 0) {
+        if (fin_next && threadIdx.x < kWave) finalize(ctl_next);
+        __syncthreads();
+        if (qn >= 0)
+            setup_query(ctl_next, g, sn, nseed, qn, k, dir_mode, alpha, beta, push_atomic_max, nnz_in, out_count,
+                        out_te, units);
+    }
+    hop_body(ctl, 1, g, s, light, hc, units);
+}
+
+__global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L, Graph g, State s, int light,
+                                                          HeavyChunks hc, int64_t *units) {
+    hop_body(ctl, L, g, s, light, hc, units);
 }
 
 // After a byte-mode push: ballot(mark AND NOT visited) per 64-vertex word is
@@ -820,8 +858,6 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
     if (lane == 0) unit_add(units, 0, 16 * found_total);
 }
 
-// End of a run: the last query's count, if it waited for its marks.
-__global__ void __launch_bounds__(kWave) plain_final_kernel(PlainCtl *ctl) { settle_pending(ctl); }
 
 __global__ void fill_kernel(int64_t *a, int64_t *b, int64_t n, int64_t value) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -834,8 +870,8 @@ __global__ void fill_kernel(int64_t *a, int64_t *b, int64_t n, int64_t value) {
 
 struct PlainCtx {
     khop_graph *g = nullptr;
-    PlainCtl *ctl = nullptr;
-    State s{};
+    PlainCtl *ctl = nullptr;  // three control slots
+    State s[2]{};             // the two query parities
     int hop_grid = 1;
     int init_grid = 1;
     int compact_grid = 1;
@@ -853,16 +889,20 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
     const size_t o_ctl = off;
-    off += al(sizeof(PlainCtl));
-    const size_t o_V = off;
-    off += al(nw * 8);
-    size_t o_F[3];
-    for (int i = 0; i < 3; ++i) {
-        o_F[i] = off;
+    off += al(3 * sizeof(PlainCtl));
+    size_t o_V[2], o_F[2][3], o_regs[2];
+    for (int p = 0; p < 2; ++p) {
+        o_V[p] = off;
         off += al(nw * 8);
+        for (int i = 0; i < 3; ++i) {
+            o_F[p][i] = off;
+            off += al(nw * 8);
+        }
+        o_regs[p] = off;
+        off += al((size_t)3 * nreg * sizeof(RegRec));
     }
     const size_t o_nb = off;
-    off += al(n);
+    off += al(nw * 64);  // the byte map, padded to whole words
     size_t o_q[2], o_qoff[2];
     for (int i = 0; i < 2; ++i) {
         o_q[i] = off;
@@ -870,8 +910,6 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
         o_qoff[i] = off;
         off += al(slots * 8);
     }
-    const size_t o_regs = off;
-    off += al((size_t)3 * nreg * sizeof(RegRec));
     hipError_t e = hipMalloc(&c->arena, off);
     if (e != hipSuccess) {
         delete c;
@@ -880,17 +918,20 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     }
     char *base = (char *)c->arena;
     c->ctl = (PlainCtl *)(base + o_ctl);
-    c->s.V = (uint64_t *)(base + o_V);
-    for (int i = 0; i < 3; ++i) c->s.F[i] = (uint64_t *)(base + o_F[i]);
-    c->s.nextb = (uint8_t *)(base + o_nb);
-    for (int i = 0; i < 2; ++i) {
-        c->s.qb[i] = (int64_t *)(base + o_q[i]);
-        c->s.qoff[i] = (int64_t *)(base + o_qoff[i]);
+    for (int p = 0; p < 2; ++p) {
+        State &st = c->s[p];
+        st.V = (uint64_t *)(base + o_V[p]);
+        for (int i = 0; i < 3; ++i) st.F[i] = (uint64_t *)(base + o_F[p][i]);
+        st.regs = (RegRec *)(base + o_regs[p]);
+        st.nextb = (uint8_t *)(base + o_nb);
+        for (int i = 0; i < 2; ++i) {
+            st.qb[i] = (int64_t *)(base + o_q[i]);
+            st.qoff[i] = (int64_t *)(base + o_qoff[i]);
+        }
+        st.nreg = nreg;
+        st.rw = rw;
+        st.rc = rc;
     }
-    c->s.regs = (RegRec *)(base + o_regs);
-    c->s.nreg = nreg;
-    c->s.rw = rw;
-    c->s.rc = rc;
     c->hop_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 7) / 8, (int64_t)g->cu_count * 4));
     c->init_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kBlock - 1) / kBlock, 512));
     c->compact_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 15) / 16, (int64_t)g->cu_count * 4));
@@ -925,40 +966,52 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
              ht.threshold};
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
     const int64_t nnz_in = g->nnz;
-    // hop 1 expands the seed alone: top-down unless forced, so a small grid suffices
-    const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::min(c->hop_grid, std::max(1, g->cu_count / 4));
-    for (int64_t i = 0; i < num_seeds; ++i) {
-        {
-            ProfScope ps(g, KK_PLAIN_INIT, st);
-            hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, c->ctl, gr, c->s, d_seeds,
-                               i, (int)k, i > 0 ? (int)k : 0, P.dir_mode, P.alpha, P.beta,
-                               (int64_t)P.push_atomic_max, nnz_in, d_counts, d_te, ps.units());
-            ps.end(0, 1);
-        }
-        for (int L = 1; L <= k; ++L) {
-            {
-                ProfScope ps(g, KK_PLAIN_HOP, st);
-                hipLaunchKernelGGL(plain_hop_kernel, dim3(L == 1 ? hop1_grid : c->hop_grid), dim3(kBlock), 0, st,
-                                   c->ctl, L, gr, c->s, P.pull_light, hc, ps.units());
-                ps.end(0, 1);
-            }
-            if (L >= 2 && L < k) {
-                ProfScope ps(g, KK_PLAIN_COMPACT, st);
-                hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, c->ctl, L, gr,
-                                   c->s, ps.units());
-                ps.end(0, 1);
-            }
-        }
-    }
-    // the last query's count (the others were closed by the next query's init)
+    const int64_t pam = (int64_t)P.push_atomic_max;
+    // hop 1 starts from the seed alone (top-down unless forced) and resets the
+    // other parity's bitmaps: the set-up grid suffices
+    const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
+    PlainCtl *ctl = c->ctl;
     {
         ProfScope ps(g, KK_PLAIN_INIT, st);
-        hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, c->ctl, gr, c->s, d_seeds,
-                           (int64_t)-1, (int)k, (int)k, P.dir_mode, P.alpha, P.beta, (int64_t)P.push_atomic_max,
-                           nnz_in, d_counts, d_te, ps.units());
+        hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, c->s[0], d_seeds,
+                           (int64_t)0, (int)k, P.dir_mode, P.alpha, P.beta, pam, nnz_in, d_counts, d_te, ps.units());
         ps.end(0, 1);
     }
-    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, c->ctl);
+    for (int64_t i = 0; i < num_seeds; ++i) {
+        const int p = (int)(i & 1);
+        PlainCtl *cq = ctl + i % 3, *cprev = ctl + (i + 2) % 3, *cnext = ctl + (i + 1) % 3;
+        {
+            ProfScope ps(g, KK_PLAIN_HOP, st);
+            hipLaunchKernelGGL(plain_hop1_kernel, dim3(hop1_grid), dim3(kBlock), 0, st, cq, cprev, cnext,
+                               (int)(i >= 1), (int)(i >= 2), gr, c->s[p], c->s[p ^ 1], d_seeds,
+                               i + 1 < num_seeds ? i + 1 : (int64_t)-1, (int)k, P.dir_mode, P.alpha, P.beta, pam,
+                               nnz_in, d_counts, d_te, P.pull_light, hc, ps.units());
+            ps.end(0, 1);
+        }
+        for (int L = 2; L <= k; ++L) {
+            {
+                ProfScope ps(g, KK_PLAIN_HOP, st);
+                hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, cq, L, gr, c->s[p],
+                                   P.pull_light, hc, ps.units());
+                ps.end(0, 1);
+            }
+            if (L < k) {
+                ProfScope ps(g, KK_PLAIN_COMPACT, st);
+                hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, cq, L, gr,
+                                   c->s[p], ps.units());
+                ps.end(0, 1);
+            }
+        }
+    }
+    // the last query's marks and the count of the one before it, then the last count
+    const int64_t m = num_seeds;
+    {
+        ProfScope ps(g, KK_PLAIN_INIT, st);
+        hipLaunchKernelGGL(plain_close_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl + (m - 1) % 3,
+                           ctl + (m + 1) % 3, (int)(m >= 2), gr, c->s[(m - 1) & 1], ps.units());
+        ps.end(0, 1);
+    }
+    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, ctl + (m - 1) % 3);
     KHOP_HIP(hipGetLastError());
 }
 
