@@ -3,8 +3,10 @@
 // One hop is the masked boolean product of the paper's Section II: the next
 // frontier is (A^T f) AND NOT visited over the (OR, AND) semiring.  A query is
 // one hop kernel per hop; a hop 2..k-1 is followed by a compaction kernel
-// (which exits at once unless the hop marked bytes).  Hop 1 never marks
-// bytes, and the last hop only counts, so neither needs a compaction.
+// (which exits at once unless the hop marked bytes).  Hop 1 claims its heads
+// atomically unless it is the last, and a last hop only counts: bottom-up it
+// counts its finds, top-down it marks bytes that the next query counts.  So
+// neither needs a compaction.
 // Consecutive queries alternate between two sets of bitmaps and region
 // counters: hop 1 of query i also counts the byte marks query i-1 left,
 // resets the other set for query i+1 and writes the count of query i-2, so a
@@ -94,12 +96,14 @@ struct Graph {
     int heavy;   // bottom-up: in-degree above which the chunk table takes a vertex
 };
 
-// The bitmaps and region counters of one query parity; the byte map and the
-// queues are shared by both.
+// The bitmaps, byte map and region counters of one query parity; the queues
+// are shared by both.  (Hop 1 of a query counts the marks the previous query
+// left while, as a last hop, it may mark its own: the byte maps must differ.)
 struct State {
     uint64_t *V;       // visited bitmap
     uint64_t *F[3];    // frontier bitmaps by hop % 3
     uint8_t *nextb;    // top-down marks (byte mode), all zero between hops
+    uint8_t *nsum;     // one byte per 64-vertex word: some mark of the word may be set
     int64_t *qb[2];    // region queues by hop parity, nreg * rc slots: the row begin of each queued vertex
     int64_t *qoff[2];  // out-degree prefix within each region's queue
     RegRec *regs;      // 3 * nreg region counters
@@ -212,10 +216,17 @@ __device__ __forceinline__ uint32_t nonzero_bytes(uint4 x) {
     return f(x.x) | (f(x.y) << 4) | (f(x.z) << 8) | (f(x.w) << 12);
 }
 
+// Marks head v in the byte map and its word in the summary (plain stores).
+__device__ __forceinline__ void mark(const State &s, int32_t v) {
+    s.nextb[v] = 1;
+    s.nsum[v >> 6] = 1;
+}
+
 // The byte marks a byte-mode last hop left on the 64 vertices of word w that
-// were unvisited (visited word vis); the marks are cleared.  The byte map is
-// padded to whole words.
+// were unvisited (visited word vis); the marks and the word's summary byte
+// are cleared.  The byte map is padded to whole words.
 __device__ __forceinline__ int64_t close_marks_word(const State &s, int64_t w, uint64_t vis) {
+    s.nsum[w] = 0;
     uint4 *mb = (uint4 *)(s.nextb + w * kWave);
     uint64_t m = 0;
 #pragma unroll
@@ -231,22 +242,26 @@ __device__ __forceinline__ void add_tail(PlainCtl *ctl, int64_t wid, int64_t v) 
     if (v) atomicAdd((unsigned long long *)&ctl->tail[wid & (kTail - 1)], (unsigned long long)v);
 }
 
-// Writes the count and traversed edges of a finished query (one wave).
+// Writes the count and traversed edges of a finished query (one wave).  Every
+// field is read first, so the loads overlap.
 __device__ void finalize(PlainCtl *ctl) {
     const int lane = lane_id();
+    const int32_t valid = ctl->valid;
+    const int64_t cacc = ctl->count_acc, teacc = ctl->te_acc;
+    int64_t *const oc = ctl->out_count, *const ot = ctl->out_te;
     int64_t t = 0;
-    for (int i = lane; i < kTail; i += kWave) {
-        t += ctl->tail[i];
-        ctl->tail[i] = 0;
-    }
+#pragma unroll
+    for (int i = 0; i < kTail / kWave; ++i) t += ctl->tail[i * kWave + lane];
+#pragma unroll
+    for (int i = 0; i < kTail / kWave; ++i) ctl->tail[i * kWave + lane] = 0;
     t = wave_sum(t);
-    if (lane == 0 && ctl->valid) {
-        *ctl->out_count = ctl->count_acc + t;
-        if (ctl->out_te) *ctl->out_te = ctl->te_acc;
+    if (lane == 0 && valid) {
+        *oc = cacc + t;
+        if (ot) *ot = teacc;
     }
 }
 
-// Block 0: the control record of query qi (seed `seed`) and the region
+// One block: the control record of query qi (seed `seed`) and the region
 // counters of its hops 0 and 1 (hop 0 holds the seed).  Its bitmap words are
 // reset by the caller's grid.
 __device__ void setup_query(PlainCtl *ctl, const Graph &g, const State &s, int32_t seed, int64_t qi, int k,
@@ -325,12 +340,17 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
 __global__ void __launch_bounds__(kBlock) plain_close_kernel(PlainCtl *ctl_last, PlainCtl *ctl_before,
                                                             int fin_before, Graph g, State s_last, int64_t *units) {
     if (ctl_last->last_bytes) {
-        int64_t fresh = 0;
+        int64_t fresh = 0, flagged = 0;
         for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock)
-            fresh += close_marks_word(s_last, w, s_last.V[w]);
+            if (s_last.nsum[w]) {
+                fresh += close_marks_word(s_last, w, s_last.V[w]);
+                ++flagged;
+            }
         fresh = wave_sum(fresh);
+        flagged = wave_sum(flagged);
         if (lane_id() == 0) add_tail(ctl_last, (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave, fresh);
-        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.n + 8 * g.nw);
+        if (lane_id() == 0) unit_add(units, 0, 72 * flagged);
+        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.nw);
     }
     if (blockIdx.x == 0 && threadIdx.x < kWave && fin_before) finalize(ctl_before);
 }
@@ -346,9 +366,35 @@ __global__ void __launch_bounds__(kWave) plain_final_kernel(PlainCtl *ctl) { fin
 // of list starts at or before it).
 // With `last` set (the query's final hop) discoveries are only counted into
 // *found: no frontier word, queue entry or degree is needed afterwards.
-__device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *epre, const int32_t *qcnt,
-                         const Graph &g, const State &s, RegRec *cur, uint64_t *smask, int64_t *found,
-                         int64_t *units) {
+// Claims head v, seen unvisited, with an atomicOr on its visited word (the
+// old value makes the discovery exactly-once) and appends it.
+__device__ __forceinline__ void push_claim(int L, const Graph &g, const State &s, RegRec *cur, uint64_t *Fn,
+                                           int32_t v) {
+    const uint64_t bit = 1ull << (v & 63);
+    const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
+    if (old & bit) return;
+    atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+    const int64_t vb = g.rowptr[v];
+    const int64_t od = g.rowptr[v + 1] - vb;
+    const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+    append_one(s, cur, L, v, vb, od, id);
+}
+
+// One frontier edge's head v: a byte mark (the visited test happens when the
+// marks are turned into frontier words or counted), or a claim.
+__device__ __forceinline__ void push_edge(int L, int mode, const Graph &g, const State &s, RegRec *cur, uint64_t *Fn,
+                                          int32_t v) {
+    if (mode == MODE_PUSH_BYTES) {
+        mark(s, v);
+    } else if (!((s.V[v >> 6] >> (v & 63)) & 1ull)) {
+        push_claim(L, g, s, cur, Fn, v);
+    }
+}
+
+constexpr int kWin = 4;  // windows of 64 frontier edges in flight per wave (short queues)
+
+__device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const int32_t *qcnt, const Graph &g,
+                         const State &s, RegRec *cur, uint64_t *smask, int64_t *units) {
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
@@ -374,6 +420,52 @@ __device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *e
         const int64_t qlen = qcnt[r];
         const int64_t *__restrict__ qb = s.qb[(L - 1) & 1] + (int64_t)r * s.rc;
         const int64_t *__restrict__ qoff = s.qoff[(L - 1) & 1] + (int64_t)r * s.rc;
+        const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
+        if (qlen <= kWave) {
+            // short queue: lane j holds entry j, so every window finds its
+            // entries with ballots and shuffles; kWin windows at a time, their
+            // column-index and visited loads issued together
+            const bool has = lane < qlen;
+            const int64_t offl = has ? qoff[lane] : INT64_MAX;
+            const int64_t begl = has ? qb[lane] : 0;
+            for (int64_t b0 = a0; b0 < a1; b0 += kWin * kWave) {
+                int64_t at[kWin];
+#pragma unroll
+                for (int r = 0; r < kWin; ++r) {
+                    const int64_t b = b0 + (int64_t)r * kWave;
+                    at[r] = -1;
+                    if (b >= a1) continue;  // uniform
+                    const int base = __popcll(ballot(offl < b));  // entries starting before the window
+                    const bool inwin = offl >= b && offl < b + kWave;
+                    if (lane == 0) smask[r] = 0;
+                    __builtin_amdgcn_wave_barrier();
+                    if (inwin) atomicOr((unsigned long long *)&smask[r], 1ull << (offl - b));
+                    __builtin_amdgcn_wave_barrier();
+                    const int owner = base + __popcll(smask[r] & le) - 1;  // entry of edge b + lane
+                    const int64_t ob = shfl64(begl, owner), oo = shfl64(offl, owner);
+                    const int64_t e = b + lane;
+                    if (e < a1) at[r] = ob + (e - oo);
+                    starts_seen += __popcll(ballot(inwin));
+                }
+                int32_t v[kWin];
+#pragma unroll
+                for (int r = 0; r < kWin; ++r) v[r] = at[r] >= 0 ? g.colidx[at[r]] : -1;
+                if (mode == MODE_PUSH_BYTES) {
+#pragma unroll
+                    for (int r = 0; r < kWin; ++r)
+                        if (v[r] >= 0) mark(s, v[r]);
+                } else {
+                    uint64_t vw[kWin];
+#pragma unroll
+                    for (int r = 0; r < kWin; ++r) vw[r] = v[r] >= 0 ? s.V[v[r] >> 6] : ~0ull;
+#pragma unroll
+                    for (int r = 0; r < kWin; ++r)
+                        if (!((vw[r] >> (v[r] & 63)) & 1ull)) push_claim(L, g, s, cur, Fn, v[r]);
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            continue;
+        }
         // base = #{ j < qlen : qoff[j] < a0 } by a 64-way search
         int64_t lo = 0, hi = qlen;
         while (hi - lo > kWave) {
@@ -411,7 +503,6 @@ __device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *e
             __builtin_amdgcn_wave_barrier();
             const uint64_t starts = *smask;
             const int ns = __popcll(ballot(inwin));
-            const uint64_t le = lane == 63 ? ~0ull : ((2ull << lane) - 1);
             const int c = __popcll(starts & le);
             const int src = c > 0 ? c - 1 : 0;
             const int64_t sb = shfl64(begj, src), so = shfl64(offj, src);
@@ -419,26 +510,7 @@ __device__ void push_hop(int L, int mode, bool last, int64_t E, const int64_t *e
             if (e < a1) {
                 const int64_t beg = c ? sb : carry_beg;
                 const int64_t off = c ? so : carry_off;
-                const int32_t v = g.colidx[beg + (e - off)];
-                const uint64_t bit = 1ull << (v & 63);
-                if (!(s.V[v >> 6] & bit)) {
-                    if (mode == MODE_PUSH_BYTES) {
-                        s.nextb[v] = 1;
-                    } else {
-                        const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
-                        if (!(old & bit)) {
-                            if (last) {
-                                *found += 1;
-                            } else {
-                                atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-                                const int64_t vb = g.rowptr[v];
-                                const int64_t od = g.rowptr[v + 1] - vb;
-                                const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
-                                append_one(s, cur, L, v, vb, od, id);
-                            }
-                        }
-                    }
-                }
+                push_edge(L, mode, g, s, cur, Fn, g.colidx[beg + (e - off)]);
             }
             if (ns > 0) {
                 carry_beg = shfl64(begj, ns - 1);
@@ -609,28 +681,30 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
 
 // Top-down hop 1: the seed alone is the frontier, so its out-edges are read
 // straight from its adjacency list (64 per wave) with no region prefix or
-// queue search; heads are claimed with atomicOr on their visited words.
-__device__ int64_t hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E, bool last, int64_t *units) {
+// queue search.  As the query's last hop it only marks bytes; otherwise heads
+// are claimed with atomicOr on their visited words (their row pointers are
+// loaded beside the claim) and appended.
+__device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E, bool last, int64_t *units) {
     const int lane = lane_id();
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     RegRec *cur = s.regs + s.nreg;  // hop 1's slot
     uint64_t *Fn = s.F[1];
-    int64_t found = 0, edges = 0;
+    int64_t edges = 0;
     for (int64_t e0 = wid * kWave; e0 < E; e0 += nwaves * kWave) {
         const int64_t e = e0 + lane;
         if (e < E) {
             const int32_t v = g.colidx[beg + e];
-            const uint64_t bit = 1ull << (v & 63);
-            const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
-            if (!(old & bit)) {
-                if (last) {
-                    ++found;
-                } else {
+            if (last) {
+                mark(s, v);
+            } else {
+                const uint64_t bit = 1ull << (v & 63);
+                const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
+                const int64_t vb = g.rowptr[v];
+                const int64_t od = g.rowptr[v + 1] - vb;
+                const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+                if (!(old & bit)) {
                     atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-                    const int64_t vb = g.rowptr[v];
-                    const int64_t od = g.rowptr[v + 1] - vb;
-                    const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
                     append_one(s, cur, 1, v, vb, od, id);
                 }
             }
@@ -639,7 +713,6 @@ __device__ int64_t hop1_push(const Graph &g, const State &s, int64_t beg, int64_
     }
     // 4 B per out-edge of the seed
     if (units && lane == 0 && edges) unit_add(units, 0, 4 * edges);
-    return wave_sum(found);
 }
 
 // One hop of query ctl on its state s.  No validity test: an invalid seed
@@ -676,19 +749,19 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
             if (blockIdx.x == 0 && t == 0) {
                 ctl->hdr[1].mu_before = mu;
                 ctl->hdr[1].dir = DIR_PUSH;
-                ctl->hdr[1].mode = MODE_PUSH_ATOMIC;
+                ctl->hdr[1].mode = last ? MODE_PUSH_BYTES : MODE_PUSH_ATOMIC;
+                if (last) ctl->last_bytes = 1;
                 ctl->te_acc += E;
                 if (units) unit_add(units, 0, 24);
             }
-            const int64_t found = hop1_push(g, s, beg, E, last, units);
-            if (last && lane == 0) add_tail(ctl, wid, found);
+            hop1_push(g, s, beg, E, last, units);
             return;
         }
     }
     __shared__ int64_t s_epre[kMaxRegions + 1];
     __shared__ int32_t s_qcnt[kMaxRegions];
     __shared__ int64_t s_tot[2][kWavesPerBlock];
-    __shared__ uint64_t s_mask[kWavesPerBlock];
+    __shared__ uint64_t s_mask[kWavesPerBlock][kWin];
     // previous hop's region counters: prefix of degree sums, totals
     const RegRec *prev = s.regs + (int64_t)((L - 1) % 3) * s.nreg;
     int64_t qd = 0, fc = 0, fd = 0;
@@ -732,10 +805,12 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
     } else {
         if (nf * (int64_t)beta < g.n) dir = DIR_PUSH;
     }
-    // hop 1 never marks bytes: no compaction launch follows it
+    // a top-down last hop only marks bytes (they are counted when the next
+    // query starts); earlier hops claim heads atomically up to push_atomic_max
+    // frontier edges
     const int mode = nf == 0 ? MODE_IDLE
                      : dir == DIR_PULL ? MODE_PULL
-                     : (E <= push_atomic_max || L == 1 ? MODE_PUSH_ATOMIC : MODE_PUSH_BYTES);
+                     : (!last && E <= push_atomic_max ? MODE_PUSH_ATOMIC : MODE_PUSH_BYTES);
     if (blockIdx.x == 0 && t == 0) {
         ctl->hdr[L % 3].mu_before = mu;
         ctl->hdr[L % 3].dir = dir;
@@ -747,7 +822,7 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
     }
     if (mode == MODE_IDLE) return;  // empty frontier: nothing left to find
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
-    int64_t found = 0;  // final hop: discoveries of this lane (push) or wave (pull)
+    int64_t found = 0;  // final bottom-up hop: discoveries of this wave
     if (mode == MODE_PULL) {
         __shared__ int64_t s_bv[kWavesPerBlock][kBufCap];
         __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
@@ -755,8 +830,7 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
         pull_hop(L, last, g, s, light, hc, cur, wb, &found, units);
         found = shfl64(found, 0);
     } else {
-        push_hop(L, mode, last, E, s_epre, s_qcnt, g, s, cur, &s_mask[wv], &found, units);
-        found = wave_sum(found);
+        push_hop(L, mode, E, s_epre, s_qcnt, g, s, cur, s_mask[wv], units);
     }
     if (last && lane == 0) add_tail(ctl, wid, found);
 }
@@ -776,18 +850,25 @@ __global__ void __launch_bounds__(kBlock) plain_hop1_kernel(PlainCtl *ctl, Plain
     const bool nvalid = nseed >= 0 && (int64_t)nseed < g.n;
     const int64_t nsw = nvalid ? (nseed >> 6) : -1;
     const uint64_t nsbit = nvalid ? (1ull << (nseed & 63)) : 0;
-    int64_t fresh = 0;
+    int64_t fresh = 0, flagged = 0;
     for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock) {
-        if (marks) fresh += close_marks_word(sn, w, sn.V[w]);
+        if (marks && sn.nsum[w]) {
+            fresh += close_marks_word(sn, w, sn.V[w]);
+            ++flagged;
+        }
         if (qn >= 0) reset_word(sn, w, nsw, nsbit);
     }
     if (marks) {
         fresh = wave_sum(fresh);
+        flagged = wave_sum(flagged);
         if (lane_id() == 0) add_tail(ctl_prev, (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave, fresh);
-        // the mark bytes and the visited words
-        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.n + 8 * g.nw);
+        // the summary bytes, then the marks and visited word of each flagged word
+        if (lane_id() == 0) unit_add(units, 0, 72 * flagged);
+        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.nw);
     }
-    if (blockIdx.x == 0) {
+    // the last block closes the slot and sets it up, beside the hop's own
+    // work, which starts at block 0
+    if (blockIdx.x == gridDim.x - 1) {
         if (fin_next && threadIdx.x < kWave) finalize(ctl_next);
         __syncthreads();
         if (qn >= 0)
@@ -813,7 +894,7 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    if (units && wid == 0 && lane == 0) unit_add(units, 0, g.n + 2 * ((g.n + 7) / 8));
+    if (units && wid == 0 && lane == 0) unit_add(units, 0, g.nw);  // the summary bytes
     __shared__ int64_t s_bv[kWavesPerBlock][kBufCap];
     __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
     const int wv = threadIdx.x / kWave;
@@ -823,13 +904,22 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
     int64_t found_total = 0;
     // four words per round: their marks and visited words are loaded before any is used
     for (int64_t w0 = wb0; w0 < wb1; w0 += 4) {
-        uint8_t nb[4];
+        uint8_t nb[4], sm[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sm[i] = w0 + i < wb1 ? s.nsum[w0 + i] : 0;
+        if (!(sm[0] | sm[1] | sm[2] | sm[3])) continue;  // no marks in these words
         uint64_t vis[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t v = (w0 + i) * kWave + lane;
-            nb[i] = (w0 + i < wb1 && v < g.n) ? s.nextb[v] : 0;
+            nb[i] = (sm[i] && v < g.n) ? s.nextb[v] : 0;
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (sm[i] && lane == 0) {
+                s.nsum[w0 + i] = 0;
+                unit_add(units, 0, 80);  // the word's marks, visited and frontier words
+            }
 #pragma unroll
         for (int i = 0; i < 4; ++i) vis[i] = ballot(nb[i]) ? s.V[w0 + i] : 0ull;
 #pragma unroll
@@ -890,8 +980,12 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     size_t off = 0;
     const size_t o_ctl = off;
     off += al(3 * sizeof(PlainCtl));
-    size_t o_V[2], o_F[2][3], o_regs[2];
+    size_t o_V[2], o_F[2][3], o_regs[2], o_nb[2], o_ns[2];
     for (int p = 0; p < 2; ++p) {
+        o_nb[p] = off;
+        off += al(nw * 64);  // the byte map, padded to whole words
+        o_ns[p] = off;
+        off += al(nw);
         o_V[p] = off;
         off += al(nw * 8);
         for (int i = 0; i < 3; ++i) {
@@ -901,8 +995,6 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
         o_regs[p] = off;
         off += al((size_t)3 * nreg * sizeof(RegRec));
     }
-    const size_t o_nb = off;
-    off += al(nw * 64);  // the byte map, padded to whole words
     size_t o_q[2], o_qoff[2];
     for (int i = 0; i < 2; ++i) {
         o_q[i] = off;
@@ -923,7 +1015,8 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
         st.V = (uint64_t *)(base + o_V[p]);
         for (int i = 0; i < 3; ++i) st.F[i] = (uint64_t *)(base + o_F[p][i]);
         st.regs = (RegRec *)(base + o_regs[p]);
-        st.nextb = (uint8_t *)(base + o_nb);
+        st.nextb = (uint8_t *)(base + o_nb[p]);
+        st.nsum = (uint8_t *)(base + o_ns[p]);
         for (int i = 0; i < 2; ++i) {
             st.qb[i] = (int64_t *)(base + o_q[i]);
             st.qoff[i] = (int64_t *)(base + o_qoff[i]);
