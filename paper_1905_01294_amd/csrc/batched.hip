@@ -327,10 +327,11 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x) {
     return x;
 }
 
-// counts_acc[w*64 + bit] += number of vertices whose word w has that bit.
-__global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__restrict__ V, int64_t n, int W,
+// counts_acc[w*64 + bit] += number of vertices whose word w has that bit, for
+// words w = w0 + blockIdx.y of rows W words long.
+__global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__restrict__ V, int64_t n, int W, int w0,
                                                             int64_t *counts_acc) {
-    const int w = blockIdx.y;
+    const int w = w0 + blockIdx.y;
     const int lane = lane_id();
     __shared__ int64_t s_acc[kWavesPerBlock][kWave];
     int64_t acc = 0;
@@ -348,6 +349,19 @@ __global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__r
         int64_t t = 0;
         for (int i = 0; i < kWavesPerBlock; ++i) t += s_acc[i][threadIdx.x];
         if (t) atomicAdd((unsigned long long *)&counts_acc[w * kWave + threadIdx.x], (unsigned long long)t);
+    }
+}
+
+// Repacks rows of W words to their first Wn words: Vn[v*Wn + w] = V[v*W + w],
+// likewise F.  The destination does not overlap the sources.
+__global__ void __launch_bounds__(kBlock) batch_narrow_kernel(const uint64_t *__restrict__ V,
+                                                             const uint64_t *__restrict__ F, int64_t n, int W, int Wn,
+                                                             uint64_t *__restrict__ Vn, uint64_t *__restrict__ Fn) {
+    const int64_t total = n * Wn;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = i / Wn, w = i - v * Wn;
+        Vn[i] = V[v * W + w];
+        Fn[i] = F[v * W + w];
     }
 }
 
@@ -521,7 +535,8 @@ void batch_ctx_destroy(BatchCtx *c) {
 int batch_ctx_words(const BatchCtx *c) { return c->W; }
 
 template <int G>
-static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, hipStream_t st, uint64_t *F, uint64_t *Fn) {
+static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hipStream_t st, uint64_t *V, uint64_t *F,
+                        uint64_t *Fn) {
     const int64_t n = g->n, nw = (n + 63) / 64;
     const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
@@ -532,7 +547,7 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, hipStream_t
     {
         ProfScope ps(g, KK_BATCH_PULL, st);
         hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx,
-                           c->V, F, Fn, n, c->W, wact, act, batch_heavy_table(g).threshold, Fbc, Fbn, Fbz,
+                           V, F, Fn, n, Wr, wact, act, batch_heavy_table(g).threshold, Fbc, Fbn, Fbz,
                            c->flags + (L - 1), c->flags + L, ps.units());
         // bytes: V read and write-back and Fn write per active word, the frontier bitmap once,
         // 4 per examined in-edge, 16 per scanned vertex, 8 per gathered word
@@ -543,8 +558,8 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, hipStream_t
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         ProfScope ps(g, KK_BATCH_PULL_HEAVY, st);
-        hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, F,
-                           Fn, c->W, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, Fbc, Fbn, c->flags + (L - 1),
+        hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, V, F, Fn,
+                           Wr, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, Fbc, Fbn, c->flags + (L - 1),
                            c->flags + L, ps.units());
         ps.end(16.0 * (double)ht.n, 0, 4.0, 0, 8.0 * wact);
     }
@@ -595,17 +610,46 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
                            c->flags + 1);
         ps.end(0);
     }
+    // Rows are Wr words long.  Seeds are sorted by k, so the active words of a
+    // level are a prefix; once they fit in half a row, the words behind them
+    // (finished seeds) are counted and the rows are repacked to the active
+    // width, which every later level then reads and writes.
+    uint64_t *V = c->V;
+    int Wr = W;
+    auto count_words = [&](int w0, int nwords) {
+        ProfScope ps(g, KK_BATCH_COUNT, st);
+        const int cgx = (int)std::max<int64_t>(1, std::min<int64_t>((n + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock),
+                                                                     (int64_t)g->cu_count * 2));
+        hipLaunchKernelGGL(batch_count_kernel, dim3(cgx, nwords), dim3(kBlock), 0, st, V, n, Wr, w0, c->acc);
+        ps.end(8.0 * n * nwords);
+    };
     for (int L = 2; L <= levels; ++L) {
         const int wa = wact[L];
         if (wa == 0) break;
+        if (2 * wa <= Wr) {
+            count_words(wa, Wr - wa);
+            // V and F move into the spare buffer (both fit: 2 * wa <= Wr); the old V becomes the next frontier's buffer
+            uint64_t *Vn = Nb, *Fnew = Nb + (int64_t)n * wa;
+            {
+                ProfScope ps(g, KK_BATCH_INIT, st);
+                const int ng = (int)std::min<int64_t>(((int64_t)n * wa + kBlock - 1) / kBlock, (int64_t)g->cu_count * 8);
+                hipLaunchKernelGGL(batch_narrow_kernel, dim3(std::max(ng, 1)), dim3(kBlock), 0, st, V, F, n, Wr, wa,
+                                   Vn, Fnew);
+                ps.end(2.0 * 8.0 * n * wa * 2);
+            }
+            Nb = V;
+            V = Vn;
+            F = Fnew;
+            Wr = wa;
+        }
         int G = 1;
         while (G < wa) G <<= 1;
         switch (G) {
-            case 1: launch_pull<1>(g, c, L, wa, st, F, Nb); break;
-            case 2: launch_pull<2>(g, c, L, wa, st, F, Nb); break;
-            case 4: launch_pull<4>(g, c, L, wa, st, F, Nb); break;
-            case 8: launch_pull<8>(g, c, L, wa, st, F, Nb); break;
-            default: launch_pull<16>(g, c, L, wa, st, F, Nb); break;
+            case 1: launch_pull<1>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            case 2: launch_pull<2>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            case 4: launch_pull<4>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            case 8: launch_pull<8>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            default: launch_pull<16>(g, c, L, wa, Wr, st, V, F, Nb); break;
         }
         std::swap(F, Nb);
         if ((L % 8) == 0 && L < levels) {
@@ -616,13 +660,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
             if (!flag) break;
         }
     }
-    {
-        ProfScope ps(g, KK_BATCH_COUNT, st);
-        const int cgx = (int)std::max<int64_t>(1, std::min<int64_t>((n + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock),
-                                                                     (int64_t)g->cu_count * 2));
-        hipLaunchKernelGGL(batch_count_kernel, dim3(cgx, W), dim3(kBlock), 0, st, c->V, n, W, c->acc);
-        ps.end(8.0 * n * W);
-    }
+    count_words(0, Wr);
     hipLaunchKernelGGL(batch_output_kernel, dim3((nslots + 255) / 256), dim3(256), 0, st, c->acc, c->perm, nslots,
                        d_counts);
     KHOP_HIP(hipGetLastError());
