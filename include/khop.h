@@ -149,7 +149,9 @@ typedef struct {
     double algorithmic_bytes; /* summed bytes the launches must move, from the per-unit traffic model */
 } khop_kernel_stat;
 
-/* enable != 0 starts collecting (and clears previous statistics); 0 stops. */
+/* enable != 0 starts collecting (and clears previous statistics); 0 stops.
+ * Enabling also times 16 empty launches bracketed the same way, reported
+ * under the name "empty_launch": the events' own share of each launch. */
 int khop_profile(khop_graph *g, int32_t enable);
 /* Copy up to max entries of the statistics collected so far; *n_out receives the count. */
 int khop_profile_read(khop_graph *g, khop_kernel_stat *out, int32_t max, int32_t *n_out);

@@ -25,7 +25,7 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line) {
 
 const char *const kKernelNames[KK_COUNT_KINDS] = {
     "plain_init", "plain_hop", "plain_compact", "batch_init", "batch_push", "batch_pull", "batch_pull_heavy",
-    "batch_count"};
+    "batch_count", "empty_launch"};
 
 template <class F>
 static int guard(F &&f) {
@@ -659,28 +659,42 @@ int khop_profile(khop_graph *g, int32_t enable) {
     return guard([&] {
         check_graph(g);
         KHOP_HIP(hipSetDevice(g->device));
-        std::lock_guard<std::mutex> lk(g->prof_mu);
-        Profiler &P = g->prof;
-        if (enable) {
-            if (!P.d_units) {
-                P.cap = 1 << 15;  // launches per collection; 2 KiB of counters each
-                if (hipMalloc(&P.d_units, (size_t)P.cap * 4 * 64 * 8) != hipSuccess) {
-                    (void)hipGetLastError();
-                    P.d_units = nullptr;
-                    fail(KHOP_ENOMEM, "device allocation for profiling counters failed");
+        {
+            std::lock_guard<std::mutex> lk(g->prof_mu);
+            Profiler &P = g->prof;
+            if (enable) {
+                if (!P.d_units) {
+                    P.cap = 1 << 15;  // launches per collection; 2 KiB of counters each
+                    if (hipMalloc(&P.d_units, (size_t)P.cap * 4 * 64 * 8) != hipSuccess) {
+                        (void)hipGetLastError();
+                        P.d_units = nullptr;
+                        fail(KHOP_ENOMEM, "device allocation for profiling counters failed");
+                    }
                 }
+                prof_collect(g);
+                KHOP_HIP(hipMemset(P.d_units, 0, (size_t)P.cap * 4 * 64 * 8));
+                KHOP_HIP(hipDeviceSynchronize());
+                P.next_slot = 0;
+                std::fill(std::begin(P.launches), std::end(P.launches), 0);
+                std::fill(std::begin(P.ms), std::end(P.ms), 0.0);
+                std::fill(std::begin(P.bytes), std::end(P.bytes), 0.0);
+                P.on = true;
+            } else {
+                prof_collect(g);
+                P.on = false;
             }
-            prof_collect(g);
-            KHOP_HIP(hipMemset(P.d_units, 0, (size_t)P.cap * 4 * 64 * 8));
-            KHOP_HIP(hipDeviceSynchronize());
-            P.next_slot = 0;
-            std::fill(std::begin(P.launches), std::end(P.launches), 0);
-            std::fill(std::begin(P.ms), std::end(P.ms), 0.0);
-            std::fill(std::begin(P.bytes), std::end(P.bytes), 0.0);
-            P.on = true;
-        } else {
-            prof_collect(g);
-            P.on = false;
+        }
+        if (enable) {
+            // the cost of the measurement itself: empty launches bracketed like every profiled one
+            hipStream_t st;
+            KHOP_HIP(hipStreamCreate(&st));
+            for (int i = 0; i < 16; ++i) {
+                ProfScope ps(g, KK_EMPTY_LAUNCH, st);
+                prof_empty(st);
+                ps.end(0);
+            }
+            KHOP_HIP(hipStreamSynchronize(st));
+            KHOP_HIP(hipStreamDestroy(st));
         }
     });
 }

@@ -84,6 +84,7 @@ enum KernelKind {
     KK_BATCH_PULL,
     KK_BATCH_PULL_HEAVY,
     KK_BATCH_COUNT,
+    KK_EMPTY_LAUNCH,  // an empty kernel timed the same way: the event bracket's own cost
     KK_COUNT_KINDS
 };
 extern const char *const kKernelNames[KK_COUNT_KINDS];
@@ -130,7 +131,8 @@ class ProfScope {
 };
 
 void prof_collect(khop_graph *g);  // caller holds g->prof_mu
-void prof_delay(hipStream_t st);    // prof.hip
+void prof_delay(hipStream_t st);
+void prof_empty(hipStream_t st);    // prof.hip
 
 }  // namespace khop
 

@@ -235,3 +235,23 @@ def test_torch_side_stream(K, g0, g0_gpu, g0_oracle):
     expect = g0_oracle.count(seeds, 3)[0]
     assert np.array_equal(d_c.cpu().numpy(), expect)
     assert np.array_equal(d_b.cpu().numpy(), expect)
+
+
+def test_profile_reports_kernels_and_event_cost(K, g0, g0_gpu, g0_oracle):
+    """khop_profile: per-kind launch counts and algorithmic bytes of a profiled
+    run, the empty launches that price the event bracket, and unchanged counts."""
+    el, _ = g0
+    seeds = graphgen.draw_seeds(el, 16, seed=5)
+    g0_gpu.profile(True)
+    c = g0_gpu.count(seeds, 2)
+    b = g0_gpu.count_batched(seeds, np.full(16, 3))
+    stats = g0_gpu.profile_read()
+    g0_gpu.profile(False)
+    assert np.array_equal(c, g0_oracle.count(seeds, 2)[0])
+    assert np.array_equal(b, g0_oracle.count(seeds, 3)[0])
+    assert stats["empty_launch"]["launches"] == 16
+    assert stats["empty_launch"]["algorithmic_bytes"] == 0
+    assert stats["plain_hop"]["launches"] == 2 * 16  # hop 1 and hop 2 of each query
+    assert stats["plain_hop"]["algorithmic_bytes"] > 0 and stats["plain_hop"]["total_ms"] > 0
+    assert stats["batch_pull"]["launches"] >= 2 and stats["batch_pull"]["algorithmic_bytes"] > 0
+    assert "batch_count" in stats and "batch_push" in stats
