@@ -36,8 +36,45 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 
+// Frontier bitmaps of one hop (bit v: some word of F[v] may be nonzero; a
+// superset only costs gathers) and 64-lane counts of their set bits.  A hop
+// reads `cur`, sets bits of `next` and clears `clear`, the bitmap of the hop
+// after it.
+struct FrontierBits {
+    const uint64_t *cur;
+    uint64_t *next;
+    uint64_t *clear;
+    const int64_t *cnt_cur;
+    int64_t *cnt_next;
+    int64_t *cnt_clear;
+};
+constexpr int kCntLanes = 64;
+// A frontier holding more than n / kDenseDiv vertices is dense: its hop skips
+// the bitmap test, since most in-edges would hit anyway.
+constexpr int kDenseDiv = 16;
+
+// Sets bit v of a frontier bitmap; returns whether this call set it.  The
+// plain read skips most repeats on hubs.
+__device__ __forceinline__ bool fb_set(uint64_t *fb, int32_t v) {
+    const uint64_t bit = 1ull << (v & 63);
+    if (fb[v >> 6] & bit) return false;
+    const uint64_t old = atomicOr((unsigned long long *)&fb[v >> 6], (unsigned long long)bit);
+    return !(old & bit);
+}
+
+// Adds a wave's count of newly set frontier bits (one lane calls).
+__device__ __forceinline__ void fb_count(int64_t *cnt, int64_t v) {
+    if (v) atomicAdd((unsigned long long *)&cnt[(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) & (kCntLanes - 1)],
+                     (unsigned long long)v);
+}
+
+// Whether the frontier counted in cnt is dense (wave-uniform).
+__device__ __forceinline__ bool fb_dense(const int64_t *cnt, int64_t n) {
+    return wave_sum(cnt[lane_id() & (kCntLanes - 1)]) * kDenseDiv > n;
+}
+
 __global__ void __launch_bounds__(kBlock) batch_zero_kernel(uint64_t *a, uint64_t *b, int64_t words, uint64_t *fb,
-                                                           int64_t fb_words, int64_t *acc, int64_t nacc,
+                                                           int64_t fb_words, int64_t *fc, int64_t *acc, int64_t nacc,
                                                            int32_t *flags, int nflags) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride) {
@@ -48,6 +85,7 @@ __global__ void __launch_bounds__(kBlock) batch_zero_kernel(uint64_t *a, uint64_
     if (blockIdx.x == 0) {
         for (int64_t i = threadIdx.x; i < nacc; i += kBlock) acc[i] = 0;
         for (int i = threadIdx.x; i < nflags; i += kBlock) flags[i] = 0;
+        for (int i = threadIdx.x; i < 3 * kCntLanes; i += kBlock) fc[i] = 0;
     }
 }
 
@@ -61,11 +99,6 @@ __global__ void __launch_bounds__(kBlock) batch_seed_kernel(uint64_t *V, const i
     atomicOr((unsigned long long *)&V[at], 1ull << (j & 63));
 }
 
-// Sets bit v of a frontier bitmap; the plain read skips most repeats on hubs.
-__device__ __forceinline__ void fb_set(uint64_t *fb, int32_t v) {
-    const uint64_t bit = 1ull << (v & 63);
-    if (!(fb[v >> 6] & bit)) atomicOr((unsigned long long *)&fb[v >> 6], (unsigned long long)bit);
-}
 
 // Hop 1: one block per seed slot with k >= 1 ORs its bit into F and V of each
 // out-neighbor and marks the neighbor in the frontier bitmap.
@@ -74,7 +107,8 @@ __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t 
                                                                  const int32_t *seeds, const int32_t *perm,
                                                                  const int32_t *ks_sorted, int nslots, int W,
                                                                  uint64_t *F, uint64_t *V, uint64_t *fb,
-                                                                 int32_t *flag) {
+                                                                 int64_t *fb_cnt, int32_t *flag) {
+    int64_t fresh = 0;
     for (int j = blockIdx.x; j < nslots; j += gridDim.x) {
         if (ks_sorted[j] < 1) continue;
         const int32_t s = seeds[perm[j]];
@@ -86,9 +120,11 @@ __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t 
             const int32_t v = colidx[x];
             atomicOr((unsigned long long *)&F[(int64_t)v * W + w], bit);
             atomicOr((unsigned long long *)&V[(int64_t)v * W + w], bit);
-            fb_set(fb, v);
+            fresh += fb_set(fb, v);
         }
     }
+    fresh = wave_sum(fresh);
+    if (lane_id() == 0) fb_count(fb_cnt, fresh);
 }
 
 // Bits of the groups of G lanes that have any bit of m: bit g for group g.
@@ -117,15 +153,17 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
                                                            uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
                                                            uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
                                                            const uint64_t *__restrict__ act, int heavy,
-                                                           const uint64_t *__restrict__ Fbc, uint64_t *Fbn,
-                                                           uint64_t *Fbz, const int32_t *prev_flag, int32_t *flag,
+                                                           FrontierBits fb, const int32_t *prev_flag, int32_t *flag,
                                                            int64_t *units) {
     if (*prev_flag == 0) return;  // empty frontier: nothing left to find
     {
         const int64_t nw = (n + kWave - 1) / kWave;
         for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBlock)
-            Fbz[i] = 0;
+            fb.clear[i] = 0;
+        if (blockIdx.x == 0 && threadIdx.x < kCntLanes) fb.cnt_clear[threadIdx.x] = 0;
     }
+    const uint64_t *__restrict__ Fbc = fb.cur;
+    const bool dense = fb_dense(fb.cnt_cur, n);
     constexpr int VPW = kWave / G;                          // vertices per wave
     constexpr int R = G == 1 ? 4 : (G >= 16 ? 1 : 16 / G);  // rounds of G in-edges per step
     const int lane = lane_id();
@@ -135,7 +173,7 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
     const uint64_t actw = wi < wact ? act[wi] : 0ull;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     bool any = false;
-    int64_t examined = 0, scanned = 0, gathered = 0;
+    int64_t examined = 0, scanned = 0, gathered = 0, fresh = 0;
     for (int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; wv * VPW < n; wv += nwaves) {
         const int64_t v = wv * VPW + grp;
         const bool valid = v < n && wi < wact;
@@ -163,7 +201,7 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
                 u[r] = (active && x < e) ? in_colidx[x] : -1;
             }
 #pragma unroll
-            for (int r = 0; r < R; ++r) hit[r] = u[r] >= 0 && test_bit(Fbc, u[r]);
+            for (int r = 0; r < R; ++r) hit[r] = u[r] >= 0 && (dense || test_bit(Fbc, u[r]));
             if constexpr (G == 1) {
 #pragma unroll
                 for (int r = 0; r < R; ++r)
@@ -209,9 +247,11 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
         const uint64_t gm = group_any<G>(ballot(nx != 0));
         if (gm && lane == 0) {
             const int64_t v0 = wv * VPW;  // VPW divides 64: the wave's vertices share one bitmap word
-            atomicOr((unsigned long long *)&Fbn[v0 >> 6], (unsigned long long)(gm << (v0 & 63)));
+            const uint64_t old = atomicOr((unsigned long long *)&fb.next[v0 >> 6], (unsigned long long)(gm << (v0 & 63)));
+            fresh += __popcll(gm << (v0 & 63) & ~old);
         }
     }
+    if (lane == 0) fb_count(fb.cnt_next, fresh);
     if (ballot(any) && lane == 0) atomicOr(flag, 1);
     if (units) {
         const int64_t ex = wave_sum(examined), sc = wave_sum(scanned), ga = wave_sum(gathered);
@@ -239,9 +279,11 @@ template <int G>
 __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     const int32_t *__restrict__ in_colidx, uint64_t *V, const uint64_t *__restrict__ F, uint64_t *Fn, int W, int wact,
     const uint64_t *__restrict__ act, const int32_t *__restrict__ hvert, const int64_t *__restrict__ hbegin,
-    const int64_t *__restrict__ hend, int64_t n_items, const uint64_t *__restrict__ Fbc, uint64_t *Fbn,
-    const int32_t *prev_flag, int32_t *flag, int64_t *units) {
+    const int64_t *__restrict__ hend, int64_t n_items, int64_t n, FrontierBits fb, const int32_t *prev_flag,
+    int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;
+    const uint64_t *__restrict__ Fbc = fb.cur;
+    const bool dense = fb_dense(fb.cnt_cur, n);
     constexpr int S = kWave / G;  // gather streams
     __shared__ int32_t s_hit[kWavesPerBlock][4 * kWave];
     const int lane = lane_id();
@@ -251,7 +293,7 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     const uint64_t actw = wi < wact ? act[wi] : 0ull;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     bool any = false;
-    int64_t examined = 0, gathered = 0;
+    int64_t examined = 0, gathered = 0, fresh = 0;
     for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wv; i < n_items; i += nwaves) {
         const int64_t v = hvert[i];
         const int64_t at = v * W + wi;
@@ -260,7 +302,22 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
         if (!ballot(need != 0)) continue;
         const int64_t b = hbegin[i], e = hend[i];
         uint64_t acc = 0;
-        for (int64_t x0 = b; x0 < e; x0 += 4 * kWave) {
+        const int64_t ex0 = examined;
+        if (dense) {
+            // every in-edge gathered: stream sg takes edges sg, sg + S, ...
+            for (int64_t x0 = b; x0 < e; x0 += 4 * S) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t x = x0 + r * S + sg;
+                    if (x < e && wi < wact) acc |= F[(int64_t)in_colidx[x] * W + wi];
+                }
+                examined += std::min<int64_t>(4 * S, e - x0);
+                const uint64_t full = subgroup_or<G>(acc);
+                if (!ballot((full & need) != need)) break;
+            }
+            gathered += examined - ex0;  // every examined in-edge is gathered
+        }
+        for (int64_t x0 = dense ? e : b; x0 < e; x0 += 4 * kWave) {
             int32_t u[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -299,8 +356,9 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
             atomicOr((unsigned long long *)&V[at], (unsigned long long)nx);
             any = true;
         }
-        if (ballot(nx != 0) && lane == 0) fb_set(Fbn, (int32_t)v);
+        if (ballot(nx != 0) && lane == 0) fresh += fb_set(fb.next, (int32_t)v);
     }
+    if (lane == 0) fb_count(fb.cnt_next, fresh);
     if (ballot(any) && lane == 0) atomicOr(flag, 1);
     if (units && lane == 0) {
         unit_add(units, 1, examined);
@@ -422,7 +480,8 @@ __global__ void serve_admit_kernel(uint64_t *V, uint64_t *F, int W, const int32_
 __global__ void __launch_bounds__(kBlock) serve_push_kernel(const int64_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ colidx, int W,
                                                            const int32_t *slots, const int32_t *seeds, int count,
-                                                           uint64_t *Fn, uint64_t *V, uint64_t *Fbn) {
+                                                           uint64_t *Fn, uint64_t *V, uint64_t *Fbn, int64_t *fb_cnt) {
+    int64_t fresh = 0;
     for (int i = blockIdx.x; i < count; i += gridDim.x) {
         const int j = slots[i];
         const int32_t s = seeds[i];
@@ -433,9 +492,11 @@ __global__ void __launch_bounds__(kBlock) serve_push_kernel(const int64_t *__res
             const int64_t at = (int64_t)v * W + (j >> 6);
             atomicOr((unsigned long long *)&Fn[at], bit);
             atomicOr((unsigned long long *)&V[at], bit);
-            fb_set(Fbn, v);
+            fresh += fb_set(Fbn, v);
         }
     }
+    fresh = wave_sum(fresh);
+    if (lane_id() == 0) fb_count(fb_cnt, fresh);
 }
 
 __global__ void fill_zero_i64(int64_t *a, int64_t n) {
@@ -449,6 +510,7 @@ struct BatchCtx {
     int W = 0;  // words per vertex (1..16)
     uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
     uint64_t *Fb = nullptr;    // three frontier bitmaps of nw words each (hop l uses slot l % 3)
+    int64_t *Fc = nullptr;     // their set-bit counts, 64 lanes each
     int64_t *acc = nullptr;    // 64 * W counters
     uint64_t *act = nullptr;   // kMaxLevels * W active masks
     int32_t *flags = nullptr;  // kMaxLevels + 1 frontier-nonempty flags
@@ -480,6 +542,8 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     off += bits;
     const size_t oFb = off;
     off += al(3 * (size_t)((n + 63) / 64) * 8);
+    const size_t oFc = off;
+    off += al(3 * kCntLanes * 8);
     const size_t oacc = off;
     off += al(64 * (size_t)words * 8);
     const size_t oact = off;
@@ -501,6 +565,7 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     c->F = (uint64_t *)(b + oF);
     c->N = (uint64_t *)(b + oN);
     c->Fb = (uint64_t *)(b + oFb);
+    c->Fc = (int64_t *)(b + oFc);
     c->acc = (int64_t *)(b + oacc);
     c->act = (uint64_t *)(b + oact);
     c->flags = (int32_t *)(b + oflags);
@@ -542,13 +607,13 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
                                                                  (int64_t)g->cu_count * 16));
     const uint64_t *act = c->act + (int64_t)(L - 1) * c->W;
-    const uint64_t *Fbc = c->Fb + ((L - 1) % 3) * nw;
-    uint64_t *Fbn = c->Fb + (L % 3) * nw, *Fbz = c->Fb + ((L + 1) % 3) * nw;
+    const FrontierBits fb{c->Fb + ((L - 1) % 3) * nw, c->Fb + (L % 3) * nw,       c->Fb + ((L + 1) % 3) * nw,
+                          c->Fc + ((L - 1) % 3) * kCntLanes, c->Fc + (L % 3) * kCntLanes, c->Fc + ((L + 1) % 3) * kCntLanes};
     {
         ProfScope ps(g, KK_BATCH_PULL, st);
         hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx,
-                           V, F, Fn, n, Wr, wact, act, batch_heavy_table(g).threshold, Fbc, Fbn, Fbz,
-                           c->flags + (L - 1), c->flags + L, ps.units());
+                           V, F, Fn, n, Wr, wact, act, batch_heavy_table(g).threshold, fb, c->flags + (L - 1),
+                           c->flags + L, ps.units());
         // bytes: V read and write-back and Fn write per active word, the frontier bitmap once,
         // 4 per examined in-edge, 16 per scanned vertex, 8 per gathered word
         ps.end(3.0 * 8.0 * (double)n * wact + 2.0 * 8.0 * nw, 0, 4.0, 16.0, 8.0 * wact);
@@ -559,7 +624,7 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         ProfScope ps(g, KK_BATCH_PULL_HEAVY, st);
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, V, F, Fn,
-                           Wr, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, Fbc, Fbn, c->flags + (L - 1),
+                           Wr, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->flags + (L - 1),
                            c->flags + L, ps.units());
         ps.end(16.0 * (double)ht.n, 0, 4.0, 0, 8.0 * wact);
     }
@@ -597,7 +662,8 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     {
         ProfScope ps(g, KK_BATCH_INIT, st);
         hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, c->F,
-                           (int64_t)n * W, c->Fb, 3 * ((n + 63) / 64), c->acc, (int64_t)64 * W, c->flags, levels + 1);
+                           (int64_t)n * W, c->Fb, 3 * ((n + 63) / 64), c->Fc, c->acc, (int64_t)64 * W, c->flags,
+                           levels + 1);
         ps.end(2.0 * 8.0 * n * W + 3.0 * 8.0 * ((n + 63) / 64));
     }
     hipLaunchKernelGGL(batch_seed_kernel, dim3((nslots + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->V, d_seeds,
@@ -607,7 +673,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         ProfScope ps(g, KK_BATCH_PUSH, st);
         hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
                            g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, F, c->V, c->Fb + (int64_t)((n + 63) / 64),
-                           c->flags + 1);
+                           c->Fc + kCntLanes, c->flags + 1);
         ps.end(0);
     }
     // Rows are Wr words long.  Seeds are sorted by k, so the active words of a
@@ -673,6 +739,7 @@ struct ServeCtx {
     int W = 0;
     uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
     uint64_t *Fb = nullptr;  // three frontier bitmaps of nw words; slot fbi holds F's
+    int64_t *Fc = nullptr;   // their set-bit counts, 64 lanes each
     int fbi = 0;
     int64_t *acc = nullptr;     // 64 * W counters
     uint64_t *d_act = nullptr;  // W active masks of the bottom-up pass
@@ -708,6 +775,8 @@ ServeCtx *serve_ctx_create(khop_graph *g, int words) {
     off += bits;
     const size_t oFb = off;
     off += al((size_t)3 * ((n + 63) / 64) * 8);
+    const size_t oFc = off;
+    off += al(3 * kCntLanes * 8);
     const size_t oacc = off;
     off += al(slots * 8);
     const size_t oact = off;
@@ -730,6 +799,7 @@ ServeCtx *serve_ctx_create(khop_graph *g, int words) {
     c->F = (uint64_t *)(b + oF);
     c->N = (uint64_t *)(b + oN);
     c->Fb = (uint64_t *)(b + oFb);
+    c->Fc = (int64_t *)(b + oFc);
     c->acc = (int64_t *)(b + oacc);
     c->d_act = (uint64_t *)(b + oact);
     c->d_fin = (uint64_t *)(b + ofin);
@@ -775,16 +845,16 @@ static void serve_pull(ServeCtx *c, hipStream_t st) {
                                                                  (int64_t)g->cu_count * 16));
     const HeavyTable &ht = batch_heavy_table(g);
     const int64_t nw = (n + 63) / 64;
-    const uint64_t *Fbc = c->Fb + c->fbi * nw;
-    uint64_t *Fbn = c->Fb + ((c->fbi + 1) % 3) * nw, *Fbz = c->Fb + ((c->fbi + 2) % 3) * nw;
+    const int i0 = c->fbi, i1 = (c->fbi + 1) % 3, i2 = (c->fbi + 2) % 3;
+    const FrontierBits fb{c->Fb + i0 * nw, c->Fb + i1 * nw, c->Fb + i2 * nw,
+                          c->Fc + i0 * kCntLanes, c->Fc + i1 * kCntLanes, c->Fc + i2 * kCntLanes};
     hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
-                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, Fbc, Fbn, Fbz, c->d_one, c->d_one + 1,
-                       nullptr);
+                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, fb, c->d_one, c->d_one + 1, nullptr);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
-                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, Fbc, Fbn, c->d_one,
+                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->d_one,
                            c->d_one + 1, nullptr);
     }
 }
@@ -829,7 +899,7 @@ void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, 
         if (n_new > 0)
             hipLaunchKernelGGL(serve_push_kernel, dim3(std::min(n_new, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
                                g->d_colidx, W, c->d_slots, c->d_seeds, n_new, c->N, c->V,
-                               c->Fb + ((c->fbi + 1) % 3) * ((n + 63) / 64));
+                               c->Fb + ((c->fbi + 1) % 3) * ((n + 63) / 64), c->Fc + ((c->fbi + 1) % 3) * kCntLanes);
         std::swap(c->F, c->N);
         c->fbi = (c->fbi + 1) % 3;
     }
