@@ -51,7 +51,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
-constexpr int kMaxRegions = kBlock;  // one region per thread in the prefix
+constexpr int kMaxRegions = 256;  // regions of a hop: four per lane of the one wave that prefixes them
 constexpr int kSumBits = 33;         // packed (count << 33) | sum
 constexpr uint64_t kSumMask = (1ull << kSumBits) - 1;
 constexpr int kTail = 256;           // lanes of a query's last-hop counter
@@ -760,38 +760,46 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
     }
     __shared__ int64_t s_epre[kMaxRegions + 1];
     __shared__ int32_t s_qcnt[kMaxRegions];
-    __shared__ int64_t s_tot[2][kWavesPerBlock];
+    __shared__ int64_t s_tot[3];
     __shared__ uint64_t s_mask[kWavesPerBlock][kWin];
-    // previous hop's region counters: prefix of degree sums, totals
-    const RegRec *prev = s.regs + (int64_t)((L - 1) % 3) * s.nreg;
-    int64_t qd = 0, fc = 0, fd = 0;
-    if (t < s.nreg) {
-        const RegRec rr = prev[t];
-        qd = pk_sum(rr.qpack);
-        fc = pk_count(rr.fpack);
-        fd = pk_sum(rr.fpack);
-        s_qcnt[t] = (int32_t)pk_count(rr.qpack);
-    }
-    const int64_t xq = wave_exclusive_sum(qd);
-    const int64_t wq = wave_sum(qd), wf = wave_sum(fc), wd = wave_sum(fd);
-    if (lane == 0) {
-        s_tot[0][wv] = wq;
-        s_tot[1][wv] = wf;
+    // previous hop's region counters: wave 0 prefixes their degree sums (four
+    // regions per lane) and totals them; one barrier publishes the result
+    constexpr int kRpl = kMaxRegions / kWave;  // regions per lane
+    if (wv == 0) {
+        const RegRec *prev = s.regs + (int64_t)((L - 1) % 3) * s.nreg;
+        int64_t q[kRpl], lq = 0, lf = 0, ld = 0;
+#pragma unroll
+        for (int j = 0; j < kRpl; ++j) {
+            const int r = lane * kRpl + j;
+            q[j] = 0;
+            int32_t qc = 0;
+            if (r < s.nreg) {
+                const RegRec rr = prev[r];
+                q[j] = pk_sum(rr.qpack);
+                qc = (int32_t)pk_count(rr.qpack);
+                lf += pk_count(rr.fpack);
+                ld += pk_sum(rr.fpack);
+            }
+            if (r < kMaxRegions) s_qcnt[r] = qc;
+            lq += q[j];
+        }
+        int64_t pre = wave_exclusive_sum(lq);
+#pragma unroll
+        for (int j = 0; j < kRpl; ++j) {
+            const int r = lane * kRpl + j;
+            if (r <= s.nreg) s_epre[r] = pre;  // entry nreg gets the total
+            pre += q[j];
+        }
+        const int64_t E = wave_sum(lq), nf = wave_sum(lf), din = wave_sum(ld);
+        if (lane == 0) {
+            s_tot[0] = E;
+            s_tot[1] = nf;
+            s_tot[2] = din;
+            if (s.nreg == kMaxRegions) s_epre[kMaxRegions] = E;
+        }
     }
     __syncthreads();
-    int64_t E = 0, nf = 0, pre = 0;
-    for (int i = 0; i < kWavesPerBlock; ++i) {
-        if (i < wv) pre += s_tot[0][i];
-        E += s_tot[0][i];
-        nf += s_tot[1][i];
-    }
-    if (t < s.nreg) s_epre[t] = pre + xq;
-    if (t == 0) s_epre[s.nreg] = E;
-    __syncthreads();
-    if (lane == 0) s_tot[0][wv] = wd;
-    __syncthreads();
-    int64_t din = 0;
-    for (int i = 0; i < kWavesPerBlock; ++i) din += s_tot[0][i];
+    const int64_t E = s_tot[0], nf = s_tot[1], din = s_tot[2];
     const int64_t mu = hp.mu_before - din;
     int dir = hp.dir;
     if (L == 1) {
