@@ -721,12 +721,24 @@ __device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E
 // counters, so their loads overlap.
 __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, int light, const HeavyChunks &hc,
                          int64_t *units) {
+    const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
+    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    // wave 0 loads the previous hop's region counters (four per lane) first, so
+    // that their loads are in flight with the control words'
+    constexpr int kRpl = kMaxRegions / kWave;  // regions per lane
+    RegRec rr[kRpl];
+    if (wv == 0) {
+        const RegRec *prev = s.regs + (int64_t)((L - 1) % 3) * s.nreg;
+#pragma unroll
+        for (int j = 0; j < kRpl; ++j) {
+            const int r = lane * kRpl + j;
+            rr[j] = r < s.nreg ? prev[r] : RegRec{0, 0};
+        }
+    }
     const int32_t k = ctl->k, dir_mode = ctl->dir_mode, alpha = ctl->alpha, beta = ctl->beta;
     const int64_t push_atomic_max = ctl->push_atomic_max;
     const HopHdr hp = ctl->hdr[(L - 1) % 3];
     const bool last = L >= k;  // the final hop only counts
-    const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
-    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wv;
     if (!last) {
         // the slots hop l+1 writes start clear
         RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
@@ -762,25 +774,17 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
     __shared__ int32_t s_qcnt[kMaxRegions];
     __shared__ int64_t s_tot[3];
     __shared__ uint64_t s_mask[kWavesPerBlock][kWin];
-    // previous hop's region counters: wave 0 prefixes their degree sums (four
-    // regions per lane) and totals them; one barrier publishes the result
-    constexpr int kRpl = kMaxRegions / kWave;  // regions per lane
+    // wave 0 prefixes the region counters' degree sums and totals them; one
+    // barrier publishes the result
     if (wv == 0) {
-        const RegRec *prev = s.regs + (int64_t)((L - 1) % 3) * s.nreg;
         int64_t q[kRpl], lq = 0, lf = 0, ld = 0;
 #pragma unroll
         for (int j = 0; j < kRpl; ++j) {
             const int r = lane * kRpl + j;
-            q[j] = 0;
-            int32_t qc = 0;
-            if (r < s.nreg) {
-                const RegRec rr = prev[r];
-                q[j] = pk_sum(rr.qpack);
-                qc = (int32_t)pk_count(rr.qpack);
-                lf += pk_count(rr.fpack);
-                ld += pk_sum(rr.fpack);
-            }
-            if (r < kMaxRegions) s_qcnt[r] = qc;
+            q[j] = pk_sum(rr[j].qpack);
+            s_qcnt[r] = (int32_t)pk_count(rr[j].qpack);
+            lf += pk_count(rr[j].fpack);
+            ld += pk_sum(rr[j].fpack);
             lq += q[j];
         }
         int64_t pre = wave_exclusive_sum(lq);
