@@ -191,12 +191,24 @@ def main():
         dom_name, dom = max(kernels.items(), key=lambda kv: kv[1]["launches"] * kv[1]["avg_us"])
         achieved = dom["gbs"]
         tr = traffic_per_launch(dom_name)
+        copy_gbs = measure_copy_gbs(torch)
+        # time-weighted aggregate over the traversal kernels
+        trav = [kv for name, kv in kernels.items()
+                if name in ("plain_hop", "plain_compact", "batch_pull", "batch_pull_heavy")]
+        trav_s = sum(kv["avg_us"] * kv["launches"] for kv in trav) * 1e-6
+        trav_gbs = sum(kv["algorithmic_bytes"] for kv in trav) / trav_s / 1e9 if trav_s > 0 else 0.0
         roofline = {"kernel": dom_name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": round(tr, 1) if tr is not None else None, "traffic_unit": "bytes per launch",
                     "launches": dom["launches"], "avg_launch_us": dom["avg_us"],
                     "event_avg_launch_us": dom["event_avg_us"], "event_overhead_us": round(overhead_us, 3),
-                    "algorithmic_bytes_per_launch": round(dom["algorithmic_bytes"] / dom["launches"], 1)}
+                    "algorithmic_bytes_per_launch": round(dom["algorithmic_bytes"] / dom["launches"], 1),
+                    "copy_ceiling_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                    "traversal_aggregate": {"kernels": ["plain_hop", "plain_compact", "batch_pull",
+                                                        "batch_pull_heavy"],
+                                            "achieved": round(trav_gbs, 1),
+                                            "frac": round(trav_gbs / HBM_PEAK_GBS, 4),
+                                            "frac_of_copy": round(trav_gbs / copy_gbs, 4)}}
 
     # ---- per-query latency through the host entry point (PCIe round trip included)
     latency = None
@@ -212,19 +224,24 @@ def main():
                                 "p99_ms": round(pct(lat, 99), 4), "n": len(lat)}
 
     sweep = None if args.no_sweep else batched_sweep(g, el, K, torch)
+    g2 = el2 = None
+    power_law = None
+    if args.twitter:
+        t0 = time.time()
+        el2 = graphgen.twitter_like(seed=1)
+        g2 = K.Graph.from_edgelist(el2)
+        log(f"power-law graph: n={g2.n} arcs={g2.num_arcs} in {time.time() - t0:.1f}s")
+        if not args.no_autotune:
+            g2.autotune(0)
+        power_law = power_law_bench(g2, el2, K, torch)
     serving = None
     if not args.no_serving:
         graphs = [("rmat21", g, el)]
-        g2 = None
-        if args.twitter:
-            t0 = time.time()
-            el2 = graphgen.twitter_like(seed=1)
-            g2 = K.Graph.from_edgelist(el2)
-            log(f"power-law graph: n={g2.n} arcs={g2.num_arcs} in {time.time() - t0:.1f}s")
+        if g2 is not None:
             graphs.append(("chunglu41.6M", g2, el2))
         serving = serving_bench(K, graphs, args.serve_seconds)
-        if g2 is not None:
-            g2.free()
+    if g2 is not None:
+        g2.free()
 
     # ---- CPU oracle baseline (host cores, same queries)
     cpu = None
@@ -248,11 +265,22 @@ def main():
             o_lat[f"k{k}"] = {"mean_ms": round(float(np.mean(lat)), 3), "p50_ms": round(pct(lat, 50), 3),
                               "p99_ms": round(pct(lat, 99), 3)}
         parity = bool(np.array_equal(np.array(o_counts), plain_counts) and np.array_equal(np.array(o_te), plain_te))
+        # the same queries over a pool of host threads, one query per thread at a time
+        from concurrent.futures import ThreadPoolExecutor
+        threads = min(os.cpu_count() or 1, 16)
+        jobs = [(int(s), k) for k, seeds in groups for s in seeds]
+        t = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            pool_counts = list(ex.map(lambda j: og.khop(j[0], j[1])[0], jobs))
+        pool_s = time.perf_counter() - t
+        parity = parity and bool(np.array_equal(np.array(pool_counts), plain_counts))
         cpu = {"value": round(sum(o_te) / t_all / 1e9, 4), "unit": "GTEPS", "cores": 1, "kind": "oracle",
                "sample": f"the full query set once ({nq} queries: 300 at k=1, 300 at k=2, 10 at k=3, 10 at k=6), "
                          f"one query at a time on one host core; adjacency build excluded",
                "seconds": round(t_all, 2), "qps": round(nq / t_all, 2), "latency": o_lat,
-               "counts_equal_gpu": parity, "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+               "counts_equal_gpu": parity, "host_cpu": _cpu_model(), "host_nproc": os.cpu_count(),
+               "pool": {"threads": threads, "seconds": round(pool_s, 3), "qps": round(nq / pool_s, 1),
+                        "gteps": round(sum(o_te) / pool_s / 1e9, 4)}}
         if not parity:
             log("WARNING: oracle counts differ from the GPU counts")
 
@@ -277,6 +305,8 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "device": device_info(torch),
+        "power_law": power_law,
     }
     print(json.dumps(out), flush=True)
     g.free()
@@ -336,6 +366,84 @@ def traffic_per_launch(kernel):
     if not e or e.get("source_sha256_16") != _source_sha(kernel):
         return None
     return 1024.0 * (e["fetch_kib_per_dispatch"] * d["fetch_scale"] + e["write_kib_per_dispatch"] * d["write_scale"])
+
+
+def measure_copy_gbs(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (bytes read + written per second): the practical streaming ceiling."""
+    a = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1000.0) / 1e9
+    del a, b
+    return gbs
+
+
+def device_info(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "l2_bytes": getattr(p, "L2_cache_size", None), "hbm_bytes": p.total_memory}
+
+
+def power_law_bench(g2, el2, K, torch):
+    """The 41.6M-vertex power-law graph: the plain protocol (300 seeds at k = 1, 2, 10 at k = 3, 6,
+    one query per launch sequence, device-resident) and one 256-seed batch at k = 3."""
+    import graphgen
+    dev = torch.device("cuda:0")
+    out = {"graph": "directed Chung-Lu, 41.6M vertices, 1.47B tuples", "vertices": g2.n, "arcs": g2.num_arcs}
+    s300 = graphgen.draw_seeds(el2, 300, seed=7, stream=0)
+    s10 = graphgen.draw_seeds(el2, 10, seed=7, stream=1)
+    tot_te, tot_ms, tot_q = 0, 0.0, 0
+    for k, seeds in ((1, s300), (2, s300), (3, s10), (6, s10)):
+        d = torch.from_numpy(seeds).to(dev)
+        c = torch.empty(len(seeds), dtype=torch.int64, device=dev)
+        te = torch.empty(len(seeds), dtype=torch.int64, device=dev)
+        g2.count_dev(d, k, c, te)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g2.count_dev(d, k, c, te)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        t = int(te.sum())
+        lat = []
+        for s in seeds[:30]:
+            t0 = time.perf_counter()
+            g2.count(np.array([s], np.int32), k)
+            lat.append((time.perf_counter() - t0) * 1000.0)
+        out[f"plain_k{k}"] = {"queries": len(seeds), "ms": round(ms, 3), "qps": round(len(seeds) / (ms / 1e3), 1),
+                              "gteps": round(t / (ms / 1e3) / 1e9, 3), "host_api_p50_ms": round(pct(lat, 50), 4),
+                              "host_api_p99_ms": round(pct(lat, 99), 4)}
+        tot_te += t
+        tot_ms += ms
+        tot_q += len(seeds)
+    out["plain_protocol"] = {"queries": tot_q, "ms": round(tot_ms, 3), "qps": round(tot_q / (tot_ms / 1e3), 1),
+                             "gteps": round(tot_te / (tot_ms / 1e3) / 1e9, 3)}
+    s256 = graphgen.draw_seeds(el2, 256, seed=13)
+    d = torch.from_numpy(s256).to(dev)
+    ks = torch.full((256,), 3, dtype=torch.int32, device=dev)
+    c = torch.empty(256, dtype=torch.int64, device=dev)
+    g2.count_batched_dev(d, ks, c)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g2.count_batched_dev(d, ks, c)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    dp = torch.empty(256, dtype=torch.int64, device=dev)
+    dte = torch.empty(256, dtype=torch.int64, device=dev)
+    g2.count_dev(d, 3, dp, dte)
+    torch.cuda.synchronize()
+    out["batch256_k3"] = {"seeds": 256, "ms": round(ms, 3), "qps": round(256 / (ms / 1e3), 1),
+                          "gteps": round(int(dte.sum()) / (ms / 1e3) / 1e9, 3),
+                          "equal_to_plain": bool(torch.equal(c, dp))}
+    log("power-law graph: " + json.dumps(out))
+    return out
 
 
 def copy_calibration(nbytes=256 << 20, reps=5):

@@ -73,13 +73,49 @@ __device__ __forceinline__ bool fb_dense(const int64_t *cnt, int64_t n) {
     return wave_sum(cnt[lane_id() & (kCntLanes - 1)]) * kDenseDiv > n;
 }
 
-__global__ void __launch_bounds__(kBlock) batch_zero_kernel(uint64_t *a, uint64_t *b, int64_t words, uint64_t *fb,
-                                                           int64_t fb_words, int64_t *fc, int64_t *acc, int64_t nacc,
-                                                           int32_t *flags, int nflags) {
+// Top-down frontier of a batched hop: every vertex the hop found is appended
+// as its chunks of out-edges (at least one chunk, empty for out-degree 0),
+// with its out-degree added to a 64-lane sum.
+constexpr int kChunk = 256;
+struct ChunkQueue {
+    uint64_t *rec;  // (vertex << 32) | chunk index
+    int64_t *len;   // records appended
+    int64_t *mf;    // out-degree sum of the appended vertices, 64 lanes
+};
+enum { HOP_PUSH = 0, HOP_PULL = 1 };
+
+// Appends the chunks of v for the lanes with app set; one atomic per wave.
+// Every lane of the wave must call it.
+__device__ __forceinline__ void cq_append(const ChunkQueue &q, bool app, int32_t v, int64_t deg) {
+    const int lane = lane_id();
+    const int64_t nch = app ? std::max<int64_t>(1, (deg + kChunk - 1) / kChunk) : 0;
+    const int64_t ex = wave_exclusive_sum(nch);
+    const int64_t tot = shfl64(ex + nch, kWave - 1);
+    if (!tot) return;  // wave-uniform
+    int64_t base = 0;
+    if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)q.len, (unsigned long long)tot);
+    base = shfl64(base, 0);
+    for (int64_t c = 0; c < nch; ++c) q.rec[base + ex + c] = ((uint64_t)(uint32_t)v << 32) | (uint64_t)c;
+    const int64_t dsum = wave_sum(app ? deg : 0);
+    if (lane == 0 && dsum)
+        atomicAdd((unsigned long long *)&q.mf[(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave) & (kCntLanes - 1)],
+                  (unsigned long long)dsum);
+}
+
+__global__ void __launch_bounds__(kBlock) batch_zero_kernel(uint64_t *a, uint64_t *b, uint64_t *c, int64_t words,
+                                                           uint64_t *fb, int64_t fb_words, int64_t *fc, int64_t *acc,
+                                                           int64_t nacc, int32_t *flags, int32_t *mode, int nflags,
+                                                           int64_t *cq_len, int64_t *cq_mf) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < words; i += stride) {
         a[i] = 0;
         b[i] = 0;
+        c[i] = 0;
+    }
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < nflags; i += kBlock) mode[i] = HOP_PUSH;
+        for (int i = threadIdx.x; i < 3 * kCntLanes; i += kBlock) cq_mf[i] = 0;
+        if (threadIdx.x < 3) cq_len[threadIdx.x] = 0;
     }
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < fb_words; i += stride) fb[i] = 0;
     if (blockIdx.x == 0) {
@@ -107,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t 
                                                                  const int32_t *seeds, const int32_t *perm,
                                                                  const int32_t *ks_sorted, int nslots, int W,
                                                                  uint64_t *F, uint64_t *V, uint64_t *fb,
-                                                                 int64_t *fb_cnt, int32_t *flag) {
+                                                                 int64_t *fb_cnt, ChunkQueue q, int32_t *flag) {
     int64_t fresh = 0;
     for (int j = blockIdx.x; j < nslots; j += gridDim.x) {
         if (ks_sorted[j] < 1) continue;
@@ -116,11 +152,20 @@ __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t 
         const unsigned long long bit = 1ull << (j & 63);
         const int w = j >> 6;
         if (e > b && threadIdx.x == 0) atomicOr(flag, 1);
-        for (int64_t x = b + threadIdx.x; x < e; x += kBlock) {
-            const int32_t v = colidx[x];
-            atomicOr((unsigned long long *)&F[(int64_t)v * W + w], bit);
-            atomicOr((unsigned long long *)&V[(int64_t)v * W + w], bit);
-            fresh += fb_set(fb, v);
+        for (int64_t x0 = b; x0 < e; x0 += kBlock) {  // block-uniform: every lane reaches the append
+            const int64_t x = x0 + threadIdx.x;
+            bool app = false;
+            int32_t v = 0;
+            int64_t deg = 0;
+            if (x < e) {
+                v = colidx[x];
+                atomicOr((unsigned long long *)&F[(int64_t)v * W + w], bit);
+                atomicOr((unsigned long long *)&V[(int64_t)v * W + w], bit);
+                app = fb_set(fb, v);
+                if (app) deg = rowptr[v + 1] - rowptr[v];
+            }
+            fresh += app;
+            cq_append(q, app, v, deg);
         }
     }
     fresh = wave_sum(fresh);
@@ -153,9 +198,10 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
                                                            uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
                                                            uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
                                                            const uint64_t *__restrict__ act, int heavy,
-                                                           FrontierBits fb, const int32_t *prev_flag, int32_t *flag,
-                                                           int64_t *units) {
+                                                           FrontierBits fb, const int32_t *mode, int L,
+                                                           const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;  // empty frontier: nothing left to find
+    if (mode && mode[L] == HOP_PUSH) return;  // this hop went top-down
     {
         const int64_t nw = (n + kWave - 1) / kWave;
         for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBlock)
@@ -279,9 +325,10 @@ template <int G>
 __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     const int32_t *__restrict__ in_colidx, uint64_t *V, const uint64_t *__restrict__ F, uint64_t *Fn, int W, int wact,
     const uint64_t *__restrict__ act, const int32_t *__restrict__ hvert, const int64_t *__restrict__ hbegin,
-    const int64_t *__restrict__ hend, int64_t n_items, int64_t n, FrontierBits fb, const int32_t *prev_flag,
-    int32_t *flag, int64_t *units) {
+    const int64_t *__restrict__ hend, int64_t n_items, int64_t n, FrontierBits fb, const int32_t *mode, int L,
+    const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;
+    if (mode && mode[L] == HOP_PUSH) return;  // this hop went top-down
     const uint64_t *__restrict__ Fbc = fb.cur;
     const bool dense = fb_dense(fb.cnt_cur, n);
     constexpr int S = kWave / G;  // gather streams
@@ -363,6 +410,102 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     if (units && lane == 0) {
         unit_add(units, 1, examined);
         unit_add(units, 3, gathered);
+    }
+}
+
+// Hop >= 2, top-down: one wave per chunk of the previous hop's queue, a group
+// of G lanes (one per active word) per out-edge, so a round covers 64/G
+// edges.  A word's candidate bits F[u] & active & NOT V[v] are claimed with
+// atomicOr on V (the old value keeps each bit exactly-once) and ORed into N;
+// a vertex gaining any bit is appended (its bitmap bit makes that once).
+// Every block first takes the direction: once a hop has gone bottom-up every
+// later hop does; otherwise top-down while the frontier's out-edges stay at
+// most nnz / push_div.  Block 0 records it for the hop's other kernels.
+template <int G>
+__global__ void __launch_bounds__(kBlock) batch_push_kernel(
+    const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx, uint64_t *V,
+    const uint64_t *__restrict__ F, uint64_t *N, int64_t n, int64_t nnz, int W, int wact,
+    const uint64_t *__restrict__ act, int push_div, ChunkQueue qin, ChunkQueue qout, FrontierBits fb, int32_t *mode,
+    int L, const int32_t *prev_flag, int32_t *flag, int64_t *units) {
+    if (*prev_flag == 0) return;
+    const int lane = lane_id();
+    const int64_t mf = wave_sum(qin.mf[lane & (kCntLanes - 1)]);
+    const bool pull = mode[L - 1] == HOP_PULL || mf * (int64_t)push_div > nnz;
+    if (blockIdx.x == 0 && threadIdx.x == 0) mode[L] = pull ? HOP_PULL : HOP_PUSH;
+    if (pull) return;
+    {
+        const int64_t nw = (n + kWave - 1) / kWave;
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBlock)
+            fb.clear[i] = 0;
+        if (blockIdx.x == 0 && threadIdx.x < kCntLanes) fb.cnt_clear[threadIdx.x] = 0;
+    }
+    constexpr int EPR = kWave / G;  // out-edges per round, one per group
+    const int grp = lane / G;
+    const int wi = lane % G;
+    const uint64_t grp_bits = ((G == 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G);
+    const uint64_t actw = wi < wact ? act[wi] : 0ull;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t nrec = *qin.len;
+    bool any = false;
+    int64_t fresh = 0, edges = 0;
+    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c < nrec; c += nwaves) {
+        const uint64_t rec = qin.rec[c];
+        const int32_t u = (int32_t)(rec >> 32);
+        const int64_t rb = rowptr[u], re = rowptr[u + 1];
+        const int64_t b = rb + (int64_t)(rec & 0xffffffffull) * kChunk, e = std::min<int64_t>(b + kChunk, re);
+        const uint64_t fu = wi < wact ? (F[(int64_t)u * W + wi] & actw) : 0ull;
+        if (!ballot(fu != 0)) continue;  // wave-uniform: the source holds no active bit
+        edges += e - b;
+        for (int64_t x0 = b; x0 < e; x0 += EPR) {
+            const int64_t x = x0 + grp;
+            const bool ve = x < e;
+            const int32_t v = ve ? colidx[x] : 0;
+            uint64_t newb = 0;
+            if (ve && fu) {
+                const int64_t at = (int64_t)v * W + wi;
+                const uint64_t cand = fu & ~V[at];
+                if (cand) {
+                    const uint64_t old = atomicOr((unsigned long long *)&V[at], (unsigned long long)cand);
+                    newb = cand & ~old;
+                    if (newb) atomicOr((unsigned long long *)&N[at], (unsigned long long)newb);
+                }
+            }
+            const bool gnew = (ballot(newb != 0) & grp_bits) != 0;
+            bool app = false;
+            int64_t deg = 0;
+            if (gnew && wi == 0 && fb_set(fb.next, v)) {
+                app = true;
+                deg = rowptr[v + 1] - rowptr[v];
+            }
+            any |= gnew;
+            fresh += app;
+            cq_append(qout, app, v, deg);
+        }
+    }
+    fresh = wave_sum(fresh);
+    if (lane == 0) fb_count(fb.cnt_next, fresh);
+    if (ballot(any) && lane == 0) atomicOr(flag, 1);
+    // 4 B per out-edge and 8 B per active word of its head's visited row
+    if (units && lane == 0) unit_add(units, 1, edges);
+}
+
+// After a top-down hop: the rows of F its queue read are cleared (F becomes
+// the next top-down hop's N), and the queue the hop after next appends to is
+// reset.
+__global__ void __launch_bounds__(kBlock) batch_push_clear_kernel(uint64_t *F, int W, ChunkQueue qread,
+                                                                 ChunkQueue qreset, const int32_t *mode, int L,
+                                                                 const int32_t *prev_flag) {
+    if (*prev_flag == 0 || mode[L] != HOP_PUSH) return;
+    const int64_t nrec = *qread.len;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nrec; c += (int64_t)gridDim.x * kBlock) {
+        const uint64_t rec = qread.rec[c];
+        if ((rec & 0xffffffffull) != 0) continue;  // each vertex once, at its first chunk
+        const int64_t u = (int64_t)(rec >> 32);
+        for (int w = 0; w < W; ++w) F[u * W + w] = 0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kCntLanes) {
+        qreset.mf[threadIdx.x] = 0;
+        if (threadIdx.x == 0) *qreset.len = 0;
     }
 }
 
@@ -503,6 +646,10 @@ __global__ void fill_zero_i64(int64_t *a, int64_t n) {
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a[i] = 0;
 }
 
+__global__ void __launch_bounds__(kBlock) fill_zero_u64(uint64_t *a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) a[i] = 0;
+}
+
 }  // namespace
 
 struct BatchCtx {
@@ -514,6 +661,10 @@ struct BatchCtx {
     int64_t *acc = nullptr;    // 64 * W counters
     uint64_t *act = nullptr;   // kMaxLevels * W active masks
     int32_t *flags = nullptr;  // kMaxLevels + 1 frontier-nonempty flags
+    int32_t *mode = nullptr;   // kMaxLevels + 1 hop directions (HOP_PUSH / HOP_PULL)
+    uint64_t *cq_rec[3] = {};  // top-down chunk queues by hop % 3
+    int64_t *cq_len = nullptr; // their lengths
+    int64_t *cq_mf = nullptr;  // their out-degree sums, 64 lanes each
     int32_t *perm = nullptr;   // slot -> caller index
     int32_t *ks = nullptr;     // k per slot (sorted)
     void *arena = nullptr;
@@ -550,6 +701,18 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     off += al((size_t)BatchCtx::kMaxLevels * words * 8);
     const size_t oflags = off;
     off += al((BatchCtx::kMaxLevels + 1) * 4);
+    const size_t omode = off;
+    off += al((BatchCtx::kMaxLevels + 1) * 4);
+    const int64_t cq_cap = n + g->nnz / kChunk + kWave;
+    size_t ocq[3];
+    for (int i = 0; i < 3; ++i) {
+        ocq[i] = off;
+        off += al((size_t)cq_cap * 8);
+    }
+    const size_t ocql = off;
+    off += al(3 * 8);
+    const size_t ocqm = off;
+    off += al(3 * kCntLanes * 8);
     const size_t operm = off;
     off += al(64 * (size_t)words * 4);
     const size_t oks = off;
@@ -569,6 +732,10 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     c->acc = (int64_t *)(b + oacc);
     c->act = (uint64_t *)(b + oact);
     c->flags = (int32_t *)(b + oflags);
+    c->mode = (int32_t *)(b + omode);
+    for (int i = 0; i < 3; ++i) c->cq_rec[i] = (uint64_t *)(b + ocq[i]);
+    c->cq_len = (int64_t *)(b + ocql);
+    c->cq_mf = (int64_t *)(b + ocqm);
     c->perm = (int32_t *)(b + operm);
     c->ks = (int32_t *)(b + oks);
     const size_t hbytes = (size_t)BatchCtx::kMaxLevels * words * 8 + 2 * 64 * (size_t)words * 4;
@@ -612,8 +779,8 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
     {
         ProfScope ps(g, KK_BATCH_PULL, st);
         hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx,
-                           V, F, Fn, n, Wr, wact, act, batch_heavy_table(g).threshold, fb, c->flags + (L - 1),
-                           c->flags + L, ps.units());
+                           V, F, Fn, n, Wr, wact, act, batch_heavy_table(g).threshold, fb, c->mode, L,
+                           c->flags + (L - 1), c->flags + L, ps.units());
         // bytes: V read and write-back and Fn write per active word, the frontier bitmap once,
         // 4 per examined in-edge, 16 per scanned vertex, 8 per gathered word
         ps.end(3.0 * 8.0 * (double)n * wact + 2.0 * 8.0 * nw, 0, 4.0, 16.0, 8.0 * wact);
@@ -624,10 +791,36 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         ProfScope ps(g, KK_BATCH_PULL_HEAVY, st);
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, V, F, Fn,
-                           Wr, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->flags + (L - 1),
-                           c->flags + L, ps.units());
+                           Wr, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->mode, L,
+                           c->flags + (L - 1), c->flags + L, ps.units());
         ps.end(16.0 * (double)ht.n, 0, 4.0, 0, 8.0 * wact);
     }
+}
+
+static ChunkQueue chunk_queue(BatchCtx *c, int slot) {
+    return ChunkQueue{c->cq_rec[slot], c->cq_len + slot, c->cq_mf + slot * kCntLanes};
+}
+
+// Hop L's top-down kernel (which also takes the hop's direction) and the
+// clearing after it; both exit at once when the hop goes bottom-up.
+template <int G>
+static void launch_push(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hipStream_t st, uint64_t *V, uint64_t *F,
+                        uint64_t *Fn) {
+    const int64_t n = g->n, nw = (n + 63) / 64;
+    const uint64_t *act = c->act + (int64_t)(L - 1) * c->W;
+    const FrontierBits fb{c->Fb + ((L - 1) % 3) * nw, c->Fb + (L % 3) * nw,       c->Fb + ((L + 1) % 3) * nw,
+                          c->Fc + ((L - 1) % 3) * kCntLanes, c->Fc + (L % 3) * kCntLanes, c->Fc + ((L + 1) % 3) * kCntLanes};
+    {
+        ProfScope ps(g, KK_BATCH_PUSH, st);
+        hipLaunchKernelGGL((batch_push_kernel<G>), dim3(g->cu_count * 8), dim3(kBlock), 0, st, g->d_rowptr,
+                           g->d_colidx, V, F, Fn, n, g->nnz, Wr, wact, act, g->params.batch_push_div,
+                           chunk_queue(c, (L - 1) % 3), chunk_queue(c, L % 3), fb, c->mode, L, c->flags + (L - 1),
+                           c->flags + L, ps.units());
+        // bytes: 4 per out-edge + 8 per active word of its head's visited and next rows
+        ps.end(0, 0, 4.0 + 16.0 * wact);
+    }
+    hipLaunchKernelGGL(batch_push_clear_kernel, dim3(g->cu_count), dim3(kBlock), 0, st, F, Wr,
+                       chunk_queue(c, (L - 1) % 3), chunk_queue(c, (L + 1) % 3), c->mode, L, c->flags + (L - 1));
 }
 
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
@@ -661,10 +854,10 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     const int zgrid = (int)std::min<int64_t>(((int64_t)n * W + kBlock - 1) / kBlock, (int64_t)g->cu_count * 8);
     {
         ProfScope ps(g, KK_BATCH_INIT, st);
-        hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, c->F,
+        hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, c->F, c->N,
                            (int64_t)n * W, c->Fb, 3 * ((n + 63) / 64), c->Fc, c->acc, (int64_t)64 * W, c->flags,
-                           levels + 1);
-        ps.end(2.0 * 8.0 * n * W + 3.0 * 8.0 * ((n + 63) / 64));
+                           c->mode, levels + 1, c->cq_len, c->cq_mf);
+        ps.end(3.0 * 8.0 * n * W + 3.0 * 8.0 * ((n + 63) / 64));
     }
     hipLaunchKernelGGL(batch_seed_kernel, dim3((nslots + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->V, d_seeds,
                        c->perm, nslots, W);
@@ -673,7 +866,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         ProfScope ps(g, KK_BATCH_PUSH, st);
         hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
                            g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, F, c->V, c->Fb + (int64_t)((n + 63) / 64),
-                           c->Fc + kCntLanes, c->flags + 1);
+                           c->Fc + kCntLanes, chunk_queue(c, 1), c->flags + 1);
         ps.end(0);
     }
     // Rows are Wr words long.  Seeds are sorted by k, so the active words of a
@@ -703,6 +896,10 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
                                    Vn, Fnew);
                 ps.end(2.0 * 8.0 * n * wa * 2);
             }
+            // the next frontier's buffer starts clear (a top-down hop only ORs into it)
+            hipLaunchKernelGGL(fill_zero_u64, dim3(std::max((int)std::min<int64_t>(((int64_t)n * wa + kBlock - 1) / kBlock,
+                                                                              (int64_t)g->cu_count * 8), 1)),
+                               dim3(kBlock), 0, st, V, (int64_t)n * wa);
             Nb = V;
             V = Vn;
             F = Fnew;
@@ -711,11 +908,14 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         int G = 1;
         while (G < wa) G <<= 1;
         switch (G) {
-            case 1: launch_pull<1>(g, c, L, wa, Wr, st, V, F, Nb); break;
-            case 2: launch_pull<2>(g, c, L, wa, Wr, st, V, F, Nb); break;
-            case 4: launch_pull<4>(g, c, L, wa, Wr, st, V, F, Nb); break;
-            case 8: launch_pull<8>(g, c, L, wa, Wr, st, V, F, Nb); break;
-            default: launch_pull<16>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            case 1: launch_push<1>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<1>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            case 2: launch_push<2>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<2>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            case 4: launch_push<4>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<4>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            case 8: launch_push<8>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<8>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            default:
+                launch_push<16>(g, c, L, wa, Wr, st, V, F, Nb);
+                launch_pull<16>(g, c, L, wa, Wr, st, V, F, Nb);
+                break;
         }
         std::swap(F, Nb);
         if ((L % 8) == 0 && L < levels) {
@@ -849,13 +1049,14 @@ static void serve_pull(ServeCtx *c, hipStream_t st) {
     const FrontierBits fb{c->Fb + i0 * nw, c->Fb + i1 * nw, c->Fb + i2 * nw,
                           c->Fc + i0 * kCntLanes, c->Fc + i1 * kCntLanes, c->Fc + i2 * kCntLanes};
     hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
-                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, fb, c->d_one, c->d_one + 1, nullptr);
+                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, fb, nullptr, 0, c->d_one, c->d_one + 1,
+                       nullptr);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
-                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->d_one,
-                           c->d_one + 1, nullptr);
+                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, nullptr, 0,
+                           c->d_one, c->d_one + 1, nullptr);
     }
 }
 

@@ -1,5 +1,6 @@
 """GPU parity of the batched multi-source path (per-vertex seed bitsets) against
-the CPU oracle and the plain GPU path, bit exact, with mixed k in one batch."""
+the CPU oracle and the plain GPU path, bit exact, with mixed k in one batch,
+with hops forced top-down, forced bottom-up and left to the direction rule."""
 import numpy as np
 import pytest
 
@@ -10,6 +11,9 @@ from tests import graphs
 pytestmark = pytest.mark.gpu
 
 KS = (1, 2, 3, 6)
+# KHOP_OPT_BATCH_PUSH divisors: 1 keeps every hop top-down, 2**30 sends every
+# hop after the first bottom-up, 64 is the default rule
+PUSH_DIVS = (1, 64, 2**30)
 
 
 def _say(*a):
@@ -40,18 +44,21 @@ def test_g0_uniform_k(K, g0, g0_gpu, g0_oracle, per):
 
 @pytest.mark.parametrize("per", [64, 256, 1024])
 @pytest.mark.parametrize("heavy", [1, 16, 256, 10**9])
-def test_g0_mixed_k_every_vertex(K, g0_gpu, g0_oracle, per, heavy):
+@pytest.mark.parametrize("push_div", PUSH_DIVS)
+def test_g0_mixed_k_every_vertex(K, g0_gpu, g0_oracle, per, heavy, push_div):
     rng = np.random.default_rng(per + heavy)
     seeds = np.nonzero(g0_oracle.degrees() > 0)[0].astype(np.int32)
     ks = rng.choice(np.array([0, 1, 2, 3, 6, 9]), size=len(seeds)).astype(np.int32)
     g0_gpu.set_option(K.KHOP_OPT_BATCH_SEEDS, per)
     g0_gpu.set_option(K.KHOP_OPT_BATCH_HEAVY, heavy)
-    _say("g0 mixed", per, heavy, len(seeds))
+    g0_gpu.set_option(K.KHOP_OPT_BATCH_PUSH, push_div)
+    _say("g0 mixed", per, heavy, push_div, len(seeds))
     got = g0_gpu.count_batched(seeds, ks)
     expect = np.array([g0_oracle.khop(int(s), int(k))[0] for s, k in zip(seeds, ks)])
     assert np.array_equal(got, expect)
     g0_gpu.set_option(K.KHOP_OPT_BATCH_SEEDS, 1024)
     g0_gpu.set_option(K.KHOP_OPT_BATCH_HEAVY, 256)
+    g0_gpu.set_option(K.KHOP_OPT_BATCH_PUSH, 64)
 
 
 def test_duplicates_and_ragged_batches(K, g0, g0_gpu, g0_oracle):
@@ -79,7 +86,8 @@ def test_device_entry_point(K, g0, g0_gpu, g0_oracle):
 
 
 @pytest.mark.parametrize("directed", [False, True])
-def test_random_graphs(K, directed):
+@pytest.mark.parametrize("push_div", PUSH_DIVS)
+def test_random_graphs(K, directed, push_div):
     rng = np.random.default_rng(7 + directed)
     for trial in range(8):
         n = int(rng.integers(2, 900))
@@ -87,6 +95,7 @@ def test_random_graphs(K, directed):
         g = K.Graph(src, dst, n, d)
         og = oracle.OracleGraph(src, dst, n, d)
         g.set_option(K.KHOP_OPT_BATCH_HEAVY, int(rng.integers(1, 40)))
+        g.set_option(K.KHOP_OPT_BATCH_PUSH, push_div)
         seeds = rng.integers(0, n, size=int(rng.integers(1, 300))).astype(np.int32)
         ks = rng.integers(0, 8, size=len(seeds)).astype(np.int32)
         _say("random", directed, trial, n, len(seeds))
@@ -96,16 +105,32 @@ def test_random_graphs(K, directed):
         g.free()
 
 
-def test_batched_equals_plain_power_law(K):
+@pytest.mark.parametrize("push_div", PUSH_DIVS)
+def test_batched_equals_plain_power_law(K, push_div):
     el = graphgen.chung_lu(80_000, 1_200_000, 5.0, seed=8)
     g = K.Graph.from_edgelist(el)
+    g.set_option(K.KHOP_OPT_BATCH_PUSH, push_div)
     og = oracle.OracleGraph.from_edgelist(el)
     seeds = graphgen.draw_seeds(el, 300, seed=3)
     for k in KS:
-        _say("chung-lu 80k", k)
+        _say("chung-lu 80k", push_div, k)
         b = g.count_batched(seeds, np.full(len(seeds), k))
         p = g.count(seeds, k)
         assert np.array_equal(b, p)
         sample = seeds[:12]
         assert np.array_equal(b[:12], og.count(sample, k)[0])
+    g.free()
+
+
+def test_narrowing_under_forced_top_down(K, g0, g0_oracle):
+    """Rows are repacked as seeds finish while hops stay top-down: 1000 seeds
+    with k falling from 9 to 1 across the batch."""
+    el, _ = g0
+    g = K.Graph.from_edgelist(el)
+    g.set_option(K.KHOP_OPT_BATCH_PUSH, 1)
+    seeds = graphgen.draw_seeds(el, 800, seed=4)
+    ks = np.repeat(np.arange(9, 0, -1), -(-len(seeds) // 9))[:len(seeds)].astype(np.int32)
+    got = g.count_batched(seeds, ks)
+    expect = np.array([g0_oracle.khop(int(s), int(k))[0] for s, k in zip(seeds, ks)])
+    assert np.array_equal(got, expect)
     g.free()
