@@ -178,8 +178,9 @@ typedef struct {
  * boundaries, while the batch keeps advancing; each graph has its own HIP
  * stream so work for different graphs overlaps on the device.
  * mem_budget_bytes bounds the bitset memory of all running batches (each
- * 64 slots of a graph with n vertices take 3 * 8 * n bytes, and each batch
- * 3 * 8 * ceil(n / 64) bytes of frontier bitmaps); requests wait
+ * 64 slots of a graph with n vertices and nnz arcs take 3 * 8 * n bytes, and
+ * each batch 3 * 8 * ceil(n / 64) bytes of frontier bitmaps plus
+ * 3 * 8 * (n + nnz / 256 + 64) bytes of frontier queues); requests wait
  * while no slot fits.  max_batch_seeds (64..1024, a multiple of 64) bounds
  * the slots of one graph's batch.
  */

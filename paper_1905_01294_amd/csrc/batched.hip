@@ -418,20 +418,30 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
 // edges.  A word's candidate bits F[u] & active & NOT V[v] are claimed with
 // atomicOr on V (the old value keeps each bit exactly-once) and ORed into N;
 // a vertex gaining any bit is appended (its bitmap bit makes that once).
-// Every block first takes the direction: once a hop has gone bottom-up every
-// later hop does; otherwise top-down while the frontier's out-edges stay at
-// most nnz / push_div.  Block 0 records it for the hop's other kernels.
+// Every block first takes the direction: top-down while the frontier's
+// out-edges stay at most nnz / push_div, and with `sticky` never again once a
+// hop has gone bottom-up.  Block 0 records it for the hop's other kernels and
+// resets the queue the next hop appends to (qreset; read and written by no
+// other kernel of this hop).
+//
+// N is not cleared between hops: a bit it still holds from an earlier hop
+// sits on a vertex its seed had already reached, whose neighbors the seed has
+// reached by now too, so the bit can never claim anything.
 template <int G>
 __global__ void __launch_bounds__(kBlock) batch_push_kernel(
     const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx, uint64_t *V,
     const uint64_t *__restrict__ F, uint64_t *N, int64_t n, int64_t nnz, int W, int wact,
-    const uint64_t *__restrict__ act, int push_div, ChunkQueue qin, ChunkQueue qout, FrontierBits fb, int32_t *mode,
-    int L, const int32_t *prev_flag, int32_t *flag, int64_t *units) {
+    const uint64_t *__restrict__ act, int push_div, ChunkQueue qin, ChunkQueue qout, ChunkQueue qreset,
+    FrontierBits fb, int32_t *mode, int L, int sticky, const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;
     const int lane = lane_id();
     const int64_t mf = wave_sum(qin.mf[lane & (kCntLanes - 1)]);
-    const bool pull = mode[L - 1] == HOP_PULL || mf * (int64_t)push_div > nnz;
-    if (blockIdx.x == 0 && threadIdx.x == 0) mode[L] = pull ? HOP_PULL : HOP_PUSH;
+    const bool pull = (sticky && mode[L - 1] == HOP_PULL) || mf * (int64_t)push_div > nnz;
+    if (blockIdx.x == 0 && threadIdx.x < kCntLanes) {
+        if (threadIdx.x == 0) mode[L] = pull ? HOP_PULL : HOP_PUSH;
+        qreset.mf[threadIdx.x] = 0;
+        if (threadIdx.x == 0) *qreset.len = 0;
+    }
     if (pull) return;
     {
         const int64_t nw = (n + kWave - 1) / kWave;
@@ -489,23 +499,23 @@ __global__ void __launch_bounds__(kBlock) batch_push_kernel(
     if (units && lane == 0) unit_add(units, 1, edges);
 }
 
-// After a top-down hop: the rows of F its queue read are cleared (F becomes
-// the next top-down hop's N), and the queue the hop after next appends to is
-// reset.
-__global__ void __launch_bounds__(kBlock) batch_push_clear_kernel(uint64_t *F, int W, ChunkQueue qread,
-                                                                 ChunkQueue qreset, const int32_t *mode, int L,
-                                                                 const int32_t *prev_flag) {
-    if (*prev_flag == 0 || mode[L] != HOP_PUSH) return;
-    const int64_t nrec = *qread.len;
-    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nrec; c += (int64_t)gridDim.x * kBlock) {
-        const uint64_t rec = qread.rec[c];
-        if ((rec & 0xffffffffull) != 0) continue;  // each vertex once, at its first chunk
-        const int64_t u = (int64_t)(rec >> 32);
-        for (int w = 0; w < W; ++w) F[u * W + w] = 0;
-    }
-    if (blockIdx.x == 0 && threadIdx.x < kCntLanes) {
-        qreset.mf[threadIdx.x] = 0;
-        if (threadIdx.x == 0) *qreset.len = 0;
+// After a bottom-up hop: the queue of the frontier it found (every vertex
+// whose bitmap bit is set), so that the next hop may go top-down.  One wave
+// per bitmap word, one lane per vertex.
+__global__ void __launch_bounds__(kBlock) queue_from_bitmap_kernel(const int64_t *__restrict__ rowptr,
+                                                                  const uint64_t *__restrict__ fb, int64_t n,
+                                                                  ChunkQueue q, const int32_t *mode, int L) {
+    if (mode[L] != HOP_PULL) return;
+    const int lane = lane_id();
+    const int64_t nw = (n + kWave - 1) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    for (int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < nw; w += nwaves) {
+        const uint64_t bits = fb[w];
+        if (!bits) continue;  // wave-uniform
+        const int64_t v = w * kWave + lane;
+        const bool app = (bits >> lane) & 1ull;
+        const int64_t deg = app ? rowptr[v + 1] - rowptr[v] : 0;
+        cq_append(q, app, (int32_t)v, deg);
     }
 }
 
@@ -618,24 +628,34 @@ __global__ void serve_admit_kernel(uint64_t *V, uint64_t *F, int W, const int32_
 }
 
 // Serving: first hop of newly admitted slots, pushed from their seeds into the
-// next frontier Fn, V and the next frontier bitmap (after the bottom-up pass
-// has written Fn).
+// next frontier Fn, V and the next frontier bitmap, after the running slots'
+// hop; vertices new to the next frontier join its queue.
 __global__ void __launch_bounds__(kBlock) serve_push_kernel(const int64_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ colidx, int W,
                                                            const int32_t *slots, const int32_t *seeds, int count,
-                                                           uint64_t *Fn, uint64_t *V, uint64_t *Fbn, int64_t *fb_cnt) {
+                                                           uint64_t *Fn, uint64_t *V, uint64_t *Fbn, int64_t *fb_cnt,
+                                                           ChunkQueue q) {
     int64_t fresh = 0;
     for (int i = blockIdx.x; i < count; i += gridDim.x) {
         const int j = slots[i];
         const int32_t s = seeds[i];
         const int64_t b = rowptr[s], e = rowptr[s + 1];
         const unsigned long long bit = 1ull << (j & 63);
-        for (int64_t x = b + threadIdx.x; x < e; x += kBlock) {
-            const int32_t v = colidx[x];
-            const int64_t at = (int64_t)v * W + (j >> 6);
-            atomicOr((unsigned long long *)&Fn[at], bit);
-            atomicOr((unsigned long long *)&V[at], bit);
-            fresh += fb_set(Fbn, v);
+        for (int64_t x0 = b; x0 < e; x0 += kBlock) {  // block-uniform: every lane reaches the append
+            const int64_t x = x0 + threadIdx.x;
+            bool app = false;
+            int32_t v = 0;
+            int64_t deg = 0;
+            if (x < e) {
+                v = colidx[x];
+                const int64_t at = (int64_t)v * W + (j >> 6);
+                atomicOr((unsigned long long *)&Fn[at], bit);
+                atomicOr((unsigned long long *)&V[at], bit);
+                app = fb_set(Fbn, v);
+                if (app) deg = rowptr[v + 1] - rowptr[v];
+            }
+            fresh += app;
+            cq_append(q, app, v, deg);
         }
     }
     fresh = wave_sum(fresh);
@@ -801,8 +821,8 @@ static ChunkQueue chunk_queue(BatchCtx *c, int slot) {
     return ChunkQueue{c->cq_rec[slot], c->cq_len + slot, c->cq_mf + slot * kCntLanes};
 }
 
-// Hop L's top-down kernel (which also takes the hop's direction) and the
-// clearing after it; both exit at once when the hop goes bottom-up.
+// Hop L's top-down kernel, which also takes the hop's direction (it exits at
+// once when the hop goes bottom-up).
 template <int G>
 static void launch_push(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hipStream_t st, uint64_t *V, uint64_t *F,
                         uint64_t *Fn) {
@@ -814,13 +834,11 @@ static void launch_push(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
         ProfScope ps(g, KK_BATCH_PUSH, st);
         hipLaunchKernelGGL((batch_push_kernel<G>), dim3(g->cu_count * 8), dim3(kBlock), 0, st, g->d_rowptr,
                            g->d_colidx, V, F, Fn, n, g->nnz, Wr, wact, act, g->params.batch_push_div,
-                           chunk_queue(c, (L - 1) % 3), chunk_queue(c, L % 3), fb, c->mode, L, c->flags + (L - 1),
-                           c->flags + L, ps.units());
+                           chunk_queue(c, (L - 1) % 3), chunk_queue(c, L % 3), chunk_queue(c, (L + 1) % 3), fb,
+                           c->mode, L, 1, c->flags + (L - 1), c->flags + L, ps.units());
         // bytes: 4 per out-edge + 8 per active word of its head's visited and next rows
         ps.end(0, 0, 4.0 + 16.0 * wact);
     }
-    hipLaunchKernelGGL(batch_push_clear_kernel, dim3(g->cu_count), dim3(kBlock), 0, st, F, Wr,
-                       chunk_queue(c, (L - 1) % 3), chunk_queue(c, (L + 1) % 3), c->mode, L, c->flags + (L - 1));
 }
 
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
@@ -941,6 +959,10 @@ struct ServeCtx {
     uint64_t *Fb = nullptr;  // three frontier bitmaps of nw words; slot fbi holds F's
     int64_t *Fc = nullptr;   // their set-bit counts, 64 lanes each
     int fbi = 0;
+    uint64_t *cq_rec[3] = {};  // frontier chunk queues, by the same rotation as Fb
+    int64_t *cq_len = nullptr;
+    int64_t *cq_mf = nullptr;
+    int32_t *d_mode = nullptr;  // [1]: this iteration's direction
     int64_t *acc = nullptr;     // 64 * W counters
     uint64_t *d_act = nullptr;  // W active masks of the bottom-up pass
     uint64_t *d_fin = nullptr;  // W finished masks
@@ -954,8 +976,11 @@ struct ServeCtx {
     void *h_arena = nullptr;
 };
 
-size_t serve_ctx_bytes(int64_t n, int words) {
-    return (size_t)3 * 8 * (size_t)n * words + (size_t)3 * 8 * (size_t)((n + 63) / 64);
+static int64_t queue_cap(int64_t n, int64_t nnz) { return n + nnz / kChunk + kWave; }
+
+size_t serve_ctx_bytes(int64_t n, int64_t nnz, int words) {
+    return (size_t)3 * 8 * (size_t)n * words + (size_t)3 * 8 * (size_t)((n + 63) / 64) +
+           (size_t)3 * 8 * (size_t)queue_cap(n, nnz);
 }
 
 ServeCtx *serve_ctx_create(khop_graph *g, int words) {
@@ -977,6 +1002,18 @@ ServeCtx *serve_ctx_create(khop_graph *g, int words) {
     off += al((size_t)3 * ((n + 63) / 64) * 8);
     const size_t oFc = off;
     off += al(3 * kCntLanes * 8);
+    const int64_t cq_cap = queue_cap(n, g->nnz);
+    size_t ocq[3];
+    for (int i = 0; i < 3; ++i) {
+        ocq[i] = off;
+        off += al((size_t)cq_cap * 8);
+    }
+    const size_t ocql = off;
+    off += al(3 * 8);
+    const size_t ocqm = off;
+    off += al(3 * kCntLanes * 8);
+    const size_t omode = off;
+    off += al(2 * 4);
     const size_t oacc = off;
     off += al(slots * 8);
     const size_t oact = off;
@@ -1000,6 +1037,10 @@ ServeCtx *serve_ctx_create(khop_graph *g, int words) {
     c->N = (uint64_t *)(b + oN);
     c->Fb = (uint64_t *)(b + oFb);
     c->Fc = (int64_t *)(b + oFc);
+    for (int i = 0; i < 3; ++i) c->cq_rec[i] = (uint64_t *)(b + ocq[i]);
+    c->cq_len = (int64_t *)(b + ocql);
+    c->cq_mf = (int64_t *)(b + ocqm);
+    c->d_mode = (int32_t *)(b + omode);
     c->acc = (int64_t *)(b + oacc);
     c->d_act = (uint64_t *)(b + oact);
     c->d_fin = (uint64_t *)(b + ofin);
@@ -1036,8 +1077,15 @@ void serve_ctx_destroy(ServeCtx *c) {
 int serve_ctx_words(const ServeCtx *c) { return c->W; }
 int64_t *serve_ctx_counts(ServeCtx *c) { return c->h_counts; }
 
+static ChunkQueue serve_queue(ServeCtx *c, int slot) {
+    return ChunkQueue{c->cq_rec[slot], c->cq_len + slot, c->cq_mf + slot * kCntLanes};
+}
+
+// The running slots' hop: top-down from the frontier's queue when its
+// out-edges are few, else bottom-up (the first kernel decides; the others
+// follow its record), then the queue of what a bottom-up hop found.
 template <int G>
-static void serve_pull(ServeCtx *c, hipStream_t st) {
+static void serve_hop(ServeCtx *c, hipStream_t st) {
     khop_graph *g = c->g;
     const int64_t n = g->n;
     const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
@@ -1048,16 +1096,24 @@ static void serve_pull(ServeCtx *c, hipStream_t st) {
     const int i0 = c->fbi, i1 = (c->fbi + 1) % 3, i2 = (c->fbi + 2) % 3;
     const FrontierBits fb{c->Fb + i0 * nw, c->Fb + i1 * nw, c->Fb + i2 * nw,
                           c->Fc + i0 * kCntLanes, c->Fc + i1 * kCntLanes, c->Fc + i2 * kCntLanes};
+    hipLaunchKernelGGL((batch_push_kernel<G>), dim3(g->cu_count * 8), dim3(kBlock), 0, st, g->d_rowptr, g->d_colidx,
+                       c->V, c->F, c->N, n, g->nnz, c->W, c->W, c->d_act, g->params.batch_push_div,
+                       serve_queue(c, i0), serve_queue(c, i1), serve_queue(c, i2), fb, c->d_mode, 1, 0, c->d_one,
+                       c->d_one + 1, nullptr);
     hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
-                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, fb, nullptr, 0, c->d_one, c->d_one + 1,
+                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, fb, c->d_mode, 1, c->d_one, c->d_one + 1,
                        nullptr);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
-                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, nullptr, 0,
+                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->d_mode, 1,
                            c->d_one, c->d_one + 1, nullptr);
     }
+    const int qgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kWavesPerBlock - 1) / kWavesPerBlock,
+                                                                  (int64_t)g->cu_count * 8));
+    hipLaunchKernelGGL(queue_from_bitmap_kernel, dim3(qgrid), dim3(kBlock), 0, st, g->d_rowptr, fb.next, n,
+                       serve_queue(c, i1), c->d_mode, 1);
 }
 
 void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
@@ -1086,21 +1142,22 @@ void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, 
                            c->d_seeds, n_new);
     }
     if (any_old || n_new > 0) {
-        // bottom-up pass for the running slots (it rewrites every word of N) ...
+        // the running slots' hop ...
         std::copy(act_old, act_old + W, c->h_act);
         KHOP_HIP(hipMemcpyAsync(c->d_act, c->h_act, W * 8, hipMemcpyHostToDevice, st));
         switch (W) {
-            case 1: serve_pull<1>(c, st); break;
-            case 2: serve_pull<2>(c, st); break;
-            case 4: serve_pull<4>(c, st); break;
-            case 8: serve_pull<8>(c, st); break;
-            default: serve_pull<16>(c, st); break;
+            case 1: serve_hop<1>(c, st); break;
+            case 2: serve_hop<2>(c, st); break;
+            case 4: serve_hop<4>(c, st); break;
+            case 8: serve_hop<8>(c, st); break;
+            default: serve_hop<16>(c, st); break;
         }
         // ... then the first hop of the new slots, pushed from their seeds
         if (n_new > 0)
             hipLaunchKernelGGL(serve_push_kernel, dim3(std::min(n_new, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
                                g->d_colidx, W, c->d_slots, c->d_seeds, n_new, c->N, c->V,
-                               c->Fb + ((c->fbi + 1) % 3) * ((n + 63) / 64), c->Fc + ((c->fbi + 1) % 3) * kCntLanes);
+                               c->Fb + ((c->fbi + 1) % 3) * ((n + 63) / 64), c->Fc + ((c->fbi + 1) % 3) * kCntLanes,
+                               serve_queue(c, (c->fbi + 1) % 3));
         std::swap(c->F, c->N);
         c->fbi = (c->fbi + 1) % 3;
     }

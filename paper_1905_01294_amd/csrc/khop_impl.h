@@ -184,7 +184,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
 
 // Serving batches (batched.hip): one per resident graph, W words of seed slots.
 struct ServeCtx;
-size_t serve_ctx_bytes(int64_t n, int words);
+size_t serve_ctx_bytes(int64_t n, int64_t nnz, int words);
 ServeCtx *serve_ctx_create(khop_graph *g, int words);
 void serve_ctx_destroy(ServeCtx *c);
 int serve_ctx_words(const ServeCtx *c);

@@ -109,11 +109,11 @@ void complete_iteration(khop_server *s, GraphServe &gs) {
 bool ensure_ctx(khop_server *s, GraphServe &gs) {
     if (gs.ctx) return true;
     const int64_t avail = s->budget - s->used;
-    if ((int64_t)khop::serve_ctx_bytes(gs.g->n, 1) > avail) return false;
+    if ((int64_t)khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, 1) > avail) return false;
     int words = 1;
-    while (words * 2 <= s->max_words && (int64_t)khop::serve_ctx_bytes(gs.g->n, words * 2) <= avail) words *= 2;
+    while (words * 2 <= s->max_words && (int64_t)khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, words * 2) <= avail) words *= 2;
     gs.ctx = khop::serve_ctx_create(gs.g, words);
-    gs.ctx_bytes = khop::serve_ctx_bytes(gs.g->n, words);
+    gs.ctx_bytes = khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, words);
     s->used += (int64_t)gs.ctx_bytes;
     gs.slots.assign((size_t)64 * words, Slot{});
     return true;

@@ -123,8 +123,10 @@ def test_open_loop_arrivals_while_running(K, graphs):
 
 def test_small_budget_one_word(K, graphs):
     (el0, _), g, o = graphs
-    # exactly one 64-slot word for the scale-10 graph: V, F, N words and three frontier bitmaps
-    budget = 3 * 8 * el0.n + 3 * 8 * ((el0.n + 63) // 64)
+    # exactly one 64-slot word for the scale-10 graph: V, F, N words, three
+    # frontier bitmaps and three frontier chunk queues (256 out-edges a chunk)
+    n, nnz = el0.n, g[0].num_arcs
+    budget = 3 * 8 * n + 3 * 8 * ((n + 63) // 64) + 3 * 8 * (n + nnz // 256 + 64)
     srv = K.Server(budget, 1024)
     gid = srv.add_graph(g[0])
     seeds = np.nonzero(o[0].degrees() > 0)[0][:300]
