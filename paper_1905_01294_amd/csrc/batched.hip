@@ -49,8 +49,8 @@ struct FrontierBits {
     int64_t *cnt_clear;
 };
 constexpr int kCntLanes = 64;
-// A frontier holding more than n / kDenseDiv vertices is dense: its hop skips
-// the bitmap test, since most in-edges would hit anyway.
+// A frontier holding more than n / kDenseDiv vertices is dense: a hop over
+// one-word rows then skips the bitmap test, since most in-edges would hit.
 constexpr int kDenseDiv = 16;
 
 // Sets bit v of a frontier bitmap; returns whether this call set it.  The
@@ -209,7 +209,9 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
         if (blockIdx.x == 0 && threadIdx.x < kCntLanes) fb.cnt_clear[threadIdx.x] = 0;
     }
     const uint64_t *__restrict__ Fbc = fb.cur;
-    const bool dense = fb_dense(fb.cnt_cur, n);
+    // skipping the bitmap test pays only with one-word rows: a wider row costs
+    // far more to gather than the test
+    const bool dense = wact == 1 && fb_dense(fb.cnt_cur, n);
     constexpr int VPW = kWave / G;                          // vertices per wave
     constexpr int R = G == 1 ? 4 : (G >= 16 ? 1 : 16 / G);  // rounds of G in-edges per step
     const int lane = lane_id();
@@ -330,7 +332,9 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     if (*prev_flag == 0) return;
     if (mode && mode[L] == HOP_PUSH) return;  // this hop went top-down
     const uint64_t *__restrict__ Fbc = fb.cur;
-    const bool dense = fb_dense(fb.cnt_cur, n);
+    // skipping the bitmap test pays only with one-word rows: a wider row costs
+    // far more to gather than the test
+    const bool dense = wact == 1 && fb_dense(fb.cnt_cur, n);
     constexpr int S = kWave / G;  // gather streams
     __shared__ int32_t s_hit[kWavesPerBlock][4 * kWave];
     const int lane = lane_id();
@@ -501,12 +505,20 @@ __global__ void __launch_bounds__(kBlock) batch_push_kernel(
 
 // After a bottom-up hop: the queue of the frontier it found (every vertex
 // whose bitmap bit is set), so that the next hop may go top-down.  One wave
-// per bitmap word, one lane per vertex.
+// per bitmap word, one lane per vertex.  A frontier of more than n / 64
+// vertices is not queued: its out-edge sum is set past nnz instead, which
+// sends the next hop bottom-up.
 __global__ void __launch_bounds__(kBlock) queue_from_bitmap_kernel(const int64_t *__restrict__ rowptr,
-                                                                  const uint64_t *__restrict__ fb, int64_t n,
-                                                                  ChunkQueue q, const int32_t *mode, int L) {
+                                                                  const uint64_t *__restrict__ fb,
+                                                                  const int64_t *__restrict__ fb_cnt, int64_t n,
+                                                                  int64_t nnz, ChunkQueue q, const int32_t *mode,
+                                                                  int L) {
     if (mode[L] != HOP_PULL) return;
     const int lane = lane_id();
+    if (wave_sum(fb_cnt[lane & (kCntLanes - 1)]) * 64 > n) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) q.mf[0] = nnz + 1;
+        return;
+    }
     const int64_t nw = (n + kWave - 1) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     for (int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < nw; w += nwaves) {
@@ -1112,8 +1124,8 @@ static void serve_hop(ServeCtx *c, hipStream_t st) {
     }
     const int qgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kWavesPerBlock - 1) / kWavesPerBlock,
                                                                   (int64_t)g->cu_count * 8));
-    hipLaunchKernelGGL(queue_from_bitmap_kernel, dim3(qgrid), dim3(kBlock), 0, st, g->d_rowptr, fb.next, n,
-                       serve_queue(c, i1), c->d_mode, 1);
+    hipLaunchKernelGGL(queue_from_bitmap_kernel, dim3(qgrid), dim3(kBlock), 0, st, g->d_rowptr, fb.next, fb.cnt_next,
+                       n, g->nnz, serve_queue(c, i1), c->d_mode, 1);
 }
 
 void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
