@@ -175,14 +175,16 @@ typedef struct {
  * serving model of the paper's Section II, where a pool of workers answers
  * concurrent queries).  Graphs stay resident; requests of mixed seed and k are
  * admitted into free bit slots of running batched traversals at hop
- * boundaries, while the batch keeps advancing; each graph has its own HIP
- * stream so work for different graphs overlaps on the device.
+ * boundaries, while the batch keeps advancing.  Each graph runs two such
+ * batches, one for queries with k <= 2 and one for deeper ones, each on its
+ * own HIP stream, so short queries do not wait behind deep ones and work for
+ * different graphs overlaps on the device.
  * mem_budget_bytes bounds the bitset memory of all running batches (each
  * 64 slots of a graph with n vertices and nnz arcs take 3 * 8 * n bytes, and
  * each batch 3 * 8 * ceil(n / 64) bytes of frontier bitmaps plus
  * 3 * 8 * (n + nnz / 256 + 64) bytes of frontier queues); requests wait
  * while no slot fits.  max_batch_seeds (64..1024, a multiple of 64) bounds
- * the slots of one graph's batch.
+ * the slots of one batch.
  */
 int khop_server_create(int64_t mem_budget_bytes, int32_t max_batch_seeds, khop_server **out);
 /* Register a loaded graph (borrowed; it must outlive the server). */

@@ -1093,11 +1093,12 @@ static ChunkQueue serve_queue(ServeCtx *c, int slot) {
     return ChunkQueue{c->cq_rec[slot], c->cq_len + slot, c->cq_mf + slot * kCntLanes};
 }
 
-// The running slots' hop: top-down from the frontier's queue when its
-// out-edges are few, else bottom-up (the first kernel decides; the others
-// follow its record), then the queue of what a bottom-up hop found.
+// The running slots' hop over the first wact words of each row (the words
+// holding live slots): top-down from the frontier's queue when its out-edges
+// are few, else bottom-up (the first kernel decides; the others follow its
+// record), then the queue of what a bottom-up hop found.
 template <int G>
-static void serve_hop(ServeCtx *c, hipStream_t st) {
+static void serve_hop(ServeCtx *c, int wact, hipStream_t st) {
     khop_graph *g = c->g;
     const int64_t n = g->n;
     const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
@@ -1109,17 +1110,17 @@ static void serve_hop(ServeCtx *c, hipStream_t st) {
     const FrontierBits fb{c->Fb + i0 * nw, c->Fb + i1 * nw, c->Fb + i2 * nw,
                           c->Fc + i0 * kCntLanes, c->Fc + i1 * kCntLanes, c->Fc + i2 * kCntLanes};
     hipLaunchKernelGGL((batch_push_kernel<G>), dim3(g->cu_count * 8), dim3(kBlock), 0, st, g->d_rowptr, g->d_colidx,
-                       c->V, c->F, c->N, n, g->nnz, c->W, c->W, c->d_act, g->params.batch_push_div,
+                       c->V, c->F, c->N, n, g->nnz, c->W, wact, c->d_act, g->params.batch_push_div,
                        serve_queue(c, i0), serve_queue(c, i1), serve_queue(c, i2), fb, c->d_mode, 1, 0, c->d_one,
                        c->d_one + 1, nullptr);
     hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
-                       c->F, c->N, n, c->W, c->W, c->d_act, ht.threshold, fb, c->d_mode, 1, c->d_one, c->d_one + 1,
+                       c->F, c->N, n, c->W, wact, c->d_act, ht.threshold, fb, c->d_mode, 1, c->d_one, c->d_one + 1,
                        nullptr);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
-                           c->N, c->W, c->W, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->d_mode, 1,
+                           c->N, c->W, wact, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->d_mode, 1,
                            c->d_one, c->d_one + 1, nullptr);
     }
     const int qgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kWavesPerBlock - 1) / kWavesPerBlock,
@@ -1129,7 +1130,7 @@ static void serve_hop(ServeCtx *c, hipStream_t st) {
 }
 
 void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
-                     const int32_t *seeds, int n_new, hipStream_t st) {
+                     const int32_t *seeds, int n_new, int wact, hipStream_t st) {
     khop_graph *g = c->g;
     const int W = c->W;
     const int64_t n = g->n;
@@ -1157,12 +1158,15 @@ void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, 
         // the running slots' hop ...
         std::copy(act_old, act_old + W, c->h_act);
         KHOP_HIP(hipMemcpyAsync(c->d_act, c->h_act, W * 8, hipMemcpyHostToDevice, st));
-        switch (W) {
-            case 1: serve_hop<1>(c, st); break;
-            case 2: serve_hop<2>(c, st); break;
-            case 4: serve_hop<4>(c, st); break;
-            case 8: serve_hop<8>(c, st); break;
-            default: serve_hop<16>(c, st); break;
+        wact = std::max(1, std::min(wact, W));
+        int G = 1;
+        while (G < wact) G <<= 1;
+        switch (G) {
+            case 1: serve_hop<1>(c, wact, st); break;
+            case 2: serve_hop<2>(c, wact, st); break;
+            case 4: serve_hop<4>(c, wact, st); break;
+            case 8: serve_hop<8>(c, wact, st); break;
+            default: serve_hop<16>(c, wact, st); break;
         }
         // ... then the first hop of the new slots, pushed from their seeds
         if (n_new > 0)

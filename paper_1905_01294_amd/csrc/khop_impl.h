@@ -193,7 +193,7 @@ int64_t *serve_ctx_counts(ServeCtx *c);  // pinned; counts of the last harvest, 
 // bits fin[W]; admit n_new seeds into slots; one hop for the running slots
 // act_old[W] (bottom-up) and the new slots (top-down from their seeds).
 void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
-                     const int32_t *seeds, int n_new, hipStream_t st);
+                     const int32_t *seeds, int n_new, int wact, hipStream_t st);
 
 // heavy.cpp: (re)built when the threshold option changes; valid until the next change.
 const HeavyTable &plain_heavy_table(khop_graph *g);

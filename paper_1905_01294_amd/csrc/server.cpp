@@ -14,7 +14,9 @@
 //   - allocates a graph's batch only while it has work, sized by what the
 //     memory budget still allows (3 bitsets of n words per 64 slots), so
 //     queries wait rather than fail when memory is short.
-// Graphs have their own HIP streams, so their iterations overlap on the device.
+// Each graph has two such batches ("lanes"), one for queries with k <= 2 and
+// one for deeper ones, each on its own HIP stream: a short query never waits
+// behind the hops of long ones, and lanes and graphs overlap on the device.
 #include <time.h>
 
 #include <algorithm>
@@ -48,6 +50,7 @@ struct Slot {
 struct GraphServe {
     khop_graph *g = nullptr;
     int id = 0;
+    int lane = 0;  // 0: queries with k <= kShortK
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
     khop::ServeCtx *ctx = nullptr;
@@ -59,6 +62,10 @@ struct GraphServe {
 };
 
 constexpr size_t kMaxQueued = 1 << 22;
+constexpr int kLanes = 2;        // per graph
+constexpr int32_t kShortK = 2;   // queries with k up to this go to lane 0
+
+int lane_of(int32_t graph_id, int32_t k) { return graph_id * kLanes + (k > kShortK ? 1 : 0); }
 
 }  // namespace
 
@@ -68,7 +75,8 @@ struct khop_server {
     int max_words = 16;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::vector<GraphServe *> graphs;
+    std::vector<GraphServe *> graphs;  // kLanes lanes per graph, graph i's at [i * kLanes, (i + 1) * kLanes)
+    int ngraphs = 0;
     std::deque<Request> incoming;
     std::deque<khop_result> done;
     uint64_t next_ticket = 1;
@@ -111,7 +119,8 @@ bool ensure_ctx(khop_server *s, GraphServe &gs) {
     const int64_t avail = s->budget - s->used;
     if ((int64_t)khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, 1) > avail) return false;
     int words = 1;
-    while (words * 2 <= s->max_words && (int64_t)khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, words * 2) <= avail) words *= 2;
+    while (words * 2 <= s->max_words && (int64_t)khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, words * 2) <= avail)
+        words *= 2;
     gs.ctx = khop::serve_ctx_create(gs.g, words);
     gs.ctx_bytes = khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, words);
     s->used += (int64_t)gs.ctx_bytes;
@@ -179,8 +188,13 @@ bool plan(khop_server *s, GraphServe &gs, int64_t now) {
         new_seeds.push_back(sl.req.seed);
     }
     if (gs.harvesting.empty() && !any_old && new_slots.empty()) return false;
+    // admission takes the lowest free slots, so the words holding live slots
+    // are a prefix; the hop only works on it
+    int wact = 1;
+    for (int j = 0; j < 64 * W; ++j)
+        if (gs.slots[j].used) wact = std::max(wact, (j >> 6) + 1);
     khop::serve_iteration(gs.ctx, fin.data(), act.data(), any_old, new_slots.data(), new_seeds.data(),
-                          (int)new_slots.size(), gs.stream);
+                          (int)new_slots.size(), wact, gs.stream);
     for (auto &sl : gs.slots)
         if (sl.used) sl.level += 1;
     KHOP_HIP(hipEventRecord(gs.ev, gs.stream));
@@ -200,7 +214,7 @@ void scheduler(khop_server *s) {
                 while (!s->incoming.empty()) {
                     Request r = s->incoming.front();
                     s->incoming.pop_front();
-                    s->graphs[r.graph_id]->queue.push_back(r);
+                    s->graphs[lane_of(r.graph_id, r.k)]->queue.push_back(r);
                 }
             }
             const int64_t now = mono_ns();
@@ -285,14 +299,17 @@ int khop_server_add_graph(khop_server *s, khop_graph *g, int32_t *graph_id) {
         if (!s->graphs.empty() && s->graphs[0]->g->device != g->device)
             khop::fail(KHOP_EINVAL, "all graphs of a server must live on one device");
         KHOP_HIP(hipSetDevice(g->device));
-        auto *gs = new GraphServe();
-        gs->g = g;
-        gs->id = (int)s->graphs.size();
-        KHOP_HIP(hipStreamCreateWithFlags(&gs->stream, hipStreamNonBlocking));
-        KHOP_HIP(hipEventCreateWithFlags(&gs->ev, hipEventDisableTiming));
+        for (int l = 0; l < kLanes; ++l) {
+            auto *gs = new GraphServe();
+            gs->g = g;
+            gs->id = s->ngraphs;
+            gs->lane = l;
+            KHOP_HIP(hipStreamCreateWithFlags(&gs->stream, hipStreamNonBlocking));
+            KHOP_HIP(hipEventCreateWithFlags(&gs->ev, hipEventDisableTiming));
+            s->graphs.push_back(gs);
+        }
         s->device = g->device;
-        s->graphs.push_back(gs);
-        *graph_id = gs->id;
+        *graph_id = s->ngraphs++;
     });
 }
 
@@ -303,8 +320,9 @@ int khop_server_submit(khop_server *s, int32_t graph_id, int32_t seed, int32_t k
         if (k < 0) khop::fail(KHOP_EINVAL, "k < 0");
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) khop::fail(KHOP_EINTERNAL, "server stopped: " + s->thread_error);
-        if (graph_id < 0 || graph_id >= (int32_t)s->graphs.size()) khop::fail(KHOP_EINVAL, "unknown graph_id");
-        if (seed < 0 || (int64_t)seed >= s->graphs[graph_id]->g->n) khop::fail(KHOP_EINVAL, "seed out of range");
+        if (graph_id < 0 || graph_id >= s->ngraphs) khop::fail(KHOP_EINVAL, "unknown graph_id");
+        if (seed < 0 || (int64_t)seed >= s->graphs[lane_of(graph_id, 0)]->g->n)
+            khop::fail(KHOP_EINVAL, "seed out of range");
         if (s->incoming.size() >= kMaxQueued) khop::fail(KHOP_EBUSY, "request queue full");
         Request r{s->next_ticket++, graph_id, seed, k, mono_ns(), deadline_ns};
         s->incoming.push_back(r);
