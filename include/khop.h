@@ -114,6 +114,37 @@ int khop_count_batched(khop_graph *g, const int32_t *seeds, const int32_t *ks, i
 int khop_count_batched_dev(khop_graph *g, const int32_t *d_seeds, const int32_t *d_ks, int64_t num_seeds,
                            int64_t *d_counts, void *hip_stream);
 
+/*
+ * Breadth-first distances from one seed: the level-synchronous search behind
+ * the k-hop count (Section III; each level one masked product of Section II)
+ * run to the end, on the kernels of khop_count plus one store per discovered
+ * vertex.  dist[v] = the hop distance from seed to v when it is at most
+ * max_depth, else -1; dist[seed] = 0.  max_depth < 0 means no limit.
+ * *count (may be NULL) = the vertices at distance 1..max_depth (the k-hop
+ * count at k = max_depth, or the size of the seed's reach minus one);
+ * *depth (may be NULL) = the largest distance found.  dist is a host array of
+ * num_vertices int32, written only on success.  Hops are launched in groups
+ * and the host checks between groups whether the frontier has emptied, so a
+ * search costs about depth + 1 hop launches whatever max_depth is.
+ * Errors: seed outside [0, n) or dist NULL -> KHOP_EINVAL; KHOP_ENOMEM when
+ * the device distance buffer cannot be allocated.
+ */
+int khop_bfs(khop_graph *g, int32_t seed, int32_t max_depth, int32_t *dist, int64_t *count, int32_t *depth);
+
+/*
+ * Device-pointer form of khop_bfs on hip_stream: d_dist (int32, num_vertices
+ * entries), d_count (one int64, may be NULL) and d_depth (one int32, may be
+ * NULL) are device pointers, written in stream order.  With max_depth >= 0
+ * exactly max_depth hops are enqueued and the host never waits (hops after
+ * the frontier empties exit at once).  With max_depth < 0 the call waits on
+ * the stream between groups of hops to learn whether the frontier has
+ * emptied, and returns once the last hop is enqueued; the caller still
+ * synchronises before reading the outputs.  Errors as khop_bfs (the seed is
+ * checked on the host).
+ */
+int khop_bfs_dev(khop_graph *g, int32_t seed, int32_t max_depth, int32_t *d_dist, int64_t *d_count,
+                 int32_t *d_depth, void *hip_stream);
+
 /* Engine options (per graph). */
 enum khop_option {
     KHOP_OPT_DIRECTION = 1,     /* KHOP_DIR_AUTO (default), KHOP_DIR_PUSH or KHOP_DIR_PULL */

@@ -47,8 +47,8 @@ KHOP_DIR_PULL = 2
 
 # Every entry point declared in include/khop.h.
 EXPORTS = ("graph_load_csr", "graph_free", "graph_info", "graph_degrees", "khop_count", "khop_count_dev",
-           "khop_count_batched", "khop_count_batched_dev", "khop_set_option", "khop_get_option", "khop_autotune",
-           "khop_profile", "khop_profile_read", "khop_server_create", "khop_server_add_graph",
+           "khop_count_batched", "khop_count_batched_dev", "khop_bfs", "khop_bfs_dev", "khop_set_option",
+           "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read", "khop_server_create", "khop_server_add_graph",
            "khop_server_submit", "khop_server_poll", "khop_server_drain", "khop_server_destroy",
            "khop_last_error", "khop_version")
 
@@ -102,6 +102,8 @@ def _load():
         "khop_count_dev": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp],),
         "khop_count_batched": ([_vp, _i32p, _i32p, ctypes.c_int64, _i64p],),
         "khop_count_batched_dev": ([_vp, _vp, _vp, ctypes.c_int64, _vp, _vp],),
+        "khop_bfs": ([_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i64p, _i32p],),
+        "khop_bfs_dev": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp],),
         "khop_set_option": ([_vp, ctypes.c_int32, ctypes.c_int64],),
         "khop_get_option": ([_vp, ctypes.c_int32, _i64p],),
         "khop_autotune": ([_vp, ctypes.c_int32],),
@@ -228,6 +230,21 @@ def khop_count_batched_dev(h, d_seeds, d_ks, d_counts, stream=None) -> None:
                                        _dev_ptr(d_counts, "torch.int64"), _stream_ptr(stream)))
 
 
+def khop_bfs(h, seed: int, n: int, max_depth: int = -1):
+    """(dist int32[n], count, depth) of a breadth-first search from seed."""
+    dist = np.empty(int(n), dtype=np.int32)
+    c, d = ctypes.c_int64(), ctypes.c_int32()
+    _check(_lib.khop_bfs(h, int(seed), int(max_depth), dist.ctypes.data_as(_i32p), ctypes.byref(c),
+                         ctypes.byref(d)))
+    return dist, int(c.value), int(d.value)
+
+
+def khop_bfs_dev(h, seed: int, d_dist, max_depth: int = -1, d_count=None, d_depth=None, stream=None) -> None:
+    _check(_lib.khop_bfs_dev(h, int(seed), int(max_depth), _dev_ptr(d_dist, "torch.int32"),
+                             _dev_ptr(d_count, "torch.int64"), _dev_ptr(d_depth, "torch.int32"),
+                             _stream_ptr(stream)))
+
+
 def khop_set_option(h, option: int, value: int) -> None:
     _check(_lib.khop_set_option(h, int(option), int(value)))
 
@@ -329,6 +346,14 @@ class Graph:
 
     def count_batched_dev(self, d_seeds, d_ks, d_counts, stream=None):
         khop_count_batched_dev(self._h, d_seeds, d_ks, d_counts, stream)
+
+    def bfs(self, seed: int, max_depth: int = -1):
+        return khop_bfs(self._h, seed, self.n, max_depth)
+
+    def bfs_dev(self, seed: int, d_dist, max_depth: int = -1, d_count=None, d_depth=None, stream=None):
+        if int(d_dist.numel()) < self.n:
+            raise ValueError("distance tensor shorter than the vertex count")
+        khop_bfs_dev(self._h, seed, d_dist, max_depth, d_count, d_depth, stream)
 
     def set_option(self, option: int, value: int):
         khop_set_option(self._h, option, value)

@@ -164,6 +164,8 @@ struct Pools {
         int64_t *d_te = nullptr;
         int64_t cap = 0;
         int64_t *h_pinned = nullptr;  // 2 int64 for per-query readback
+        int32_t *d_dist = nullptr;    // breadth-first distances (n), then the depth
+        int64_t dist_cap = 0;
     };
     std::vector<Buffers *> bufs;
 };
@@ -209,6 +211,7 @@ static void pools_drop(khop_graph *g) {
         (void)hipFree(b->d_seeds);
         (void)hipFree(b->d_counts);
         (void)hipFree(b->d_te);
+        (void)hipFree(b->d_dist);
         if (b->h_pinned) (void)hipHostFree(b->h_pinned);
         delete b;
     }
@@ -303,6 +306,19 @@ static Pools::Buffers *take_buffers(khop_graph *g, int64_t need) {
         b->cap = cap;
     }
     return b;
+}
+
+// Grows the distance buffer to n + 1 int32 (the distances, then the depth).
+static void ensure_dist(Pools::Buffers *b, int64_t n) {
+    if (b->dist_cap >= n + 1) return;
+    (void)hipFree(b->d_dist);
+    b->d_dist = nullptr;
+    b->dist_cap = 0;
+    if (hipMalloc(&b->d_dist, (size_t)(n + 1) * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(KHOP_ENOMEM, "device allocation of a distance vector failed");
+    }
+    b->dist_cap = n + 1;
 }
 
 static void give_buffers(khop_graph *g, Pools::Buffers *b) {
@@ -583,6 +599,63 @@ int khop_count_batched_dev(khop_graph *g, const int32_t *d_seeds, const int32_t 
         for (int64_t i = 0; i < num_seeds; ++i)
             if (hk[i] < 0) fail(KHOP_EINVAL, "k < 0 at index " + std::to_string(i));
         run_batched(g, d_seeds, hk.data(), num_seeds, d_counts, st);
+    });
+}
+
+int khop_bfs(khop_graph *g, int32_t seed, int32_t max_depth, int32_t *dist, int64_t *count, int32_t *depth) {
+    return guard([&] {
+        check_graph(g);
+        if (!dist) fail(KHOP_EINVAL, "dist is NULL");
+        validate_seeds(g, &seed, 1);
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = g->stream;
+        Pools::Buffers *b = take_buffers(g, 1);
+        PlainSlot s{nullptr, {}};
+        int64_t c = 0;
+        int32_t d = 0;
+        try {
+            ensure_dist(b, g->n);
+            s = take_plain(g, st);
+            plain_bfs(g, s.ctx, seed, max_depth, b->d_dist, b->d_counts, b->d_dist + g->n, (int32_t *)b->h_pinned,
+                      st);
+            KHOP_HIP(hipMemcpyAsync(dist, b->d_dist, (size_t)g->n * 4, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipMemcpyAsync(b->h_pinned, b->d_counts, 8, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipMemcpyAsync(b->h_pinned + 1, b->d_dist + g->n, 4, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipStreamSynchronize(st));
+            c = b->h_pinned[0];
+            d = *(const int32_t *)(b->h_pinned + 1);
+        } catch (...) {
+            if (s.ctx) give_plain(g, s, st);
+            give_buffers(g, b);
+            throw;
+        }
+        give_plain(g, s, st);
+        give_buffers(g, b);
+        if (count) *count = c;
+        if (depth) *depth = d;
+    });
+}
+
+int khop_bfs_dev(khop_graph *g, int32_t seed, int32_t max_depth, int32_t *d_dist, int64_t *d_count, int32_t *d_depth,
+                 void *hip_stream) {
+    return guard([&] {
+        check_graph(g);
+        if (!d_dist) fail(KHOP_EINVAL, "d_dist is NULL");
+        validate_seeds(g, &seed, 1);
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = (hipStream_t)hip_stream;
+        Pools::Buffers *b = max_depth < 0 ? take_buffers(g, 1) : nullptr;
+        PlainSlot s{nullptr, {}};
+        try {
+            s = take_plain(g, st);
+            plain_bfs(g, s.ctx, seed, max_depth, d_dist, d_count, d_depth, b ? (int32_t *)b->h_pinned : nullptr, st);
+        } catch (...) {
+            if (s.ctx) give_plain(g, s, st);
+            if (b) give_buffers(g, b);
+            throw;
+        }
+        give_plain(g, s, st);
+        if (b) give_buffers(g, b);
     });
 }
 

@@ -79,6 +79,8 @@ struct PlainCtl {
     int32_t k, dir_mode, alpha, beta;
     int32_t valid;
     int32_t last_bytes;  // the last hop left byte marks (counted by the next query's hop 1)
+    int32_t reached;     // largest level found non-empty so far (the seed's is 0)
+    int32_t more;        // breadth-first search: the level the last probe read is non-empty
     int64_t seed_beg;    // the seed's first out-edge, its out- and in-degree (hop 1 reads them)
     int64_t seed_od;
     int64_t seed_id;
@@ -104,6 +106,7 @@ struct State {
     uint64_t *F[3];    // frontier bitmaps by hop % 3
     uint8_t *nextb;    // top-down marks (byte mode), all zero between hops
     uint8_t *nsum;     // one byte per 64-vertex word: some mark of the word may be set
+    int32_t *dist;     // breadth-first search: distance of each vertex, set when it is found (else null)
     int64_t *qb[2];    // region queues by hop parity, nreg * rc slots: the row begin of each queued vertex
     int64_t *qoff[2];  // out-degree prefix within each region's queue
     RegRec *regs;      // 3 * nreg region counters
@@ -282,6 +285,8 @@ __device__ void setup_query(PlainCtl *ctl, const Graph &g, const State &s, int32
     ctl->k = k;
     ctl->valid = valid;
     ctl->last_bytes = 0;
+    ctl->reached = 0;
+    ctl->more = 1;
     ctl->push_atomic_max = push_atomic_max;
     ctl->count_acc = 0;
     ctl->te_acc = 0;
@@ -374,6 +379,7 @@ __device__ __forceinline__ void push_claim(int L, const Graph &g, const State &s
     const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
     if (old & bit) return;
     atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+    if (s.dist) s.dist[v] = L;
     const int64_t vb = g.rowptr[v];
     const int64_t od = g.rowptr[v + 1] - vb;
     const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
@@ -620,6 +626,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
                 atomicOr((unsigned long long *)&s.V[w], (unsigned long long)fm);
                 atomicOr((unsigned long long *)&Fn[w], (unsigned long long)fm);
             }
+            if (found && s.dist) s.dist[v] = L;
             int64_t od = 0, vb = b;  // undirected: the in-row is the out-row
             if (found && g.directed) {
                 vb = g.rowptr[v];
@@ -664,6 +671,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
                     *found_out += 1;
                 } else {
                     atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                    if (s.dist) s.dist[v] = L;
                     const int64_t vb = g.rowptr[v];
                     const int64_t od = g.rowptr[v + 1] - vb;
                     const int64_t id = g.in_rowptr[v + 1] - g.in_rowptr[v];
@@ -705,6 +713,7 @@ __device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E
                 const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
                 if (!(old & bit)) {
                     atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                    if (s.dist) s.dist[v] = 1;
                     append_one(s, cur, 1, v, vb, od, id);
                 }
             }
@@ -829,6 +838,7 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
         ctl->hdr[L % 3].mode = mode;
         if (last) ctl->last_bytes = mode == MODE_PUSH_BYTES;
         if (L >= 2) ctl->count_acc += nf;
+        if (nf > 0) ctl->reached = L - 1;
         ctl->te_acc += E;
         if (units) unit_add(units, 0, 16 * s.nreg);
     }
@@ -942,6 +952,7 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
             const bool fresh = nb[i] && !((vis[i] >> lane) & 1ull);
             const uint64_t m = ballot(fresh);
             if (nb[i]) s.nextb[v] = 0;
+            if (fresh && s.dist) s.dist[v] = L;
             if (lane == 0 && m) {
                 s.V[w] = vis[i] | m;
                 Fn[w] = m;
@@ -960,6 +971,50 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
     if (lane == 0) unit_add(units, 0, 16 * found_total);
 }
 
+// ------------------------------------------------------------------ breadth-first search to the end
+
+// The hop kernels above, with no hop marked last, are a level-synchronous
+// breadth-first search; with s.dist set, every vertex found at hop l gets
+// distance l, written once by the wave or lane whose claim (atomicOr on its
+// visited word, or the ballot of a word's fresh bits) found it.
+
+// Set-up: the distance vector (0 at the seed, -1 elsewhere), the visited and
+// frontier bitmaps, and the control record with no last hop.
+__global__ void __launch_bounds__(kBlock) plain_bfs_init_kernel(PlainCtl *ctl, Graph g, State s, int32_t seed,
+                                                               int dir_mode, int alpha, int beta,
+                                                               int64_t push_atomic_max, int64_t nnz_in,
+                                                               int64_t *units) {
+    const int64_t sw = seed >> 6;
+    const uint64_t sbit = 1ull << (seed & 63);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += stride) reset_word(s, w, sw, sbit);
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < g.n; v += stride)
+        s.dist[v] = v == seed ? 0 : -1;
+    if (blockIdx.x == 0)
+        setup_query(ctl, g, s, seed, 0, INT32_MAX, dir_mode, alpha, beta, push_atomic_max, nnz_in, nullptr, nullptr,
+                    units);
+    if (units && blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, 4 * g.n);
+}
+
+// After hop L (one wave): whether level L is non-empty (ctl->more), the
+// largest non-empty level (ctl->reached), and into the outputs given, the
+// count of levels 1..L and that level.  Level L's region counters stay intact
+// until hop L+2 clears them.
+__global__ void __launch_bounds__(kWave) plain_bfs_probe_kernel(PlainCtl *ctl, State s, int L, int64_t *out_count,
+                                                               int32_t *out_depth) {
+    const int lane = lane_id();
+    const RegRec *lv = s.regs + (int64_t)(L % 3) * s.nreg;
+    int64_t nf = 0;
+    for (int r = lane; r < s.nreg; r += kWave) nf += pk_count(lv[r].fpack);
+    nf = wave_sum(nf);
+    if (lane != 0) return;
+    if (L == 0) nf = 0;  // level 0 is the seed, never counted
+    const int32_t depth = nf > 0 ? L : ctl->reached;
+    ctl->reached = depth;
+    ctl->more = nf > 0;
+    if (out_count) *out_count = ctl->count_acc + nf;
+    if (out_depth) *out_depth = depth;
+}
 
 __global__ void fill_kernel(int64_t *a, int64_t *b, int64_t n, int64_t value) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -1117,6 +1172,67 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         ps.end(0, 1);
     }
     hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, ctl + (m - 1) % 3);
+    KHOP_HIP(hipGetLastError());
+}
+
+void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int32_t *d_dist, int64_t *d_count,
+               int32_t *d_depth, int32_t *h_flags, hipStream_t st) {
+    const Params &P = g->params;
+    const HeavyTable &ht = plain_heavy_table(g);
+    Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
+             ht.threshold};
+    HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
+    const int64_t pam = (int64_t)P.push_atomic_max;
+    const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
+    State s = c->s[0];
+    s.dist = d_dist;
+    PlainCtl *ctl = c->ctl;
+    {
+        ProfScope ps(g, KK_PLAIN_INIT, st);
+        hipLaunchKernelGGL(plain_bfs_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, s, seed,
+                           P.dir_mode, P.alpha, P.beta, pam, g->nnz, ps.units());
+        ps.end(0, 1);
+    }
+    const int64_t limit = max_depth < 0 ? INT32_MAX : max_depth;
+    int64_t H = 0;  // hops launched
+    // hops per group between host checks: one more than the last search's depth
+    int64_t group = std::max(2, g->bfs_hops_hint.load(std::memory_order_relaxed));
+    while (H < limit) {
+        const int64_t upto = h_flags ? std::min(limit, H + group) : limit;
+        for (int64_t L = H + 1; L <= upto; ++L) {
+            ProfScope ps(g, KK_PLAIN_HOP, st);
+            if (L == 1) {
+                // the set-up above replaces the pipeline's close and set-up work (no previous or next query)
+                hipLaunchKernelGGL(plain_hop1_kernel, dim3(hop1_grid), dim3(kBlock), 0, st, ctl, ctl + 2, ctl + 1, 0,
+                                   0, gr, s, c->s[1], (const int32_t *)nullptr, (int64_t)-1, INT32_MAX, P.dir_mode,
+                                   P.alpha, P.beta, pam, g->nnz, (int64_t *)nullptr, (int64_t *)nullptr,
+                                   P.pull_light, hc, ps.units());
+                ps.end(0, 1);
+                continue;
+            }
+            hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
+                               P.pull_light, hc, ps.units());
+            ps.end(0, 1);
+            ProfScope pc(g, KK_PLAIN_COMPACT, st);
+            hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
+                               pc.units());
+            pc.end(0, 1);
+        }
+        H = upto;
+        if (!h_flags || H >= limit) break;
+        hipLaunchKernelGGL(plain_bfs_probe_kernel, dim3(1), dim3(kWave), 0, st, ctl, s, (int)H, (int64_t *)nullptr,
+                           (int32_t *)nullptr);
+        // reached and more are adjacent in the control record
+        KHOP_HIP(hipMemcpyAsync(h_flags, &ctl->reached, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        KHOP_HIP(hipStreamSynchronize(st));
+        if (!h_flags[1]) {
+            // a search of depth D ends after D + 1 hops (the last finds nothing)
+            g->bfs_hops_hint.store(h_flags[0] + 1, std::memory_order_relaxed);
+            break;
+        }
+        group = std::min<int64_t>(2 * group, 1024);
+    }
+    hipLaunchKernelGGL(plain_bfs_probe_kernel, dim3(1), dim3(kWave), 0, st, ctl, s, (int)H, d_count, d_depth);
     KHOP_HIP(hipGetLastError());
 }
 
