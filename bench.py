@@ -66,6 +66,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched seeds-per-launch sweep")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--no-bfs", action="store_true", help="skip the full-depth breadth-first search measurement")
     ap.add_argument("--twitter", action="store_true",
                     help="also load the 41.6M-vertex power-law graph and serve both graphs")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per offered-load level")
@@ -224,6 +225,7 @@ def main():
                                 "p99_ms": round(pct(lat, 99), 4), "n": len(lat)}
 
     sweep = None if args.no_sweep else batched_sweep(g, el, K, torch)
+    bfs = None if args.no_bfs else bfs_bench(g, el, K, torch, cpu_leg=not args.no_cpu_baseline)
     g2 = el2 = None
     power_law = None
     if args.twitter:
@@ -302,6 +304,7 @@ def main():
         "latency_host_api": latency,
         "batched_sweep": sweep,
         "serving": serving,
+        "bfs": bfs,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
@@ -443,6 +446,75 @@ def power_law_bench(g2, el2, K, torch):
                           "gteps": round(int(dte.sum()) / (ms / 1e3) / 1e9, 3),
                           "equal_to_plain": bool(torch.equal(c, dp))}
     log("power-law graph: " + json.dumps(out))
+    return out
+
+
+def bfs_bench(g, el, K, torch, n_seeds=64, cpu_leg=True):
+    """Full-depth breadth-first distances (no depth limit) from sampled seeds,
+    device-resident, through khop_bfs_dev on one stream."""
+    import graphgen
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    seeds = graphgen.draw_seeds(el, n_seeds, seed=7, stream=2)
+    deg = g.degrees()
+    d_dist = torch.empty(g.n, dtype=torch.int32, device=dev)
+    d_count = torch.empty(1, dtype=torch.int64, device=dev)
+    d_depth = torch.empty(1, dtype=torch.int32, device=dev)
+    # untimed pass: the traversed edges (out-arcs of every reached vertex), depth and reach of each search
+    te, depth, reach = [], [], []
+    for s in seeds:
+        g.bfs_dev(int(s), d_dist, -1, d_count, d_depth, stream=stream)
+        dist = d_dist.cpu().numpy()
+        te.append(int(deg[dist >= 0].sum()))
+        depth.append(int(d_depth.item()))
+        reach.append(int(d_count.item()) + 1)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    t0 = time.perf_counter()
+    for s in seeds:
+        ev[0].record(stream)
+        g.bfs_dev(int(s), d_dist, -1, d_count, d_depth, stream=stream)
+        ev[1].record(stream)
+        ev[1].synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    wall = time.perf_counter() - t0
+    # per-kernel times of the same searches
+    g.profile(True)
+    for s in seeds[:16]:
+        g.bfs_dev(int(s), d_dist, -1, d_count, d_depth, stream=stream)
+    torch.cuda.synchronize()
+    kern = g.profile_read()
+    g.profile(False)
+    empty = kern.pop("empty_launch", None)
+    overhead_us = 1000.0 * empty["total_ms"] / empty["launches"] if empty and empty["launches"] else 0.0
+    kinds = {}
+    for name, kv in kern.items():
+        avg = max(1000.0 * kv["total_ms"] / max(kv["launches"], 1) - overhead_us, 0.0)
+        kinds[name] = {"launches_per_search": round(kv["launches"] / 16, 2), "avg_us": round(avg, 3),
+                       "gbs": round(kv["algorithmic_bytes"] / kv["launches"] / (avg * 1e-6) / 1e9, 1)
+                       if avg > 0 else 0}
+    tot_te = sum(te)
+    out = {"seeds": len(seeds), "max_depth": "none", "ms_per_search": round(float(np.mean(ms)), 4),
+           "p50_ms": round(pct(ms, 50), 4), "p99_ms": round(pct(ms, 99), 4),
+           "searches_per_s": round(len(seeds) / wall, 1),
+           "gteps": round(tot_te / (sum(ms) / 1e3) / 1e9, 2),
+           "teps_edges": "stored out-arcs of every reached vertex (each undirected edge twice)",
+           "depth_mean": round(float(np.mean(depth)), 2), "depth_max": int(max(depth)),
+           "reach_mean": round(float(np.mean(reach)), 1), "kernels": kinds}
+    log(f"bfs: {out['ms_per_search']} ms per search, {out['gteps']} GTEPS, depth {out['depth_mean']}")
+    if cpu_leg:
+        import oracle
+        og = oracle.OracleGraph.from_edgelist(el)
+        c_ms, equal = [], True
+        for i, s in enumerate(seeds[:2]):
+            t = time.perf_counter()
+            ref = og.distances(int(s), 2**31 - 1)
+            c_ms.append((time.perf_counter() - t) * 1000.0)
+            g.bfs_dev(int(s), d_dist, -1, stream=stream)
+            equal = equal and bool(np.array_equal(d_dist.cpu().numpy(), ref))
+        out["cpu_oracle"] = {"searches": 2, "cores": 1, "ms_per_search": round(float(np.mean(c_ms)), 1),
+                             "gteps": round(sum(te[:2]) / (sum(c_ms) / 1e3) / 1e9, 4), "distances_equal_gpu": equal}
     return out
 
 
