@@ -145,6 +145,38 @@ int khop_bfs(khop_graph *g, int32_t seed, int32_t max_depth, int32_t *dist, int6
 int khop_bfs_dev(khop_graph *g, int32_t seed, int32_t max_depth, int32_t *d_dist, int64_t *d_count,
                  int32_t *d_depth, void *hip_stream);
 
+/*
+ * Exactly-l counts: level_counts[l-1] = |{ v : dist(seed, v) = l }| for
+ * l = 1..k, from one search of depth k (the sizes of the frontiers the masked
+ * products of Section II produce; their sum is the k-hop count).  Host array
+ * of k int64.  Errors: seed outside [0, n), k < 0, or level_counts NULL with
+ * k > 0 -> KHOP_EINVAL.  k == 0 writes nothing.
+ */
+int khop_levels(khop_graph *g, int32_t seed, int32_t k, int64_t *level_counts);
+
+/* Device-pointer form of khop_levels on hip_stream (k hops enqueued, no host wait). */
+int khop_levels_dev(khop_graph *g, int32_t seed, int32_t k, int64_t *d_level_counts, void *hip_stream);
+
+/*
+ * The k-hop neighborhood itself, { v : 1 <= dist(seed, v) <= k }, as
+ * ascending vertex ids (the result set a graph query returns, Section III;
+ * k < 0: everything the seed reaches).  The first min(count, capacity) ids go
+ * to ids (host, capacity int32), and *count receives the full size, so a
+ * caller with too small a buffer learns the size it needs.  Errors: seed
+ * outside [0, n), capacity < 0, ids NULL with capacity > 0, or count NULL ->
+ * KHOP_EINVAL.
+ */
+int khop_neighborhood(khop_graph *g, int32_t seed, int32_t k, int32_t *ids, int64_t capacity, int64_t *count);
+
+/*
+ * Device-pointer form of khop_neighborhood on hip_stream: d_ids (capacity
+ * int32) and d_count (one int64) are device pointers written in stream order.
+ * With k >= 0 the host never waits; with k < 0 it waits between groups of
+ * hops as khop_bfs_dev does.
+ */
+int khop_neighborhood_dev(khop_graph *g, int32_t seed, int32_t k, int32_t *d_ids, int64_t capacity,
+                          int64_t *d_count, void *hip_stream);
+
 /* Engine options (per graph). */
 enum khop_option {
     KHOP_OPT_DIRECTION = 1,     /* KHOP_DIR_AUTO (default), KHOP_DIR_PUSH or KHOP_DIR_PULL */

@@ -47,7 +47,8 @@ KHOP_DIR_PULL = 2
 
 # Every entry point declared in include/khop.h.
 EXPORTS = ("graph_load_csr", "graph_free", "graph_info", "graph_degrees", "khop_count", "khop_count_dev",
-           "khop_count_batched", "khop_count_batched_dev", "khop_bfs", "khop_bfs_dev", "khop_set_option",
+           "khop_count_batched", "khop_count_batched_dev", "khop_bfs", "khop_bfs_dev", "khop_levels",
+           "khop_levels_dev", "khop_neighborhood", "khop_neighborhood_dev", "khop_set_option",
            "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read", "khop_server_create", "khop_server_add_graph",
            "khop_server_submit", "khop_server_poll", "khop_server_drain", "khop_server_destroy",
            "khop_last_error", "khop_version")
@@ -104,6 +105,10 @@ def _load():
         "khop_count_batched_dev": ([_vp, _vp, _vp, ctypes.c_int64, _vp, _vp],),
         "khop_bfs": ([_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i64p, _i32p],),
         "khop_bfs_dev": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp],),
+        "khop_levels": ([_vp, ctypes.c_int32, ctypes.c_int32, _i64p],),
+        "khop_levels_dev": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp],),
+        "khop_neighborhood": ([_vp, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_int64, _i64p],),
+        "khop_neighborhood_dev": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp],),
         "khop_set_option": ([_vp, ctypes.c_int32, ctypes.c_int64],),
         "khop_get_option": ([_vp, ctypes.c_int32, _i64p],),
         "khop_autotune": ([_vp, ctypes.c_int32],),
@@ -245,6 +250,32 @@ def khop_bfs_dev(h, seed: int, d_dist, max_depth: int = -1, d_count=None, d_dept
                              _stream_ptr(stream)))
 
 
+def khop_levels(h, seed: int, k: int) -> np.ndarray:
+    """int64[k]: the number of vertices at distance exactly 1..k."""
+    out = np.zeros(max(int(k), 0), dtype=np.int64)
+    _check(_lib.khop_levels(h, int(seed), int(k), out.ctypes.data_as(_i64p) if k > 0 else None))
+    return out
+
+
+def khop_levels_dev(h, seed: int, k: int, d_levels, stream=None) -> None:
+    if k > 0 and int(d_levels.numel()) < k:
+        raise ValueError("level tensor shorter than k")
+    _check(_lib.khop_levels_dev(h, int(seed), int(k), _dev_ptr(d_levels, "torch.int64"), _stream_ptr(stream)))
+
+
+def khop_neighborhood(h, seed: int, k: int, capacity: int):
+    """(ascending ids of the k-hop neighborhood, at most `capacity` of them; its full size)."""
+    ids = np.empty(max(int(capacity), 1), dtype=np.int32)
+    c = ctypes.c_int64()
+    _check(_lib.khop_neighborhood(h, int(seed), int(k), ids.ctypes.data_as(_i32p), int(capacity), ctypes.byref(c)))
+    return ids[:min(int(c.value), int(capacity))].copy(), int(c.value)
+
+
+def khop_neighborhood_dev(h, seed: int, k: int, d_ids, d_count, stream=None) -> None:
+    _check(_lib.khop_neighborhood_dev(h, int(seed), int(k), _dev_ptr(d_ids, "torch.int32"), int(d_ids.numel()),
+                                      _dev_ptr(d_count, "torch.int64"), _stream_ptr(stream)))
+
+
 def khop_set_option(h, option: int, value: int) -> None:
     _check(_lib.khop_set_option(h, int(option), int(value)))
 
@@ -354,6 +385,20 @@ class Graph:
         if int(d_dist.numel()) < self.n:
             raise ValueError("distance tensor shorter than the vertex count")
         khop_bfs_dev(self._h, seed, d_dist, max_depth, d_count, d_depth, stream)
+
+    def levels(self, seed: int, k: int) -> np.ndarray:
+        return khop_levels(self._h, seed, k)
+
+    def levels_dev(self, seed: int, k: int, d_levels, stream=None):
+        khop_levels_dev(self._h, seed, k, d_levels, stream)
+
+    def neighborhood(self, seed: int, k: int, capacity: int = None):
+        """Ascending ids of { v : 1 <= dist(seed, v) <= k } (k < 0: the whole reach)."""
+        ids, c = khop_neighborhood(self._h, seed, k, self.n if capacity is None else capacity)
+        return ids if capacity is None else (ids, c)
+
+    def neighborhood_dev(self, seed: int, k: int, d_ids, d_count, stream=None):
+        khop_neighborhood_dev(self._h, seed, k, d_ids, d_count, stream)
 
     def set_option(self, option: int, value: int):
         khop_set_option(self._h, option, value)

@@ -616,8 +616,8 @@ int khop_bfs(khop_graph *g, int32_t seed, int32_t max_depth, int32_t *dist, int6
         try {
             ensure_dist(b, g->n);
             s = take_plain(g, st);
-            plain_bfs(g, s.ctx, seed, max_depth, b->d_dist, b->d_counts, b->d_dist + g->n, (int32_t *)b->h_pinned,
-                      st);
+            plain_bfs(g, s.ctx, seed, max_depth, b->d_dist, b->d_counts, b->d_dist + g->n, nullptr, 0,
+                      (int32_t *)b->h_pinned, st);
             KHOP_HIP(hipMemcpyAsync(dist, b->d_dist, (size_t)g->n * 4, hipMemcpyDeviceToHost, st));
             KHOP_HIP(hipMemcpyAsync(b->h_pinned, b->d_counts, 8, hipMemcpyDeviceToHost, st));
             KHOP_HIP(hipMemcpyAsync(b->h_pinned + 1, b->d_dist + g->n, 4, hipMemcpyDeviceToHost, st));
@@ -648,7 +648,120 @@ int khop_bfs_dev(khop_graph *g, int32_t seed, int32_t max_depth, int32_t *d_dist
         PlainSlot s{nullptr, {}};
         try {
             s = take_plain(g, st);
-            plain_bfs(g, s.ctx, seed, max_depth, d_dist, d_count, d_depth, b ? (int32_t *)b->h_pinned : nullptr, st);
+            plain_bfs(g, s.ctx, seed, max_depth, d_dist, d_count, d_depth, nullptr, 0,
+                      b ? (int32_t *)b->h_pinned : nullptr, st);
+        } catch (...) {
+            if (s.ctx) give_plain(g, s, st);
+            if (b) give_buffers(g, b);
+            throw;
+        }
+        give_plain(g, s, st);
+        if (b) give_buffers(g, b);
+    });
+}
+
+int khop_levels(khop_graph *g, int32_t seed, int32_t k, int64_t *level_counts) {
+    return guard([&] {
+        check_graph(g);
+        if (k < 0) fail(KHOP_EINVAL, "k < 0");
+        validate_seeds(g, &seed, 1);
+        if (k == 0) return;
+        if (!level_counts) fail(KHOP_EINVAL, "level_counts is NULL");
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = g->stream;
+        Pools::Buffers *b = take_buffers(g, k);
+        PlainSlot s{nullptr, {}};
+        std::vector<int64_t> lv((size_t)k);
+        try {
+            s = take_plain(g, st);
+            plain_bfs(g, s.ctx, seed, k, nullptr, nullptr, nullptr, b->d_counts, k, (int32_t *)b->h_pinned, st);
+            KHOP_HIP(hipMemcpyAsync(lv.data(), b->d_counts, (size_t)k * 8, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+            if (s.ctx) give_plain(g, s, st);
+            give_buffers(g, b);
+            throw;
+        }
+        give_plain(g, s, st);
+        give_buffers(g, b);
+        std::copy(lv.begin(), lv.end(), level_counts);
+    });
+}
+
+int khop_levels_dev(khop_graph *g, int32_t seed, int32_t k, int64_t *d_level_counts, void *hip_stream) {
+    return guard([&] {
+        check_graph(g);
+        if (k < 0) fail(KHOP_EINVAL, "k < 0");
+        validate_seeds(g, &seed, 1);
+        if (k == 0) return;
+        if (!d_level_counts) fail(KHOP_EINVAL, "d_level_counts is NULL");
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = (hipStream_t)hip_stream;
+        PlainSlot s = take_plain(g, st);
+        try {
+            plain_bfs(g, s.ctx, seed, k, nullptr, nullptr, nullptr, d_level_counts, k, nullptr, st);
+        } catch (...) {
+            give_plain(g, s, st);
+            throw;
+        }
+        give_plain(g, s, st);
+    });
+}
+
+int khop_neighborhood(khop_graph *g, int32_t seed, int32_t k, int32_t *ids, int64_t capacity, int64_t *count) {
+    return guard([&] {
+        check_graph(g);
+        if (capacity < 0) fail(KHOP_EINVAL, "capacity < 0");
+        if (capacity > 0 && !ids) fail(KHOP_EINVAL, "ids is NULL with capacity > 0");
+        if (!count) fail(KHOP_EINVAL, "count is NULL");
+        validate_seeds(g, &seed, 1);
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = g->stream;
+        Pools::Buffers *b = take_buffers(g, 1);
+        PlainSlot s{nullptr, {}};
+        int64_t c = 0;
+        const int64_t cap = std::min<int64_t>(capacity, g->n);
+        try {
+            ensure_dist(b, g->n);
+            s = take_plain(g, st);
+            plain_bfs(g, s.ctx, seed, k, nullptr, nullptr, nullptr, nullptr, 0, (int32_t *)b->h_pinned, st);
+            plain_set(g, s.ctx, seed, b->d_dist, cap, b->d_counts, st);
+            KHOP_HIP(hipMemcpyAsync(b->h_pinned, b->d_counts, 8, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipStreamSynchronize(st));
+            c = b->h_pinned[0];
+            const int64_t m = std::min(c, cap);
+            if (m > 0) {
+                KHOP_HIP(hipMemcpyAsync(ids, b->d_dist, (size_t)m * 4, hipMemcpyDeviceToHost, st));
+                KHOP_HIP(hipStreamSynchronize(st));
+            }
+        } catch (...) {
+            if (s.ctx) give_plain(g, s, st);
+            give_buffers(g, b);
+            throw;
+        }
+        give_plain(g, s, st);
+        give_buffers(g, b);
+        *count = c;
+    });
+}
+
+int khop_neighborhood_dev(khop_graph *g, int32_t seed, int32_t k, int32_t *d_ids, int64_t capacity, int64_t *d_count,
+                          void *hip_stream) {
+    return guard([&] {
+        check_graph(g);
+        if (capacity < 0) fail(KHOP_EINVAL, "capacity < 0");
+        if (capacity > 0 && !d_ids) fail(KHOP_EINVAL, "d_ids is NULL with capacity > 0");
+        if (!d_count) fail(KHOP_EINVAL, "d_count is NULL");
+        validate_seeds(g, &seed, 1);
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = (hipStream_t)hip_stream;
+        Pools::Buffers *b = k < 0 ? take_buffers(g, 1) : nullptr;
+        PlainSlot s{nullptr, {}};
+        try {
+            s = take_plain(g, st);
+            plain_bfs(g, s.ctx, seed, k, nullptr, nullptr, nullptr, nullptr, 0, b ? (int32_t *)b->h_pinned : nullptr,
+                      st);
+            plain_set(g, s.ctx, seed, d_ids, std::min<int64_t>(capacity, g->n), d_count, st);
         } catch (...) {
             if (s.ctx) give_plain(g, s, st);
             if (b) give_buffers(g, b);

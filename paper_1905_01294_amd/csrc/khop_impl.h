@@ -169,13 +169,20 @@ void plain_ctx_destroy(PlainCtx *c);
 void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k,
                int64_t *d_counts, int64_t *d_te, hipStream_t st);
 void plain_fill_zero_outputs(int64_t *d_counts, int64_t *d_te, int64_t n, hipStream_t st);
-// Breadth-first distances from one (valid) seed into d_dist[n], up to max_depth
-// hops (< 0: no limit); the count of levels 1..max_depth and the largest
-// non-empty level go to d_count / d_depth when not null.  h_flags (pinned, two
-// int32) lets the host check between groups of hops whether the frontier is
-// empty; without it exactly max_depth hops are enqueued (max_depth >= 0 then).
+// Breadth-first search from one (valid) seed, up to max_depth hops (< 0: no
+// limit), on the context's first state.  Distances go to d_dist[n] and the
+// size of each level 1..level_cap to d_levels when those are not null; the
+// count of levels 1..max_depth and the largest non-empty level go to d_count /
+// d_depth when not null.  h_flags (pinned, two int32) lets the host check
+// between groups of hops whether the frontier is empty; without it exactly
+// max_depth hops are enqueued (max_depth >= 0 then).
 void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int32_t *d_dist, int64_t *d_count,
-               int32_t *d_depth, int32_t *h_flags, hipStream_t st);
+               int32_t *d_depth, int64_t *d_levels, int64_t level_cap, int32_t *h_flags, hipStream_t st);
+// After plain_bfs on the same context and stream: the searched neighborhood
+// (visited vertices but the seed) as ascending ids, the first `capacity` of
+// them into d_ids, and their number into *d_count (device pointers).
+void plain_set(khop_graph *g, PlainCtx *c, int32_t seed, int32_t *d_ids, int64_t capacity, int64_t *d_count,
+               hipStream_t st);
 
 // abi.cpp: batched launches of a seed set (seeds on the device, ks on the host), pooled contexts
 void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int64_t num, int64_t *d_counts,

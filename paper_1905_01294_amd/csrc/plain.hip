@@ -81,6 +81,8 @@ struct PlainCtl {
     int32_t last_bytes;  // the last hop left byte marks (counted by the next query's hop 1)
     int32_t reached;     // largest level found non-empty so far (the seed's is 0)
     int32_t more;        // breadth-first search: the level the last probe read is non-empty
+    int64_t *level_out;  // breadth-first search: size of each level 1..level_cap (else null)
+    int64_t level_cap;
     int64_t seed_beg;    // the seed's first out-edge, its out- and in-degree (hop 1 reads them)
     int64_t seed_od;
     int64_t seed_id;
@@ -287,6 +289,8 @@ __device__ void setup_query(PlainCtl *ctl, const Graph &g, const State &s, int32
     ctl->last_bytes = 0;
     ctl->reached = 0;
     ctl->more = 1;
+    ctl->level_out = nullptr;
+    ctl->level_cap = 0;
     ctl->push_atomic_max = push_atomic_max;
     ctl->count_acc = 0;
     ctl->te_acc = 0;
@@ -839,6 +843,7 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
         if (last) ctl->last_bytes = mode == MODE_PUSH_BYTES;
         if (L >= 2) ctl->count_acc += nf;
         if (nf > 0) ctl->reached = L - 1;
+        if (L >= 2 && L - 1 <= ctl->level_cap) ctl->level_out[L - 2] = nf;
         ctl->te_acc += E;
         if (units) unit_add(units, 0, 16 * s.nreg);
     }
@@ -978,22 +983,31 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
 // distance l, written once by the wave or lane whose claim (atomicOr on its
 // visited word, or the ballot of a word's fresh bits) found it.
 
-// Set-up: the distance vector (0 at the seed, -1 elsewhere), the visited and
-// frontier bitmaps, and the control record with no last hop.
+// Set-up: the distance vector when there is one (0 at the seed, -1
+// elsewhere), the level sizes when asked for (zero), the visited and frontier
+// bitmaps, and the control record with no last hop.
 __global__ void __launch_bounds__(kBlock) plain_bfs_init_kernel(PlainCtl *ctl, Graph g, State s, int32_t seed,
-                                                               int dir_mode, int alpha, int beta,
-                                                               int64_t push_atomic_max, int64_t nnz_in,
-                                                               int64_t *units) {
+                                                               int64_t *levels, int64_t level_cap, int dir_mode,
+                                                               int alpha, int beta, int64_t push_atomic_max,
+                                                               int64_t nnz_in, int64_t *units) {
     const int64_t sw = seed >> 6;
     const uint64_t sbit = 1ull << (seed & 63);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += stride) reset_word(s, w, sw, sbit);
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < g.n; v += stride)
-        s.dist[v] = v == seed ? 0 : -1;
-    if (blockIdx.x == 0)
+    const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int64_t w = t0; w < g.nw; w += stride) reset_word(s, w, sw, sbit);
+    if (s.dist)
+        for (int64_t v = t0; v < g.n; v += stride) s.dist[v] = v == seed ? 0 : -1;
+    if (levels)
+        for (int64_t l = t0; l < level_cap; l += stride) levels[l] = 0;
+    if (blockIdx.x == 0) {
         setup_query(ctl, g, s, seed, 0, INT32_MAX, dir_mode, alpha, beta, push_atomic_max, nnz_in, nullptr, nullptr,
                     units);
-    if (units && blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, 4 * g.n);
+        if (threadIdx.x == 0) {
+            ctl->level_out = levels;
+            ctl->level_cap = levels ? level_cap : 0;
+            if (units && s.dist) unit_add(units, 0, 4 * g.n);
+        }
+    }
 }
 
 // After hop L (one wave): whether level L is non-empty (ctl->more), the
@@ -1012,8 +1026,82 @@ __global__ void __launch_bounds__(kWave) plain_bfs_probe_kernel(PlainCtl *ctl, S
     const int32_t depth = nf > 0 ? L : ctl->reached;
     ctl->reached = depth;
     ctl->more = nf > 0;
+    if (L >= 1 && L <= ctl->level_cap) ctl->level_out[L - 1] = nf;
     if (out_count) *out_count = ctl->count_acc + nf;
     if (out_depth) *out_depth = depth;
+}
+
+// ------------------------------------------------------------------ the neighborhood as vertex ids
+
+// After a search with no last hop, the visited bitmap is {v : dist <= depth};
+// without the seed's bit it is the k-hop neighborhood.  Three launches turn it
+// into ascending vertex ids: per-block popcounts of kBlock words, one block
+// scanning those into offsets, and a write in which each wave takes 64 words,
+// one at a time, and its lanes store the word's ids side by side.
+__device__ __forceinline__ uint64_t set_word(const uint64_t *V, int64_t w, int32_t seed) {
+    const uint64_t m = V[w];
+    return w == (seed >> 6) ? m & ~(1ull << (seed & 63)) : m;
+}
+
+__device__ __forceinline__ int64_t block_exclusive_sum(int64_t v, int64_t *lds_waves, int64_t *total) {
+    const int lane = lane_id(), wv = threadIdx.x / kWave;
+    const int64_t x = wave_exclusive_sum(v);
+    if (lane == kWave - 1) lds_waves[wv] = x + v;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+    for (int i = 0; i < kWavesPerBlock; ++i) {
+        const int64_t t = lds_waves[i];
+        if (i < wv) before += t;
+        all += t;
+    }
+    __syncthreads();
+    *total = all;
+    return before + x;
+}
+
+__global__ void __launch_bounds__(kBlock) plain_set_count_kernel(const uint64_t *V, int64_t nw, int32_t seed,
+                                                                int64_t *partial) {
+    __shared__ int64_t s_w[kWavesPerBlock];
+    const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t pc = w < nw ? __popcll(set_word(V, w, seed)) : 0;
+    int64_t total = 0;
+    block_exclusive_sum(pc, s_w, &total);
+    if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// One block: exclusive prefix of the nb block counts in place, the total to *count.
+__global__ void __launch_bounds__(kBlock) plain_set_scan_kernel(int64_t *partial, int64_t nb, int64_t *count) {
+    __shared__ int64_t s_w[kWavesPerBlock];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+        const int64_t b = b0 + threadIdx.x;
+        const int64_t v = b < nb ? partial[b] : 0;
+        int64_t total = 0;
+        const int64_t x = block_exclusive_sum(v, s_w, &total);
+        if (b < nb) partial[b] = carry + x;
+        carry += total;
+    }
+    if (threadIdx.x == 0 && count) *count = carry;
+}
+
+__global__ void __launch_bounds__(kBlock) plain_set_write_kernel(const uint64_t *V, int64_t nw, int32_t seed,
+                                                                const int64_t *offsets, int32_t *ids, int64_t cap) {
+    __shared__ int64_t s_w[kWavesPerBlock];
+    const int lane = lane_id();
+    const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t m = w < nw ? set_word(V, w, seed) : 0;
+    int64_t total = 0;
+    const int64_t pos = offsets[blockIdx.x] + block_exclusive_sum(__popcll(m), s_w, &total);
+    const int64_t w0 = w - lane;  // the wave's first word
+    for (int j = 0; j < kWave; ++j) {
+        const uint64_t mj = (uint64_t)shfl64((int64_t)m, j);
+        const int64_t pj = shfl64(pos, j);
+        if (!mj || pj >= cap) continue;  // wave-uniform
+        if ((mj >> lane) & 1ull) {
+            const int64_t at = pj + __popcll(mj & ((1ull << lane) - 1));
+            if (at < cap) ids[at] = (int32_t)((w0 + j) * kWave + lane);
+        }
+    }
 }
 
 __global__ void fill_kernel(int64_t *a, int64_t *b, int64_t n, int64_t value) {
@@ -1032,6 +1120,8 @@ struct PlainCtx {
     int hop_grid = 1;
     int init_grid = 1;
     int compact_grid = 1;
+    int64_t *set_partial = nullptr;  // block counts, then offsets, of the neighborhood-set kernels
+    int64_t set_blocks = 0;
     void *arena = nullptr;
 };
 
@@ -1062,6 +1152,9 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
         o_regs[p] = off;
         off += al((size_t)3 * nreg * sizeof(RegRec));
     }
+    const int64_t set_blocks = (nw + kBlock - 1) / kBlock;
+    const size_t o_part = off;
+    off += al((size_t)set_blocks * 8);
     size_t o_q[2], o_qoff[2];
     for (int i = 0; i < 2; ++i) {
         o_q[i] = off;
@@ -1077,6 +1170,8 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     }
     char *base = (char *)c->arena;
     c->ctl = (PlainCtl *)(base + o_ctl);
+    c->set_partial = (int64_t *)(base + o_part);
+    c->set_blocks = set_blocks;
     for (int p = 0; p < 2; ++p) {
         State &st = c->s[p];
         st.V = (uint64_t *)(base + o_V[p]);
@@ -1176,7 +1271,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
 }
 
 void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int32_t *d_dist, int64_t *d_count,
-               int32_t *d_depth, int32_t *h_flags, hipStream_t st) {
+               int32_t *d_depth, int64_t *d_levels, int64_t level_cap, int32_t *h_flags, hipStream_t st) {
     const Params &P = g->params;
     const HeavyTable &ht = plain_heavy_table(g);
     Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
@@ -1189,8 +1284,8 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
     PlainCtl *ctl = c->ctl;
     {
         ProfScope ps(g, KK_PLAIN_INIT, st);
-        hipLaunchKernelGGL(plain_bfs_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, s, seed,
-                           P.dir_mode, P.alpha, P.beta, pam, g->nnz, ps.units());
+        hipLaunchKernelGGL(plain_bfs_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, s, seed, d_levels,
+                           d_levels ? level_cap : (int64_t)0, P.dir_mode, P.alpha, P.beta, pam, g->nnz, ps.units());
         ps.end(0, 1);
     }
     const int64_t limit = max_depth < 0 ? INT32_MAX : max_depth;
@@ -1233,6 +1328,19 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
         group = std::min<int64_t>(2 * group, 1024);
     }
     hipLaunchKernelGGL(plain_bfs_probe_kernel, dim3(1), dim3(kWave), 0, st, ctl, s, (int)H, d_count, d_depth);
+    KHOP_HIP(hipGetLastError());
+}
+
+void plain_set(khop_graph *g, PlainCtx *c, int32_t seed, int32_t *d_ids, int64_t capacity, int64_t *d_count,
+               hipStream_t st) {
+    const int64_t nw = (g->n + 63) / 64;
+    const int64_t nb = c->set_blocks;
+    const uint64_t *V = c->s[0].V;
+    hipLaunchKernelGGL(plain_set_count_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, V, nw, seed, c->set_partial);
+    hipLaunchKernelGGL(plain_set_scan_kernel, dim3(1), dim3(kBlock), 0, st, c->set_partial, nb, d_count);
+    if (capacity > 0 && d_ids)
+        hipLaunchKernelGGL(plain_set_write_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, V, nw, seed,
+                           (const int64_t *)c->set_partial, d_ids, capacity);
     KHOP_HIP(hipGetLastError());
 }
 
