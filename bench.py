@@ -226,6 +226,7 @@ def main():
 
     sweep = None if args.no_sweep else batched_sweep(g, el, K, torch)
     bfs = None if args.no_bfs else bfs_bench(g, el, K, torch, cpu_leg=not args.no_cpu_baseline)
+    sets = None if args.no_bfs else sets_bench(g, el, groups, K, torch, cpu_leg=not args.no_cpu_baseline)
     g2 = el2 = None
     power_law = None
     if args.twitter:
@@ -305,6 +306,7 @@ def main():
         "batched_sweep": sweep,
         "serving": serving,
         "bfs": bfs,
+        "neighborhood_sets": sets,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
@@ -515,6 +517,74 @@ def bfs_bench(g, el, K, torch, n_seeds=64, cpu_leg=True):
             equal = equal and bool(np.array_equal(d_dist.cpu().numpy(), ref))
         out["cpu_oracle"] = {"searches": 2, "cores": 1, "ms_per_search": round(float(np.mean(c_ms)), 1),
                              "gteps": round(sum(te[:2]) / (sum(c_ms) / 1e3) / 1e9, 4), "distances_equal_gpu": equal}
+    return out
+
+
+def sets_bench(g, el, groups, K, torch, cpu_leg=True):
+    """The k = 2 neighborhoods of the protocol's 300 k = 2 seeds returned as
+    vertex ids (device-resident and through the host entry point), and the
+    exactly-l level sizes of its 10 k = 6 seeds."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    seeds = dict(groups)[2]
+    deep = dict(groups)[6]
+    d_ids = torch.empty(g.n, dtype=torch.int32, device=dev)
+    d_count = torch.empty(1, dtype=torch.int64, device=dev)
+    d_lv = torch.empty(6, dtype=torch.int64, device=dev)
+    sizes = []
+    for s in seeds:
+        g.neighborhood_dev(int(s), 2, d_ids, d_count, stream=stream)
+        sizes.append(int(d_count.item()))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for s in seeds:
+        g.neighborhood_dev(int(s), 2, d_ids, d_count, stream=stream)
+    ev[1].record(stream)
+    ev[1].synchronize()
+    dev_ms = ev[0].elapsed_time(ev[1]) / len(seeds)
+    ev[0].record(stream)
+    for s in deep:
+        g.levels_dev(int(s), 6, d_lv, stream=stream)
+    ev[1].record(stream)
+    ev[1].synchronize()
+    lv_ms = ev[0].elapsed_time(ev[1]) / len(deep)
+    # the set kernels' own time and bytes
+    g.profile(True)
+    for s in seeds[:32]:
+        g.neighborhood_dev(int(s), 2, d_ids, d_count, stream=stream)
+    torch.cuda.synchronize()
+    kern = g.profile_read()
+    g.profile(False)
+    empty = kern.pop("empty_launch", None)
+    overhead_us = 1000.0 * empty["total_ms"] / empty["launches"] if empty and empty["launches"] else 0.0
+    st = kern.get("plain_set", {"launches": 0})
+    set_us = max(1000.0 * st["total_ms"] / st["launches"] - overhead_us, 0.0) if st["launches"] else 0.0
+    set_gbs = st["algorithmic_bytes"] / st["launches"] / (set_us * 1e-6) / 1e9 if set_us > 0 else 0.0
+    # through the host entry point: ids copied to host memory
+    host = []
+    for s in seeds[:100]:
+        t = time.perf_counter()
+        ids = g.neighborhood(int(s), 2)
+        host.append((time.perf_counter() - t) * 1000.0)
+    out = {"k": 2, "seeds": len(seeds), "ids_mean": round(float(np.mean(sizes)), 1), "ids_max": int(max(sizes)),
+           "device_ms_per_query": round(dev_ms, 4), "device_ids_per_s": round(float(np.sum(sizes)) / (dev_ms * len(seeds) / 1e3), 1),
+           "set_kernels": {"avg_us": round(set_us, 3), "gbs": round(set_gbs, 1),
+                           "bytes": "visited bitmap read twice, block counts, 4 B per id written"},
+           "host_api_p50_ms": round(pct(host, 50), 4), "host_api_p99_ms": round(pct(host, 99), 4),
+           "levels_k6_ms_per_query": round(lv_ms, 4)}
+    log(f"sets: k=2 {out['ids_mean']} ids per query, {out['device_ms_per_query']} ms device, "
+        f"{out['host_api_p50_ms']} ms host p50; set kernels {out['set_kernels']}")
+    if cpu_leg:
+        import oracle
+        og = oracle.OracleGraph.from_edgelist(el)
+        equal = True
+        for s in seeds[:3]:
+            d = og.distances(int(s), 2)
+            equal = equal and bool(np.array_equal(g.neighborhood(int(s), 2), np.nonzero(d >= 1)[0]))
+        for s in deep[:2]:
+            equal = equal and bool(np.array_equal(g.levels(int(s), 6), og.khop(int(s), 6)[2]))
+        out["equal_oracle"] = equal
     return out
 
 

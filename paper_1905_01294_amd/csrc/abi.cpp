@@ -25,7 +25,7 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line) {
 
 const char *const kKernelNames[KK_COUNT_KINDS] = {
     "plain_init", "plain_hop", "plain_compact", "batch_init", "batch_push", "batch_pull", "batch_pull_heavy",
-    "batch_count", "empty_launch"};
+    "batch_count", "plain_set", "empty_launch"};
 
 template <class F>
 static int guard(F &&f) {

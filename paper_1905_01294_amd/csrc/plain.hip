@@ -1085,7 +1085,8 @@ __global__ void __launch_bounds__(kBlock) plain_set_scan_kernel(int64_t *partial
 }
 
 __global__ void __launch_bounds__(kBlock) plain_set_write_kernel(const uint64_t *V, int64_t nw, int32_t seed,
-                                                                const int64_t *offsets, int32_t *ids, int64_t cap) {
+                                                                const int64_t *offsets, int32_t *ids, int64_t cap,
+                                                                int64_t *units) {
     __shared__ int64_t s_w[kWavesPerBlock];
     const int lane = lane_id();
     const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1101,6 +1102,11 @@ __global__ void __launch_bounds__(kBlock) plain_set_write_kernel(const uint64_t 
             const int64_t at = pj + __popcll(mj & ((1ull << lane) - 1));
             if (at < cap) ids[at] = (int32_t)((w0 + j) * kWave + lane);
         }
+    }
+    if (units) {
+        // 4 B per id written
+        const int64_t written = wave_sum(std::min<int64_t>(pos + __popcll(m), cap) - std::min(pos, cap));
+        if (lane == 0) unit_add(units, 0, 4 * written);
     }
 }
 
@@ -1336,11 +1342,15 @@ void plain_set(khop_graph *g, PlainCtx *c, int32_t seed, int32_t *d_ids, int64_t
     const int64_t nw = (g->n + 63) / 64;
     const int64_t nb = c->set_blocks;
     const uint64_t *V = c->s[0].V;
+    ProfScope ps(g, KK_PLAIN_SET, st);
     hipLaunchKernelGGL(plain_set_count_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, V, nw, seed, c->set_partial);
     hipLaunchKernelGGL(plain_set_scan_kernel, dim3(1), dim3(kBlock), 0, st, c->set_partial, nb, d_count);
-    if (capacity > 0 && d_ids)
+    const bool write = capacity > 0 && d_ids;
+    if (write)
         hipLaunchKernelGGL(plain_set_write_kernel, dim3((unsigned)nb), dim3(kBlock), 0, st, V, nw, seed,
-                           (const int64_t *)c->set_partial, d_ids, capacity);
+                           (const int64_t *)c->set_partial, d_ids, capacity, ps.units());
+    // the visited bitmap read once per pass, the block counts written, scanned and read
+    ps.end((double)(write ? 2 : 1) * 8.0 * (double)nw + (write ? 4.0 : 2.0) * 8.0 * (double)nb, 1);
     KHOP_HIP(hipGetLastError());
 }
 
