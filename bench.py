@@ -66,7 +66,11 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the batched seeds-per-launch sweep")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--no-bfs", action="store_true", help="skip the full-depth breadth-first search measurement")
+    ap.add_argument("--no-bfs", action="store_true",
+                    help="skip the breadth-first search, neighborhood-set and level measurements")
+    ap.add_argument("--only-bfs", action="store_true",
+                    help="print only the breadth-first search, neighborhood-set and level measurements (one JSON "
+                         "line, not the benchmark line)")
     ap.add_argument("--twitter", action="store_true",
                     help="also load the 41.6M-vertex power-law graph and serve both graphs")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per offered-load level")
@@ -111,6 +115,13 @@ def main():
                 ("pull_heavy", K.KHOP_OPT_PULL_HEAVY), ("push_atomic", K.KHOP_OPT_PUSH_ATOMIC),
                 ("batch_seeds", K.KHOP_OPT_BATCH_SEEDS),
                 ("batch_heavy", K.KHOP_OPT_BATCH_HEAVY))))
+
+    if args.only_bfs:
+        cpu_leg = not args.no_cpu_baseline
+        print(json.dumps({"bfs": bfs_bench(g, el, K, torch, cpu_leg=cpu_leg),
+                          "neighborhood_sets": sets_bench(g, el, groups, K, torch, cpu_leg=cpu_leg)}), flush=True)
+        g.free()
+        return
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
