@@ -187,15 +187,44 @@ __device__ __forceinline__ uint64_t group_any(uint64_t m) {
     }
 }
 
+// The frontier word of vertex u that lane word wi gathers.  With one-word
+// rows whose active seeds all sit in the low 16 or 32 bits, the bottom-up
+// kernels read a narrow copy Fs instead (fs_bits = 16 or 32, else 0): a hit
+// then costs 2 or 4 bytes of a line shared by 64 or 32 vertices, and the copy
+// (4 or 8 MB for two million vertices) stays far more in L2 than F does.
+template <int FS>
+__device__ __forceinline__ uint64_t frontier_word(const uint64_t *__restrict__ F, const void *__restrict__ Fs,
+                                                  int64_t u, int W, int wi) {
+    if constexpr (FS == 16) return ((const uint16_t *)Fs)[u];
+    else if constexpr (FS == 32) return ((const uint32_t *)Fs)[u];
+    else return F[u * W + wi];
+}
+
+// Builds that narrow copy of a one-word frontier (bits = 16 or 32); it exits
+// at once when the hop went top-down or the frontier is empty.
+__global__ void __launch_bounds__(kBlock) batch_frontier_copy_kernel(const uint64_t *__restrict__ F, int64_t n,
+                                                                    void *Fs, int bits, const int32_t *mode, int L,
+                                                                    const int32_t *prev_flag) {
+    if (*prev_flag == 0) return;
+    if (mode && mode[L] == HOP_PUSH) return;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
+        const uint64_t x = F[v];
+        if (bits == 16) ((uint16_t *)Fs)[v] = (uint16_t)x;
+        else ((uint32_t *)Fs)[v] = (uint32_t)x;
+    }
+}
+
 // Hop >= 2, light vertices: G lanes per vertex (lane word = lane % G).  Each
 // step the group's lanes read R rounds of G consecutive in-edges and test them
 // against the frontier bitmap Fbc; for every hit the G lanes gather their
-// words of F[u].  Vertices with a new bit are marked in Fbn; Fbz (the bitmap
-// of the hop after this one) is cleared on the way.
-template <int G>
+// words of F[u] (of the narrow copy Fs when FS is 16 or 32).  Vertices with a
+// new bit are marked in Fbn; Fbz (the bitmap of the hop after this one) is
+// cleared on the way.
+template <int G, int FS = 0>
 __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__restrict__ in_rowptr,
                                                            const int32_t *__restrict__ in_colidx,
                                                            uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
+                                                           const void *__restrict__ Fs,
                                                            uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
                                                            const uint64_t *__restrict__ act, int heavy,
                                                            FrontierBits fb, const int32_t *mode, int L,
@@ -254,7 +283,7 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
 #pragma unroll
                 for (int r = 0; r < R; ++r)
                     if (hit[r]) {
-                        acc |= F[(int64_t)u[r] * W];
+                        acc |= frontier_word<FS>(F, Fs, u[r], W, 0);
                         ++gathered;
                     }
             } else {
@@ -322,10 +351,11 @@ __device__ __forceinline__ uint64_t subgroup_or(uint64_t v) {
 // wave tests 64 in-edges per round against the frontier bitmap, packs the hits
 // of four rounds in LDS and gathers their words with 64/G streams of G lanes;
 // the chunk's findings are ORed into the vertex's next-frontier and visited
-// words atomically (the light kernel left zeros).
-template <int G>
+// words atomically (the light kernel left zeros).  FS as in the light kernel.
+template <int G, int FS = 0>
 __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
-    const int32_t *__restrict__ in_colidx, uint64_t *V, const uint64_t *__restrict__ F, uint64_t *Fn, int W, int wact,
+    const int32_t *__restrict__ in_colidx, uint64_t *V, const uint64_t *__restrict__ F, const void *__restrict__ Fs,
+    uint64_t *Fn, int W, int wact,
     const uint64_t *__restrict__ act, const int32_t *__restrict__ hvert, const int64_t *__restrict__ hbegin,
     const int64_t *__restrict__ hend, int64_t n_items, int64_t n, FrontierBits fb, const int32_t *mode, int L,
     const int32_t *prev_flag, int32_t *flag, int64_t *units) {
@@ -360,7 +390,7 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int64_t x = x0 + r * S + sg;
-                    if (x < e && wi < wact) acc |= F[(int64_t)in_colidx[x] * W + wi];
+                    if (x < e && wi < wact) acc |= frontier_word<FS>(F, Fs, in_colidx[x], W, wi);
                 }
                 examined += std::min<int64_t>(4 * S, e - x0);
                 const uint64_t full = subgroup_or<G>(acc);
@@ -390,7 +420,7 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             if (wi < wact)
-                for (int j = sg; j < nh; j += S) acc |= F[(int64_t)s_hit[wv][j] * W + wi];
+                for (int j = sg; j < nh; j += S) acc |= frontier_word<FS>(F, Fs, s_hit[wv][j], W, wi);
             gathered += nh;
             examined += std::min<int64_t>(4 * kWave, e - x0);
             // the row is rewritten next round only after every lane has read it
@@ -688,6 +718,7 @@ struct BatchCtx {
     khop_graph *g = nullptr;
     int W = 0;  // words per vertex (1..16)
     uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
+    void *Fs = nullptr;        // narrow copy of a one-word frontier (n uint16 or uint32)
     uint64_t *Fb = nullptr;    // three frontier bitmaps of nw words each (hop l uses slot l % 3)
     int64_t *Fc = nullptr;     // their set-bit counts, 64 lanes each
     int64_t *acc = nullptr;    // 64 * W counters
@@ -725,6 +756,8 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     off += bits;
     const size_t oFb = off;
     off += al(3 * (size_t)((n + 63) / 64) * 8);
+    const size_t oFs = off;
+    off += al((size_t)n * 4);
     const size_t oFc = off;
     off += al(3 * kCntLanes * 8);
     const size_t oacc = off;
@@ -760,6 +793,7 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     c->F = (uint64_t *)(b + oF);
     c->N = (uint64_t *)(b + oN);
     c->Fb = (uint64_t *)(b + oFb);
+    c->Fs = (void *)(b + oFs);
     c->Fc = (int64_t *)(b + oFc);
     c->acc = (int64_t *)(b + oacc);
     c->act = (uint64_t *)(b + oact);
@@ -800,7 +834,7 @@ int batch_ctx_words(const BatchCtx *c) { return c->W; }
 
 template <int G>
 static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hipStream_t st, uint64_t *V, uint64_t *F,
-                        uint64_t *Fn) {
+                        uint64_t *Fn, int fs_bits) {
     const int64_t n = g->n, nw = (n + 63) / 64;
     const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
@@ -810,22 +844,27 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
                           c->Fc + ((L - 1) % 3) * kCntLanes, c->Fc + (L % 3) * kCntLanes, c->Fc + ((L + 1) % 3) * kCntLanes};
     {
         ProfScope ps(g, KK_BATCH_PULL, st);
-        hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx,
-                           V, F, Fn, n, Wr, wact, act, batch_heavy_table(g).threshold, fb, c->mode, L,
+        auto k = fs_bits == 16 ? batch_pull_kernel<G, 16> : fs_bits == 32 ? batch_pull_kernel<G, 32>
+                                                                           : batch_pull_kernel<G, 0>;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, V, F,
+                           (const void *)c->Fs, Fn, n, Wr, wact, act, batch_heavy_table(g).threshold, fb, c->mode, L,
                            c->flags + (L - 1), c->flags + L, ps.units());
         // bytes: V read and write-back and Fn write per active word, the frontier bitmap once,
-        // 4 per examined in-edge, 16 per scanned vertex, 8 per gathered word
-        ps.end(3.0 * 8.0 * (double)n * wact + 2.0 * 8.0 * nw, 0, 4.0, 16.0, 8.0 * wact);
+        // 4 per examined in-edge, 16 per scanned vertex, 8 per gathered word (fs_bits / 8 from the narrow copy)
+        const double gw = fs_bits ? fs_bits / 8.0 : 8.0 * wact;
+        ps.end(3.0 * 8.0 * (double)n * wact + 2.0 * 8.0 * nw, 0, 4.0, 16.0, gw);
     }
     const HeavyTable &ht = batch_heavy_table(g);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         ProfScope ps(g, KK_BATCH_PULL_HEAVY, st);
-        hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, V, F, Fn,
-                           Wr, wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->mode, L,
-                           c->flags + (L - 1), c->flags + L, ps.units());
-        ps.end(16.0 * (double)ht.n, 0, 4.0, 0, 8.0 * wact);
+        auto k = fs_bits == 16 ? batch_pull_heavy_kernel<G, 16> : fs_bits == 32 ? batch_pull_heavy_kernel<G, 32>
+                                                                                 : batch_pull_heavy_kernel<G, 0>;
+        hipLaunchKernelGGL(k, dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, V, F, (const void *)c->Fs, Fn, Wr,
+                           wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->mode, L, c->flags + (L - 1),
+                           c->flags + L, ps.units());
+        ps.end(16.0 * (double)ht.n, 0, 4.0, 0, fs_bits ? fs_bits / 8.0 : 8.0 * wact);
     }
 }
 
@@ -938,13 +977,32 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         int G = 1;
         while (G < wa) G <<= 1;
         switch (G) {
-            case 1: launch_push<1>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<1>(g, c, L, wa, Wr, st, V, F, Nb); break;
-            case 2: launch_push<2>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<2>(g, c, L, wa, Wr, st, V, F, Nb); break;
-            case 4: launch_push<4>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<4>(g, c, L, wa, Wr, st, V, F, Nb); break;
-            case 8: launch_push<8>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<8>(g, c, L, wa, Wr, st, V, F, Nb); break;
+            case 1: {
+                launch_push<1>(g, c, L, wa, Wr, st, V, F, Nb);
+                // one-word rows whose active seeds fit in 16 or 32 bits are gathered from a narrow copy
+                int fs_bits = 0;
+                if (Wr == 1) {
+                    const uint64_t a = act[(size_t)(L - 1) * W];
+                    const int top = a ? 63 - __builtin_clzll(a) : 0;
+                    fs_bits = top < 16 ? 16 : top < 32 ? 32 : 0;
+                }
+                if (fs_bits) {
+                    ProfScope ps(g, KK_BATCH_INIT, st);
+                    const int cg = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock,
+                                                                               (int64_t)g->cu_count * 8));
+                    hipLaunchKernelGGL(batch_frontier_copy_kernel, dim3(cg), dim3(kBlock), 0, st, F, n, c->Fs, fs_bits,
+                                       c->mode, L, c->flags + (L - 1));
+                    ps.end(8.0 * n + n * fs_bits / 8.0);
+                }
+                launch_pull<1>(g, c, L, wa, Wr, st, V, F, Nb, fs_bits);
+                break;
+            }
+            case 2: launch_push<2>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<2>(g, c, L, wa, Wr, st, V, F, Nb, 0); break;
+            case 4: launch_push<4>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<4>(g, c, L, wa, Wr, st, V, F, Nb, 0); break;
+            case 8: launch_push<8>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<8>(g, c, L, wa, Wr, st, V, F, Nb, 0); break;
             default:
                 launch_push<16>(g, c, L, wa, Wr, st, V, F, Nb);
-                launch_pull<16>(g, c, L, wa, Wr, st, V, F, Nb);
+                launch_pull<16>(g, c, L, wa, Wr, st, V, F, Nb, 0);
                 break;
         }
         std::swap(F, Nb);
@@ -1114,14 +1172,14 @@ static void serve_hop(ServeCtx *c, int wact, hipStream_t st) {
                        serve_queue(c, i0), serve_queue(c, i1), serve_queue(c, i2), fb, c->d_mode, 1, 0, c->d_one,
                        c->d_one + 1, nullptr);
     hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
-                       c->F, c->N, n, c->W, wact, c->d_act, ht.threshold, fb, c->d_mode, 1, c->d_one, c->d_one + 1,
-                       nullptr);
+                       c->F, (const void *)nullptr, c->N, n, c->W, wact, c->d_act, ht.threshold, fb, c->d_mode, 1,
+                       c->d_one, c->d_one + 1, nullptr);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
-                           c->N, c->W, wact, c->d_act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->d_mode, 1,
-                           c->d_one, c->d_one + 1, nullptr);
+                           (const void *)nullptr, c->N, c->W, wact, c->d_act, ht.d_vert, ht.d_begin, ht.d_end,
+                           ht.n, n, fb, c->d_mode, 1, c->d_one, c->d_one + 1, nullptr);
     }
     const int qgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kWavesPerBlock - 1) / kWavesPerBlock,
                                                                   (int64_t)g->cu_count * 8));
