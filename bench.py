@@ -458,6 +458,24 @@ def power_law_bench(g2, el2, K, torch):
     out["batch256_k3"] = {"seeds": 256, "ms": round(ms, 3), "qps": round(256 / (ms / 1e3), 1),
                           "gteps": round(int(dte.sum()) / (ms / 1e3) / 1e9, 3),
                           "equal_to_plain": bool(torch.equal(c, dp))}
+    # full-depth breadth-first distances from 8 of the 300 seeds
+    deg = g2.degrees()
+    d_dist = torch.empty(g2.n, dtype=torch.int32, device=dev)
+    d_depth = torch.empty(1, dtype=torch.int32, device=dev)
+    bte, bdepth, bms = [], [], []
+    for s in s300[:8]:
+        g2.bfs_dev(int(s), d_dist, -1, None, d_depth)
+        dist = d_dist.cpu().numpy()
+        bte.append(int(deg[dist >= 0].sum()))
+        bdepth.append(int(d_depth.item()))
+        e0.record()
+        g2.bfs_dev(int(s), d_dist, -1)
+        e1.record()
+        e1.synchronize()
+        bms.append(e0.elapsed_time(e1))
+    out["bfs"] = {"seeds": 8, "ms_per_search": round(float(np.mean(bms)), 3), "p50_ms": round(pct(bms, 50), 3),
+                  "gteps": round(sum(bte) / (sum(bms) / 1e3) / 1e9, 2), "depth_mean": round(float(np.mean(bdepth)), 2),
+                  "teps_edges": "stored out-arcs of every reached vertex"}
     log("power-law graph: " + json.dumps(out))
     return out
 

@@ -72,3 +72,18 @@ def test_batched_256_at_k3(g2):
     b = g.count_batched(s256, np.full(256, 3))
     assert np.array_equal(b, g.count(s256, 3))
     assert np.array_equal(b[:3], og.count(s256[:3], 3)[0])
+
+
+def test_full_depth_distances_and_sets(g2):
+    """Breadth-first distances with no depth limit, level sizes and a k = 2
+    neighborhood as ids, each against the oracle, from two seeds."""
+    el, g, og, seeds, _, K = g2
+    for s in seeds[:2]:
+        t = time.time()
+        dist, count, depth = g.bfs(int(s))
+        _say("bfs seed", int(s), "depth", depth, "reach", count + 1, round(time.time() - t, 2), "s")
+        ref = og.distances(int(s), 2**31 - 1)
+        assert np.array_equal(dist, ref)
+        assert count == int((ref > 0).sum()) and depth == int(ref.max())
+        assert np.array_equal(g.levels(int(s), 6), og.khop(int(s), 6)[2])
+        assert np.array_equal(g.neighborhood(int(s), 2), np.nonzero((ref >= 1) & (ref <= 2))[0])
