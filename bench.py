@@ -741,6 +741,7 @@ def serving_bench(K, graphs, seconds):
         got = collect(n)
         lat = []
         by_gk = {}
+        single = 0
         done_last = 0
         for t, (due, i) in tick.items():
             r = got.get(t)
@@ -748,6 +749,7 @@ def serving_bench(K, graphs, seconds):
                 continue
             ms = (r.t_done_ns - due) / 1e6
             lat.append(ms)
+            single += r.path == K.KHOP_PATH_SINGLE
             by_gk.setdefault(f"{graphs[qs[i][0]][0]}_k{qs[i][2]}", []).append(ms)
             done_last = max(done_last, r.t_done_ns)
             if len(check) < 400 and i % 25 == 0:
@@ -756,6 +758,7 @@ def serving_bench(K, graphs, seconds):
         levels.append({"offered_qps": round(qps, 1), "achieved_qps": round(len(lat) / span, 1), "n": n,
                        "completed": len(lat), "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
                        "mean_ms": round(float(np.mean(lat)), 3),
+                       "single_query_share": round(single / max(len(lat), 1), 3),
                        "by_graph_k": {key: {"n": len(v), "p50_ms": round(pct(v, 50), 3), "p99_ms": round(pct(v, 99), 3)}
                                       for key, v in sorted(by_gk.items())}})
         log(f"serving at {qps:.0f} q/s offered: p50 {levels[-1]['p50_ms']} ms, p99 {levels[-1]['p99_ms']} ms")

@@ -229,9 +229,12 @@ typedef struct {
     int32_t k;
     int64_t count;
     int64_t t_submit_ns;  /* CLOCK_MONOTONIC at submission */
-    int64_t t_admit_ns;   /* when the request's seed bit entered a running batch */
+    int64_t t_admit_ns;   /* when its seed bit entered a running batch, or its single-query group started */
     int64_t t_done_ns;    /* when its count reached the host */
+    int32_t path;         /* KHOP_PATH_BATCH or KHOP_PATH_SINGLE: what answered it */
+    int32_t reserved;     /* 0 */
 } khop_result;
+enum { KHOP_PATH_BATCH = 0, KHOP_PATH_SINGLE = 1 };
 
 /*
  * A continuous-batching server for k-hop queries (the throughput-oriented
@@ -241,7 +244,18 @@ typedef struct {
  * boundaries, while the batch keeps advancing.  Each graph runs two such
  * batches, one for queries with k <= 2 and one for deeper ones, each on its
  * own HIP stream, so short queries do not wait behind deep ones and work for
- * different graphs overlaps on the device.
+ * different graphs overlaps on the device.  Each graph also has a
+ * single-query lane on a third stream that answers queries one at a time
+ * through the plain path (the paper's one query per worker), in groups of
+ * one k.  A single query costs more device time than its share of a batch,
+ * so that lane takes arrivals only while the device time it would need stays
+ * low (decayed sums over about 5 ms of the arrivals' measured single-query
+ * costs: cheap queries, up to 0.05 ms, while theirs stays under half the
+ * device; dearer ones while all arrivals' stays under the whole, with
+ * hysteresis) and its backlog would still answer before k + 1 measured batch
+ * iterations.  So queries get the single-query latency at low load and the
+ * batches' throughput at high load; khop_result.path says which answered,
+ * and khop_server_set_option can force one path.
  * mem_budget_bytes bounds the bitset memory of all running batches (each
  * 64 slots of a graph with n vertices and nnz arcs take 3 * 8 * n bytes, and
  * each batch 3 * 8 * ceil(n / 64) bytes of frontier bitmaps plus
@@ -250,8 +264,20 @@ typedef struct {
  * the slots of one batch.
  */
 int khop_server_create(int64_t mem_budget_bytes, int32_t max_batch_seeds, khop_server **out);
-/* Register a loaded graph (borrowed; it must outlive the server). */
+/*
+ * Register a loaded graph (borrowed; it must outlive the server).  Its
+ * single-query lane's state (about 35 bytes per vertex: bitmaps, byte marks
+ * and frontier queues) is allocated here, outside mem_budget_bytes.
+ */
 int khop_server_add_graph(khop_server *s, khop_graph *g, int32_t *graph_id);
+
+/* Server options. */
+enum khop_server_option {
+    KHOP_SERVER_ROUTE = 1 /* KHOP_ROUTE_AUTO (default), KHOP_ROUTE_BATCH or KHOP_ROUTE_PLAIN */
+};
+enum { KHOP_ROUTE_AUTO = 0, KHOP_ROUTE_BATCH = 1, KHOP_ROUTE_PLAIN = 2 };
+/* Set a server option; it applies to requests submitted afterwards.  Unknown option or value -> KHOP_EINVAL. */
+int khop_server_set_option(khop_server *s, int32_t option, int64_t value);
 /* Queue one query; deadline_ns is an absolute CLOCK_MONOTONIC time, 0 = none. */
 int khop_server_submit(khop_server *s, int32_t graph_id, int32_t seed, int32_t k, int64_t deadline_ns,
                        uint64_t *ticket);

@@ -44,13 +44,19 @@ KHOP_OPT_PUSH_ATOMIC = 9
 KHOP_DIR_AUTO = 0
 KHOP_DIR_PUSH = 1
 KHOP_DIR_PULL = 2
+KHOP_SERVER_ROUTE = 1
+KHOP_ROUTE_AUTO = 0
+KHOP_ROUTE_BATCH = 1
+KHOP_ROUTE_PLAIN = 2
+KHOP_PATH_BATCH = 0
+KHOP_PATH_SINGLE = 1
 
 # Every entry point declared in include/khop.h.
 EXPORTS = ("graph_load_csr", "graph_free", "graph_info", "graph_degrees", "khop_count", "khop_count_dev",
            "khop_count_batched", "khop_count_batched_dev", "khop_bfs", "khop_bfs_dev", "khop_levels",
            "khop_levels_dev", "khop_neighborhood", "khop_neighborhood_dev", "khop_set_option",
            "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read", "khop_server_create", "khop_server_add_graph",
-           "khop_server_submit", "khop_server_poll", "khop_server_drain", "khop_server_destroy",
+           "khop_server_set_option", "khop_server_submit", "khop_server_poll", "khop_server_drain", "khop_server_destroy",
            "khop_last_error", "khop_version")
 
 
@@ -68,7 +74,8 @@ class KernelStat(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32), ("graph_id", ctypes.c_int32),
                 ("seed", ctypes.c_int32), ("k", ctypes.c_int32), ("count", ctypes.c_int64),
-                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
+                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+                ("path", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -116,6 +123,7 @@ def _load():
         "khop_profile_read": ([_vp, ctypes.POINTER(KernelStat), ctypes.c_int32, _i32p],),
         "khop_server_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(_vp)],),
         "khop_server_add_graph": ([_vp, _vp, _i32p],),
+        "khop_server_set_option": ([_vp, ctypes.c_int32, ctypes.c_int64],),
         "khop_server_submit": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                 ctypes.POINTER(ctypes.c_uint64)],),
         "khop_server_poll": ([_vp, ctypes.POINTER(Result), ctypes.c_int64, _i64p],),
@@ -314,6 +322,10 @@ def khop_server_add_graph(server, graph) -> int:
     return int(gid.value)
 
 
+def khop_server_set_option(server, option: int, value: int) -> None:
+    _check(_lib.khop_server_set_option(server, int(option), int(value)))
+
+
 def khop_server_submit(server, graph_id: int, seed: int, k: int, deadline_ns: int = 0) -> int:
     t = ctypes.c_uint64()
     _check(_lib.khop_server_submit(server, int(graph_id), int(seed), int(k), int(deadline_ns), ctypes.byref(t)))
@@ -427,6 +439,9 @@ class Server:
         gid = khop_server_add_graph(self._h, graph.handle)
         self._graphs.append(graph)  # keep the graph alive while served
         return gid
+
+    def set_option(self, option: int, value: int):
+        khop_server_set_option(self._h, option, value)
 
     def submit(self, graph_id: int, seed: int, k: int, deadline_ns: int = 0) -> int:
         return khop_server_submit(self._h, graph_id, seed, k, deadline_ns)

@@ -141,6 +141,7 @@ def test_small_budget_one_word(K, graphs):
 def test_deadlines_when_no_memory(K, graphs):
     (el0, _), g, o = graphs
     srv = K.Server(1024, 64)  # too small for any batch: requests wait, then time out
+    srv.set_option(K.KHOP_SERVER_ROUTE, K.KHOP_ROUTE_BATCH)  # (the single-query lane is outside the budget)
     gid = srv.add_graph(g[0])
     t = srv.submit(gid, 1, 2, deadline_ns=K.monotonic_ns() + 20_000_000)
     srv.drain(5000)
@@ -161,4 +162,54 @@ def test_k0_and_invalid(K, graphs):
         srv.submit(gid, el0.n, 1)
     with pytest.raises(K.KhopError):
         srv.submit(gid, 0, -1)
+    srv.close()
+
+
+@pytest.mark.parametrize("route", ["ROUTE_BATCH", "ROUTE_PLAIN", "ROUTE_AUTO"])
+def test_each_route_matches_oracle(K, graphs, route):
+    """Every query through the batches only, the single-query lanes only, or the
+    automatic choice between them, with arrivals spread over time."""
+    (el0, el1), g, o = graphs
+    srv = K.Server(1 << 30, 256)
+    srv.set_option(K.KHOP_SERVER_ROUTE, getattr(K, "KHOP_" + route))
+    ids = [srv.add_graph(x) for x in g]
+    rng = np.random.default_rng(77)
+    reqs = []
+    for i in range(900):
+        gi = int(rng.integers(0, 2))
+        s = int(rng.integers(0, (el0, el1)[gi].n))
+        k = int(rng.choice([0, 1, 2, 3, 6, 9]))
+        reqs.append((srv.submit(ids[gi], s, k), gi, s, k))
+        if i % 100 == 99:
+            time.sleep(0.002)
+    srv.drain(120000)
+    got = _collect(srv, len(reqs))
+    for t, gi, s, k in reqs:
+        r = got[t]
+        assert r.status == K.KHOP_OK
+        assert r.count == o[gi].khop(s, k)[0], (route, gi, s, k)
+        assert r.t_submit_ns <= r.t_admit_ns <= r.t_done_ns or k == 0
+        if route == "ROUTE_PLAIN" and k > 0:
+            assert r.path == K.KHOP_PATH_SINGLE
+        if route == "ROUTE_BATCH":
+            assert r.path == K.KHOP_PATH_BATCH
+    srv.close()
+
+
+def test_plain_lane_takes_light_load(K, graphs):
+    """At a trickle of queries the automatic route answers from the single-query lane in well under a millisecond."""
+    (el0, _), g, o = graphs
+    srv = K.Server(1 << 30, 1024)
+    gid = srv.add_graph(g[0])
+    seeds = np.nonzero(o[0].degrees() > 0)[0][:60]
+    lat = []
+    for s in seeds:
+        t = srv.submit(gid, int(s), 2)
+        srv.drain(10000)
+        r = _collect(srv, 1)[t]
+        assert r.count == o[0].khop(int(s), 2)[0]
+        assert r.path == K.KHOP_PATH_SINGLE
+        lat.append((r.t_done_ns - r.t_submit_ns) / 1e6)
+    _say("trickle latency ms p50", float(np.median(lat)))
+    assert float(np.median(lat)) < 2.0
     srv.close()

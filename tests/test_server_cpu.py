@@ -36,3 +36,15 @@ def test_null_handles():
     assert lib.khop_server_drain(None, 0) == K.KHOP_EINVAL
     assert lib.khop_server_add_graph(None, None, None) == K.KHOP_EINVAL
     assert lib.khop_server_destroy(None) == K.KHOP_OK
+
+
+def test_route_option_validation():
+    s = K.Server(1 << 30, 256)
+    for v in (K.KHOP_ROUTE_AUTO, K.KHOP_ROUTE_BATCH, K.KHOP_ROUTE_PLAIN):
+        s.set_option(K.KHOP_SERVER_ROUTE, v)
+    for opt, v in ((K.KHOP_SERVER_ROUTE, 3), (K.KHOP_SERVER_ROUTE, -1), (99, 0)):
+        with pytest.raises(K.KhopError) as ei:
+            s.set_option(opt, v)
+        assert ei.value.status == K.KHOP_EINVAL
+    assert K._lib.khop_server_set_option(None, K.KHOP_SERVER_ROUTE, 0) == K.KHOP_EINVAL
+    s.close()
