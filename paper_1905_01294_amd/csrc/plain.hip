@@ -691,44 +691,46 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
     }
 }
 
-// Top-down hop 1 of a seed with at most kBlock neighbors, not the query's
-// last hop: block 0 alone.  Every neighbor is new (the visited set holds only
-// the seed, and a row has no duplicates and no self-loop), so no claim is
-// needed: the visited and frontier bits are set with atomics whose old value
-// is not read, and wave w appends neighbors 64w..64w+63 to region w's queue
-// with a wave prefix of their out-degrees and plain stores of the region's
-// counters (the queue's regions need not match the vertices' ids).
-__device__ void hop1_push_small(const Graph &g, const State &s, int64_t beg, int64_t E, int64_t *units) {
-    if (blockIdx.x != 0) return;
-    const int lane = lane_id(), wv = threadIdx.x / kWave;
-    const int64_t e = (int64_t)wv * kWave + lane;
-    if ((int64_t)wv * kWave >= E) return;  // wave-uniform
+// Top-down hop 1 of a seed with at most 64 * nreg neighbors, not the query's
+// last hop.  Every neighbor is new (the visited set holds only the seed, and
+// a row has no duplicates and no self-loop), so no claim is needed: the
+// visited and frontier bits are set with atomics whose old value is not read,
+// and the wave that takes neighbors 64c..64c+63 appends them to region c's
+// queue with a wave prefix of their out-degrees and plain stores of the
+// region's counters (the queue's regions need not match the vertices' ids;
+// full regions of at most 64 entries keep hop 2's sweep on its short path).
+__device__ void hop1_push_free(const Graph &g, const State &s, int64_t beg, int64_t E, int64_t *units) {
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     RegRec *cur = s.regs + s.nreg;  // hop 1's slot
-    int64_t vb = 0, od = 0, id = 0;
-    if (e < E) {
-        const int32_t v = g.colidx[beg + e];
-        vb = g.rowptr[v];
-        od = g.rowptr[v + 1] - vb;
-        id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
-        const uint64_t bit = 1ull << (v & 63);
-        __hip_atomic_fetch_or(&s.V[v >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_or(&s.F[1][v >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (s.dist) s.dist[v] = 1;
-    }
-    const uint64_t qm = ballot(od > 0);
-    const int64_t off = wave_exclusive_sum(od);  // lists with no edges add nothing
-    const int64_t at = (int64_t)wv * s.rc + mask_rank(qm);
-    if (od > 0) {
-        s.qb[1][at] = vb;
-        s.qoff[1][at] = off;
-    }
-    const int64_t esum = wave_sum(od), isum = wave_sum(id);
-    const int64_t nf = std::min<int64_t>(kWave, E - (int64_t)wv * kWave);
-    if (lane == 0) {
-        cur[wv].qpack = pk(__popcll(qm), esum);
-        cur[wv].fpack = pk(nf, isum);
-        // 4 B per out-edge of the seed, 20 B (row pointers, queue entry, offset) per neighbor
-        if (units) unit_add(units, 0, 24 * nf);
+    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c * kWave < E; c += nwaves) {
+        const int64_t e = c * kWave + lane;
+        int64_t vb = 0, od = 0, id = 0;
+        if (e < E) {
+            const int32_t v = g.colidx[beg + e];
+            vb = g.rowptr[v];
+            od = g.rowptr[v + 1] - vb;
+            id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+            const uint64_t bit = 1ull << (v & 63);
+            __hip_atomic_fetch_or(&s.V[v >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(&s.F[1][v >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (s.dist) s.dist[v] = 1;
+        }
+        const uint64_t qm = ballot(od > 0);
+        const int64_t off = wave_exclusive_sum(od);  // lists with no edges add nothing
+        const int64_t at = c * s.rc + mask_rank(qm);
+        if (od > 0) {
+            s.qb[1][at] = vb;
+            s.qoff[1][at] = off;
+        }
+        const int64_t esum = wave_sum(od), isum = wave_sum(id);
+        const int64_t nf = std::min<int64_t>(kWave, E - c * kWave);
+        if (lane == 0) {
+            cur[c].qpack = pk(__popcll(qm), esum);
+            cur[c].fpack = pk(nf, isum);
+            // 4 B per out-edge of the seed, 20 B (row pointers, queue entry, offset) per neighbor
+            if (units) unit_add(units, 0, 24 * nf);
+        }
     }
 }
 
@@ -820,10 +822,9 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
                 ctl->te_acc += E;
                 if (units) unit_add(units, 0, 24);
             }
-            // (the small form needs kBlock <= 4 regions of 64 slots: nreg >= 4 and rc >= 64 always hold
-            // once n >= 256; smaller graphs take the general form)
-            if (!last && E <= kBlock && s.nreg >= kWavesPerBlock)
-                hop1_push_small(g, s, beg, E, units);
+            // (one region of rc >= 64 slots per 64 neighbors)
+            if (!last && E <= (int64_t)kWave * s.nreg)
+                hop1_push_free(g, s, beg, E, units);
             else
                 hop1_push(g, s, beg, E, last, units);
             return;
