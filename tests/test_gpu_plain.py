@@ -255,3 +255,29 @@ def test_profile_reports_kernels_and_event_cost(K, g0, g0_gpu, g0_oracle):
     assert stats["plain_hop"]["algorithmic_bytes"] > 0 and stats["plain_hop"]["total_ms"] > 0
     assert stats["batch_pull"]["launches"] >= 2 and stats["batch_pull"]["algorithmic_bytes"] > 0
     assert "batch_count" in stats and "batch_push" in stats
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_hub_seed_takes_the_claiming_hop1(K, mode):
+    """A seed with more neighbors than the regions hold in 64-entry chunks
+    (40 000 > 64 * 256) takes hop 1's claiming form; its leaves take the
+    claim-free one.  A few leaf-to-leaf edges make hop 2 find something."""
+    n = 40000
+    src = np.concatenate([np.zeros(n - 1, np.int32), np.arange(1, 2001, 2, dtype=np.int32)])
+    dst = np.concatenate([np.arange(1, n, dtype=np.int32), np.arange(2, 2002, 2, dtype=np.int32)])
+    extra_s = np.arange(n, n + 500, dtype=np.int32)  # a tail hanging off leaf 7: depth up to 502
+    extra_d = extra_s + 1
+    src = np.concatenate([src, [7], extra_s[:-1]]).astype(np.int32)
+    dst = np.concatenate([dst, [n], extra_d[:-1]]).astype(np.int32)
+    N = n + 500
+    g = K.Graph(src, dst, N)
+    og = oracle.OracleGraph(src, dst, N, False)
+    _set_mode(K, g, mode)
+    for s in (0, 7, 1999, n - 1, n + 250):
+        for k in (1, 2, 3, 6):
+            c, te = g.count(np.array([s], np.int32), k, with_te=True)
+            oc, ote = og.count(np.array([s], np.int32), k)
+            assert (int(c[0]), int(te[0])) == (int(oc[0]), int(ote[0])), (mode, s, k)
+        dist, count, depth = g.bfs(s)
+        assert np.array_equal(dist, og.distances(s, 2**31 - 1)), (mode, s)
+    g.free()
