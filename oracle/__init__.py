@@ -54,6 +54,9 @@ def _load():
         lib.oracle_khop_many.argtypes = [ctypes.c_void_p, _i32p, ctypes.c_int64, ctypes.c_int32, _i64p,
                                          _i64p]
         lib.oracle_khop_many.restype = ctypes.c_int
+        lib.oracle_khop_filtered.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_uint8), _i64p]
+        lib.oracle_khop_filtered.restype = ctypes.c_int64
         _lib = lib
     return _lib
 
@@ -110,6 +113,18 @@ class OracleGraph:
         if c < 0:
             raise ValueError(f"oracle_khop failed ({c})")
         return d
+
+    def khop_filtered(self, seed: int, k: int, allowed):
+        """(count, te) of the search that enters only vertices with allowed[v] (the seed exempt)."""
+        a = np.ascontiguousarray(allowed, dtype=np.uint8)
+        if a.shape != (self.n,):
+            raise ValueError("allowed must have one entry per vertex")
+        te = ctypes.c_int64(0)
+        c = _lib.oracle_khop_filtered(self._h, int(seed), int(k), a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                      ctypes.byref(te))
+        if c < 0:
+            raise ValueError(f"oracle_khop_filtered failed ({c})")
+        return int(c), int(te.value)
 
     def count(self, seeds, k: int):
         """(counts, te) arrays for many seeds at one k."""

@@ -23,6 +23,12 @@
  * distance 0..k-1 of their out-degree (distinct neighbors, self excluded),
  * which is what a top-down search must inspect; benchmarks divide it by time.
  *
+ * A filtered form (oracle_khop_filtered) restricts the search to the vertices
+ * an `allowed` array marks: a vertex other than the seed is reached only if
+ * it is allowed, so paths run through allowed vertices only (the seed itself
+ * is always the start).  Restricting the relation types is a filter on the
+ * tuples before the adjacency is built, so it needs nothing here.
+ *
  * The adjacency is built here from the tuples with its own counting sort and
  * duplicate marking; nothing is shared with the GPU library.
  */
@@ -151,6 +157,42 @@ int64_t oracle_khop(const oracle_graph *g, int32_t s, int32_t k, int64_t *level_
     if (te) *te = edges;
     if (dist_out)
         for (int64_t v = 0; v < n; ++v) dist_out[v] = dist[v];
+    free(dist);
+    free(queue);
+    return count;
+}
+
+/*
+ * Breadth-first search from s over levels 0 .. k-1 that enters only vertices
+ * with allowed[v] != 0 (allowed has n entries; the seed is exempt).  Returns
+ * the number of vertices found at distance 1..k; *te (may be NULL) receives
+ * the out-degree sum of the vertices expanded (distance 0..k-1).  -1 on
+ * invalid arguments, -2 on allocation failure.
+ */
+int64_t oracle_khop_filtered(const oracle_graph *g, int32_t s, int32_t k, const uint8_t *allowed, int64_t *te) {
+    if (!g || !allowed || s < 0 || s >= g->n || k < 0) return -1;
+    const int64_t n = g->n;
+    int32_t *dist = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!dist || !queue) { free(dist); free(queue); return -2; }
+    for (int64_t v = 0; v < n; ++v) dist[v] = -1;
+    int64_t head = 0, tail = 0, count = 0, edges = 0;
+    dist[s] = 0;
+    queue[tail++] = s;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        if (dist[u] >= k) continue;
+        edges += g->off[u + 1] - g->off[u];
+        for (int64_t i = g->off[u]; i < g->off[u + 1]; ++i) {
+            int32_t v = g->adj[i];
+            if (dist[v] < 0 && allowed[v]) {
+                dist[v] = dist[u] + 1;
+                queue[tail++] = v;
+                count += 1;
+            }
+        }
+    }
+    if (te) *te = edges;
     free(dist);
     free(queue);
     return count;
