@@ -66,6 +66,19 @@ enum { KHOP_UNDIRECTED = 0, KHOP_DIRECTED = 1 };
 int graph_load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, int64_t num_vertices,
                    uint32_t flags, khop_graph **out);
 
+/*
+ * Typed form of graph_load_csr: tuple i carries a relation type rel[i] in
+ * [0, 64), and only the tuples whose type has its bit set in rel_mask are
+ * kept.  The graph is the union of the selected relations' adjacency
+ * matrices (the paper's storage model keeps one matrix per relation type,
+ * Section II), so every count, search and server entry point traverses only
+ * those relations.  rel is a host array of num_edges bytes.  Errors as
+ * graph_load_csr, plus KHOP_EINVAL for rel NULL with num_edges > 0 or a type
+ * of 64 or more; endpoints are checked on the kept tuples only.
+ */
+int graph_load_csr_typed(const int32_t *src, const int32_t *dst, const uint8_t *rel, int64_t num_edges,
+                         int64_t num_vertices, uint32_t flags, uint64_t rel_mask, khop_graph **out);
+
 /* Release a graph and its device memory.  NULL is accepted (KHOP_OK). */
 int graph_free(khop_graph *g);
 
@@ -99,6 +112,28 @@ int khop_count(khop_graph *g, const int32_t *seeds, int64_t num_seeds, int32_t k
  */
 int khop_count_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
                    int64_t *d_traversed_edges, void *hip_stream);
+
+/*
+ * Label-filtered count: the k-hop count of each seed in the subgraph of the
+ * vertices whose bit is set in label_bits (bit v % 64 of word v / 64; the
+ * seed itself is always the start, labeled or not), i.e. counts[i] =
+ * |{ v labeled : 1 <= dist'(seeds[i], v) <= k }| where dist' only follows
+ * paths through labeled vertices.  This is the vertex-label mask of a typed
+ * query plan applied inside each masked product: the vertices outside the
+ * mask start visited, so NOT visited excludes them.  traversed_edges (may be
+ * NULL) as in khop_count, over the vertices the filtered search expands.
+ * Host pointers: label_bits has ceil(n / 64) words (bits past n ignored),
+ * seeds/counts num_seeds entries.  All seeds run as one launch sequence each,
+ * enqueued back to back, then one synchronisation.  Errors as khop_count,
+ * plus label_bits NULL -> KHOP_EINVAL.
+ */
+int khop_count_labeled(khop_graph *g, const int32_t *seeds, int64_t num_seeds, int32_t k, const uint64_t *label_bits,
+                       int64_t *counts, int64_t *traversed_edges);
+
+/* Device-pointer form of khop_count_labeled (d_label_bits on the device), as khop_count_dev. */
+int khop_count_labeled_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k,
+                           const uint64_t *d_label_bits, int64_t *d_counts, int64_t *d_traversed_edges,
+                           void *hip_stream);
 
 /*
  * Batched multi-source path: seeds travel together as per-vertex 64-bit seed

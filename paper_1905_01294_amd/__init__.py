@@ -52,7 +52,8 @@ KHOP_PATH_BATCH = 0
 KHOP_PATH_SINGLE = 1
 
 # Every entry point declared in include/khop.h.
-EXPORTS = ("graph_load_csr", "graph_free", "graph_info", "graph_degrees", "khop_count", "khop_count_dev",
+EXPORTS = ("graph_load_csr", "graph_load_csr_typed", "graph_free", "graph_info", "graph_degrees", "khop_count", "khop_count_dev", "khop_count_labeled",
+           "khop_count_labeled_dev",
            "khop_count_batched", "khop_count_batched_dev", "khop_bfs", "khop_bfs_dev", "khop_levels",
            "khop_levels_dev", "khop_neighborhood", "khop_neighborhood_dev", "khop_set_option",
            "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read", "khop_server_create", "khop_server_add_graph",
@@ -103,11 +104,16 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "graph_load_csr": ([_i32p, _i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32, ctypes.POINTER(_vp)],),
+        "graph_load_csr_typed": ([_i32p, _i32p, ctypes.POINTER(ctypes.c_uint8), ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(_vp)],),
         "graph_free": ([_vp],),
         "graph_info": ([_vp, _i64p, _i64p, _i32p],),
         "graph_degrees": ([_vp, _i64p],),
         "khop_count": ([_vp, _i32p, ctypes.c_int64, ctypes.c_int32, _i64p, _i64p],),
         "khop_count_dev": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp],),
+        "khop_count_labeled": ([_vp, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), _i64p,
+                                _i64p],),
+        "khop_count_labeled_dev": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp],),
         "khop_count_batched": ([_vp, _i32p, _i32p, ctypes.c_int64, _i64p],),
         "khop_count_batched_dev": ([_vp, _vp, _vp, ctypes.c_int64, _vp, _vp],),
         "khop_bfs": ([_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i64p, _i32p],),
@@ -194,6 +200,26 @@ def graph_load_csr(src, dst, num_vertices: int, flags: int = KHOP_UNDIRECTED):
     return h
 
 
+def graph_load_csr_typed(src, dst, rel, num_vertices: int, rel_mask: int, flags: int = KHOP_UNDIRECTED):
+    """A graph of the tuples whose relation type rel[i] (< 64) has its bit set in rel_mask."""
+    s, sp = _i32(src)
+    d, dp = _i32(dst)
+    r = np.ascontiguousarray(rel, dtype=np.uint8)
+    if s.shape != d.shape or s.shape != r.shape:
+        raise ValueError("src, dst and rel differ in length")
+    h = _vp()
+    _check(_lib.graph_load_csr_typed(sp, dp, r.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), s.shape[0],
+                                     int(num_vertices), int(flags), ctypes.c_uint64(int(rel_mask)), ctypes.byref(h)))
+    return h
+
+
+def label_bits(labeled, n: int) -> np.ndarray:
+    """The vertex mask words (bit v % 64 of word v // 64) of a boolean array of n entries."""
+    a = np.zeros(((int(n) + 63) // 64) * 64, dtype=bool)
+    a[:int(n)] = np.asarray(labeled, dtype=bool)
+    return np.packbits(a.reshape(-1, 8)[:, ::-1], axis=1).reshape(-1).view(np.uint64).copy()
+
+
 def graph_free(h) -> None:
     _check(_lib.graph_free(h))
 
@@ -225,6 +251,25 @@ def khop_count_dev(h, d_seeds, k: int, d_counts, d_te=None, stream=None) -> None
         raise ValueError("output tensors shorter than the seed tensor")
     _check(_lib.khop_count_dev(h, _dev_ptr(d_seeds, "torch.int32"), n, int(k), _dev_ptr(d_counts, "torch.int64"),
                                _dev_ptr(d_te, "torch.int64"), _stream_ptr(stream)))
+
+
+def khop_count_labeled(h, seeds, k: int, bits, with_te: bool = False):
+    s, sp = _i32(seeds)
+    b = np.ascontiguousarray(bits, dtype=np.uint64)
+    counts = np.empty(s.shape[0], dtype=np.int64)
+    te = np.empty(s.shape[0], dtype=np.int64) if with_te else None
+    _check(_lib.khop_count_labeled(h, sp, s.shape[0], int(k), b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                   counts.ctypes.data_as(_i64p), te.ctypes.data_as(_i64p) if te is not None else None))
+    return (counts, te) if with_te else counts
+
+
+def khop_count_labeled_dev(h, d_seeds, k: int, d_bits, d_counts, d_te=None, stream=None) -> None:
+    n = int(d_seeds.numel())
+    if int(d_counts.numel()) < n or (d_te is not None and int(d_te.numel()) < n):
+        raise ValueError("output tensors shorter than the seed tensor")
+    _check(_lib.khop_count_labeled_dev(h, _dev_ptr(d_seeds, "torch.int32"), n, int(k), _dev_ptr(d_bits, "torch.int64"),
+                                       _dev_ptr(d_counts, "torch.int64"), _dev_ptr(d_te, "torch.int64"),
+                                       _stream_ptr(stream)))
 
 
 def khop_count_batched(h, seeds, ks) -> np.ndarray:
@@ -357,6 +402,15 @@ class Graph:
         self.n, self.num_arcs, self.directed = graph_info(self._h)
 
     @classmethod
+    def typed(cls, src, dst, rel, num_vertices: int, rel_mask: int, directed: bool = False) -> "Graph":
+        """The graph of the tuples whose relation type rel[i] has its bit set in rel_mask."""
+        self = cls.__new__(cls)
+        self._h = graph_load_csr_typed(src, dst, rel, num_vertices, rel_mask,
+                                       KHOP_DIRECTED if directed else KHOP_UNDIRECTED)
+        self.n, self.num_arcs, self.directed = graph_info(self._h)
+        return self
+
+    @classmethod
     def from_edgelist(cls, el) -> "Graph":
         return cls(el.src, el.dst, el.n, el.directed)
 
@@ -383,6 +437,15 @@ class Graph:
 
     def count_dev(self, d_seeds, k: int, d_counts, d_te=None, stream=None):
         khop_count_dev(self._h, d_seeds, k, d_counts, d_te, stream)
+
+    def count_labeled(self, seeds, k: int, labeled, with_te: bool = False):
+        """Counts in the subgraph of the vertices with labeled[v] true (the seeds exempt)."""
+        return khop_count_labeled(self._h, seeds, k, label_bits(labeled, self.n), with_te)
+
+    def count_labeled_dev(self, d_seeds, k: int, d_bits, d_counts, d_te=None, stream=None):
+        if int(d_bits.numel()) < (self.n + 63) // 64:
+            raise ValueError("mask tensor shorter than ceil(n / 64) words")
+        khop_count_labeled_dev(self._h, d_seeds, k, d_bits, d_counts, d_te, stream)
 
     def count_batched(self, seeds, ks):
         return khop_count_batched(self._h, seeds, ks)

@@ -166,6 +166,8 @@ struct Pools {
         int64_t *h_pinned = nullptr;  // 2 int64 for per-query readback
         int32_t *d_dist = nullptr;    // breadth-first distances (n), then the depth
         int64_t dist_cap = 0;
+        uint64_t *d_label = nullptr;  // a vertex mask (ceil(n / 64) words)
+        int64_t label_cap = 0;
     };
     std::vector<Buffers *> bufs;
 };
@@ -212,6 +214,7 @@ static void pools_drop(khop_graph *g) {
         (void)hipFree(b->d_counts);
         (void)hipFree(b->d_te);
         (void)hipFree(b->d_dist);
+        (void)hipFree(b->d_label);
         if (b->h_pinned) (void)hipHostFree(b->h_pinned);
         delete b;
     }
@@ -321,6 +324,19 @@ static void ensure_dist(Pools::Buffers *b, int64_t n) {
     b->dist_cap = n + 1;
 }
 
+// Grows the vertex-mask buffer to `words` words.
+static void ensure_label(Pools::Buffers *b, int64_t words) {
+    if (b->label_cap >= words) return;
+    (void)hipFree(b->d_label);
+    b->d_label = nullptr;
+    b->label_cap = 0;
+    if (hipMalloc(&b->d_label, (size_t)words * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(KHOP_ENOMEM, "device allocation of a vertex mask failed");
+    }
+    b->label_cap = words;
+}
+
 static void give_buffers(khop_graph *g, Pools::Buffers *b) {
     Pools *p = pools_of(g);
     std::lock_guard<std::mutex> lk(g->mu);
@@ -367,88 +383,120 @@ const char *khop_last_error(void) { return t_err.c_str(); }
 
 const char *khop_version(void) { return "khop-mi355x 0.1 (gfx950)"; }
 
+}  // extern "C"
+
+// Builds a device graph from tuples (the body of graph_load_csr; throws khop::Error).
+static void load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, int64_t num_vertices, uint32_t flags,
+                     khop_graph **out) {
+    if (!out) fail(KHOP_EINVAL, "out is NULL");
+    if (num_edges < 0) fail(KHOP_EINVAL, "num_edges < 0");
+    if (num_edges > 0 && (!src || !dst)) fail(KHOP_EINVAL, "src or dst is NULL with num_edges > 0");
+    if (num_vertices <= 0) fail(KHOP_EINVAL, "num_vertices must be positive");
+    if (num_vertices > INT32_MAX) fail(KHOP_ERANGE, "num_vertices exceeds INT32_MAX (int32 column indices)");
+    if (flags != KHOP_UNDIRECTED && flags != KHOP_DIRECTED) fail(KHOP_EINVAL, "unknown flags");
+    if (num_edges > ((int64_t)1 << 61)) fail(KHOP_ERANGE, "too many edges");
+    // endpoint range check, in parallel
+    {
+        const int T = host_threads();
+        std::vector<int64_t> bad((size_t)T, -1);
+        std::vector<std::thread> pool;
+        for (int t = 0; t < T; ++t)
+            pool.emplace_back([&, t] {
+                const int64_t lo = num_edges * t / T, hi = num_edges * (t + 1) / T;
+                for (int64_t i = lo; i < hi; ++i)
+                    if (src[i] < 0 || src[i] >= num_vertices || dst[i] < 0 || dst[i] >= num_vertices) {
+                        bad[(size_t)t] = i;
+                        return;
+                    }
+            });
+        for (auto &th : pool) th.join();
+        for (int64_t b : bad)
+            if (b >= 0)
+                fail(KHOP_EINVAL, "edge " + std::to_string(b) + " has an endpoint outside [0, " +
+                                      std::to_string(num_vertices) + ")");
+    }
+    const int dev = require_device();
+    KHOP_HIP(hipSetDevice(dev));
+    const bool directed = flags == KHOP_DIRECTED;
+    HostCSR out_csr = build_csr(src, dst, num_edges, num_vertices, !directed);
+    HostCSR in_csr;
+    if (directed) in_csr = build_csr(dst, src, num_edges, num_vertices, false);
+    // per-hop counters pack a degree sum into 33 bits
+    if ((int64_t)out_csr.colidx.size() >= ((int64_t)1 << 33))
+        fail(KHOP_ERANGE, "more than 2^33 stored arcs");
+    auto *g = new khop_graph();
+    g->device = dev;
+    g->n = num_vertices;
+    g->nnz = (int64_t)out_csr.colidx.size();
+    g->directed = directed ? 1 : 0;
+    g->hash = csr_hash(out_csr);
+    {
+        hipDeviceProp_t p;
+        KHOP_HIP(hipGetDeviceProperties(&p, dev));
+        g->cu_count = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+    }
+    g->h_outdeg.resize((size_t)g->n);
+    for (int64_t v = 0; v < g->n; ++v) g->h_outdeg[v] = out_csr.rowptr[v + 1] - out_csr.rowptr[v];
+    if (directed) {
+        g->h_indeg.resize((size_t)g->n);
+        for (int64_t v = 0; v < g->n; ++v) g->h_indeg[v] = in_csr.rowptr[v + 1] - in_csr.rowptr[v];
+    } else {
+        g->h_indeg = g->h_outdeg;
+    }
+    auto upload = [&](const HostCSR &c, int64_t **rp, int32_t **ci) {
+        if (hipMalloc(rp, (c.rowptr.size()) * 8) != hipSuccess ||
+            hipMalloc(ci, std::max<size_t>(c.colidx.size(), 1) * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(KHOP_ENOMEM, "device allocation for the CSR failed");
+        }
+        KHOP_HIP(hipMemcpy(*rp, c.rowptr.data(), c.rowptr.size() * 8, hipMemcpyHostToDevice));
+        if (!c.colidx.empty())
+            KHOP_HIP(hipMemcpy(*ci, c.colidx.data(), c.colidx.size() * 4, hipMemcpyHostToDevice));
+    };
+    try {
+        upload(out_csr, &g->d_rowptr, &g->d_colidx);
+        if (directed) {
+            upload(in_csr, &g->d_in_rowptr, &g->d_in_colidx);
+        } else {
+            g->d_in_rowptr = g->d_rowptr;
+            g->d_in_colidx = g->d_colidx;
+        }
+        KHOP_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    } catch (...) {
+        graph_free(g);
+        throw;
+    }
+    *out = g;
+    }
+
+extern "C" {
+
 int graph_load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, int64_t num_vertices, uint32_t flags,
                    khop_graph **out) {
     return guard([&] {
-        if (!out) fail(KHOP_EINVAL, "out is NULL");
+        load_csr(src, dst, num_edges, num_vertices, flags, out);
+    });
+}
+
+int graph_load_csr_typed(const int32_t *src, const int32_t *dst, const uint8_t *rel, int64_t num_edges,
+                         int64_t num_vertices, uint32_t flags, uint64_t rel_mask, khop_graph **out) {
+    return guard([&] {
         if (num_edges < 0) fail(KHOP_EINVAL, "num_edges < 0");
-        if (num_edges > 0 && (!src || !dst)) fail(KHOP_EINVAL, "src or dst is NULL with num_edges > 0");
-        if (num_vertices <= 0) fail(KHOP_EINVAL, "num_vertices must be positive");
-        if (num_vertices > INT32_MAX) fail(KHOP_ERANGE, "num_vertices exceeds INT32_MAX (int32 column indices)");
-        if (flags != KHOP_UNDIRECTED && flags != KHOP_DIRECTED) fail(KHOP_EINVAL, "unknown flags");
-        if (num_edges > ((int64_t)1 << 61)) fail(KHOP_ERANGE, "too many edges");
-        // endpoint range check, in parallel
-        {
-            const int T = host_threads();
-            std::vector<int64_t> bad((size_t)T, -1);
-            std::vector<std::thread> pool;
-            for (int t = 0; t < T; ++t)
-                pool.emplace_back([&, t] {
-                    const int64_t lo = num_edges * t / T, hi = num_edges * (t + 1) / T;
-                    for (int64_t i = lo; i < hi; ++i)
-                        if (src[i] < 0 || src[i] >= num_vertices || dst[i] < 0 || dst[i] >= num_vertices) {
-                            bad[(size_t)t] = i;
-                            return;
-                        }
-                });
-            for (auto &th : pool) th.join();
-            for (int64_t b : bad)
-                if (b >= 0)
-                    fail(KHOP_EINVAL, "edge " + std::to_string(b) + " has an endpoint outside [0, " +
-                                          std::to_string(num_vertices) + ")");
-        }
-        const int dev = require_device();
-        KHOP_HIP(hipSetDevice(dev));
-        const bool directed = flags == KHOP_DIRECTED;
-        HostCSR out_csr = build_csr(src, dst, num_edges, num_vertices, !directed);
-        HostCSR in_csr;
-        if (directed) in_csr = build_csr(dst, src, num_edges, num_vertices, false);
-        // per-hop counters pack a degree sum into 33 bits
-        if ((int64_t)out_csr.colidx.size() >= ((int64_t)1 << 33))
-            fail(KHOP_ERANGE, "more than 2^33 stored arcs");
-        auto *g = new khop_graph();
-        g->device = dev;
-        g->n = num_vertices;
-        g->nnz = (int64_t)out_csr.colidx.size();
-        g->directed = directed ? 1 : 0;
-        g->hash = csr_hash(out_csr);
-        {
-            hipDeviceProp_t p;
-            KHOP_HIP(hipGetDeviceProperties(&p, dev));
-            g->cu_count = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
-        }
-        g->h_outdeg.resize((size_t)g->n);
-        for (int64_t v = 0; v < g->n; ++v) g->h_outdeg[v] = out_csr.rowptr[v + 1] - out_csr.rowptr[v];
-        if (directed) {
-            g->h_indeg.resize((size_t)g->n);
-            for (int64_t v = 0; v < g->n; ++v) g->h_indeg[v] = in_csr.rowptr[v + 1] - in_csr.rowptr[v];
-        } else {
-            g->h_indeg = g->h_outdeg;
-        }
-        auto upload = [&](const HostCSR &c, int64_t **rp, int32_t **ci) {
-            if (hipMalloc(rp, (c.rowptr.size()) * 8) != hipSuccess ||
-                hipMalloc(ci, std::max<size_t>(c.colidx.size(), 1) * 4) != hipSuccess) {
-                (void)hipGetLastError();
-                fail(KHOP_ENOMEM, "device allocation for the CSR failed");
+        if (num_edges > 0 && (!src || !dst || !rel)) fail(KHOP_EINVAL, "src, dst or rel is NULL with num_edges > 0");
+        // the union of the selected relations' adjacency matrices: the tuples of those relations
+        std::vector<int32_t> fs, fd;
+        fs.reserve((size_t)num_edges);
+        fd.reserve((size_t)num_edges);
+        for (int64_t i = 0; i < num_edges; ++i) {
+            if (rel[i] >= 64)
+                fail(KHOP_EINVAL, "relation type " + std::to_string(rel[i]) + " at index " + std::to_string(i) +
+                                      " is not below 64");
+            if ((rel_mask >> rel[i]) & 1ull) {
+                fs.push_back(src[i]);
+                fd.push_back(dst[i]);
             }
-            KHOP_HIP(hipMemcpy(*rp, c.rowptr.data(), c.rowptr.size() * 8, hipMemcpyHostToDevice));
-            if (!c.colidx.empty())
-                KHOP_HIP(hipMemcpy(*ci, c.colidx.data(), c.colidx.size() * 4, hipMemcpyHostToDevice));
-        };
-        try {
-            upload(out_csr, &g->d_rowptr, &g->d_colidx);
-            if (directed) {
-                upload(in_csr, &g->d_in_rowptr, &g->d_in_colidx);
-            } else {
-                g->d_in_rowptr = g->d_rowptr;
-                g->d_in_colidx = g->d_colidx;
-            }
-            KHOP_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
-        } catch (...) {
-            graph_free(g);
-            throw;
         }
-        *out = g;
+        load_csr(fs.data(), fd.data(), (int64_t)fs.size(), num_vertices, flags, out);
     });
 }
 
@@ -546,6 +594,73 @@ int khop_count_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int
         PlainSlot s = take_plain(g, st);
         try {
             plain_run(g, s.ctx, d_seeds, num_seeds, k, d_counts, d_traversed_edges, st);
+        } catch (...) {
+            give_plain(g, s, st);
+            throw;
+        }
+        give_plain(g, s, st);
+    });
+}
+
+int khop_count_labeled(khop_graph *g, const int32_t *seeds, int64_t num_seeds, int32_t k, const uint64_t *label_bits,
+                       int64_t *counts, int64_t *traversed_edges) {
+    return guard([&] {
+        check_graph(g);
+        if (num_seeds < 0) fail(KHOP_EINVAL, "num_seeds < 0");
+        if (k < 0) fail(KHOP_EINVAL, "k < 0");
+        if (num_seeds == 0) return;
+        if (!seeds || !counts || !label_bits) fail(KHOP_EINVAL, "seeds, counts or label_bits is NULL");
+        validate_seeds(g, seeds, num_seeds);
+        if (k == 0) {
+            std::fill(counts, counts + num_seeds, 0);
+            if (traversed_edges) std::fill(traversed_edges, traversed_edges + num_seeds, 0);
+            return;
+        }
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = g->stream;
+        const int64_t words = (g->n + 63) / 64;
+        Pools::Buffers *b = take_buffers(g, num_seeds);
+        PlainSlot s{nullptr, {}};
+        std::vector<int64_t> c((size_t)num_seeds), t((size_t)num_seeds);
+        try {
+            ensure_label(b, words);
+            KHOP_HIP(hipMemcpyAsync(b->d_label, label_bits, (size_t)words * 8, hipMemcpyHostToDevice, st));
+            KHOP_HIP(hipMemcpyAsync(b->d_seeds, seeds, (size_t)num_seeds * 4, hipMemcpyHostToDevice, st));
+            s = take_plain(g, st);
+            plain_run(g, s.ctx, b->d_seeds, num_seeds, k, b->d_counts, b->d_te, st, b->d_label);
+            KHOP_HIP(hipMemcpyAsync(c.data(), b->d_counts, (size_t)num_seeds * 8, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipMemcpyAsync(t.data(), b->d_te, (size_t)num_seeds * 8, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+            if (s.ctx) give_plain(g, s, st);
+            give_buffers(g, b);
+            throw;
+        }
+        give_plain(g, s, st);
+        give_buffers(g, b);
+        std::copy(c.begin(), c.end(), counts);
+        if (traversed_edges) std::copy(t.begin(), t.end(), traversed_edges);
+    });
+}
+
+int khop_count_labeled_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k,
+                           const uint64_t *d_label_bits, int64_t *d_counts, int64_t *d_traversed_edges,
+                           void *hip_stream) {
+    return guard([&] {
+        check_graph(g);
+        if (num_seeds < 0) fail(KHOP_EINVAL, "num_seeds < 0");
+        if (k < 0) fail(KHOP_EINVAL, "k < 0");
+        if (num_seeds == 0) return;
+        if (!d_seeds || !d_counts || !d_label_bits) fail(KHOP_EINVAL, "d_seeds, d_counts or d_label_bits is NULL");
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (k == 0) {
+            plain_fill_zero_outputs(d_counts, d_traversed_edges, num_seeds, st);
+            return;
+        }
+        PlainSlot s = take_plain(g, st);
+        try {
+            plain_run(g, s.ctx, d_seeds, num_seeds, k, d_counts, d_traversed_edges, st, d_label_bits);
         } catch (...) {
             give_plain(g, s, st);
             throw;

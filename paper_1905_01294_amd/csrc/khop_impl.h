@@ -167,8 +167,9 @@ namespace khop {
 // plain.hip
 PlainCtx *plain_ctx_create(khop_graph *g);
 void plain_ctx_destroy(PlainCtx *c);
+// d_vmask (may be null): one bit per vertex, the vertices the searches may enter (the seeds are exempt).
 void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k,
-               int64_t *d_counts, int64_t *d_te, hipStream_t st);
+               int64_t *d_counts, int64_t *d_te, hipStream_t st, const uint64_t *d_vmask = nullptr);
 void plain_fill_zero_outputs(int64_t *d_counts, int64_t *d_te, int64_t n, hipStream_t st);
 // Breadth-first search from one (valid) seed, up to max_depth hops (< 0: no
 // limit), on the context's first state.  Distances go to d_dist[n] and the

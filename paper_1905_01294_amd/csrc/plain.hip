@@ -109,6 +109,7 @@ struct State {
     uint8_t *nextb;    // top-down marks (byte mode), all zero between hops
     uint8_t *nsum;     // one byte per 64-vertex word: some mark of the word may be set
     int32_t *dist;     // breadth-first search: distance of each vertex, set when it is found (else null)
+    const uint64_t *vmask;  // vertices the search may enter, one bit each (null: all); the others start visited
     int64_t *qb[2];    // region queues by hop parity, nreg * rc slots: the row begin of each queued vertex
     int64_t *qoff[2];  // out-degree prefix within each region's queue
     RegRec *regs;      // 3 * nreg region counters
@@ -319,10 +320,18 @@ __device__ void setup_query(PlainCtl *ctl, const Graph &g, const State &s, int32
 }
 
 // Word w of a query's visited and frontier bitmaps at its start: the seed's
-// bit only (sw = -1: no seed).
-__device__ __forceinline__ void reset_word(const State &s, int64_t w, int64_t sw, uint64_t sbit) {
+// bit only (sw = -1: no seed).  With a vertex mask, the vertices outside it
+// start visited, so that the mask of every masked product (NOT visited)
+// excludes them too and the search never enters them (bits past the last
+// vertex stay clear).
+__device__ __forceinline__ void reset_word(const State &s, const Graph &g, int64_t w, int64_t sw, uint64_t sbit) {
     const uint64_t x = (w == sw) ? sbit : 0ull;
-    s.V[w] = x;
+    uint64_t v = x;
+    if (s.vmask) {
+        const uint64_t valid = (w == g.nw - 1 && (g.n & 63)) ? ((1ull << (g.n & 63)) - 1) : ~0ull;
+        v |= ~s.vmask[w] & valid;
+    }
+    s.V[w] = v;
     s.F[0][w] = x;
     s.F[1][w] = 0;
 }
@@ -338,7 +347,7 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
     const int64_t sw = valid ? (seed >> 6) : -1;
     const uint64_t sbit = valid ? (1ull << (seed & 63)) : 0;
     for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock)
-        reset_word(s, w, sw, sbit);
+        reset_word(s, g, w, sw, sbit);
     if (blockIdx.x == 0)
         setup_query(ctl, g, s, seed, qi, k, dir_mode, alpha, beta, push_atomic_max, nnz_in, out_count, out_te,
                     units);
@@ -706,8 +715,13 @@ __device__ void hop1_push_free(const Graph &g, const State &s, int64_t beg, int6
     for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c * kWave < E; c += nwaves) {
         const int64_t e = c * kWave + lane;
         int64_t vb = 0, od = 0, id = 0;
-        if (e < E) {
-            const int32_t v = g.colidx[beg + e];
+        bool take = e < E;
+        int32_t v = 0;
+        if (take) {
+            v = g.colidx[beg + e];
+            take = !s.vmask || ((s.vmask[v >> 6] >> (v & 63)) & 1ull);  // outside the vertex mask: never entered
+        }
+        if (take) {
             vb = g.rowptr[v];
             od = g.rowptr[v + 1] - vb;
             id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
@@ -724,12 +738,12 @@ __device__ void hop1_push_free(const Graph &g, const State &s, int64_t beg, int6
             s.qoff[1][at] = off;
         }
         const int64_t esum = wave_sum(od), isum = wave_sum(id);
-        const int64_t nf = std::min<int64_t>(kWave, E - c * kWave);
+        const int64_t nf = __popcll(ballot(take));
         if (lane == 0) {
             cur[c].qpack = pk(__popcll(qm), esum);
             cur[c].fpack = pk(nf, isum);
-            // 4 B per out-edge of the seed, 20 B (row pointers, queue entry, offset) per neighbor
-            if (units) unit_add(units, 0, 24 * nf);
+            // 4 B per out-edge of the seed, 20 B (row pointers, queue entry, offset) per neighbor taken
+            if (units) unit_add(units, 0, 4 * std::min<int64_t>(kWave, E - c * kWave) + 20 * nf);
         }
     }
 }
@@ -930,7 +944,7 @@ __global__ void __launch_bounds__(kBlock) plain_hop1_kernel(PlainCtl *ctl, Plain
             fresh += close_marks_word(sn, w, sn.V[w]);
             ++flagged;
         }
-        if (qn >= 0) reset_word(sn, w, nsw, nsbit);
+        if (qn >= 0) reset_word(sn, g, w, nsw, nsbit);
     }
     if (marks) {
         fresh = wave_sum(fresh);
@@ -1041,7 +1055,7 @@ __global__ void __launch_bounds__(kBlock) plain_bfs_init_kernel(PlainCtl *ctl, G
     const uint64_t sbit = 1ull << (seed & 63);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (int64_t w = t0; w < g.nw; w += stride) reset_word(s, w, sw, sbit);
+    for (int64_t w = t0; w < g.nw; w += stride) reset_word(s, g, w, sw, sbit);
     if (s.dist)
         for (int64_t v = t0; v < g.n; v += stride) s.dist[v] = v == seed ? 0 : -1;
     if (levels)
@@ -1262,7 +1276,7 @@ void plain_fill_zero_outputs(int64_t *d_counts, int64_t *d_te, int64_t n, hipStr
 }
 
 void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
-               int64_t *d_te, hipStream_t st) {
+               int64_t *d_te, hipStream_t st, const uint64_t *d_vmask) {
     if (num_seeds <= 0) return;
     if (k == 0) {
         plain_fill_zero_outputs(d_counts, d_te, num_seeds, st);
@@ -1279,9 +1293,11 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     // other parity's bitmaps: the set-up grid suffices
     const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
     PlainCtl *ctl = c->ctl;
+    State sp[2] = {c->s[0], c->s[1]};  // the two parities, with the vertex mask of this run
+    sp[0].vmask = sp[1].vmask = d_vmask;
     {
         ProfScope ps(g, KK_PLAIN_INIT, st);
-        hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, c->s[0], d_seeds,
+        hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, sp[0], d_seeds,
                            (int64_t)0, (int)k, P.dir_mode, P.alpha, P.beta, pam, nnz_in, d_counts, d_te, ps.units());
         ps.end(0, 1);
     }
@@ -1291,7 +1307,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         {
             ProfScope ps(g, KK_PLAIN_HOP, st);
             hipLaunchKernelGGL(plain_hop1_kernel, dim3(hop1_grid), dim3(kBlock), 0, st, cq, cprev, cnext,
-                               (int)(i >= 1), (int)(i >= 2), gr, c->s[p], c->s[p ^ 1], d_seeds,
+                               (int)(i >= 1), (int)(i >= 2), gr, sp[p], sp[p ^ 1], d_seeds,
                                i + 1 < num_seeds ? i + 1 : (int64_t)-1, (int)k, P.dir_mode, P.alpha, P.beta, pam,
                                nnz_in, d_counts, d_te, P.pull_light, hc, ps.units());
             ps.end(0, 1);
@@ -1299,14 +1315,14 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         for (int L = 2; L <= k; ++L) {
             {
                 ProfScope ps(g, KK_PLAIN_HOP, st);
-                hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, cq, L, gr, c->s[p],
+                hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, cq, L, gr, sp[p],
                                    P.pull_light, hc, ps.units());
                 ps.end(0, 1);
             }
             if (L < k) {
                 ProfScope ps(g, KK_PLAIN_COMPACT, st);
                 hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, cq, L, gr,
-                                   c->s[p], ps.units());
+                                   sp[p], ps.units());
                 ps.end(0, 1);
             }
         }
@@ -1316,7 +1332,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     {
         ProfScope ps(g, KK_PLAIN_INIT, st);
         hipLaunchKernelGGL(plain_close_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl + (m - 1) % 3,
-                           ctl + (m + 1) % 3, (int)(m >= 2), gr, c->s[(m - 1) & 1], ps.units());
+                           ctl + (m + 1) % 3, (int)(m >= 2), gr, sp[(m - 1) & 1], ps.units());
         ps.end(0, 1);
     }
     hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, ctl + (m - 1) % 3);
@@ -1334,6 +1350,7 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
     const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
     State s = c->s[0];
     s.dist = d_dist;
+    s.vmask = nullptr;
     PlainCtl *ctl = c->ctl;
     {
         ProfScope ps(g, KK_PLAIN_INIT, st);

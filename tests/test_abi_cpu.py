@@ -109,3 +109,22 @@ def test_one_hip_runtime_in_process():
             if "libamdhip64" in line:
                 paths.add(line.split()[-1])
     assert len(paths) <= 1, paths
+
+
+def test_label_bits_layout():
+    """Bit v % 64 of word v // 64 is vertex v's label; bits past n are clear."""
+    rng = np.random.default_rng(3)
+    for n in (1, 63, 64, 65, 200):
+        lab = rng.random(n) < 0.5
+        words = K.label_bits(lab, n)
+        assert words.dtype == np.uint64 and words.shape == ((n + 63) // 64,)
+        for v in range(((n + 63) // 64) * 64):
+            bit = (int(words[v // 64]) >> (v % 64)) & 1
+            assert bit == (int(lab[v]) if v < n else 0)
+
+
+def test_typed_and_labeled_validation_without_gpu():
+    lib = K._lib
+    h = ctypes.c_void_p()
+    assert lib.graph_load_csr_typed(None, None, None, 3, 4, 0, 1, ctypes.byref(h)) == K.KHOP_EINVAL
+    assert lib.khop_count_labeled(None, None, 1, 1, None, None, None) == K.KHOP_EINVAL
