@@ -119,7 +119,8 @@ def main():
     if args.only_bfs:
         cpu_leg = not args.no_cpu_baseline
         print(json.dumps({"bfs": bfs_bench(g, el, K, torch, cpu_leg=cpu_leg),
-                          "neighborhood_sets": sets_bench(g, el, groups, K, torch, cpu_leg=cpu_leg)}), flush=True)
+                          "neighborhood_sets": sets_bench(g, el, groups, K, torch, cpu_leg=cpu_leg),
+                          "label_filtered": filtered_bench(g, el, groups, K, torch, cpu_leg=cpu_leg)}), flush=True)
         g.free()
         return
 
@@ -238,6 +239,7 @@ def main():
     sweep = None if args.no_sweep else batched_sweep(g, el, K, torch)
     bfs = None if args.no_bfs else bfs_bench(g, el, K, torch, cpu_leg=not args.no_cpu_baseline)
     sets = None if args.no_bfs else sets_bench(g, el, groups, K, torch, cpu_leg=not args.no_cpu_baseline)
+    filtered = None if args.no_bfs else filtered_bench(g, el, groups, K, torch, cpu_leg=not args.no_cpu_baseline)
     g2 = el2 = None
     power_law = None
     if args.twitter:
@@ -318,6 +320,7 @@ def main():
         "serving": serving,
         "bfs": bfs,
         "neighborhood_sets": sets,
+        "label_filtered": filtered,
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
@@ -614,6 +617,51 @@ def sets_bench(g, el, groups, K, torch, cpu_leg=True):
         for s in deep[:2]:
             equal = equal and bool(np.array_equal(g.levels(int(s), 6), og.khop(int(s), 6)[2]))
         out["equal_oracle"] = equal
+    return out
+
+
+def filtered_bench(g, el, groups, K, torch, cpu_leg=True):
+    """The protocol's query set counted in the subgraph of a random half of the
+    vertices (a vertex-label filter), device-resident, one launch sequence per query."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    lab = np.random.default_rng(2024).random(g.n) < 0.5
+    d_bits = torch.from_numpy(K.label_bits(lab, g.n).view(np.int64)).to(dev)
+    runs = []
+    for k, seeds in groups:
+        ds = torch.from_numpy(seeds).to(dev)
+        dc = torch.empty(len(seeds), dtype=torch.int64, device=dev)
+        dt = torch.empty(len(seeds), dtype=torch.int64, device=dev)
+        runs.append((k, seeds, ds, dc, dt))
+
+    def one_pass():
+        for k, _, ds, dc, dt in runs:
+            g.count_labeled_dev(ds, k, d_bits, dc, dt, stream=stream)
+
+    for _ in range(2):
+        one_pass()
+    torch.cuda.synchronize()
+    te = sum(int(dt.sum()) for *_, dt in runs)
+    nq = sum(len(s) for _, s, *_ in runs)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(5):
+        one_pass()
+    ev[1].record(stream)
+    ev[1].synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / 5
+    out = {"label_density": 0.5, "queries": nq, "ms_per_pass": round(ms, 3), "qps": round(nq / (ms / 1e3), 1),
+           "gteps": round(te / (ms / 1e3) / 1e9, 2)}
+    log(f"label-filtered protocol: {out['ms_per_pass']} ms per {nq} queries, {out['gteps']} GTEPS")
+    if cpu_leg:
+        import oracle
+        og = oracle.OracleGraph.from_edgelist(el)
+        equal = True
+        for k, seeds, ds, dc, dt in runs:
+            got = dc.cpu().numpy()
+            for i in range(0, len(seeds), max(1, len(seeds) // 5)):
+                equal = equal and og.khop_filtered(int(seeds[i]), k, lab.astype(np.uint8))[0] == int(got[i])
+        out["sample_equal_oracle"] = bool(equal)
     return out
 
 
