@@ -3,10 +3,11 @@
 // One hop is the masked boolean product of the paper's Section II: the next
 // frontier is (A^T f) AND NOT visited over the (OR, AND) semiring.  A query is
 // one hop kernel per hop; a hop 2..k-1 is followed by a compaction kernel
-// (which exits at once unless the hop marked bytes).  Hop 1 claims its heads
-// atomically unless it is the last, and a last hop only counts: bottom-up it
-// counts its finds, top-down it marks bytes that the next query counts.  So
-// neither needs a compaction.
+// (which exits at once unless the hop marked bytes).  Hop 1 needs no claims
+// unless the seed has more than 64 neighbors per region (all its neighbors
+// are new; it queues them 64 to a region), and a last hop only counts:
+// bottom-up it counts its finds, top-down it marks bytes that the next query
+// counts.  So neither needs a compaction.
 // Consecutive queries alternate between two sets of bitmaps and region
 // counters: hop 1 of query i also counts the byte marks query i-1 left,
 // resets the other set for query i+1 and writes the count of query i-2, so a
