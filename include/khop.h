@@ -311,7 +311,8 @@ enum khop_server_option {
     KHOP_SERVER_ROUTE = 1 /* KHOP_ROUTE_AUTO (default), KHOP_ROUTE_BATCH or KHOP_ROUTE_PLAIN */
 };
 enum { KHOP_ROUTE_AUTO = 0, KHOP_ROUTE_BATCH = 1, KHOP_ROUTE_PLAIN = 2 };
-/* Set a server option; it applies to requests submitted afterwards.  Unknown option or value -> KHOP_EINVAL. */
+/* Set a server option.  It applies to requests the scheduler has not routed yet (in practice, those
+ * submitted after the call).  Unknown option or value -> KHOP_EINVAL. */
 int khop_server_set_option(khop_server *s, int32_t option, int64_t value);
 /* Queue one query; deadline_ns is an absolute CLOCK_MONOTONIC time, 0 = none. */
 int khop_server_submit(khop_server *s, int32_t graph_id, int32_t seed, int32_t k, int64_t deadline_ns,
