@@ -724,7 +724,8 @@ def batched_sweep(g, el, K, torch):
 
 
 def serving_bench(K, graphs, seconds):
-    """Open-loop Poisson arrivals at 0.25, 0.5 and 0.8 of the closed-loop saturation rate.
+    """Open-loop Poisson arrivals at 0.25, 0.5 and 0.8 of the closed-loop saturation rate, at least
+    10^4 queries per level.
 
     Queries: k in {1, 2, 3, 6} with weights 0.4/0.3/0.2/0.1, seeds uniform over
     non-isolated vertices, graph uniform over the resident graphs.  Latency is
@@ -769,7 +770,7 @@ def serving_bench(K, graphs, seconds):
     check = []
     for frac in (0.25, 0.5, 0.8):
         qps = frac * sat
-        n = int(min(max(qps * seconds, 200), 60000))
+        n = int(min(max(qps * seconds, 10000), 60000))  # at least 10^4 queries per level
         qs = make(n)
         gaps = rng.exponential(1.0 / qps, size=n)
         sched = np.cumsum(gaps)
@@ -807,7 +808,8 @@ def serving_bench(K, graphs, seconds):
                        "completed": len(lat), "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
                        "mean_ms": round(float(np.mean(lat)), 3),
                        "single_query_share": round(single / max(len(lat), 1), 3),
-                       "by_graph_k": {key: {"n": len(v), "p50_ms": round(pct(v, 50), 3), "p99_ms": round(pct(v, 99), 3)}
+                       "by_graph_k": {key: {"n": len(v), "mean_ms": round(float(np.mean(v)), 3),
+                                            "p50_ms": round(pct(v, 50), 3), "p99_ms": round(pct(v, 99), 3)}
                                       for key, v in sorted(by_gk.items())}})
         log(f"serving at {qps:.0f} q/s offered: p50 {levels[-1]['p50_ms']} ms, p99 {levels[-1]['p99_ms']} ms")
     srv.close()
