@@ -150,6 +150,16 @@ int khop_count_batched_dev(khop_graph *g, const int32_t *d_seeds, const int32_t 
                            int64_t *d_counts, void *hip_stream);
 
 /*
+ * Batched form of khop_count_labeled: counts[i] is the label-filtered k-hop
+ * count of seeds[i] at depth ks[i].  Every seed's visited bits start set on
+ * the vertices outside label_bits, so no hop enters them, and the per-seed
+ * count skips them.  Host pointers (label_bits ceil(n / 64) words).  Errors
+ * as khop_count_batched, plus label_bits NULL -> KHOP_EINVAL.
+ */
+int khop_count_batched_labeled(khop_graph *g, const int32_t *seeds, const int32_t *ks, int64_t num_seeds,
+                               const uint64_t *label_bits, int64_t *counts);
+
+/*
  * Breadth-first distances from one seed: the level-synchronous search behind
  * the k-hop count (Section III; each level one masked product of Section II)
  * run to the end, on the kernels of khop_count plus one store per discovered

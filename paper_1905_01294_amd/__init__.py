@@ -52,13 +52,13 @@ KHOP_PATH_BATCH = 0
 KHOP_PATH_SINGLE = 1
 
 # Every entry point declared in include/khop.h.
-EXPORTS = ("graph_load_csr", "graph_load_csr_typed", "graph_free", "graph_info", "graph_degrees", "khop_count", "khop_count_dev", "khop_count_labeled",
-           "khop_count_labeled_dev",
-           "khop_count_batched", "khop_count_batched_dev", "khop_bfs", "khop_bfs_dev", "khop_levels",
-           "khop_levels_dev", "khop_neighborhood", "khop_neighborhood_dev", "khop_set_option",
-           "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read", "khop_server_create", "khop_server_add_graph",
-           "khop_server_set_option", "khop_server_submit", "khop_server_poll", "khop_server_drain", "khop_server_destroy",
-           "khop_last_error", "khop_version")
+EXPORTS = ("graph_load_csr", "graph_load_csr_typed", "graph_free", "graph_info", "graph_degrees",
+           "khop_count", "khop_count_dev", "khop_count_labeled", "khop_count_labeled_dev",
+           "khop_count_batched", "khop_count_batched_dev", "khop_count_batched_labeled",
+           "khop_bfs", "khop_bfs_dev", "khop_levels", "khop_levels_dev", "khop_neighborhood", "khop_neighborhood_dev",
+           "khop_set_option", "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read",
+           "khop_server_create", "khop_server_add_graph", "khop_server_set_option", "khop_server_submit",
+           "khop_server_poll", "khop_server_drain", "khop_server_destroy", "khop_last_error", "khop_version")
 
 
 class KhopError(RuntimeError):
@@ -116,6 +116,7 @@ def _load():
         "khop_count_labeled_dev": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp],),
         "khop_count_batched": ([_vp, _i32p, _i32p, ctypes.c_int64, _i64p],),
         "khop_count_batched_dev": ([_vp, _vp, _vp, ctypes.c_int64, _vp, _vp],),
+        "khop_count_batched_labeled": ([_vp, _i32p, _i32p, ctypes.c_int64, ctypes.POINTER(ctypes.c_uint64), _i64p],),
         "khop_bfs": ([_vp, ctypes.c_int32, ctypes.c_int32, _i32p, _i64p, _i32p],),
         "khop_bfs_dev": ([_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, _vp, _vp],),
         "khop_levels": ([_vp, ctypes.c_int32, ctypes.c_int32, _i64p],),
@@ -277,6 +278,16 @@ def khop_count_batched(h, seeds, ks) -> np.ndarray:
     kk, kp = _i32(np.broadcast_to(np.asarray(ks, dtype=np.int32), s.shape))
     counts = np.empty(s.shape[0], dtype=np.int64)
     _check(_lib.khop_count_batched(h, sp, kp, s.shape[0], counts.ctypes.data_as(_i64p)))
+    return counts
+
+
+def khop_count_batched_labeled(h, seeds, ks, bits) -> np.ndarray:
+    s, sp = _i32(seeds)
+    kk, kp = _i32(np.broadcast_to(np.asarray(ks, dtype=np.int32), s.shape))
+    b = np.ascontiguousarray(bits, dtype=np.uint64)
+    counts = np.empty(s.shape[0], dtype=np.int64)
+    _check(_lib.khop_count_batched_labeled(h, sp, kp, s.shape[0], b.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                           counts.ctypes.data_as(_i64p)))
     return counts
 
 
@@ -449,6 +460,10 @@ class Graph:
 
     def count_batched(self, seeds, ks):
         return khop_count_batched(self._h, seeds, ks)
+
+    def count_batched_labeled(self, seeds, ks, labeled):
+        """Batched counts in the subgraph of the vertices with labeled[v] true (the seeds exempt)."""
+        return khop_count_batched_labeled(self._h, seeds, ks, label_bits(labeled, self.n))
 
     def count_batched_dev(self, d_seeds, d_ks, d_counts, stream=None):
         khop_count_batched_dev(self._h, d_seeds, d_ks, d_counts, stream)

@@ -352,7 +352,7 @@ static void validate_seeds(const khop_graph *g, const int32_t *seeds, int64_t nu
 
 // Runs a sorted batch plan: slots grouped in launches of at most `per` seeds.
 void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int64_t num,
-                        int64_t *d_counts, hipStream_t st) {
+                        int64_t *d_counts, hipStream_t st, const uint64_t *d_vmask) {
     std::vector<int32_t> order((size_t)num);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return h_ks[a] > h_ks[b]; });
@@ -364,7 +364,7 @@ void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int
         for (int64_t j = 0; j < cnt; ++j) ks[j] = h_ks[order[at + j]];
         BatchSlot s = take_batch(g, words, st);
         try {
-            batch_run(g, s.ctx, d_seeds, order.data() + at, ks.data(), cnt, d_counts, st);
+            batch_run(g, s.ctx, d_seeds, order.data() + at, ks.data(), cnt, d_counts, st, d_vmask);
         } catch (...) {
             give_batch(g, s, st);
             throw;
@@ -884,6 +884,37 @@ int khop_neighborhood_dev(khop_graph *g, int32_t seed, int32_t k, int32_t *d_ids
         }
         give_plain(g, s, st);
         if (b) give_buffers(g, b);
+    });
+}
+
+int khop_count_batched_labeled(khop_graph *g, const int32_t *seeds, const int32_t *ks, int64_t num_seeds,
+                               const uint64_t *label_bits, int64_t *counts) {
+    return guard([&] {
+        check_graph(g);
+        if (num_seeds < 0) fail(KHOP_EINVAL, "num_seeds < 0");
+        if (num_seeds == 0) return;
+        if (!seeds || !ks || !counts || !label_bits) fail(KHOP_EINVAL, "seeds, ks, counts or label_bits is NULL");
+        validate_seeds(g, seeds, num_seeds);
+        for (int64_t i = 0; i < num_seeds; ++i)
+            if (ks[i] < 0) fail(KHOP_EINVAL, "k < 0 at index " + std::to_string(i));
+        KHOP_HIP(hipSetDevice(g->device));
+        hipStream_t st = g->stream;
+        const int64_t words = (g->n + 63) / 64;
+        Pools::Buffers *b = take_buffers(g, num_seeds);
+        std::vector<int64_t> c((size_t)num_seeds);
+        try {
+            ensure_label(b, words);
+            KHOP_HIP(hipMemcpyAsync(b->d_label, label_bits, (size_t)words * 8, hipMemcpyHostToDevice, st));
+            KHOP_HIP(hipMemcpyAsync(b->d_seeds, seeds, (size_t)num_seeds * 4, hipMemcpyHostToDevice, st));
+            run_batched(g, b->d_seeds, ks, num_seeds, b->d_counts, st, b->d_label);
+            KHOP_HIP(hipMemcpyAsync(c.data(), b->d_counts, (size_t)num_seeds * 8, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+            give_buffers(g, b);
+            throw;
+        }
+        give_buffers(g, b);
+        std::copy(c.begin(), c.end(), counts);
     });
 }
 

@@ -143,7 +143,8 @@ __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t 
                                                                  const int32_t *seeds, const int32_t *perm,
                                                                  const int32_t *ks_sorted, int nslots, int W,
                                                                  uint64_t *F, uint64_t *V, uint64_t *fb,
-                                                                 int64_t *fb_cnt, ChunkQueue q, int32_t *flag) {
+                                                                 int64_t *fb_cnt, ChunkQueue q, int32_t *flag,
+                                                                 const uint64_t *__restrict__ vmask) {
     int64_t fresh = 0;
     for (int j = blockIdx.x; j < nslots; j += gridDim.x) {
         if (ks_sorted[j] < 1) continue;
@@ -157,8 +158,9 @@ __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t 
             bool app = false;
             int32_t v = 0;
             int64_t deg = 0;
-            if (x < e) {
-                v = colidx[x];
+            if (x < e) v = colidx[x];
+            // every neighbor is new, unless a vertex mask leaves it out (it is never entered)
+            if (x < e && (!vmask || ((vmask[v >> 6] >> (v & 63)) & 1ull))) {
                 atomicOr((unsigned long long *)&F[(int64_t)v * W + w], bit);
                 atomicOr((unsigned long long *)&V[(int64_t)v * W + w], bit);
                 app = fb_set(fb, v);
@@ -582,8 +584,9 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x) {
 
 // counts_acc[w*64 + bit] += number of vertices whose word w has that bit, for
 // words w = w0 + blockIdx.y of rows W words long.
+// With a vertex mask (vmask, one bit per vertex) only the vertices in it are counted.
 __global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__restrict__ V, int64_t n, int W, int w0,
-                                                            int64_t *counts_acc) {
+                                                            const uint64_t *__restrict__ vmask, int64_t *counts_acc) {
     const int w = w0 + blockIdx.y;
     const int lane = lane_id();
     __shared__ int64_t s_acc[kWavesPerBlock][kWave];
@@ -592,7 +595,8 @@ __global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__r
     for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c < nchunks;
          c += (int64_t)gridDim.x * kWavesPerBlock) {
         const int64_t v = c * kWave + lane;
-        const uint64_t x = v < n ? V[v * W + w] : 0ull;
+        const bool in = v < n && (!vmask || ((vmask[c] >> lane) & 1ull));
+        const uint64_t x = in ? V[v * W + w] : 0ull;
         if (!ballot(x != 0)) continue;
         acc += __popcll(transpose64(x));
     }
@@ -618,9 +622,25 @@ __global__ void __launch_bounds__(kBlock) batch_narrow_kernel(const uint64_t *__
     }
 }
 
-__global__ void batch_output_kernel(const int64_t *counts_acc, const int32_t *perm, int nslots, int64_t *out) {
+// A slot's count less its seed, which the count includes unless a vertex mask left the seed out.
+__global__ void batch_output_kernel(const int64_t *counts_acc, const int32_t *perm, int nslots,
+                                    const int32_t *seeds, const uint64_t *vmask, int64_t *out) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < nslots) out[perm[j]] = counts_acc[j] - 1;
+    if (j >= nslots) return;
+    const int32_t s = seeds[perm[j]];
+    const int64_t self = (!vmask || ((vmask[s >> 6] >> (s & 63)) & 1ull)) ? 1 : 0;
+    out[perm[j]] = counts_acc[j] - self;
+}
+
+// With a vertex mask: every seed starts with the vertices outside the mask
+// visited (all bits of their rows set), so no hop enters them.
+__global__ void __launch_bounds__(kBlock) batch_mask_kernel(uint64_t *V, int64_t n, int W,
+                                                           const uint64_t *__restrict__ vmask) {
+    const int64_t total = n * W;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = i / W;
+        if (!((vmask[v >> 6] >> (v & 63)) & 1ull)) V[i] = ~0ull;
+    }
 }
 
 // Serving: counts of the finished seed bits of the words in `fin` (word w's
@@ -893,7 +913,8 @@ static void launch_push(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
 }
 
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
-               const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st) {
+               const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st,
+               const uint64_t *d_vmask) {
     const int W = c->W;
     const int nslots = (int)num_seeds;
     const int64_t n = g->n;
@@ -928,6 +949,8 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
                            c->mode, levels + 1, c->cq_len, c->cq_mf);
         ps.end(3.0 * 8.0 * n * W + 3.0 * 8.0 * ((n + 63) / 64));
     }
+    if (d_vmask)
+        hipLaunchKernelGGL(batch_mask_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, n, W, d_vmask);
     hipLaunchKernelGGL(batch_seed_kernel, dim3((nslots + kBlock - 1) / kBlock), dim3(kBlock), 0, st, c->V, d_seeds,
                        c->perm, nslots, W);
     uint64_t *F = c->F, *Nb = c->N;
@@ -935,7 +958,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         ProfScope ps(g, KK_BATCH_PUSH, st);
         hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
                            g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, F, c->V, c->Fb + (int64_t)((n + 63) / 64),
-                           c->Fc + kCntLanes, chunk_queue(c, 1), c->flags + 1);
+                           c->Fc + kCntLanes, chunk_queue(c, 1), c->flags + 1, d_vmask);
         ps.end(0);
     }
     // Rows are Wr words long.  Seeds are sorted by k, so the active words of a
@@ -948,7 +971,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         ProfScope ps(g, KK_BATCH_COUNT, st);
         const int cgx = (int)std::max<int64_t>(1, std::min<int64_t>((n + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock),
                                                                      (int64_t)g->cu_count * 2));
-        hipLaunchKernelGGL(batch_count_kernel, dim3(cgx, nwords), dim3(kBlock), 0, st, V, n, Wr, w0, c->acc);
+        hipLaunchKernelGGL(batch_count_kernel, dim3(cgx, nwords), dim3(kBlock), 0, st, V, n, Wr, w0, d_vmask, c->acc);
         ps.end(8.0 * n * nwords);
     };
     for (int L = 2; L <= levels; ++L) {
@@ -1016,7 +1039,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     }
     count_words(0, Wr);
     hipLaunchKernelGGL(batch_output_kernel, dim3((nslots + 255) / 256), dim3(256), 0, st, c->acc, c->perm, nslots,
-                       d_counts);
+                       d_seeds, d_vmask, d_counts);
     KHOP_HIP(hipGetLastError());
 }
 

@@ -188,7 +188,7 @@ void plain_set(khop_graph *g, PlainCtx *c, int32_t seed, int32_t *d_ids, int64_t
 
 // abi.cpp: batched launches of a seed set (seeds on the device, ks on the host), pooled contexts
 void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int64_t num, int64_t *d_counts,
-                 hipStream_t st);
+                 hipStream_t st, const uint64_t *d_vmask = nullptr);
 
 // batched.hip
 BatchCtx *batch_ctx_create(khop_graph *g, int words);
@@ -196,8 +196,10 @@ void batch_ctx_destroy(BatchCtx *c);
 int batch_ctx_words(const BatchCtx *c);
 // Runs one batch of at most 64 * words seeds.  Slot j is seed d_seeds[h_perm[j]]
 // at depth h_ks_sorted[j] (non-increasing in j); its count goes to d_counts[h_perm[j]].
+// d_vmask (may be null): one bit per vertex, the vertices the searches may enter (the seeds are exempt).
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
-               const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st);
+               const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st,
+               const uint64_t *d_vmask = nullptr);
 
 // Serving batches (batched.hip): one per resident graph, W words of seed slots.
 struct ServeCtx;

@@ -160,3 +160,37 @@ def test_rmat21_labeled(K):
         _check_labeled(g, og, seeds, k, lab, "rmat21")
     _say("rmat21 labeled ok")
     g.free()
+
+
+@pytest.mark.parametrize("p", [0.9, 0.5, 0.15])
+def test_batched_labeled(K, g0, g0_gpu, g0_oracle, p):
+    """Batched label-filtered counts, mixed k, seeds labeled or not, equal to the oracle and to the plain form."""
+    el, seeds = g0
+    rng = np.random.default_rng(int(p * 1000))
+    lab = rng.random(el.n) < p
+    every = np.nonzero(g0_oracle.degrees() > 0)[0].astype(np.int32)
+    ks = rng.integers(0, 8, size=every.size).astype(np.int32)
+    got = g0_gpu.count_batched_labeled(every, ks, lab)
+    for i in range(0, every.size, 3):
+        assert int(got[i]) == g0_oracle.khop_filtered(int(every[i]), int(ks[i]), lab.astype(np.uint8))[0], \
+            (p, int(every[i]), int(ks[i]))
+    for k in (1, 3):
+        sel = ks == k
+        assert np.array_equal(got[sel], g0_gpu.count_labeled(every[sel], k, lab))
+    # the mask does not leak into a later unfiltered batch
+    assert np.array_equal(g0_gpu.count_batched(seeds, np.full(len(seeds), 3)), g0_oracle.count(seeds, 3)[0])
+
+
+@pytest.mark.parametrize("directed", [False, True])
+def test_batched_labeled_ragged(K, directed):
+    rng = np.random.default_rng(29 + directed)
+    src, dst, n, d = graphs.random_graph(rng, 70001, 250000, directed)
+    g = K.Graph(src, dst, n, d)
+    og = oracle.OracleGraph(src, dst, n, d)
+    lab = rng.random(n) < 0.6
+    seeds = np.concatenate([rng.integers(0, n, size=150), [0, n - 1]]).astype(np.int32)
+    ks = rng.integers(1, 9, size=seeds.size).astype(np.int32)
+    got = g.count_batched_labeled(seeds, ks, lab)
+    for i in range(seeds.size):
+        assert int(got[i]) == og.khop_filtered(int(seeds[i]), int(ks[i]), lab.astype(np.uint8))[0], (directed, i)
+    g.free()
