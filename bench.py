@@ -652,7 +652,19 @@ def filtered_bench(g, el, groups, K, torch, cpu_leg=True):
     ms = ev[0].elapsed_time(ev[1]) / 5
     out = {"label_density": 0.5, "queries": nq, "ms_per_pass": round(ms, 3), "qps": round(nq / (ms / 1e3), 1),
            "gteps": round(te / (ms / 1e3) / 1e9, 2)}
-    log(f"label-filtered protocol: {out['ms_per_pass']} ms per {nq} queries, {out['gteps']} GTEPS")
+    # the same queries as one batched call (host entry point: mask and seeds copied in, counts out)
+    all_seeds = np.concatenate([s for _, s, *_ in runs]).astype(np.int32)
+    all_ks = np.concatenate([np.full(len(s), k, np.int32) for k, s, *_ in runs])
+    plain_counts = np.concatenate([dc.cpu().numpy() for *_, dc, _ in runs])
+    b = g.count_batched_labeled(all_seeds, all_ks, lab)
+    t = time.perf_counter()
+    for _ in range(5):
+        b = g.count_batched_labeled(all_seeds, all_ks, lab)
+    bms = (time.perf_counter() - t) * 1000.0 / 5
+    out["batched"] = {"ms_per_pass_host": round(bms, 3), "qps": round(nq / (bms / 1e3), 1),
+                      "equal_to_plain": bool(np.array_equal(b, plain_counts))}
+    log(f"label-filtered protocol: {out['ms_per_pass']} ms per {nq} queries, {out['gteps']} GTEPS; "
+        f"batched {out['batched']}")
     if cpu_leg:
         import oracle
         og = oracle.OracleGraph.from_edgelist(el)
