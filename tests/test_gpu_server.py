@@ -213,3 +213,20 @@ def test_plain_lane_takes_light_load(K, graphs):
     _say("trickle latency ms p50", float(np.median(lat)))
     assert float(np.median(lat)) < 2.0
     srv.close()
+
+
+@pytest.mark.parametrize("route", ["ROUTE_PLAIN", "ROUTE_BATCH"])
+def test_expired_deadline_on_each_path(K, graphs, route):
+    """A request whose deadline has already passed times out on either path; the rest are answered."""
+    (el0, _), g, o = graphs
+    srv = K.Server(1 << 28, 64)
+    srv.set_option(K.KHOP_SERVER_ROUTE, getattr(K, "KHOP_" + route))
+    gid = srv.add_graph(g[0])
+    past = K.monotonic_ns() - 1_000_000
+    t_late = srv.submit(gid, 5, 2, deadline_ns=past)
+    t_ok = srv.submit(gid, 5, 2)
+    srv.drain(10000)
+    got = _collect(srv, 2)
+    assert got[t_late].status == K.KHOP_ETIMEDOUT
+    assert got[t_ok].status == K.KHOP_OK and got[t_ok].count == o[0].khop(5, 2)[0]
+    srv.close()
