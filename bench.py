@@ -354,7 +354,8 @@ def pmc_summary(d, copy_bytes=256 << 20):
     import re
     out = {"fetch_scale": None, "write_scale": None, "kernels": {}}
     for c, key in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
-        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(os.path.join(d, f"copy_{c}_counter_collection.csv")))
+        rows = csv.DictReader(open(os.path.join(d, f"copy_{c}_counter_collection.csv")))
+        vals = [float(r["Counter_Value"]) for r in rows
                 if "copyBuffer" in r["Kernel_Name"]]
         out[f"{key}_scale"] = round(copy_bytes / 1024.0 / (sum(vals) / len(vals)), 4)
         acc = {}
@@ -600,7 +601,8 @@ def sets_bench(g, el, groups, K, torch, cpu_leg=True):
         ids = g.neighborhood(int(s), 2)
         host.append((time.perf_counter() - t) * 1000.0)
     out = {"k": 2, "seeds": len(seeds), "ids_mean": round(float(np.mean(sizes)), 1), "ids_max": int(max(sizes)),
-           "device_ms_per_query": round(dev_ms, 4), "device_ids_per_s": round(float(np.sum(sizes)) / (dev_ms * len(seeds) / 1e3), 1),
+           "device_ms_per_query": round(dev_ms, 4),
+           "device_ids_per_s": round(float(np.sum(sizes)) / (dev_ms * len(seeds) / 1e3), 1),
            "set_kernels": {"avg_us": round(set_us, 3), "gbs": round(set_gbs, 1),
                            "bytes": "visited bitmap read twice, block counts, 4 B per id written"},
            "host_api_p50_ms": round(pct(host, 50), 4), "host_api_p99_ms": round(pct(host, 99), 4),

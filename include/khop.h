@@ -232,7 +232,8 @@ enum khop_option {
     KHOP_OPT_BATCH_HEAVY = 6,   /* batched bottom-up: degree above which a whole wave takes a vertex */
     KHOP_OPT_BATCH_PUSH = 7,    /* batched: frontier-degree fraction (1/x of arcs) under which a level goes top-down */
     KHOP_OPT_PULL_HEAVY = 8,    /* bottom-up: in-degree above which a vertex's in-edges are split into chunks */
-    KHOP_OPT_PUSH_ATOMIC = 9    /* top-down: frontier edges up to which heads are claimed atomically (else byte marks) */
+    KHOP_OPT_PUSH_ATOMIC = 9    /* top-down: frontier edges up to which heads are claimed atomically
+                                   (else byte marks) */
 };
 enum { KHOP_DIR_AUTO = 0, KHOP_DIR_PUSH = 1, KHOP_DIR_PULL = 2 };
 
