@@ -2,18 +2,25 @@
 //
 // One hop is the masked boolean product of the paper's Section II: the next
 // frontier is (A^T f) AND NOT visited over the (OR, AND) semiring.  A query is
-// one hop kernel per hop; a hop 2..k-1 is followed by a compaction kernel
-// (which exits at once unless the hop marked bytes).  Hop 1 needs no claims
-// unless the seed has more than 64 neighbors per region (all its neighbors
-// are new; it queues them 64 to a region), and a last hop only counts:
-// bottom-up it counts its finds, top-down it marks bytes that the next query
-// counts.  So neither needs a compaction.
-// Consecutive queries alternate between two sets of bitmaps and region
-// counters: hop 1 of query i also counts the byte marks query i-1 left,
-// resets the other set for query i+1 and writes the count of query i-2, so a
-// query needs no launch of its own for set-up.  Control records rotate over
-// three slots.  Every cross-block hand-off happens at a kernel boundary
-// (intra-kernel release fences would write back L2 on this multi-XCD part).
+// one hop per launch; a hop 2..k-1 is followed by a compaction kernel
+// (which exits at once unless the hop marked bytes).  All of the seed's
+// neighbors are new (a row has no duplicate and no self-loop), so hop 1
+// needs no claims unless the seed has more than 64 neighbors per region (it
+// queues them 64 to a region), and as a last hop it counts them straight
+// from the seed's row.  A later last hop only counts: bottom-up it counts
+// its finds, top-down it marks bytes that a later launch counts.  So no last
+// hop needs a compaction.
+// Consecutive queries are pipelined.  A step launch runs the last hop of
+// query i-1 and hop 1 of query i side by side on separate blocks, and on a
+// third set of blocks counts the byte marks an earlier query's last hop left,
+// writes that query's predecessor's count and sets up query i+1 (its
+// control record, and its bitmaps reset).  So a query needs no launch of its
+// own for set-up, and one of k >= 2 hops costs k-1 launches plus
+// compactions.
+// Bitmaps and region counters rotate over three states, control records over
+// four slots and queues over two sets.  Every cross-block hand-off happens at
+// a kernel boundary (intra-kernel release fences would write back L2 on this
+// multi-XCD part).
 //
 // The frontier queue is split into regions of consecutive vertices; region r
 // owns queue slots [r*RC, (r+1)*RC) and one packed 64-bit counter
@@ -36,9 +43,9 @@
 //      first hit; the ballot of hits is the word's new frontier bits.
 //      In-edges of vertices above the heavy threshold are split into chunks
 //      that any wave may scan.
-// Block 0 keeps the running count and traversed-edge sum.  Hop records,
-// region counters and frontier bitmaps rotate over three slots (hop l writes
-// slot l, reads slot l-1 and clears slot l+1), queues over two.
+// Block 0 keeps the running count and traversed-edge sum.  Within a query,
+// hop records, region counters and frontier bitmaps rotate over three slots
+// (hop l writes slot l, reads slot l-1 and clears slot l+1), queues over two.
 #include <algorithm>
 
 #include "khop_impl.h"
@@ -79,7 +86,7 @@ struct PlainCtl {
     int64_t push_atomic_max;  // frontier edges up to which a push claims heads atomically
     int32_t k, dir_mode, alpha, beta;
     int32_t valid;
-    int32_t last_bytes;  // the last hop left byte marks (counted by the next query's hop 1)
+    int32_t last_bytes;  // the last hop left byte marks (counted by a later step launch)
     int32_t reached;     // largest level found non-empty so far (the seed's is 0)
     int32_t more;        // breadth-first search: the level the last probe read is non-empty
     int64_t *level_out;  // breadth-first search: size of each level 1..level_cap (else null)
@@ -101,9 +108,10 @@ struct Graph {
     int heavy;   // bottom-up: in-degree above which the chunk table takes a vertex
 };
 
-// The bitmaps, byte map and region counters of one query parity; the queues
-// are shared by both.  (Hop 1 of a query counts the marks the previous query
-// left while, as a last hop, it may mark its own: the byte maps must differ.)
+// What one query runs on: the bitmaps, byte map and region counters of one
+// of the three states, and the queues of one of the two sets.  (A step
+// launch counts the marks an earlier query left while the query whose last
+// hop it runs may mark its own: the byte maps must differ.)
 struct State {
     uint64_t *V;       // visited bitmap
     uint64_t *F[3];    // frontier bitmaps by hop % 3
@@ -124,6 +132,14 @@ struct HeavyChunks {
     const int64_t *begin;  // first in-edge of each chunk
     const int64_t *end;    // one past its last in-edge
     int64_t n;
+};
+
+// The blocks of a launch that run one piece of its work: a launch may split
+// its grid between a hop of one query and hop 1 of the next, and each piece
+// sees only its own block index and block count.
+struct Part {
+    int64_t bid;  // block index within the piece
+    int64_t nb;   // blocks of the piece
 };
 
 
@@ -414,10 +430,10 @@ __device__ __forceinline__ void push_edge(int L, int mode, const Graph &g, const
 constexpr int kWin = 4;  // windows of 64 frontier edges in flight per wave (short queues)
 
 __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const int32_t *qcnt, const Graph &g,
-                         const State &s, RegRec *cur, uint64_t *smask, int64_t *units) {
+                         const State &s, RegRec *cur, uint64_t *smask, int64_t *units, const Part &pt) {
     const int lane = lane_id();
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = pt.nb * kWavesPerBlock;
+    const int64_t wid = pt.bid * kWavesPerBlock + threadIdx.x / kWave;
     const int64_t e0 = E * wid / nwaves, e1 = E * (wid + 1) / nwaves;
     if (e0 >= e1) return;
     uint64_t *Fn = s.F[L % 3];
@@ -553,13 +569,13 @@ __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const 
 // whole wave, 256 in-edges per round; heavier vertices come from the chunk
 // table after the words.
 __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int light, const HeavyChunks &hc,
-                         RegRec *cur, WaveBuf &wb, int64_t *found_out, int64_t *units) {
+                         RegRec *cur, WaveBuf &wb, int64_t *found_out, int64_t *units, const Part &pt) {
     const int lane = lane_id();
     light = std::min(light, g.heavy);  // the chunk table alone takes vertices above g.heavy
     const uint64_t *__restrict__ Fc = s.F[(L - 1) % 3];
     uint64_t *Fn = s.F[L % 3];
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = pt.nb * kWavesPerBlock;
+    const int64_t wid = pt.bid * kWavesPerBlock + threadIdx.x / kWave;
     int64_t c_pe = 0, c_pv = 0;
     // a contiguous run of words per wave keeps its discoveries in one or two regions
     const int64_t wpw = (g.nw + nwaves - 1) / nwaves;
@@ -709,11 +725,12 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
 // queue with a wave prefix of their out-degrees and plain stores of the
 // region's counters (the queue's regions need not match the vertices' ids;
 // full regions of at most 64 entries keep hop 2's sweep on its short path).
-__device__ void hop1_push_free(const Graph &g, const State &s, int64_t beg, int64_t E, int64_t *units) {
+__device__ void hop1_push_free(const Graph &g, const State &s, int64_t beg, int64_t E, int64_t *units,
+                               const Part &pt) {
     const int lane = lane_id();
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
+    const int64_t nwaves = pt.nb * kWavesPerBlock;
     RegRec *cur = s.regs + s.nreg;  // hop 1's slot
-    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c * kWave < E; c += nwaves) {
+    for (int64_t c = pt.bid * kWavesPerBlock + threadIdx.x / kWave; c * kWave < E; c += nwaves) {
         const int64_t e = c * kWave + lane;
         int64_t vb = 0, od = 0, id = 0;
         bool take = e < E;
@@ -749,15 +766,15 @@ __device__ void hop1_push_free(const Graph &g, const State &s, int64_t beg, int6
     }
 }
 
-// Top-down hop 1: the seed alone is the frontier, so its out-edges are read
-// straight from its adjacency list (64 per wave) with no region prefix or
-// queue search.  As the query's last hop it only marks bytes; otherwise heads
-// are claimed with atomicOr on their visited words (their row pointers are
-// loaded beside the claim) and appended.
-__device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E, bool last, int64_t *units) {
+// Top-down hop 1 of a hub seed, not the query's last hop: the seed alone is
+// the frontier, so its out-edges are read straight from its adjacency list
+// (64 per wave) with no region prefix or queue search.  Heads are claimed
+// with atomicOr on their visited words (their row pointers are loaded beside
+// the claim) and appended to the regions of their ids.
+__device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E, int64_t *units, const Part &pt) {
     const int lane = lane_id();
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    const int64_t nwaves = pt.nb * kWavesPerBlock;
+    const int64_t wid = pt.bid * kWavesPerBlock + threadIdx.x / kWave;
     RegRec *cur = s.regs + s.nreg;  // hop 1's slot
     uint64_t *Fn = s.F[1];
     int64_t edges = 0;
@@ -765,19 +782,15 @@ __device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E
         const int64_t e = e0 + lane;
         if (e < E) {
             const int32_t v = g.colidx[beg + e];
-            if (last) {
-                mark(s, v);
-            } else {
-                const uint64_t bit = 1ull << (v & 63);
-                const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
-                const int64_t vb = g.rowptr[v];
-                const int64_t od = g.rowptr[v + 1] - vb;
-                const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
-                if (!(old & bit)) {
-                    atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
-                    if (s.dist) s.dist[v] = 1;
-                    append_one(s, cur, 1, v, vb, od, id);
-                }
+            const uint64_t bit = 1ull << (v & 63);
+            const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
+            const int64_t vb = g.rowptr[v];
+            const int64_t od = g.rowptr[v + 1] - vb;
+            const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
+            if (!(old & bit)) {
+                atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                if (s.dist) s.dist[v] = 1;
+                append_one(s, cur, 1, v, vb, od, id);
             }
         }
         edges += std::min<int64_t>(kWave, E - e0);
@@ -786,14 +799,41 @@ __device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E
     if (units && lane == 0 && edges) unit_add(units, 0, 4 * edges);
 }
 
+// Top-down hop 1 as the query's last hop: the seed's row is tested against
+// the visited bitmap (the seed and, under a vertex mask, the vertices outside
+// it) and the new heads are counted.  A row holds no duplicate, so each head
+// is counted once with no claim, and nothing is left for a later count.
+__device__ void hop1_last(PlainCtl *ctl, const Graph &g, const State &s, int64_t beg, int64_t E, int64_t *units,
+                          const Part &pt) {
+    const int lane = lane_id();
+    const int64_t nwaves = pt.nb * kWavesPerBlock;
+    const int64_t wid = pt.bid * kWavesPerBlock + threadIdx.x / kWave;
+    int64_t found = 0, edges = 0;
+    for (int64_t e0 = wid * kWave; e0 < E; e0 += nwaves * kWave) {
+        const int64_t e = e0 + lane;
+        bool fresh = false;
+        if (e < E) {
+            const int32_t v = g.colidx[beg + e];
+            fresh = !((s.V[v >> 6] >> (v & 63)) & 1ull);
+        }
+        found += __popcll(ballot(fresh));
+        edges += std::min<int64_t>(kWave, E - e0);
+    }
+    if (lane == 0) {
+        add_tail(ctl, wid, found);
+        // 4 B per out-edge of the seed and 8 B of its head's visited word
+        if (units && edges) unit_add(units, 0, 12 * edges);
+    }
+}
+
 // One hop of query ctl on its state s.  No validity test: an invalid seed
 // leaves every region counter at zero, so each of its hops sees an empty
 // frontier.  The control words are read up front, beside the region
 // counters, so their loads overlap.
 __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, int light, const HeavyChunks &hc,
-                         int64_t *units) {
+                         int64_t *units, const Part &pt) {
     const int t = threadIdx.x, lane = lane_id(), wv = t / kWave;
-    const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + wv;
+    const int64_t wid = pt.bid * kWavesPerBlock + wv;
     // wave 0 loads the previous hop's region counters (four per lane) first, so
     // that their loads are in flight with the control words'
     constexpr int kRpl = kMaxRegions / kWave;  // regions per lane
@@ -813,12 +853,12 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
     if (!last) {
         // the slots hop l+1 writes start clear
         RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
-        for (int64_t i = (int64_t)blockIdx.x * kBlock + t; i < s.nreg; i += (int64_t)gridDim.x * kBlock) {
+        for (int64_t i = pt.bid * kBlock + t; i < s.nreg; i += pt.nb * kBlock) {
             nx[i].qpack = 0;
             nx[i].fpack = 0;
         }
         uint64_t *Fz = s.F[(L + 1) % 3];
-        for (int64_t w = (int64_t)blockIdx.x * kBlock + t; w < g.nw; w += (int64_t)gridDim.x * kBlock) Fz[w] = 0;
+        for (int64_t w = pt.bid * kBlock + t; w < g.nw; w += pt.nb * kBlock) Fz[w] = 0;
     }
     if (L == 1) {
         // the same direction test as below, on the seed's degrees; when it
@@ -829,19 +869,20 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
                                          (dir_mode != DIR_PULL && (hp.dir == DIR_PUSH ? E * (int64_t)alpha <= mu
                                                                                        : (int64_t)beta < g.n)));
         if (push) {
-            if (blockIdx.x == 0 && t == 0) {
+            if (pt.bid == 0 && t == 0) {
                 ctl->hdr[1].mu_before = mu;
                 ctl->hdr[1].dir = DIR_PUSH;
-                ctl->hdr[1].mode = last ? MODE_PUSH_BYTES : MODE_PUSH_ATOMIC;
-                if (last) ctl->last_bytes = 1;
+                ctl->hdr[1].mode = MODE_PUSH_ATOMIC;
                 ctl->te_acc += E;
                 if (units) unit_add(units, 0, 24);
             }
             // (one region of rc >= 64 slots per 64 neighbors)
-            if (!last && E <= (int64_t)kWave * s.nreg)
-                hop1_push_free(g, s, beg, E, units);
+            if (last)
+                hop1_last(ctl, g, s, beg, E, units, pt);
+            else if (E <= (int64_t)kWave * s.nreg)
+                hop1_push_free(g, s, beg, E, units, pt);
             else
-                hop1_push(g, s, beg, E, last, units);
+                hop1_push(g, s, beg, E, units, pt);
             return;
         }
     }
@@ -898,7 +939,7 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
     const int mode = nf == 0 ? MODE_IDLE
                      : dir == DIR_PULL ? MODE_PULL
                      : (!last && E <= push_atomic_max ? MODE_PUSH_ATOMIC : MODE_PUSH_BYTES);
-    if (blockIdx.x == 0 && t == 0) {
+    if (pt.bid == 0 && t == 0) {
         ctl->hdr[L % 3].mu_before = mu;
         ctl->hdr[L % 3].dir = dir;
         ctl->hdr[L % 3].mode = mode;
@@ -916,60 +957,89 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
         __shared__ int64_t s_bv[kWavesPerBlock][kBufCap];
         __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
         WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
-        pull_hop(L, last, g, s, light, hc, cur, wb, &found, units);
+        pull_hop(L, last, g, s, light, hc, cur, wb, &found, units, pt);
         found = shfl64(found, 0);
     } else {
-        push_hop(L, mode, E, s_epre, s_qcnt, g, s, cur, s_mask[wv], units);
+        push_hop(L, mode, E, s_epre, s_qcnt, g, s, cur, s_mask[wv], units, pt);
     }
     if (last && lane == 0) add_tail(ctl, wid, found);
 }
 
-// Hop 1 of query ctl (state s).  Before it: the byte marks the previous query
-// (ctl_prev, state sn) left are counted, sn is reset for the next query qn,
-// and the control slot ctl_next, which still holds the query two back, is
-// finalized and then set up for qn.
-__global__ void __launch_bounds__(kBlock) plain_hop1_kernel(PlainCtl *ctl, PlainCtl *ctl_prev, PlainCtl *ctl_next,
-                                                           int close_prev, int fin_next, Graph g, State s, State sn,
-                                                           const int32_t *seeds, int64_t qn, int k, int dir_mode,
-                                                           int alpha, int beta, int64_t push_atomic_max,
-                                                           int64_t nnz_in, int64_t *out_count, int64_t *out_te,
-                                                           int light, HeavyChunks hc, int64_t *units) {
-    const bool marks = close_prev && ctl_prev->last_bytes;  // ctl_prev is not written in this kernel
-    const int32_t nseed = qn >= 0 ? seeds[qn] : -1;
+// The work of a step launch besides its hops: the byte marks that a finished
+// query's last hop left are counted, the count of the query before it is
+// written, and the next query is set up (its record, and its state's bitmaps
+// reset).  The marks' state may be the one reset: each word is counted before
+// it is reset, by the same thread.
+struct StepBook {
+    PlainCtl *ctl_marks;  // the query whose marks are counted (null: none)
+    PlainCtl *ctl_fin;    // the query whose count is written (null: none)
+    PlainCtl *ctl_setup;  // the record set up for query qn (may be ctl_fin's slot: written after it)
+    int64_t qn;           // next query, -1 if none
+    const int32_t *seeds;
+    int64_t *out_count;
+    int64_t *out_te;
+    int64_t push_atomic_max;
+    int64_t nnz_in;
+    int32_t k, dir_mode, alpha, beta;
+};
+
+// One step of the query pipeline, three pieces of work in one launch, each on
+// blocks of its own: the last hop (hop k) of the previous query (nb_last
+// blocks, ctl_last on state sl), hop 1 of the current query (nb_h1 blocks,
+// ctl_h1 on state s1), and the bookkeeping of bk on the remaining blocks
+// (marks of state sm, reset of state sr).  The pieces share no memory but the
+// profiling counters, so the second query's hop 1 overlaps the first's last
+// hop.  Every hand-off between them happens at the launch boundary.
+__global__ void __launch_bounds__(kBlock) plain_step_kernel(PlainCtl *ctl_last, State sl, int64_t nb_last,
+                                                           PlainCtl *ctl_h1, State s1, int64_t nb_h1, StepBook bk,
+                                                           State sm, State sr, Graph g, int light, HeavyChunks hc,
+                                                           int64_t *units) {
+    const int64_t b = blockIdx.x;
+    if (b < nb_last) {
+        hop_body(ctl_last, bk.k, g, sl, light, hc, units, Part{b, nb_last});
+        return;
+    }
+    if (b < nb_last + nb_h1) {
+        hop_body(ctl_h1, 1, g, s1, light, hc, units, Part{b - nb_last, nb_h1});
+        return;
+    }
+    const Part pt{b - nb_last - nb_h1, (int64_t)gridDim.x - nb_last - nb_h1};
+    const int t = threadIdx.x;
+    const bool marks = bk.ctl_marks && bk.ctl_marks->last_bytes;  // not written in this launch
+    const int32_t nseed = bk.qn >= 0 ? bk.seeds[bk.qn] : -1;
     const bool nvalid = nseed >= 0 && (int64_t)nseed < g.n;
     const int64_t nsw = nvalid ? (nseed >> 6) : -1;
     const uint64_t nsbit = nvalid ? (1ull << (nseed & 63)) : 0;
     int64_t fresh = 0, flagged = 0;
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock) {
-        if (marks && sn.nsum[w]) {
-            fresh += close_marks_word(sn, w, sn.V[w]);
+    for (int64_t w = pt.bid * kBlock + t; w < g.nw; w += pt.nb * kBlock) {
+        if (marks && sm.nsum[w]) {
+            fresh += close_marks_word(sm, w, sm.V[w]);
             ++flagged;
         }
-        if (qn >= 0) reset_word(sn, g, w, nsw, nsbit);
+        if (bk.qn >= 0) reset_word(sr, g, w, nsw, nsbit);
     }
     if (marks) {
         fresh = wave_sum(fresh);
         flagged = wave_sum(flagged);
-        if (lane_id() == 0) add_tail(ctl_prev, (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave, fresh);
+        if (lane_id() == 0) add_tail(bk.ctl_marks, pt.bid * kWavesPerBlock + t / kWave, fresh);
         // the summary bytes, then the marks and visited word of each flagged word
         if (lane_id() == 0) unit_add(units, 0, 72 * flagged);
-        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.nw);
+        if (pt.bid == 0 && t == 0) unit_add(units, 0, g.nw);
     }
-    // the last block closes the slot and sets it up, beside the hop's own
-    // work, which starts at block 0
-    if (blockIdx.x == gridDim.x - 1) {
-        if (fin_next && threadIdx.x < kWave) finalize(ctl_next);
+    // the last block writes the finished count, then sets up the next query
+    // (possibly in the same slot)
+    if (pt.bid == pt.nb - 1) {
+        if (bk.ctl_fin && t < kWave) finalize(bk.ctl_fin);
         __syncthreads();
-        if (qn >= 0)
-            setup_query(ctl_next, g, sn, nseed, qn, k, dir_mode, alpha, beta, push_atomic_max, nnz_in, out_count,
-                        out_te, units);
+        if (bk.qn >= 0)
+            setup_query(bk.ctl_setup, g, sr, nseed, bk.qn, bk.k, bk.dir_mode, bk.alpha, bk.beta, bk.push_atomic_max,
+                        bk.nnz_in, bk.out_count, bk.out_te, units);
     }
-    hop_body(ctl, 1, g, s, light, hc, units);
 }
 
 __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L, Graph g, State s, int light,
                                                           HeavyChunks hc, int64_t *units) {
-    hop_body(ctl, L, g, s, light, hc, units);
+    hop_body(ctl, L, g, s, light, hc, units, Part{(int64_t)blockIdx.x, (int64_t)gridDim.x});
 }
 
 // After a byte-mode push: ballot(mark AND NOT visited) per 64-vertex word is
@@ -1181,10 +1251,20 @@ __global__ void fill_kernel(int64_t *a, int64_t *b, int64_t n, int64_t value) {
 
 }  // namespace
 
+// Three bitmap states and four control slots rotate over consecutive queries
+// (query q uses state q % 3 and slot q % 4): a step launch works on the last
+// hop of query q-1 and hop 1 of query q, counts the marks of an earlier query
+// and resets the state of query q+1.  Queues are needed only by the two
+// queries with hops in flight, so they rotate by query parity.
+constexpr int kStates = 3;
+constexpr int kSlots = 4;
+
 struct PlainCtx {
     khop_graph *g = nullptr;
-    PlainCtl *ctl = nullptr;  // three control slots
-    State s[2]{};             // the two query parities
+    PlainCtl *ctl = nullptr;  // kSlots control slots
+    State s[kStates]{};       // bitmaps, byte maps and region counters of each state
+    int64_t *qb[2][2]{};      // queue sets by query parity, each by hop parity
+    int64_t *qoff[2][2]{};
     int hop_grid = 1;
     int init_grid = 1;
     int compact_grid = 1;
@@ -1192,6 +1272,24 @@ struct PlainCtx {
     int64_t set_blocks = 0;
     void *arena = nullptr;
 };
+
+namespace {
+
+// The state query q runs on: bitmaps of state q % 3, queues of set q % 2.
+State query_state(const PlainCtx *c, int64_t q, const uint64_t *vmask, int32_t *dist) {
+    State x = c->s[q % kStates];
+    for (int i = 0; i < 2; ++i) {
+        x.qb[i] = c->qb[q & 1][i];
+        x.qoff[i] = c->qoff[q & 1][i];
+    }
+    x.vmask = vmask;
+    x.dist = dist;
+    return x;
+}
+
+PlainCtl *query_slot(const PlainCtx *c, int64_t q) { return c->ctl + q % kSlots; }
+
+}  // namespace
 
 PlainCtx *plain_ctx_create(khop_graph *g) {
     PlainCtx *c = new PlainCtx();
@@ -1204,9 +1302,9 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     size_t off = 0;
     const size_t o_ctl = off;
-    off += al(3 * sizeof(PlainCtl));
-    size_t o_V[2], o_F[2][3], o_regs[2], o_nb[2], o_ns[2];
-    for (int p = 0; p < 2; ++p) {
+    off += al(kSlots * sizeof(PlainCtl));
+    size_t o_V[kStates], o_F[kStates][3], o_regs[kStates], o_nb[kStates], o_ns[kStates];
+    for (int p = 0; p < kStates; ++p) {
         o_nb[p] = off;
         off += al(nw * 64);  // the byte map, padded to whole words
         o_ns[p] = off;
@@ -1223,13 +1321,14 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     const int64_t set_blocks = (nw + kBlock - 1) / kBlock;
     const size_t o_part = off;
     off += al((size_t)set_blocks * 8);
-    size_t o_q[2], o_qoff[2];
-    for (int i = 0; i < 2; ++i) {
-        o_q[i] = off;
-        off += al(slots * 8);
-        o_qoff[i] = off;
-        off += al(slots * 8);
-    }
+    size_t o_q[2][2], o_qoff[2][2];
+    for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) {
+            o_q[j][i] = off;
+            off += al(slots * 8);
+            o_qoff[j][i] = off;
+            off += al(slots * 8);
+        }
     hipError_t e = hipMalloc(&c->arena, off);
     if (e != hipSuccess) {
         delete c;
@@ -1240,17 +1339,18 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     c->ctl = (PlainCtl *)(base + o_ctl);
     c->set_partial = (int64_t *)(base + o_part);
     c->set_blocks = set_blocks;
-    for (int p = 0; p < 2; ++p) {
+    for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) {
+            c->qb[j][i] = (int64_t *)(base + o_q[j][i]);
+            c->qoff[j][i] = (int64_t *)(base + o_qoff[j][i]);
+        }
+    for (int p = 0; p < kStates; ++p) {
         State &st = c->s[p];
         st.V = (uint64_t *)(base + o_V[p]);
         for (int i = 0; i < 3; ++i) st.F[i] = (uint64_t *)(base + o_F[p][i]);
         st.regs = (RegRec *)(base + o_regs[p]);
         st.nextb = (uint8_t *)(base + o_nb[p]);
         st.nsum = (uint8_t *)(base + o_ns[p]);
-        for (int i = 0; i < 2; ++i) {
-            st.qb[i] = (int64_t *)(base + o_q[i]);
-            st.qoff[i] = (int64_t *)(base + o_qoff[i]);
-        }
         st.nreg = nreg;
         st.rw = rw;
         st.rc = rc;
@@ -1290,53 +1390,66 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
     const int64_t nnz_in = g->nnz;
     const int64_t pam = (int64_t)P.push_atomic_max;
-    // hop 1 starts from the seed alone (top-down unless forced) and resets the
-    // other parity's bitmaps: the set-up grid suffices
-    const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
-    PlainCtl *ctl = c->ctl;
-    State sp[2] = {c->s[0], c->s[1]};  // the two parities, with the vertex mask of this run
-    sp[0].vmask = sp[1].vmask = d_vmask;
+    // hop 1 starts from the seed alone (top-down unless forced): the set-up
+    // grid suffices
+    const int h1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
+    auto state = [&](int64_t q) { return query_state(c, q, d_vmask, nullptr); };
+    auto slot = [&](int64_t q) { return query_slot(c, q); };
     {
         ProfScope ps(g, KK_PLAIN_INIT, st);
-        hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, sp[0], d_seeds,
-                           (int64_t)0, (int)k, P.dir_mode, P.alpha, P.beta, pam, nnz_in, d_counts, d_te, ps.units());
+        hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, slot(0), gr, state(0),
+                           d_seeds, (int64_t)0, (int)k, P.dir_mode, P.alpha, P.beta, pam, nnz_in, d_counts, d_te,
+                           ps.units());
         ps.end(0, 1);
     }
-    for (int64_t i = 0; i < num_seeds; ++i) {
-        const int p = (int)(i & 1);
-        PlainCtl *cq = ctl + i % 3, *cprev = ctl + (i + 2) % 3, *cnext = ctl + (i + 1) % 3;
+    // Step j runs the last hop of query j-1 (when k >= 2) beside hop 1 of
+    // query j; hops 2..k-1 of query j follow it.  A query's last-hop marks
+    // are counted by the step after the one that ran that hop, and its count
+    // is written by the step after that.
+    const int64_t m = num_seeds;
+    for (int64_t j = 0; j <= m; ++j) {
+        const bool h1 = j < m, lastp = k >= 2 && j >= 1;
+        if (!h1 && !lastp) break;
+        const int64_t qm = k >= 2 ? j - 2 : j - 1;  // marks left by the previous step
+        const int64_t qn = j + 1 < m ? j + 1 : -1;
+        const StepBook bk{qm >= 0 ? slot(qm) : nullptr, qm >= 1 ? slot(qm - 1) : nullptr,
+                          qn >= 0 ? slot(qn) : nullptr, qn, d_seeds, d_counts, d_te, pam, nnz_in, (int32_t)k,
+                          (int32_t)P.dir_mode, (int32_t)P.alpha, (int32_t)P.beta};
+        const int64_t nb_last = lastp ? c->hop_grid : 0, nb_h1 = h1 ? h1_grid : 0;
+        const int64_t nb_book = (qm >= 0 || qn >= 0) ? c->init_grid : 0;
         {
             ProfScope ps(g, KK_PLAIN_HOP, st);
-            hipLaunchKernelGGL(plain_hop1_kernel, dim3(hop1_grid), dim3(kBlock), 0, st, cq, cprev, cnext,
-                               (int)(i >= 1), (int)(i >= 2), gr, sp[p], sp[p ^ 1], d_seeds,
-                               i + 1 < num_seeds ? i + 1 : (int64_t)-1, (int)k, P.dir_mode, P.alpha, P.beta, pam,
-                               nnz_in, d_counts, d_te, P.pull_light, hc, ps.units());
+            hipLaunchKernelGGL(plain_step_kernel, dim3((unsigned)(nb_last + nb_h1 + nb_book)), dim3(kBlock), 0, st,
+                               lastp ? slot(j - 1) : nullptr, lastp ? state(j - 1) : State{}, nb_last,
+                               h1 ? slot(j) : nullptr, h1 ? state(j) : State{}, nb_h1, bk,
+                               qm >= 0 ? state(qm) : State{}, qn >= 0 ? state(qn) : State{}, gr, P.pull_light, hc,
+                               ps.units());
             ps.end(0, 1);
         }
-        for (int L = 2; L <= k; ++L) {
+        if (!h1) continue;
+        PlainCtl *cq = slot(j);
+        const State sq = state(j);
+        for (int L = 2; L < k; ++L) {
             {
                 ProfScope ps(g, KK_PLAIN_HOP, st);
-                hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, cq, L, gr, sp[p],
+                hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, cq, L, gr, sq,
                                    P.pull_light, hc, ps.units());
                 ps.end(0, 1);
             }
-            if (L < k) {
-                ProfScope ps(g, KK_PLAIN_COMPACT, st);
-                hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, cq, L, gr,
-                                   sp[p], ps.units());
-                ps.end(0, 1);
-            }
+            ProfScope ps(g, KK_PLAIN_COMPACT, st);
+            hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, cq, L, gr, sq,
+                               ps.units());
+            ps.end(0, 1);
         }
     }
     // the last query's marks and the count of the one before it, then the last count
-    const int64_t m = num_seeds;
     {
         ProfScope ps(g, KK_PLAIN_INIT, st);
-        hipLaunchKernelGGL(plain_close_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl + (m - 1) % 3,
-                           ctl + (m + 1) % 3, (int)(m >= 2), gr, sp[(m - 1) & 1], ps.units());
+        hipLaunchKernelGGL(plain_close_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, slot(m - 1),
+                           m >= 2 ? slot(m - 2) : nullptr, (int)(m >= 2), gr, state(m - 1), ps.units());
         ps.end(0, 1);
     }
-    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, ctl + (m - 1) % 3);
+    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, slot(m - 1));
     KHOP_HIP(hipGetLastError());
 }
 
@@ -1349,10 +1462,8 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
     const int64_t pam = (int64_t)P.push_atomic_max;
     const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
-    State s = c->s[0];
-    s.dist = d_dist;
-    s.vmask = nullptr;
-    PlainCtl *ctl = c->ctl;
+    const State s = query_state(c, 0, nullptr, d_dist);
+    PlainCtl *ctl = query_slot(c, 0);
     {
         ProfScope ps(g, KK_PLAIN_INIT, st);
         hipLaunchKernelGGL(plain_bfs_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, s, seed, d_levels,
@@ -1368,10 +1479,11 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
         for (int64_t L = H + 1; L <= upto; ++L) {
             ProfScope ps(g, KK_PLAIN_HOP, st);
             if (L == 1) {
-                // the set-up above replaces the pipeline's close and set-up work (no previous or next query)
-                hipLaunchKernelGGL(plain_hop1_kernel, dim3(hop1_grid), dim3(kBlock), 0, st, ctl, ctl + 2, ctl + 1, 0,
-                                   0, gr, s, c->s[1], (const int32_t *)nullptr, (int64_t)-1, INT32_MAX, P.dir_mode,
-                                   P.alpha, P.beta, pam, g->nnz, (int64_t *)nullptr, (int64_t *)nullptr,
+                // hop 1 alone: the set-up above replaces the pipeline's other work
+                const StepBook bk{nullptr, nullptr, nullptr, -1, nullptr, nullptr, nullptr, pam, g->nnz, INT32_MAX,
+                                  (int32_t)P.dir_mode, (int32_t)P.alpha, (int32_t)P.beta};
+                hipLaunchKernelGGL(plain_step_kernel, dim3(hop1_grid), dim3(kBlock), 0, st, (PlainCtl *)nullptr,
+                                   State{}, (int64_t)0, ctl, s, (int64_t)hop1_grid, bk, State{}, State{}, gr,
                                    P.pull_light, hc, ps.units());
                 ps.end(0, 1);
                 continue;
