@@ -194,3 +194,15 @@ def test_batched_labeled_ragged(K, directed):
     for i in range(seeds.size):
         assert int(got[i]) == og.khop_filtered(int(seeds[i]), int(ks[i]), lab.astype(np.uint8))[0], (directed, i)
     g.free()
+
+
+def test_pipeline_run_lengths_labeled(K, g0, g0_gpu, g0_oracle):
+    """Label-filtered runs of 1 to 9 queries at k = 1..3 through the host entry
+    point, which runs all of a call's seeds as one pipelined sequence."""
+    el, seeds = g0
+    rng = np.random.default_rng(55)
+    lab = rng.random(el.n) < 0.5
+    for k in (1, 2, 3):
+        for m in rng.permutation(np.arange(1, 10)):
+            s = seeds[rng.integers(0, len(seeds), size=int(m))].astype(np.int32)
+            _check_labeled(g0_gpu, g0_oracle, s, k, lab, ("run", k, int(m)))

@@ -281,3 +281,55 @@ def test_hub_seed_takes_the_claiming_hop1(K, mode):
         dist, count, depth = g.bfs(s)
         assert np.array_equal(dist, og.distances(s, 2**31 - 1)), (mode, s)
     g.free()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_pipeline_run_lengths(K, g0, g0_gpu, g0_oracle, mode):
+    """Device runs of 1 to 9 queries at k = 1..4, back to back on one context.
+    Consecutive queries share launches: a query's last hop runs beside the
+    next one's hop 1, and bitmaps, control records and queues rotate over
+    three, four and two sets.  Every length puts the run's end at a different
+    phase of that rotation, and each run starts from the first set again."""
+    import torch
+    el, seeds = g0
+    _set_mode(K, g0_gpu, mode)
+    rng = np.random.default_rng(77)
+    for k in (1, 2, 3, 4):
+        for m in rng.permutation(np.arange(1, 10)):
+            s = seeds[rng.integers(0, len(seeds), size=int(m))].astype(np.int32)
+            d_s = torch.from_numpy(s).cuda()
+            d_c = torch.full((int(m),), -7, dtype=torch.int64, device="cuda")
+            d_t = torch.full((int(m),), -7, dtype=torch.int64, device="cuda")
+            g0_gpu.count_dev(d_s, k, d_c, d_t)
+            torch.cuda.synchronize()
+            oc, ote = g0_oracle.count(s, k)
+            assert np.array_equal(d_c.cpu().numpy(), oc), (mode, k, int(m))
+            assert np.array_equal(d_t.cpu().numpy(), ote), (mode, k, int(m))
+    _set_mode(K, g0_gpu, "auto")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_pipeline_hub_and_leaf_seeds(K, mode):
+    """Hub seeds (40 000 neighbors: the claiming hop 1) between leaf seeds in
+    one device run, so the hub's hop 1 shares its launch with a leaf query's
+    last hop and the other way round; invalid seeds in between answer -1."""
+    import torch
+    n = 40000
+    src = np.concatenate([np.zeros(n - 1, np.int32), np.arange(1, 4001, 2, dtype=np.int32)])
+    dst = np.concatenate([np.arange(1, n, dtype=np.int32), np.arange(2, 4002, 2, dtype=np.int32)])
+    g = K.Graph(src, dst, n)
+    og = oracle.OracleGraph(src, dst, n, False)
+    _set_mode(K, g, mode)
+    s = np.array([0, 5, 0, 0, 3001, -1, 0, 12, n, 39999, 0], np.int32)
+    ok = (s >= 0) & (s < n)
+    d_s = torch.from_numpy(s).cuda()
+    for k in (1, 2, 3):
+        d_c = torch.zeros(len(s), dtype=torch.int64, device="cuda")
+        d_t = torch.zeros(len(s), dtype=torch.int64, device="cuda")
+        g.count_dev(d_s, k, d_c, d_t)
+        torch.cuda.synchronize()
+        c, t = d_c.cpu().numpy(), d_t.cpu().numpy()
+        oc, ote = og.count(s[ok], k)
+        assert np.array_equal(c[ok], oc) and np.array_equal(t[ok], ote), (mode, k)
+        assert (c[~ok] == -1).all() and (t[~ok] == -1).all(), (mode, k)
+    g.free()
