@@ -355,7 +355,10 @@ void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int
                         int64_t *d_counts, hipStream_t st, const uint64_t *d_vmask) {
     std::vector<int32_t> order((size_t)num);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return h_ks[a] > h_ks[b]; });
+    // by k, largest first, except that one-hop queries go last: they take no
+    // bit (a launch answers them from their seeds' rows)
+    auto key = [&](int32_t i) { return h_ks[i] == 1 ? -1 : h_ks[i]; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) > key(b); });
     const int per = std::max(64, std::min(1024, g->params.batch_seeds));
     for (int64_t at = 0; at < num; at += per) {
         const int64_t cnt = std::min<int64_t>(per, num - at);

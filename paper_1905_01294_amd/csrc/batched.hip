@@ -174,6 +174,38 @@ __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t 
     if (lane_id() == 0) fb_count(fb_cnt, fresh);
 }
 
+// One-hop queries take no bit: a wave per seed tests the seed's row against
+// the visited set a one-hop search starts from (the seed and, under a vertex
+// mask, the vertices outside it) and counts the neighbors that pass.  A row
+// holds no duplicate, so each neighbor counts once, as its bit would in the
+// bit-column count.
+__global__ void __launch_bounds__(kBlock) batch_row_count_kernel(const int64_t *__restrict__ rowptr,
+                                                                const int32_t *__restrict__ colidx,
+                                                                const int32_t *seeds, const int32_t *perm, int nq,
+                                                                const uint64_t *__restrict__ vmask, int64_t *out,
+                                                                int64_t *units) {
+    const int lane = lane_id();
+    const int q = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
+    if (q >= nq) return;  // wave-uniform
+    const int32_t i = perm[q];
+    const int32_t s = seeds[i];
+    const int64_t b = rowptr[s], e = rowptr[s + 1];
+    int64_t c = 0;
+    for (int64_t x0 = b; x0 < e; x0 += kWave) {
+        const int64_t x = x0 + lane;
+        bool fresh = false;
+        if (x < e) {
+            const int32_t v = colidx[x];
+            fresh = v != s && (!vmask || ((vmask[v >> 6] >> (v & 63)) & 1ull));
+        }
+        c += __popcll(ballot(fresh));
+    }
+    if (lane == 0) {
+        out[i] = c;
+        if (units) unit_add(units, 0, e - b);
+    }
+}
+
 // Bits of the groups of G lanes that have any bit of m: bit g for group g.
 template <int G>
 __device__ __forceinline__ uint64_t group_any(uint64_t m) {
@@ -915,8 +947,13 @@ static void launch_push(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
                const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st,
                const uint64_t *d_vmask) {
-    const int W = c->W;
-    const int nslots = (int)num_seeds;
+    // Slots come sorted by k, largest first, with the one-hop queries last:
+    // those are answered from their seeds' rows and take no bit, so the rows
+    // of the bitsets are W words wide for the other nslots slots.
+    int nslots = (int)num_seeds;
+    while (nslots > 0 && h_ks_sorted[nslots - 1] == 1) --nslots;
+    const int W = std::max(1, (nslots + 63) / 64);
+    const int Wc = c->W;  // the stride of the active-mask table
     const int64_t n = g->n;
     int kmax = 0;
     for (int j = 0; j < nslots; ++j) kmax = std::max(kmax, h_ks_sorted[j]);
@@ -925,22 +962,33 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     KHOP_HIP(hipEventSynchronize(c->stage_ev));
     // active masks and active word counts per level
     uint64_t *act = c->h_act;
-    std::fill(act, act + (size_t)std::max(levels, 1) * W, 0ull);
+    std::fill(act, act + (size_t)std::max(levels, 1) * Wc, 0ull);
     std::vector<int> wact(std::max(levels, 1) + 1, 0);
     for (int L = 1; L <= levels; ++L) {
         for (int j = 0; j < nslots; ++j)
             if (h_ks_sorted[j] >= L) {
-                act[(size_t)(L - 1) * W + (j >> 6)] |= 1ull << (j & 63);
+                act[(size_t)(L - 1) * Wc + (j >> 6)] |= 1ull << (j & 63);
                 wact[L] = std::max(wact[L], (j >> 6) + 1);
             }
     }
-    std::copy(h_perm, h_perm + nslots, c->h_perm);
-    std::copy(h_ks_sorted, h_ks_sorted + nslots, c->h_ks);
+    std::copy(h_perm, h_perm + num_seeds, c->h_perm);
+    std::copy(h_ks_sorted, h_ks_sorted + num_seeds, c->h_ks);
     if (levels > 0)
-        KHOP_HIP(hipMemcpyAsync(c->act, act, (size_t)levels * W * 8, hipMemcpyHostToDevice, st));
-    KHOP_HIP(hipMemcpyAsync(c->perm, c->h_perm, (size_t)nslots * 4, hipMemcpyHostToDevice, st));
-    KHOP_HIP(hipMemcpyAsync(c->ks, c->h_ks, (size_t)nslots * 4, hipMemcpyHostToDevice, st));
+        KHOP_HIP(hipMemcpyAsync(c->act, act, (size_t)levels * Wc * 8, hipMemcpyHostToDevice, st));
+    KHOP_HIP(hipMemcpyAsync(c->perm, c->h_perm, (size_t)num_seeds * 4, hipMemcpyHostToDevice, st));
+    KHOP_HIP(hipMemcpyAsync(c->ks, c->h_ks, (size_t)num_seeds * 4, hipMemcpyHostToDevice, st));
     KHOP_HIP(hipEventRecord(c->stage_ev, st));
+    if (num_seeds > nslots) {
+        const int nq = (int)num_seeds - nslots;
+        ProfScope ps(g, KK_BATCH_PUSH, st);
+        hipLaunchKernelGGL(batch_row_count_kernel, dim3((nq + kWavesPerBlock - 1) / kWavesPerBlock), dim3(kBlock), 0,
+                           st, g->d_rowptr, g->d_colidx, d_seeds, c->perm + nslots, nq, d_vmask, d_counts,
+                           ps.units());
+        // bytes: the seed's row pointers, 4 per out-edge
+        ps.end(16.0 * nq, 4.0);
+        KHOP_HIP(hipGetLastError());
+    }
+    if (nslots == 0) return;
     const int zgrid = (int)std::min<int64_t>(((int64_t)n * W + kBlock - 1) / kBlock, (int64_t)g->cu_count * 8);
     {
         ProfScope ps(g, KK_BATCH_INIT, st);
@@ -1005,7 +1053,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
                 // one-word rows whose active seeds fit in 16 or 32 bits are gathered from a narrow copy
                 int fs_bits = 0;
                 if (Wr == 1) {
-                    const uint64_t a = act[(size_t)(L - 1) * W];
+                    const uint64_t a = act[(size_t)(L - 1) * Wc];
                     const int top = a ? 63 - __builtin_clzll(a) : 0;
                     fs_bits = top < 16 ? 16 : top < 32 ? 32 : 0;
                 }

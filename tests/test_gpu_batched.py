@@ -134,3 +134,28 @@ def test_narrowing_under_forced_top_down(K, g0, g0_oracle):
     expect = np.array([g0_oracle.khop(int(s), int(k))[0] for s, k in zip(seeds, ks)])
     assert np.array_equal(got, expect)
     g.free()
+
+
+@pytest.mark.parametrize("per", [64, 1024])
+def test_one_hop_queries_take_no_bit(K, per):
+    """One-hop queries are answered from their seeds' rows beside the bitset
+    batch: launches with only one-hop slots, with one-hop slots behind k = 0
+    and k = 2 slots, isolated seeds, and a hub of 40 000 neighbors."""
+    n = 40000
+    src = np.concatenate([np.zeros(n - 2, np.int32), np.arange(1, 4001, 2, dtype=np.int32)])
+    dst = np.concatenate([np.arange(1, n - 1, dtype=np.int32), np.arange(2, 4002, 2, dtype=np.int32)])
+    g = K.Graph(src, dst, n)  # vertex n - 1 is isolated
+    og = oracle.OracleGraph(src, dst, n, False)
+    g.set_option(K.KHOP_OPT_BATCH_SEEDS, per)
+    rng = np.random.default_rng(per)
+    seeds = np.concatenate([[0, n - 1, 3001, 0], rng.integers(0, n, size=300)]).astype(np.int32)
+    for ks in (np.ones(len(seeds), np.int32),
+               rng.choice(np.array([0, 1, 1, 1, 2]), size=len(seeds)).astype(np.int32)):
+        got = g.count_batched(seeds, ks)
+        expect = np.array([og.khop(int(s), int(k))[0] for s, k in zip(seeds, ks)])
+        assert np.array_equal(got, expect), per
+    lab = rng.random(n) < 0.5
+    got = g.count_batched_labeled(seeds, np.ones(len(seeds), np.int32), lab)
+    expect = np.array([og.khop_filtered(int(s), 1, lab.astype(np.uint8))[0] for s in seeds])
+    assert np.array_equal(got, expect)
+    g.free()
