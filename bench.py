@@ -342,8 +342,9 @@ def _source_sha(kernel):
 
 
 # GPU kernel name stem -> the kernel kind khop_profile reports it under
-KERNEL_KIND = {"plain_close": "plain_init", "plain_final": "plain_init", "batch_zero": "batch_init",
-               "batch_narrow": "batch_init", "batch_push_seeds": "batch_push", "batch_seed": "batch_init",
+KERNEL_KIND = {"plain_close": "plain_init", "plain_final": "plain_init", "plain_step": "plain_hop",
+               "batch_zero": "batch_init", "batch_narrow": "batch_init", "batch_push_seeds": "batch_push",
+               "batch_row_count": "batch_push", "batch_seed": "batch_init", "batch_frontier_copy": "batch_init",
                "batch_output": "batch_count"}
 
 
