@@ -108,7 +108,9 @@ int khop_count(khop_graph *g, const int32_t *seeds, int64_t num_seeds, int32_t k
  * d_seeds (int32), d_counts and d_traversed_edges (int64, may be NULL) are
  * device pointers of length num_seeds.  Seeds are validated on the device:
  * a seed outside [0, n) yields count -1 and traversed edges -1 for that query.
- * The caller synchronises the stream before reading the outputs.
+ * The caller synchronises the stream before reading the outputs.  The seeds
+ * are answered in order, and consecutive queries overlap by one launch: the
+ * last hop of one runs beside hop 1 of the next.
  */
 int khop_count_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
                    int64_t *d_traversed_edges, void *hip_stream);
@@ -123,8 +125,8 @@ int khop_count_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int
  * mask start visited, so NOT visited excludes them.  traversed_edges (may be
  * NULL) as in khop_count, over the vertices the filtered search expands.
  * Host pointers: label_bits has ceil(n / 64) words (bits past n ignored),
- * seeds/counts num_seeds entries.  All seeds run as one launch sequence each,
- * enqueued back to back, then one synchronisation.  Errors as khop_count,
+ * seeds/counts num_seeds entries.  All seeds are enqueued as one pipelined
+ * sequence (as khop_count_dev), then one synchronisation.  Errors as khop_count,
  * plus label_bits NULL -> KHOP_EINVAL.
  */
 int khop_count_labeled(khop_graph *g, const int32_t *seeds, int64_t num_seeds, int32_t k, const uint64_t *label_bits,
