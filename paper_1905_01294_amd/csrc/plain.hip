@@ -49,6 +49,7 @@
 #include <algorithm>
 
 #include "khop_impl.h"
+#include "plain_plan.h"
 #include "wave.h"
 
 namespace khop {
@@ -1251,13 +1252,14 @@ __global__ void fill_kernel(int64_t *a, int64_t *b, int64_t n, int64_t value) {
 
 }  // namespace
 
-// Three bitmap states and four control slots rotate over consecutive queries
-// (query q uses state q % 3 and slot q % 4): a step launch works on the last
-// hop of query q-1 and hop 1 of query q, counts the marks of an earlier query
-// and resets the state of query q+1.  Queues are needed only by the two
-// queries with hops in flight, so they rotate by query parity.
-constexpr int kStates = 3;
-constexpr int kSlots = 4;
+// Bitmap states, control slots and queue sets rotate over consecutive
+// queries as plain_plan.h lays out: a step launch works on the last hop of
+// query q-1 and hop 1 of query q, counts the marks of an earlier query and
+// resets the state of query q+1.  Queues are needed only by the two queries
+// with hops in flight, so two sets suffice.
+constexpr int kStates = kPlanStates;
+constexpr int kSlots = kPlanSlots;
+static_assert(kPlanQueueSets == 2, "queue sets rotate by query parity");
 
 struct PlainCtx {
     khop_graph *g = nullptr;
@@ -1403,32 +1405,30 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         ps.end(0, 1);
     }
     // Step j runs the last hop of query j-1 (when k >= 2) beside hop 1 of
-    // query j; hops 2..k-1 of query j follow it.  A query's last-hop marks
-    // are counted by the step after the one that ran that hop, and its count
-    // is written by the step after that.
+    // query j; hops 2..k-1 of query j follow it (plain_plan.h).
     const int64_t m = num_seeds;
-    for (int64_t j = 0; j <= m; ++j) {
-        const bool h1 = j < m, lastp = k >= 2 && j >= 1;
-        if (!h1 && !lastp) break;
-        const int64_t qm = k >= 2 ? j - 2 : j - 1;  // marks left by the previous step
-        const int64_t qn = j + 1 < m ? j + 1 : -1;
-        const StepBook bk{qm >= 0 ? slot(qm) : nullptr, qm >= 1 ? slot(qm - 1) : nullptr,
+    const int64_t nsteps = plain_plan_steps(k, m);
+    for (int64_t j = 0; j < nsteps; ++j) {
+        const PlainStep ps_j = plain_plan_step(k, m, j);
+        const int64_t qm = ps_j.marks, qn = ps_j.setup;
+        const StepBook bk{qm >= 0 ? slot(qm) : nullptr, ps_j.fin >= 0 ? slot(ps_j.fin) : nullptr,
                           qn >= 0 ? slot(qn) : nullptr, qn, d_seeds, d_counts, d_te, pam, nnz_in, (int32_t)k,
                           (int32_t)P.dir_mode, (int32_t)P.alpha, (int32_t)P.beta};
-        const int64_t nb_last = lastp ? c->hop_grid : 0, nb_h1 = h1 ? h1_grid : 0;
+        const int64_t nb_last = ps_j.last >= 0 ? c->hop_grid : 0, nb_h1 = ps_j.h1 >= 0 ? h1_grid : 0;
         const int64_t nb_book = (qm >= 0 || qn >= 0) ? c->init_grid : 0;
         {
             ProfScope ps(g, KK_PLAIN_HOP, st);
             hipLaunchKernelGGL(plain_step_kernel, dim3((unsigned)(nb_last + nb_h1 + nb_book)), dim3(kBlock), 0, st,
-                               lastp ? slot(j - 1) : nullptr, lastp ? state(j - 1) : State{}, nb_last,
-                               h1 ? slot(j) : nullptr, h1 ? state(j) : State{}, nb_h1, bk,
-                               qm >= 0 ? state(qm) : State{}, qn >= 0 ? state(qn) : State{}, gr, P.pull_light, hc,
-                               ps.units());
+                               ps_j.last >= 0 ? slot(ps_j.last) : nullptr,
+                               ps_j.last >= 0 ? state(ps_j.last) : State{}, nb_last,
+                               ps_j.h1 >= 0 ? slot(ps_j.h1) : nullptr, ps_j.h1 >= 0 ? state(ps_j.h1) : State{},
+                               nb_h1, bk, qm >= 0 ? state(qm) : State{}, qn >= 0 ? state(qn) : State{}, gr,
+                               P.pull_light, hc, ps.units());
             ps.end(0, 1);
         }
-        if (!h1) continue;
-        PlainCtl *cq = slot(j);
-        const State sq = state(j);
+        if (ps_j.h1 < 0) continue;
+        PlainCtl *cq = slot(ps_j.h1);
+        const State sq = state(ps_j.h1);
         for (int L = 2; L < k; ++L) {
             {
                 ProfScope ps(g, KK_PLAIN_HOP, st);
@@ -1444,9 +1444,11 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     }
     // the last query's marks and the count of the one before it, then the last count
     {
+        const PlainStep cl = plain_plan_close(m);
         ProfScope ps(g, KK_PLAIN_INIT, st);
-        hipLaunchKernelGGL(plain_close_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, slot(m - 1),
-                           m >= 2 ? slot(m - 2) : nullptr, (int)(m >= 2), gr, state(m - 1), ps.units());
+        hipLaunchKernelGGL(plain_close_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, slot(cl.marks),
+                           cl.fin >= 0 ? slot(cl.fin) : nullptr, (int)(cl.fin >= 0), gr, state(cl.marks),
+                           ps.units());
         ps.end(0, 1);
     }
     hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, slot(m - 1));
