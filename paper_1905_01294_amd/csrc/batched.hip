@@ -137,7 +137,10 @@ __global__ void __launch_bounds__(kBlock) batch_seed_kernel(uint64_t *V, const i
 
 
 // Hop 1: one block per seed slot with k >= 1 ORs its bit into F and V of each
-// out-neighbor and marks the neighbor in the frontier bitmap.
+// out-neighbor and marks the neighbor in the frontier bitmap.  A seed's row is
+// split into kSeedParts spans of whole 256-edge rounds, each a work item of
+// its own, so that a hub seed does not hold up the launch.
+constexpr int kSeedParts = 8;
 __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t *__restrict__ rowptr,
                                                                  const int32_t *__restrict__ colidx,
                                                                  const int32_t *seeds, const int32_t *perm,
@@ -146,13 +149,17 @@ __global__ void __launch_bounds__(kBlock) batch_push_seeds_kernel(const int64_t 
                                                                  int64_t *fb_cnt, ChunkQueue q, int32_t *flag,
                                                                  const uint64_t *__restrict__ vmask) {
     int64_t fresh = 0;
-    for (int j = blockIdx.x; j < nslots; j += gridDim.x) {
+    for (int64_t t = blockIdx.x; t < (int64_t)nslots * kSeedParts; t += gridDim.x) {
+        const int j = (int)(t / kSeedParts), part = (int)(t % kSeedParts);
         if (ks_sorted[j] < 1) continue;
         const int32_t s = seeds[perm[j]];
-        const int64_t b = rowptr[s], e = rowptr[s + 1];
+        const int64_t rb = rowptr[s], re = rowptr[s + 1];
+        const int64_t span = ((re - rb + kSeedParts - 1) / kSeedParts + kBlock - 1) / kBlock * kBlock;
+        const int64_t b = rb + part * span, e = std::min(re, b + span);
+        if (b >= e) continue;  // block-uniform
         const unsigned long long bit = 1ull << (j & 63);
         const int w = j >> 6;
-        if (e > b && threadIdx.x == 0) atomicOr(flag, 1);
+        if (part == 0 && threadIdx.x == 0) atomicOr(flag, 1);
         for (int64_t x0 = b; x0 < e; x0 += kBlock) {  // block-uniform: every lane reaches the append
             const int64_t x = x0 + threadIdx.x;
             bool app = false;
@@ -1004,9 +1011,10 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     uint64_t *F = c->F, *Nb = c->N;
     if (levels >= 1) {
         ProfScope ps(g, KK_BATCH_PUSH, st);
-        hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
-                           g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, F, c->V, c->Fb + (int64_t)((n + 63) / 64),
-                           c->Fc + kCntLanes, chunk_queue(c, 1), c->flags + 1, d_vmask);
+        hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots * kSeedParts, 4096)), dim3(kBlock), 0, st,
+                           g->d_rowptr, g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, F, c->V,
+                           c->Fb + (int64_t)((n + 63) / 64), c->Fc + kCntLanes, chunk_queue(c, 1), c->flags + 1,
+                           d_vmask);
         ps.end(0);
     }
     // Rows are Wr words long.  Seeds are sorted by k, so the active words of a
