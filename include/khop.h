@@ -142,7 +142,9 @@ int khop_count_labeled_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_se
  * bitsets, so each hop becomes a boolean sparse matrix - dense bit-matrix
  * product (OR-accumulate), masked by the complement of each seed's visited
  * bits.  counts[i] is the k-hop count of seeds[i] at depth ks[i] (mixed k in
- * one call).  Host pointers of length num_seeds.  Errors as khop_count.
+ * one call).  Seeds with k = 1 take no bit: their counts come from their own
+ * rows, beside the bitset launches.  Host pointers of length num_seeds.
+ * Errors as khop_count.
  */
 int khop_count_batched(khop_graph *g, const int32_t *seeds, const int32_t *ks, int64_t num_seeds,
                        int64_t *counts);
