@@ -236,8 +236,10 @@ enum khop_option {
     KHOP_OPT_BATCH_HEAVY = 6,   /* batched bottom-up: degree above which a whole wave takes a vertex */
     KHOP_OPT_BATCH_PUSH = 7,    /* batched: frontier-degree fraction (1/x of arcs) under which a level goes top-down */
     KHOP_OPT_PULL_HEAVY = 8,    /* bottom-up: in-degree above which a vertex's in-edges are split into chunks */
-    KHOP_OPT_PUSH_ATOMIC = 9    /* top-down: frontier edges up to which heads are claimed atomically
+    KHOP_OPT_PUSH_ATOMIC = 9,   /* top-down: frontier edges up to which heads are claimed atomically
                                    (else byte marks) */
+    KHOP_OPT_PLAIN_GRID = 10,   /* plain hop and compaction launches: blocks per compute unit (1..64) */
+    KHOP_OPT_BATCH_GRID = 11    /* batched bottom-up launches: blocks per compute unit (1..64) */
 };
 enum { KHOP_DIR_AUTO = 0, KHOP_DIR_PUSH = 1, KHOP_DIR_PULL = 2 };
 
@@ -245,14 +247,24 @@ int khop_set_option(khop_graph *g, int32_t option, int64_t value);
 int khop_get_option(const khop_graph *g, int32_t option, int64_t *value);
 
 /*
- * Autotuner: times candidate settings (direction thresholds, bottom-up lane
- * threshold, batched seeds per launch and heavy-vertex threshold) on the
- * resident graph with seeds drawn from its non-isolated vertices, keeps the
- * fastest, and leaves the graph's options set to it.  seeds_per_launch > 0
+ * Autotuner: times candidate settings on the resident graph with seeds drawn
+ * from its non-isolated vertices, keeps the fastest, and leaves the graph's
+ * options set to it: for the plain path the direction thresholds, the
+ * bottom-up lane and chunk thresholds, the atomic top-down limit and the
+ * hop kernels' blocks per compute unit; for the batched path the seeds per
+ * launch with the heavy-vertex threshold, the top-down/bottom-up switch and
+ * the bottom-up kernels' blocks per compute unit.  seeds_per_launch > 0
  * restricts the batched search to that batch size.  Results are cached per
- * (device, graph content hash).
+ * (library sources, device, graph content hash) in memory and in the file
+ * named by $KHOP_TUNE_CACHE (default ~/.cache/khop/tune.txt), so settings
+ * tuned for other kernels are never reused.  A forced direction option is
+ * left as it is.
  */
 int khop_autotune(khop_graph *g, int32_t seeds_per_launch);
+
+/* Seconds the last khop_autotune call in this process spent searching; 0 when
+ * its settings came from the cache (or no call has run). */
+double khop_autotune_seconds(void);
 
 /* Per-kernel timing of the engine, measured with HIP events on the stream each kernel runs on. */
 typedef struct {

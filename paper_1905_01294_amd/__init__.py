@@ -41,6 +41,8 @@ KHOP_OPT_BATCH_HEAVY = 6
 KHOP_OPT_BATCH_PUSH = 7
 KHOP_OPT_PULL_HEAVY = 8
 KHOP_OPT_PUSH_ATOMIC = 9
+KHOP_OPT_PLAIN_GRID = 10
+KHOP_OPT_BATCH_GRID = 11
 KHOP_DIR_AUTO = 0
 KHOP_DIR_PUSH = 1
 KHOP_DIR_PULL = 2
@@ -58,7 +60,8 @@ EXPORTS = ("graph_load_csr", "graph_load_csr_typed", "graph_free", "graph_info",
            "khop_bfs", "khop_bfs_dev", "khop_levels", "khop_levels_dev", "khop_neighborhood", "khop_neighborhood_dev",
            "khop_set_option", "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read",
            "khop_server_create", "khop_server_add_graph", "khop_server_set_option", "khop_server_submit",
-           "khop_server_poll", "khop_server_drain", "khop_server_destroy", "khop_last_error", "khop_version")
+           "khop_server_poll", "khop_server_drain", "khop_server_destroy", "khop_last_error", "khop_version",
+           "khop_autotune_seconds")
 
 
 class KhopError(RuntimeError):
@@ -145,6 +148,8 @@ def _load():
     lib.khop_last_error.restype = ctypes.c_char_p
     lib.khop_version.argtypes = []
     lib.khop_version.restype = ctypes.c_char_p
+    lib.khop_autotune_seconds.argtypes = []
+    lib.khop_autotune_seconds.restype = ctypes.c_double
     return lib
 
 
@@ -184,6 +189,11 @@ def _dev_ptr(t, dtype_name):
 
 def khop_version() -> str:
     return _lib.khop_version().decode()
+
+
+def khop_autotune_seconds() -> float:
+    """Seconds the last khop_autotune call spent searching (0 when served from the cache)."""
+    return float(_lib.khop_autotune_seconds())
 
 
 def khop_last_error() -> str:

@@ -359,7 +359,7 @@ void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int
     // bit (a launch answers them from their seeds' rows)
     auto key = [&](int32_t i) { return h_ks[i] == 1 ? -1 : h_ks[i]; };
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) > key(b); });
-    const int per = std::max(64, std::min(1024, g->params.batch_seeds));
+    const int per = std::max(64, std::min(1024, params_of(g).batch_seeds));
     for (int64_t at = 0; at < num; at += per) {
         const int64_t cnt = std::min<int64_t>(per, num - at);
         const int words = (int)((cnt + 63) / 64);  // exact: unused words would only widen every gather
@@ -384,7 +384,10 @@ extern "C" {
 
 const char *khop_last_error(void) { return t_err.c_str(); }
 
-const char *khop_version(void) { return "khop-mi355x 0.1 (gfx950)"; }
+const char *khop_version(void) {
+    static const std::string v = std::string("khop-mi355x 0.2 (gfx950, sources ") + source_hash() + ")";
+    return v.c_str();
+}
 
 }  // extern "C"
 
@@ -924,6 +927,7 @@ int khop_count_batched_labeled(khop_graph *g, const int32_t *seeds, const int32_
 int khop_set_option(khop_graph *g, int32_t option, int64_t value) {
     return guard([&] {
         check_graph(g);
+        std::lock_guard<std::mutex> lk(g->params_mu);
         Params &P = g->params;
         switch (option) {
             case KHOP_OPT_DIRECTION:
@@ -964,6 +968,14 @@ int khop_set_option(khop_graph *g, int32_t option, int64_t value) {
                 if (value < 0 || value > INT32_MAX) fail(KHOP_EINVAL, "push atomic limit out of range [0, 2^31)");
                 P.push_atomic_max = (int)value;
                 break;
+            case KHOP_OPT_PLAIN_GRID:
+                if (value < 1 || value > 64) fail(KHOP_EINVAL, "plain grid out of range [1, 64] blocks per CU");
+                P.plain_grid = (int)value;
+                break;
+            case KHOP_OPT_BATCH_GRID:
+                if (value < 1 || value > 64) fail(KHOP_EINVAL, "batch grid out of range [1, 64] blocks per CU");
+                P.batch_grid = (int)value;
+                break;
             default:
                 fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
@@ -974,7 +986,7 @@ int khop_get_option(const khop_graph *g, int32_t option, int64_t *value) {
     return guard([&] {
         check_graph(g);
         if (!value) fail(KHOP_EINVAL, "value is NULL");
-        const Params &P = g->params;
+        const Params P = params_of(const_cast<khop_graph *>(g));
         switch (option) {
             case KHOP_OPT_DIRECTION: *value = P.dir_mode; break;
             case KHOP_OPT_ALPHA: *value = P.alpha; break;
@@ -985,6 +997,8 @@ int khop_get_option(const khop_graph *g, int32_t option, int64_t *value) {
             case KHOP_OPT_BATCH_PUSH: *value = P.batch_push_div; break;
             case KHOP_OPT_PULL_HEAVY: *value = P.pull_heavy; break;
             case KHOP_OPT_PUSH_ATOMIC: *value = P.push_atomic_max; break;
+            case KHOP_OPT_PLAIN_GRID: *value = P.plain_grid; break;
+            case KHOP_OPT_BATCH_GRID: *value = P.batch_grid; break;
             default: fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
     });

@@ -244,10 +244,10 @@ __device__ __forceinline__ uint64_t frontier_word(const uint64_t *__restrict__ F
 // Builds that narrow copy of a one-word frontier (bits = 16 or 32); it exits
 // at once when the hop went top-down or the frontier is empty.
 __global__ void __launch_bounds__(kBlock) batch_frontier_copy_kernel(const uint64_t *__restrict__ F, int64_t n,
-                                                                    void *Fs, int bits, const int32_t *mode, int L,
+                                                                    void *Fs, int bits, const int32_t *mode_l,
                                                                     const int32_t *prev_flag) {
     if (*prev_flag == 0) return;
-    if (mode && mode[L] == HOP_PUSH) return;
+    if (mode_l && *mode_l == HOP_PUSH) return;
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < n; v += (int64_t)gridDim.x * kBlock) {
         const uint64_t x = F[v];
         if (bits == 16) ((uint16_t *)Fs)[v] = (uint16_t)x;
@@ -268,10 +268,10 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
                                                            const void *__restrict__ Fs,
                                                            uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
                                                            const uint64_t *__restrict__ act, int heavy,
-                                                           FrontierBits fb, const int32_t *mode, int L,
+                                                           FrontierBits fb, const int32_t *mode_l,
                                                            const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;  // empty frontier: nothing left to find
-    if (mode && mode[L] == HOP_PUSH) return;  // this hop went top-down
+    if (mode_l && *mode_l == HOP_PUSH) return;  // this hop went top-down
     {
         const int64_t nw = (n + kWave - 1) / kWave;
         for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < nw; i += (int64_t)gridDim.x * kBlock)
@@ -398,10 +398,10 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     const int32_t *__restrict__ in_colidx, uint64_t *V, const uint64_t *__restrict__ F, const void *__restrict__ Fs,
     uint64_t *Fn, int W, int wact,
     const uint64_t *__restrict__ act, const int32_t *__restrict__ hvert, const int64_t *__restrict__ hbegin,
-    const int64_t *__restrict__ hend, int64_t n_items, int64_t n, FrontierBits fb, const int32_t *mode, int L,
+    const int64_t *__restrict__ hend, int64_t n_items, int64_t n, FrontierBits fb, const int32_t *mode_l,
     const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;
-    if (mode && mode[L] == HOP_PUSH) return;  // this hop went top-down
+    if (mode_l && *mode_l == HOP_PUSH) return;  // this hop went top-down
     const uint64_t *__restrict__ Fbc = fb.cur;
     // skipping the bitmap test pays only with one-word rows: a wider row costs
     // far more to gather than the test
@@ -507,13 +507,14 @@ __global__ void __launch_bounds__(kBlock) batch_push_kernel(
     const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx, uint64_t *V,
     const uint64_t *__restrict__ F, uint64_t *N, int64_t n, int64_t nnz, int W, int wact,
     const uint64_t *__restrict__ act, int push_div, ChunkQueue qin, ChunkQueue qout, ChunkQueue qreset,
-    FrontierBits fb, int32_t *mode, int L, int sticky, const int32_t *prev_flag, int32_t *flag, int64_t *units) {
+    FrontierBits fb, const int32_t *mode_prev, int32_t *mode_l, const int32_t *prev_flag, int32_t *flag,
+    int64_t *units) {
     if (*prev_flag == 0) return;
     const int lane = lane_id();
     const int64_t mf = wave_sum(qin.mf[lane & (kCntLanes - 1)]);
-    const bool pull = (sticky && mode[L - 1] == HOP_PULL) || mf * (int64_t)push_div > nnz;
+    const bool pull = (mode_prev && *mode_prev == HOP_PULL) || mf * (int64_t)push_div > nnz;
     if (blockIdx.x == 0 && threadIdx.x < kCntLanes) {
-        if (threadIdx.x == 0) mode[L] = pull ? HOP_PULL : HOP_PUSH;
+        if (threadIdx.x == 0) *mode_l = pull ? HOP_PULL : HOP_PUSH;
         qreset.mf[threadIdx.x] = 0;
         if (threadIdx.x == 0) *qreset.len = 0;
     }
@@ -582,9 +583,9 @@ __global__ void __launch_bounds__(kBlock) batch_push_kernel(
 __global__ void __launch_bounds__(kBlock) queue_from_bitmap_kernel(const int64_t *__restrict__ rowptr,
                                                                   const uint64_t *__restrict__ fb,
                                                                   const int64_t *__restrict__ fb_cnt, int64_t n,
-                                                                  int64_t nnz, ChunkQueue q, const int32_t *mode,
-                                                                  int L) {
-    if (mode[L] != HOP_PULL) return;
+                                                                  int64_t nnz, ChunkQueue q,
+                                                                  const int32_t *mode_l) {
+    if (*mode_l != HOP_PULL) return;
     const int lane = lane_id();
     if (wave_sum(fb_cnt[lane & (kCntLanes - 1)]) * 64 > n) {
         if (blockIdx.x == 0 && threadIdx.x == 0) q.mf[0] = nnz + 1;
@@ -781,9 +782,9 @@ struct BatchCtx {
     uint64_t *Fb = nullptr;    // three frontier bitmaps of nw words each (hop l uses slot l % 3)
     int64_t *Fc = nullptr;     // their set-bit counts, 64 lanes each
     int64_t *acc = nullptr;    // 64 * W counters
-    uint64_t *act = nullptr;   // kMaxLevels * W active masks
-    int32_t *flags = nullptr;  // kMaxLevels + 1 frontier-nonempty flags
-    int32_t *mode = nullptr;   // kMaxLevels + 1 hop directions (HOP_PUSH / HOP_PULL)
+    uint64_t *act = nullptr;   // kActRows * W active masks, one row per distinct set of active seeds
+    int32_t *flags = nullptr;  // kRing frontier-nonempty flags, level l at l % kRing
+    int32_t *mode = nullptr;   // kRing hop directions (HOP_PUSH / HOP_PULL), level l at l % kRing
     uint64_t *cq_rec[3] = {};  // top-down chunk queues by hop % 3
     int64_t *cq_len = nullptr; // their lengths
     int64_t *cq_mf = nullptr;  // their out-degree sums, 64 lanes each
@@ -796,7 +797,11 @@ struct BatchCtx {
     int32_t *h_ks = nullptr;
     void *h_arena = nullptr;
     hipEvent_t stage_ev = nullptr;
-    static constexpr int kMaxLevels = 4096;
+    // Per-level records live in a ring: a hop reads its own level's and the
+    // level before's, and the run clears ring slots ahead of the levels that
+    // reuse them, so traversals of any depth fit.
+    static constexpr int kRing = 4096;
+    int act_rows = 0;          // 64 * W + 1: seeds sorted by k make the active sets a chain of prefixes
 };
 
 BatchCtx *batch_ctx_create(khop_graph *g, int words) {
@@ -821,12 +826,13 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     off += al(3 * kCntLanes * 8);
     const size_t oacc = off;
     off += al(64 * (size_t)words * 8);
+    c->act_rows = 64 * words + 1;
     const size_t oact = off;
-    off += al((size_t)BatchCtx::kMaxLevels * words * 8);
+    off += al((size_t)c->act_rows * words * 8);
     const size_t oflags = off;
-    off += al((BatchCtx::kMaxLevels + 1) * 4);
+    off += al(BatchCtx::kRing * 4);
     const size_t omode = off;
-    off += al((BatchCtx::kMaxLevels + 1) * 4);
+    off += al(BatchCtx::kRing * 4);
     const int64_t cq_cap = n + g->nnz / kChunk + kWave;
     size_t ocq[3];
     for (int i = 0; i < 3; ++i) {
@@ -863,7 +869,7 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     c->cq_mf = (int64_t *)(b + ocqm);
     c->perm = (int32_t *)(b + operm);
     c->ks = (int32_t *)(b + oks);
-    const size_t hbytes = (size_t)BatchCtx::kMaxLevels * words * 8 + 2 * 64 * (size_t)words * 4;
+    const size_t hbytes = (size_t)c->act_rows * words * 8 + 2 * 64 * (size_t)words * 4;
     if (hipHostMalloc(&c->h_arena, hbytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipFree(c->arena);
@@ -871,7 +877,7 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
         fail(KHOP_ENOMEM, "pinned host allocation for a batch context failed");
     }
     c->h_act = (uint64_t *)c->h_arena;
-    c->h_perm = (int32_t *)(c->h_act + (size_t)BatchCtx::kMaxLevels * words);
+    c->h_perm = (int32_t *)(c->h_act + (size_t)c->act_rows * words);
     c->h_ks = c->h_perm + 64 * words;
     KHOP_HIP(hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming));
     KHOP_HIP(hipEventRecord(c->stage_ev, nullptr));
@@ -891,29 +897,52 @@ void batch_ctx_destroy(BatchCtx *c) {
 
 int batch_ctx_words(const BatchCtx *c) { return c->W; }
 
+// The per-level records one hop of a batch run uses: the active seeds' bits
+// of the level, and the ring slots of the level's and the previous level's
+// direction and frontier-nonempty flag.
+struct LevelCtl {
+    const uint64_t *act;
+    const int32_t *mode_prev;
+    int32_t *mode_l;
+    const int32_t *flag_prev;
+    int32_t *flag_l;
+};
+
+static int ring_slot(int64_t L) { return (int)(L % BatchCtx::kRing); }
+
+static LevelCtl level_ctl(BatchCtx *c, int64_t L, const uint64_t *act) {
+    return LevelCtl{act, c->mode + ring_slot(L - 1), c->mode + ring_slot(L), c->flags + ring_slot(L - 1),
+                    c->flags + ring_slot(L)};
+}
+
+static FrontierBits frontier_bits(BatchCtx *c, int64_t n, int64_t L) {
+    const int64_t nw = (n + 63) / 64;
+    const int a = (int)((L - 1) % 3), b = (int)(L % 3), z = (int)((L + 1) % 3);
+    return FrontierBits{c->Fb + a * nw, c->Fb + b * nw, c->Fb + z * nw,
+                        c->Fc + a * kCntLanes, c->Fc + b * kCntLanes, c->Fc + z * kCntLanes};
+}
+
 template <int G>
-static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hipStream_t st, uint64_t *V, uint64_t *F,
-                        uint64_t *Fn, int fs_bits) {
+static void launch_pull(khop_graph *g, BatchCtx *c, const HeavyTable &ht, int grid_per_cu, int64_t L,
+                        const LevelCtl &lc, int wact, int Wr, hipStream_t st, uint64_t *V, uint64_t *F, uint64_t *Fn,
+                        int fs_bits) {
     const int64_t n = g->n, nw = (n + 63) / 64;
     const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
-                                                                 (int64_t)g->cu_count * 16));
-    const uint64_t *act = c->act + (int64_t)(L - 1) * c->W;
-    const FrontierBits fb{c->Fb + ((L - 1) % 3) * nw, c->Fb + (L % 3) * nw,       c->Fb + ((L + 1) % 3) * nw,
-                          c->Fc + ((L - 1) % 3) * kCntLanes, c->Fc + (L % 3) * kCntLanes, c->Fc + ((L + 1) % 3) * kCntLanes};
+                                                                 (int64_t)g->cu_count * grid_per_cu));
+    const FrontierBits fb = frontier_bits(c, n, L);
     {
         ProfScope ps(g, KK_BATCH_PULL, st);
         auto k = fs_bits == 16 ? batch_pull_kernel<G, 16> : fs_bits == 32 ? batch_pull_kernel<G, 32>
                                                                            : batch_pull_kernel<G, 0>;
         hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, V, F,
-                           (const void *)c->Fs, Fn, n, Wr, wact, act, batch_heavy_table(g).threshold, fb, c->mode, L,
-                           c->flags + (L - 1), c->flags + L, ps.units());
+                           (const void *)c->Fs, Fn, n, Wr, wact, lc.act, ht.threshold, fb, lc.mode_l, lc.flag_prev,
+                           lc.flag_l, ps.units());
         // bytes: V read and write-back and Fn write per active word, the frontier bitmap once,
         // 4 per examined in-edge, 16 per scanned vertex, 8 per gathered word (fs_bits / 8 from the narrow copy)
         const double gw = fs_bits ? fs_bits / 8.0 : 8.0 * wact;
         ps.end(3.0 * 8.0 * (double)n * wact + 2.0 * 8.0 * nw, 0, 4.0, 16.0, gw);
     }
-    const HeavyTable &ht = batch_heavy_table(g);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
@@ -921,8 +950,8 @@ static void launch_pull(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hip
         auto k = fs_bits == 16 ? batch_pull_heavy_kernel<G, 16> : fs_bits == 32 ? batch_pull_heavy_kernel<G, 32>
                                                                                  : batch_pull_heavy_kernel<G, 0>;
         hipLaunchKernelGGL(k, dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, V, F, (const void *)c->Fs, Fn, Wr,
-                           wact, act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, c->mode, L, c->flags + (L - 1),
-                           c->flags + L, ps.units());
+                           wact, lc.act, ht.d_vert, ht.d_begin, ht.d_end, ht.n, n, fb, lc.mode_l, lc.flag_prev,
+                           lc.flag_l, ps.units());
         ps.end(16.0 * (double)ht.n, 0, 4.0, 0, fs_bits ? fs_bits / 8.0 : 8.0 * wact);
     }
 }
@@ -934,26 +963,35 @@ static ChunkQueue chunk_queue(BatchCtx *c, int slot) {
 // Hop L's top-down kernel, which also takes the hop's direction (it exits at
 // once when the hop goes bottom-up).
 template <int G>
-static void launch_push(khop_graph *g, BatchCtx *c, int L, int wact, int Wr, hipStream_t st, uint64_t *V, uint64_t *F,
-                        uint64_t *Fn) {
-    const int64_t n = g->n, nw = (n + 63) / 64;
-    const uint64_t *act = c->act + (int64_t)(L - 1) * c->W;
-    const FrontierBits fb{c->Fb + ((L - 1) % 3) * nw, c->Fb + (L % 3) * nw,       c->Fb + ((L + 1) % 3) * nw,
-                          c->Fc + ((L - 1) % 3) * kCntLanes, c->Fc + (L % 3) * kCntLanes, c->Fc + ((L + 1) % 3) * kCntLanes};
+static void launch_push(khop_graph *g, BatchCtx *c, int push_div, int64_t L, const LevelCtl &lc, int wact, int Wr,
+                        hipStream_t st, uint64_t *V, uint64_t *F, uint64_t *Fn) {
+    const int64_t n = g->n;
+    const FrontierBits fb = frontier_bits(c, n, L);
+    const int a = (int)((L - 1) % 3), b = (int)(L % 3), z = (int)((L + 1) % 3);
     {
         ProfScope ps(g, KK_BATCH_PUSH, st);
         hipLaunchKernelGGL((batch_push_kernel<G>), dim3(g->cu_count * 8), dim3(kBlock), 0, st, g->d_rowptr,
-                           g->d_colidx, V, F, Fn, n, g->nnz, Wr, wact, act, g->params.batch_push_div,
-                           chunk_queue(c, (L - 1) % 3), chunk_queue(c, L % 3), chunk_queue(c, (L + 1) % 3), fb,
-                           c->mode, L, 1, c->flags + (L - 1), c->flags + L, ps.units());
+                           g->d_colidx, V, F, Fn, n, g->nnz, Wr, wact, lc.act, push_div, chunk_queue(c, a),
+                           chunk_queue(c, b), chunk_queue(c, z), fb, lc.mode_prev, lc.mode_l, lc.flag_prev,
+                           lc.flag_l, ps.units());
         // bytes: 4 per out-edge + 8 per active word of its head's visited and next rows
         ps.end(0, 0, 4.0 + 16.0 * wact);
+    }
+}
+
+__global__ void clear_ring_kernel(int32_t *flags, int32_t *mode, int start, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        const int at = (start + i) % BatchCtx::kRing;
+        flags[at] = 0;
+        mode[at] = HOP_PUSH;
     }
 }
 
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
                const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st,
                const uint64_t *d_vmask) {
+    const Params P = params_of(g);
+    const HeavyTable ht = batch_heavy_table(g, P.batch_heavy);
     // Slots come sorted by k, largest first, with the one-hop queries last:
     // those are answered from their seeds' rows and take no bit, so the rows
     // of the bitsets are W words wide for the other nslots slots.
@@ -962,26 +1000,31 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     const int W = std::max(1, (nslots + 63) / 64);
     const int Wc = c->W;  // the stride of the active-mask table
     const int64_t n = g->n;
-    int kmax = 0;
-    for (int j = 0; j < nslots; ++j) kmax = std::max(kmax, h_ks_sorted[j]);
-    const int levels = (int)std::min<int64_t>(kmax, std::min<int64_t>(n, BatchCtx::kMaxLevels - 1));
+    int64_t kmax = 0;
+    for (int j = 0; j < nslots; ++j) kmax = std::max<int64_t>(kmax, h_ks_sorted[j]);
+    // no search goes deeper than n - 1 hops: a hop past that finds nothing
+    const int64_t levels = std::min<int64_t>(kmax, n);
+    // The seeds active at level l are those with k >= l: a prefix of the
+    // slots.  One row of the table per distinct k (largest first): row r
+    // holds the slots with k >= dk[r], and level l uses the last row whose
+    // dk is still >= l.
+    std::vector<int64_t> dk;
+    std::vector<int> dcnt;
+    for (int j = 0; j < nslots; ++j) {
+        if (h_ks_sorted[j] < 1) break;  // k = 0 slots (after every k >= 2) are never active
+        if (dk.empty() || h_ks_sorted[j] != dk.back()) dk.push_back(h_ks_sorted[j]);
+        if (j + 1 == nslots || h_ks_sorted[j + 1] != h_ks_sorted[j]) dcnt.push_back(j + 1);
+    }
+    const int rows = (int)dk.size();
     // the staging buffer may still feed the previous batch's copies
     KHOP_HIP(hipEventSynchronize(c->stage_ev));
-    // active masks and active word counts per level
     uint64_t *act = c->h_act;
-    std::fill(act, act + (size_t)std::max(levels, 1) * Wc, 0ull);
-    std::vector<int> wact(std::max(levels, 1) + 1, 0);
-    for (int L = 1; L <= levels; ++L) {
-        for (int j = 0; j < nslots; ++j)
-            if (h_ks_sorted[j] >= L) {
-                act[(size_t)(L - 1) * Wc + (j >> 6)] |= 1ull << (j & 63);
-                wact[L] = std::max(wact[L], (j >> 6) + 1);
-            }
-    }
+    std::fill(act, act + (size_t)std::max(rows, 1) * Wc, 0ull);
+    for (int r = 0; r < rows; ++r)
+        for (int j = 0; j < dcnt[r]; ++j) act[(size_t)r * Wc + (j >> 6)] |= 1ull << (j & 63);
     std::copy(h_perm, h_perm + num_seeds, c->h_perm);
     std::copy(h_ks_sorted, h_ks_sorted + num_seeds, c->h_ks);
-    if (levels > 0)
-        KHOP_HIP(hipMemcpyAsync(c->act, act, (size_t)levels * Wc * 8, hipMemcpyHostToDevice, st));
+    if (rows > 0) KHOP_HIP(hipMemcpyAsync(c->act, act, (size_t)rows * Wc * 8, hipMemcpyHostToDevice, st));
     KHOP_HIP(hipMemcpyAsync(c->perm, c->h_perm, (size_t)num_seeds * 4, hipMemcpyHostToDevice, st));
     KHOP_HIP(hipMemcpyAsync(c->ks, c->h_ks, (size_t)num_seeds * 4, hipMemcpyHostToDevice, st));
     KHOP_HIP(hipEventRecord(c->stage_ev, st));
@@ -1001,7 +1044,7 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         ProfScope ps(g, KK_BATCH_INIT, st);
         hipLaunchKernelGGL(batch_zero_kernel, dim3(std::max(zgrid, 1)), dim3(kBlock), 0, st, c->V, c->F, c->N,
                            (int64_t)n * W, c->Fb, 3 * ((n + 63) / 64), c->Fc, c->acc, (int64_t)64 * W, c->flags,
-                           c->mode, levels + 1, c->cq_len, c->cq_mf);
+                           c->mode, BatchCtx::kRing, c->cq_len, c->cq_mf);
         ps.end(3.0 * 8.0 * n * W + 3.0 * 8.0 * ((n + 63) / 64));
     }
     if (d_vmask)
@@ -1013,8 +1056,8 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         ProfScope ps(g, KK_BATCH_PUSH, st);
         hipLaunchKernelGGL(batch_push_seeds_kernel, dim3(std::min(nslots * kSeedParts, 4096)), dim3(kBlock), 0, st,
                            g->d_rowptr, g->d_colidx, d_seeds, c->perm, c->ks, nslots, W, F, c->V,
-                           c->Fb + (int64_t)((n + 63) / 64), c->Fc + kCntLanes, chunk_queue(c, 1), c->flags + 1,
-                           d_vmask);
+                           c->Fb + (int64_t)((n + 63) / 64), c->Fc + kCntLanes, chunk_queue(c, 1),
+                           c->flags + ring_slot(1), d_vmask);
         ps.end(0);
     }
     // Rows are Wr words long.  Seeds are sorted by k, so the active words of a
@@ -1030,9 +1073,17 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
         hipLaunchKernelGGL(batch_count_kernel, dim3(cgx, nwords), dim3(kBlock), 0, st, V, n, Wr, w0, d_vmask, c->acc);
         ps.end(8.0 * n * nwords);
     };
-    for (int L = 2; L <= levels; ++L) {
-        const int wa = wact[L];
-        if (wa == 0) break;
+    int r = rows - 1;  // the table row of the current level
+    constexpr int kHalf = BatchCtx::kRing / 2;
+    for (int64_t L = 2; L <= levels; ++L) {
+        while (r >= 0 && dk[r] < L) --r;
+        if (r < 0) break;
+        const int wa = (dcnt[r] + 63) / 64;
+        if (L % kHalf == 0) {
+            // ring slots of levels L + 1 .. L + kHalf last served levels a whole ring earlier
+            hipLaunchKernelGGL(clear_ring_kernel, dim3(1), dim3(256), 0, st, c->flags, c->mode, ring_slot(L + 1),
+                               kHalf);
+        }
         if (2 * wa <= Wr) {
             count_words(wa, Wr - wa);
             // V and F move into the spare buffer (both fit: 2 * wa <= Wr); the old V becomes the next frontier's buffer
@@ -1053,16 +1104,16 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
             F = Fnew;
             Wr = wa;
         }
+        const LevelCtl lc = level_ctl(c, L, c->act + (size_t)r * Wc);
         int G = 1;
         while (G < wa) G <<= 1;
         switch (G) {
             case 1: {
-                launch_push<1>(g, c, L, wa, Wr, st, V, F, Nb);
+                launch_push<1>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
                 // one-word rows whose active seeds fit in 16 or 32 bits are gathered from a narrow copy
                 int fs_bits = 0;
                 if (Wr == 1) {
-                    const uint64_t a = act[(size_t)(L - 1) * Wc];
-                    const int top = a ? 63 - __builtin_clzll(a) : 0;
+                    const int top = dcnt[r] - 1;
                     fs_bits = top < 16 ? 16 : top < 32 ? 32 : 0;
                 }
                 if (fs_bits) {
@@ -1070,25 +1121,34 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
                     const int cg = (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock,
                                                                                (int64_t)g->cu_count * 8));
                     hipLaunchKernelGGL(batch_frontier_copy_kernel, dim3(cg), dim3(kBlock), 0, st, F, n, c->Fs, fs_bits,
-                                       c->mode, L, c->flags + (L - 1));
+                                       lc.mode_l, lc.flag_prev);
                     ps.end(8.0 * n + n * fs_bits / 8.0);
                 }
-                launch_pull<1>(g, c, L, wa, Wr, st, V, F, Nb, fs_bits);
+                launch_pull<1>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, fs_bits);
                 break;
             }
-            case 2: launch_push<2>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<2>(g, c, L, wa, Wr, st, V, F, Nb, 0); break;
-            case 4: launch_push<4>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<4>(g, c, L, wa, Wr, st, V, F, Nb, 0); break;
-            case 8: launch_push<8>(g, c, L, wa, Wr, st, V, F, Nb); launch_pull<8>(g, c, L, wa, Wr, st, V, F, Nb, 0); break;
+            case 2:
+                launch_push<2>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
+                launch_pull<2>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
+                break;
+            case 4:
+                launch_push<4>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
+                launch_pull<4>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
+                break;
+            case 8:
+                launch_push<8>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
+                launch_pull<8>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
+                break;
             default:
-                launch_push<16>(g, c, L, wa, Wr, st, V, F, Nb);
-                launch_pull<16>(g, c, L, wa, Wr, st, V, F, Nb, 0);
+                launch_push<16>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
+                launch_pull<16>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
                 break;
         }
         std::swap(F, Nb);
         if ((L % 8) == 0 && L < levels) {
             // long traversals: stop once the frontier is empty
             int32_t flag = 1;
-            KHOP_HIP(hipMemcpyAsync(&flag, c->flags + L, 4, hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipMemcpyAsync(&flag, c->flags + ring_slot(L), 4, hipMemcpyDeviceToHost, st));
             KHOP_HIP(hipStreamSynchronize(st));
             if (!flag) break;
         }
@@ -1241,29 +1301,30 @@ static void serve_hop(ServeCtx *c, int wact, hipStream_t st) {
     const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
                                                                  (int64_t)g->cu_count * 16));
-    const HeavyTable &ht = batch_heavy_table(g);
+    const Params P = params_of(g);
+    const HeavyTable ht = batch_heavy_table(g, P.batch_heavy);
     const int64_t nw = (n + 63) / 64;
     const int i0 = c->fbi, i1 = (c->fbi + 1) % 3, i2 = (c->fbi + 2) % 3;
     const FrontierBits fb{c->Fb + i0 * nw, c->Fb + i1 * nw, c->Fb + i2 * nw,
                           c->Fc + i0 * kCntLanes, c->Fc + i1 * kCntLanes, c->Fc + i2 * kCntLanes};
     hipLaunchKernelGGL((batch_push_kernel<G>), dim3(g->cu_count * 8), dim3(kBlock), 0, st, g->d_rowptr, g->d_colidx,
-                       c->V, c->F, c->N, n, g->nnz, c->W, wact, c->d_act, g->params.batch_push_div,
-                       serve_queue(c, i0), serve_queue(c, i1), serve_queue(c, i2), fb, c->d_mode, 1, 0, c->d_one,
+                       c->V, c->F, c->N, n, g->nnz, c->W, wact, c->d_act, P.batch_push_div,
+                       serve_queue(c, i0), serve_queue(c, i1), serve_queue(c, i2), fb, nullptr, c->d_mode + 1, c->d_one,
                        c->d_one + 1, nullptr);
     hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
-                       c->F, (const void *)nullptr, c->N, n, c->W, wact, c->d_act, ht.threshold, fb, c->d_mode, 1,
+                       c->F, (const void *)nullptr, c->N, n, c->W, wact, c->d_act, ht.threshold, fb, c->d_mode + 1,
                        c->d_one, c->d_one + 1, nullptr);
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(
             1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
         hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
                            (const void *)nullptr, c->N, c->W, wact, c->d_act, ht.d_vert, ht.d_begin, ht.d_end,
-                           ht.n, n, fb, c->d_mode, 1, c->d_one, c->d_one + 1, nullptr);
+                           ht.n, n, fb, c->d_mode + 1, c->d_one, c->d_one + 1, nullptr);
     }
     const int qgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kWavesPerBlock - 1) / kWavesPerBlock,
                                                                   (int64_t)g->cu_count * 8));
     hipLaunchKernelGGL(queue_from_bitmap_kernel, dim3(qgrid), dim3(kBlock), 0, st, g->d_rowptr, fb.next, fb.cnt_next,
-                       n, g->nnz, serve_queue(c, i1), c->d_mode, 1);
+                       n, g->nnz, serve_queue(c, i1), c->d_mode + 1);
 }
 
 void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,

@@ -1,6 +1,13 @@
 // Edge-chunk tables of high in-degree vertices for the bottom-up hops.  A hub
 // scanned by one wave would serialise thousands of dependent rounds; cut into
 // fixed-size chunks it is shared by as many waves as it has chunks.
+//
+// A table is rebuilt when its threshold option changes.  Callers take a copy
+// of the table's description and launch kernels on it later, possibly while
+// another thread changes the threshold, so a replaced table is not freed: it
+// is retired and released with the graph.  Retired tables are few (one per
+// threshold ever used) and small (one record per 256 or 1024 in-edges of the
+// vertices above the threshold).
 #include <algorithm>
 
 #include "khop_impl.h"
@@ -14,12 +21,10 @@ static void free_table(HeavyTable &t) {
     t = HeavyTable{};
 }
 
-static const HeavyTable &build(khop_graph *g, HeavyTable &t, int threshold, int64_t chunk) {
-    std::lock_guard<std::mutex> lk(g->mu);
+static HeavyTable build(khop_graph *g, HeavyTable &t, int threshold, int64_t chunk) {
+    std::lock_guard<std::mutex> lk(g->heavy_mu);
     if (t.threshold == threshold && t.chunk == chunk) return t;
-    // the previous table may still be read by queued kernels
-    KHOP_HIP(hipDeviceSynchronize());
-    free_table(t);
+    HeavyTable nt;
     std::vector<int32_t> vert;
     std::vector<int64_t> begin, end;
     {
@@ -41,31 +46,54 @@ static const HeavyTable &build(khop_graph *g, HeavyTable &t, int threshold, int6
             }
         off += d;
     }
-    t.threshold = threshold;
-    t.chunk = chunk;
-    t.n = (int64_t)vert.size();
-    if (t.n > 0) {
-        if (hipMalloc(&t.d_vert, vert.size() * 4) != hipSuccess || hipMalloc(&t.d_begin, begin.size() * 8) != hipSuccess ||
-            hipMalloc(&t.d_end, end.size() * 8) != hipSuccess) {
+    nt.threshold = threshold;
+    nt.chunk = chunk;
+    nt.n = (int64_t)vert.size();
+    if (nt.n > 0) {
+        if (hipMalloc(&nt.d_vert, vert.size() * 4) != hipSuccess ||
+            hipMalloc(&nt.d_begin, begin.size() * 8) != hipSuccess ||
+            hipMalloc(&nt.d_end, end.size() * 8) != hipSuccess) {
             (void)hipGetLastError();
-            free_table(t);
+            free_table(nt);
             fail(KHOP_ENOMEM, "device allocation for a heavy-vertex chunk table failed");
         }
-        KHOP_HIP(hipMemcpy(t.d_vert, vert.data(), vert.size() * 4, hipMemcpyHostToDevice));
-        KHOP_HIP(hipMemcpy(t.d_begin, begin.data(), begin.size() * 8, hipMemcpyHostToDevice));
-        KHOP_HIP(hipMemcpy(t.d_end, end.data(), end.size() * 8, hipMemcpyHostToDevice));
+        try {
+            KHOP_HIP(hipMemcpy(nt.d_vert, vert.data(), vert.size() * 4, hipMemcpyHostToDevice));
+            KHOP_HIP(hipMemcpy(nt.d_begin, begin.data(), begin.size() * 8, hipMemcpyHostToDevice));
+            KHOP_HIP(hipMemcpy(nt.d_end, end.data(), end.size() * 8, hipMemcpyHostToDevice));
+        } catch (...) {
+            free_table(nt);
+            throw;
+        }
     }
+    // kernels already queued (or about to be, from a copy) may still read the old table
+    if (t.threshold >= 0) g->heavy_retired.push_back(t);
+    t = nt;
     return t;
 }
 
 // 256-edge chunks: one round of 4 in-edges per lane of a wave
-const HeavyTable &plain_heavy_table(khop_graph *g) { return build(g, g->plain_heavy, g->params.pull_heavy, 256); }
+HeavyTable plain_heavy_table(khop_graph *g, int threshold) { return build(g, g->plain_heavy, threshold, 256); }
 
-const HeavyTable &batch_heavy_table(khop_graph *g) { return build(g, g->batch_heavy, g->params.batch_heavy, 1024); }
+HeavyTable batch_heavy_table(khop_graph *g, int threshold) { return build(g, g->batch_heavy, threshold, 1024); }
 
+// Called by graph_free after the device has finished all work.
 void heavy_tables_free(khop_graph *g) {
+    std::lock_guard<std::mutex> lk(g->heavy_mu);
     free_table(g->plain_heavy);
     free_table(g->batch_heavy);
+    for (auto &t : g->heavy_retired) free_table(t);
+    g->heavy_retired.clear();
+}
+
+Params params_of(khop_graph *g) {
+    std::lock_guard<std::mutex> lk(g->params_mu);
+    return g->params;
+}
+
+void params_set(khop_graph *g, const Params &p) {
+    std::lock_guard<std::mutex> lk(g->params_mu);
+    g->params = p;
 }
 
 }  // namespace khop

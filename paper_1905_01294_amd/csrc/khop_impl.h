@@ -53,6 +53,8 @@ struct Params {
     int batch_seeds = 1024;    // batched: seeds per launch (64 * words)
     int batch_heavy = 256;     // batched bottom-up: wave-per-vertex above this in-degree
     int batch_push_div = 64;   // batched: top-down level when frontier arcs * div < total arcs
+    int plain_grid = 4;        // plain hop and compaction kernels: blocks per compute unit
+    int batch_grid = 16;       // batched bottom-up kernel: blocks per compute unit
 };
 
 struct PlainCtx;
@@ -148,10 +150,13 @@ struct khop_graph {
     int32_t *d_in_colidx = nullptr;
     khop::HeavyTable plain_heavy;    // chunks for the plain bottom-up hop
     khop::HeavyTable batch_heavy;    // chunks for the batched bottom-up hop
+    std::vector<khop::HeavyTable> heavy_retired;  // replaced tables, freed with the graph
+    std::mutex heavy_mu;             // guards the tables above
     std::vector<int64_t> h_outdeg;   // host copy of out-degrees
     std::vector<int64_t> h_indeg;
     uint64_t hash = 0;
-    khop::Params params;
+    khop::Params params;             // read through params_of(), written through params_set()
+    std::mutex params_mu;
     hipStream_t stream = nullptr;    // stream of the host-pointer entry points
     std::mutex mu;                   // guards the context pools, heavy list and profiler
     std::vector<khop::PlainCtx *> plain_free;
@@ -214,9 +219,17 @@ int64_t *serve_ctx_counts(ServeCtx *c);  // pinned; counts of the last harvest, 
 void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
                      const int32_t *seeds, int n_new, int wact, hipStream_t st);
 
-// heavy.cpp: (re)built when the threshold option changes; valid until the next change.
-const HeavyTable &plain_heavy_table(khop_graph *g);
-const HeavyTable &batch_heavy_table(khop_graph *g);
+// heavy.cpp: the chunk table for a threshold, (re)built when the threshold
+// changes.  The copy returned stays valid until graph_free.
+HeavyTable plain_heavy_table(khop_graph *g, int threshold);
+HeavyTable batch_heavy_table(khop_graph *g, int threshold);
 void heavy_tables_free(khop_graph *g);
+// A consistent copy of the graph's options, and their replacement (options
+// change between calls; a call runs on the copy it took when it started).
+Params params_of(khop_graph *g);
+void params_set(khop_graph *g, const Params &p);
+
+// tune.cpp: hash of the library's sources, fixed at build time
+const char *source_hash();
 
 }  // namespace khop

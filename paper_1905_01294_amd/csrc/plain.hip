@@ -1145,10 +1145,12 @@ __global__ void __launch_bounds__(kBlock) plain_bfs_init_kernel(PlainCtl *ctl, G
 
 // After hop L (one wave): whether level L is non-empty (ctl->more), the
 // largest non-empty level (ctl->reached), and into the outputs given, the
-// count of levels 1..L and that level.  Level L's region counters stay intact
-// until hop L+2 clears them.
+// count of levels 1..L, that level, and the out-degree sum of levels 0..L-1
+// (the traversed edges of a search of depth L).  Level L's region counters
+// stay intact until hop L+2 clears them.  A query with an invalid seed
+// already holds -1 in its outputs and is left alone.
 __global__ void __launch_bounds__(kWave) plain_bfs_probe_kernel(PlainCtl *ctl, State s, int L, int64_t *out_count,
-                                                               int32_t *out_depth) {
+                                                               int32_t *out_depth, int64_t *out_te) {
     const int lane = lane_id();
     const RegRec *lv = s.regs + (int64_t)(L % 3) * s.nreg;
     int64_t nf = 0;
@@ -1160,8 +1162,10 @@ __global__ void __launch_bounds__(kWave) plain_bfs_probe_kernel(PlainCtl *ctl, S
     ctl->reached = depth;
     ctl->more = nf > 0;
     if (L >= 1 && L <= ctl->level_cap) ctl->level_out[L - 1] = nf;
+    if (!ctl->valid) return;
     if (out_count) *out_count = ctl->count_acc + nf;
     if (out_depth) *out_depth = depth;
+    if (out_te) *out_te = ctl->te_acc;
 }
 
 // ------------------------------------------------------------------ the neighborhood as vertex ids
@@ -1267,12 +1271,11 @@ struct PlainCtx {
     State s[kStates]{};       // bitmaps, byte maps and region counters of each state
     int64_t *qb[2][2]{};      // queue sets by query parity, each by hop parity
     int64_t *qoff[2][2]{};
-    int hop_grid = 1;
     int init_grid = 1;
-    int compact_grid = 1;
     int64_t *set_partial = nullptr;  // block counts, then offsets, of the neighborhood-set kernels
     int64_t set_blocks = 0;
     void *arena = nullptr;
+    int32_t *h_flags = nullptr;  // pinned: a deep query's reached level and frontier-nonempty flag
 };
 
 namespace {
@@ -1290,6 +1293,17 @@ State query_state(const PlainCtx *c, int64_t q, const uint64_t *vmask, int32_t *
 }
 
 PlainCtl *query_slot(const PlainCtx *c, int64_t q) { return c->ctl + q % kSlots; }
+
+// Blocks of the hop and compaction launches: plain_grid per compute unit,
+// and no more than the bitmap has 8 (hop) or 16 (compaction) words per block.
+struct Grids {
+    int hop, compact;
+};
+Grids grids(const khop_graph *g, const Params &P) {
+    const int64_t nw = (g->n + 63) / 64, cap = (int64_t)g->cu_count * P.plain_grid;
+    return Grids{(int)std::max<int64_t>(1, std::min<int64_t>((nw + 7) / 8, cap)),
+                 (int)std::max<int64_t>(1, std::min<int64_t>((nw + 15) / 16, cap))};
+}
 
 }  // namespace
 
@@ -1357,9 +1371,13 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
         st.rw = rw;
         st.rc = rc;
     }
-    c->hop_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 7) / 8, (int64_t)g->cu_count * 4));
     c->init_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kBlock - 1) / kBlock, 512));
-    c->compact_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + 15) / 16, (int64_t)g->cu_count * 4));
+    if (hipHostMalloc((void **)&c->h_flags, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(c->arena);
+        delete c;
+        fail(KHOP_ENOMEM, "pinned host allocation for a query context failed");
+    }
     KHOP_HIP(hipMemset(c->arena, 0, off));
     KHOP_HIP(hipDeviceSynchronize());
     return c;
@@ -1368,6 +1386,7 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
 void plain_ctx_destroy(PlainCtx *c) {
     if (!c) return;
     if (c->arena) (void)hipFree(c->arena);
+    if (c->h_flags) (void)hipHostFree(c->h_flags);
     delete c;
 }
 
@@ -1378,6 +1397,71 @@ void plain_fill_zero_outputs(int64_t *d_counts, int64_t *d_te, int64_t n, hipStr
     KHOP_HIP(hipGetLastError());
 }
 
+// Hops a query of the pipelined path may have.  A deeper k (a request to
+// count everything within reach, in effect) runs its queries one at a time as
+// searches with no last hop, launched in groups, with a host check between
+// groups that ends the query once its frontier is empty: past its seed's
+// eccentricity every further hop would find nothing.
+constexpr int kDeepHops = 32;
+
+static void plain_deep(khop_graph *g, PlainCtx *c, const Params &P, const Graph &gr, const HeavyChunks &hc,
+                       const Grids &gd, const int32_t *d_seeds, int64_t num_seeds, int64_t k, int64_t *d_counts,
+                       int64_t *d_te, hipStream_t st, const uint64_t *d_vmask) {
+    const int64_t pam = (int64_t)P.push_atomic_max;
+    const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? gd.hop : std::max(c->init_grid, g->cu_count / 4);
+    const State s = query_state(c, 0, d_vmask, nullptr);
+    PlainCtl *ctl = query_slot(c, 0);
+    for (int64_t i = 0; i < num_seeds; ++i) {
+        {
+            ProfScope ps(g, KK_PLAIN_INIT, st);
+            hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, ctl, gr, s, d_seeds, i,
+                               (int)INT32_MAX, P.dir_mode, P.alpha, P.beta, pam, g->nnz, d_counts, d_te, ps.units());
+            ps.end(0, 1);
+        }
+        int64_t H = 0;  // hops launched
+        int64_t group = std::max(2, g->bfs_hops_hint.load(std::memory_order_relaxed));
+        while (H < k) {
+            const int64_t upto = std::min(k, H + group);
+            for (int64_t L = H + 1; L <= upto; ++L) {
+                ProfScope ps(g, KK_PLAIN_HOP, st);
+                if (L == 1) {
+                    const StepBook bk{nullptr, nullptr, nullptr, -1, nullptr, nullptr, nullptr, pam, g->nnz,
+                                      INT32_MAX, (int32_t)P.dir_mode, (int32_t)P.alpha, (int32_t)P.beta};
+                    hipLaunchKernelGGL(plain_step_kernel, dim3(hop1_grid), dim3(kBlock), 0, st, (PlainCtl *)nullptr,
+                                       State{}, (int64_t)0, ctl, s, (int64_t)hop1_grid, bk, State{}, State{}, gr,
+                                       P.pull_light, hc, ps.units());
+                    ps.end(0, 1);
+                    continue;
+                }
+                hipLaunchKernelGGL(plain_hop_kernel, dim3(gd.hop), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
+                                   P.pull_light, hc, ps.units());
+                ps.end(0, 1);
+                ProfScope pc(g, KK_PLAIN_COMPACT, st);
+                hipLaunchKernelGGL(plain_compact_kernel, dim3(gd.compact), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
+                                   pc.units());
+                pc.end(0, 1);
+            }
+            H = upto;
+            if (H >= k) break;
+            hipLaunchKernelGGL(plain_bfs_probe_kernel, dim3(1), dim3(kWave), 0, st, ctl, s, (int)H,
+                               (int64_t *)nullptr, (int32_t *)nullptr, (int64_t *)nullptr);
+            // reached and more are adjacent in the control record
+            KHOP_HIP(hipMemcpyAsync(c->h_flags, &ctl->reached, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            KHOP_HIP(hipStreamSynchronize(st));
+            if (!c->h_flags[1]) {
+                if (c->h_flags[0] > 0) g->bfs_hops_hint.store(c->h_flags[0] + 1, std::memory_order_relaxed);
+                break;
+            }
+            group = std::min<int64_t>(2 * group, 1024);
+        }
+        // the count of levels 1..H and the out-degree sum of levels 0..H-1: the
+        // query's answer, since any level past H is empty (or H = k)
+        hipLaunchKernelGGL(plain_bfs_probe_kernel, dim3(1), dim3(kWave), 0, st, ctl, s, (int)H, d_counts + i,
+                           (int32_t *)nullptr, d_te ? d_te + i : (int64_t *)nullptr);
+    }
+    KHOP_HIP(hipGetLastError());
+}
+
 void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
                int64_t *d_te, hipStream_t st, const uint64_t *d_vmask) {
     if (num_seeds <= 0) return;
@@ -1385,16 +1469,22 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         plain_fill_zero_outputs(d_counts, d_te, num_seeds, st);
         return;
     }
-    const Params &P = g->params;
-    const HeavyTable &ht = plain_heavy_table(g);
+    const Params P = params_of(g);
+    const HeavyTable ht = plain_heavy_table(g, P.pull_heavy);
+    const Grids gd = grids(g, P);
     Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
              ht.threshold};
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
+    if (k > kDeepHops) {
+        // no search goes deeper than n - 1 hops: a larger k counts the same
+        plain_deep(g, c, P, gr, hc, gd, d_seeds, num_seeds, std::min<int64_t>(k, g->n), d_counts, d_te, st, d_vmask);
+        return;
+    }
     const int64_t nnz_in = g->nnz;
     const int64_t pam = (int64_t)P.push_atomic_max;
     // hop 1 starts from the seed alone (top-down unless forced): the set-up
     // grid suffices
-    const int h1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
+    const int h1_grid = P.dir_mode == KHOP_DIR_PULL ? gd.hop : std::max(c->init_grid, g->cu_count / 4);
     auto state = [&](int64_t q) { return query_state(c, q, d_vmask, nullptr); };
     auto slot = [&](int64_t q) { return query_slot(c, q); };
     {
@@ -1414,7 +1504,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         const StepBook bk{qm >= 0 ? slot(qm) : nullptr, ps_j.fin >= 0 ? slot(ps_j.fin) : nullptr,
                           qn >= 0 ? slot(qn) : nullptr, qn, d_seeds, d_counts, d_te, pam, nnz_in, (int32_t)k,
                           (int32_t)P.dir_mode, (int32_t)P.alpha, (int32_t)P.beta};
-        const int64_t nb_last = ps_j.last >= 0 ? c->hop_grid : 0, nb_h1 = ps_j.h1 >= 0 ? h1_grid : 0;
+        const int64_t nb_last = ps_j.last >= 0 ? gd.hop : 0, nb_h1 = ps_j.h1 >= 0 ? h1_grid : 0;
         const int64_t nb_book = (qm >= 0 || qn >= 0) ? c->init_grid : 0;
         {
             ProfScope ps(g, KK_PLAIN_HOP, st);
@@ -1432,12 +1522,12 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         for (int L = 2; L < k; ++L) {
             {
                 ProfScope ps(g, KK_PLAIN_HOP, st);
-                hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, cq, L, gr, sq,
+                hipLaunchKernelGGL(plain_hop_kernel, dim3(gd.hop), dim3(kBlock), 0, st, cq, L, gr, sq,
                                    P.pull_light, hc, ps.units());
                 ps.end(0, 1);
             }
             ProfScope ps(g, KK_PLAIN_COMPACT, st);
-            hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, cq, L, gr, sq,
+            hipLaunchKernelGGL(plain_compact_kernel, dim3(gd.compact), dim3(kBlock), 0, st, cq, L, gr, sq,
                                ps.units());
             ps.end(0, 1);
         }
@@ -1457,13 +1547,14 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
 
 void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int32_t *d_dist, int64_t *d_count,
                int32_t *d_depth, int64_t *d_levels, int64_t level_cap, int32_t *h_flags, hipStream_t st) {
-    const Params &P = g->params;
-    const HeavyTable &ht = plain_heavy_table(g);
+    const Params P = params_of(g);
+    const HeavyTable ht = plain_heavy_table(g, P.pull_heavy);
+    const Grids gd = grids(g, P);
     Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
              ht.threshold};
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
     const int64_t pam = (int64_t)P.push_atomic_max;
-    const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? c->hop_grid : std::max(c->init_grid, g->cu_count / 4);
+    const int hop1_grid = P.dir_mode == KHOP_DIR_PULL ? gd.hop : std::max(c->init_grid, g->cu_count / 4);
     const State s = query_state(c, 0, nullptr, d_dist);
     PlainCtl *ctl = query_slot(c, 0);
     {
@@ -1490,18 +1581,18 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
                 ps.end(0, 1);
                 continue;
             }
-            hipLaunchKernelGGL(plain_hop_kernel, dim3(c->hop_grid), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
+            hipLaunchKernelGGL(plain_hop_kernel, dim3(gd.hop), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
                                P.pull_light, hc, ps.units());
             ps.end(0, 1);
             ProfScope pc(g, KK_PLAIN_COMPACT, st);
-            hipLaunchKernelGGL(plain_compact_kernel, dim3(c->compact_grid), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
+            hipLaunchKernelGGL(plain_compact_kernel, dim3(gd.compact), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
                                pc.units());
             pc.end(0, 1);
         }
         H = upto;
         if (!h_flags || H >= limit) break;
         hipLaunchKernelGGL(plain_bfs_probe_kernel, dim3(1), dim3(kWave), 0, st, ctl, s, (int)H, (int64_t *)nullptr,
-                           (int32_t *)nullptr);
+                           (int32_t *)nullptr, (int64_t *)nullptr);
         // reached and more are adjacent in the control record
         KHOP_HIP(hipMemcpyAsync(h_flags, &ctl->reached, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         KHOP_HIP(hipStreamSynchronize(st));
@@ -1512,7 +1603,8 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
         }
         group = std::min<int64_t>(2 * group, 1024);
     }
-    hipLaunchKernelGGL(plain_bfs_probe_kernel, dim3(1), dim3(kWave), 0, st, ctl, s, (int)H, d_count, d_depth);
+    hipLaunchKernelGGL(plain_bfs_probe_kernel, dim3(1), dim3(kWave), 0, st, ctl, s, (int)H, d_count, d_depth,
+                       (int64_t *)nullptr);
     KHOP_HIP(hipGetLastError());
 }
 

@@ -3,11 +3,15 @@
 //
 // Plain path: coordinate descent (two sweeps) over the push->pull threshold
 // alpha, the pull->push threshold beta, the lane-serial bottom-up degree, the
-// chunked bottom-up degree and the atomic top-down edge limit, timing queries
-// at k = 2 and 3 from sample seeds.  Batched path: seeds per launch and the
-// heavy-vertex threshold, timing a k = 3 batch.  Results are cached per
-// (device architecture, graph content hash, seeds per launch) in memory and in
-// a text file ($KHOP_TUNE_CACHE, default ~/.cache/khop/tune.txt).
+// chunked bottom-up degree, the atomic top-down edge limit and the hop
+// kernels' blocks per compute unit, timing queries at k = 2 and 3 from sample
+// seeds.  Batched path: seeds per launch and the heavy-vertex threshold
+// (jointly), then the top-down/bottom-up switch and the bottom-up kernel's
+// blocks per compute unit, timing a batch of mixed k (2, 3, 3, 6).  Results
+// are cached per (library sources, device architecture, graph content hash,
+// seeds per launch) in memory and in a text file ($KHOP_TUNE_CACHE, default
+// ~/.cache/khop/tune.txt); the source hash keeps settings tuned for other
+// kernels from being reused.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -18,15 +22,29 @@
 
 #include "khop_impl.h"
 
+#ifndef KHOP_SOURCE_HASH
+#define KHOP_SOURCE_HASH "unversioned"
+#endif
+
 namespace {
 
+constexpr int kFields = 11;  // Params fields the tuner sets
+
 struct Tuned {
-    int alpha, beta, pull_light, pull_heavy, push_atomic_max, batch_seeds, batch_heavy;
+    int v[kFields];
 };
+
+int *field(khop::Params &P, int i) {
+    int *f[kFields] = {&P.alpha,       &P.beta,           &P.pull_light,  &P.pull_heavy,
+                       &P.push_atomic_max, &P.batch_seeds, &P.batch_heavy, &P.batch_push_div,
+                       &P.plain_grid,  &P.batch_grid,     &P.dir_mode};
+    return f[i];
+}
 
 std::mutex g_cache_mu;
 std::map<std::string, Tuned> g_cache;
 bool g_cache_loaded = false;
+double g_last_seconds = 0;  // duration of the last search (0 when served from the cache)
 
 std::string cache_path() {
     if (const char *p = std::getenv("KHOP_TUNE_CACHE")) return p;
@@ -34,16 +52,29 @@ std::string cache_path() {
     return std::string(home ? home : "/tmp") + "/.cache/khop/tune.txt";
 }
 
+// One line per entry: the key, then the kFields values (dir_mode last, always
+// KHOP_DIR_AUTO: the tuner does not force a direction).  Lines in any other
+// format are skipped.
 void load_cache() {
     if (g_cache_loaded) return;
     g_cache_loaded = true;
     FILE *f = std::fopen(cache_path().c_str(), "r");
     if (!f) return;
-    char key[256];
-    Tuned t;
-    while (std::fscanf(f, "%255s %d %d %d %d %d %d %d", key, &t.alpha, &t.beta, &t.pull_light, &t.pull_heavy,
-                       &t.push_atomic_max, &t.batch_seeds, &t.batch_heavy) == 8)
-        g_cache[key] = t;
+    char line[1024];
+    while (std::fgets(line, sizeof(line), f)) {
+        char key[512];
+        Tuned t;
+        int used = 0;
+        if (std::sscanf(line, "%511s%n", key, &used) != 1) continue;
+        const char *p = line + used;
+        int i = 0;
+        for (; i < kFields; ++i) {
+            int adv = 0;
+            if (std::sscanf(p, "%d%n", &t.v[i], &adv) != 1) break;
+            p += adv;
+        }
+        if (i == kFields) g_cache[key] = t;
+    }
     std::fclose(f);
 }
 
@@ -57,25 +88,22 @@ void save_cache() {
     }
     FILE *f = std::fopen(p.c_str(), "w");
     if (!f) return;  // the cache is an optimisation only
-    for (auto &kv : g_cache)
-        std::fprintf(f, "%s %d %d %d %d %d %d %d\n", kv.first.c_str(), kv.second.alpha, kv.second.beta,
-                     kv.second.pull_light, kv.second.pull_heavy, kv.second.push_atomic_max, kv.second.batch_seeds,
-                     kv.second.batch_heavy);
+    for (auto &kv : g_cache) {
+        std::fprintf(f, "%s", kv.first.c_str());
+        for (int i = 0; i < kFields; ++i) std::fprintf(f, " %d", kv.second.v[i]);
+        std::fprintf(f, "\n");
+    }
     std::fclose(f);
 }
 
-Tuned current(const khop::Params &P) {
-    return {P.alpha, P.beta, P.pull_light, P.pull_heavy, P.push_atomic_max, P.batch_seeds, P.batch_heavy};
+Tuned current(khop::Params P) {
+    Tuned t;
+    for (int i = 0; i < kFields; ++i) t.v[i] = *field(P, i);
+    return t;
 }
 
 void apply(khop::Params &P, const Tuned &t) {
-    P.alpha = t.alpha;
-    P.beta = t.beta;
-    P.pull_light = t.pull_light;
-    P.pull_heavy = t.pull_heavy;
-    P.push_atomic_max = t.push_atomic_max;
-    P.batch_seeds = t.batch_seeds;
-    P.batch_heavy = t.batch_heavy;
+    for (int i = 0; i < kFields; ++i) *field(P, i) = t.v[i];
 }
 
 // Deterministic sample of non-isolated vertices, spread over the id range.
@@ -135,6 +163,12 @@ float best_of(F &&f, int reps) {
 
 }  // namespace
 
+namespace khop {
+const char *source_hash() { return KHOP_SOURCE_HASH; }
+}  // namespace khop
+
+extern "C" double khop_autotune_seconds(void) { return g_last_seconds; }
+
 extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
     try {
         if (!g) khop::fail(KHOP_EINVAL, "graph is NULL");
@@ -144,9 +178,9 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         KHOP_HIP(hipSetDevice(g->device));
         hipDeviceProp_t prop;
         KHOP_HIP(hipGetDeviceProperties(&prop, g->device));
-        char keybuf[200];
-        std::snprintf(keybuf, sizeof(keybuf), "%s:%016llx:%lld:%d", prop.gcnArchName, (unsigned long long)g->hash,
-                      (long long)g->n, seeds_per_launch);
+        char keybuf[320];
+        std::snprintf(keybuf, sizeof(keybuf), "%s:%s:%016llx:%lld:%d", KHOP_SOURCE_HASH, prop.gcnArchName,
+                      (unsigned long long)g->hash, (long long)g->n, seeds_per_launch);
         std::string key(keybuf);
         for (char &c : key)
             if (c == ' ') c = '_';
@@ -155,10 +189,17 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
             load_cache();
             auto it = g_cache.find(key);
             if (it != g_cache.end()) {
-                apply(g->params, it->second);
+                khop::Params P = khop::params_of(g);
+                const int dir = P.dir_mode;
+                apply(P, it->second);
+                P.dir_mode = dir;
+                khop::params_set(g, P);
+                g_last_seconds = 0;
                 return KHOP_OK;
             }
         }
+        timespec t_start;
+        clock_gettime(CLOCK_MONOTONIC, &t_start);
         const int plain_seeds = 48, batch_seeds = 1024;
         std::vector<int32_t> seeds = sample_seeds(g, batch_seeds);
         if (seeds.empty()) return KHOP_OK;  // no edges: nothing to tune
@@ -168,6 +209,7 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         KHOP_HIP(hipEventCreate(&b.e1));
         const bool prof_on = g->prof.on;
         g->prof.on = false;
+        const khop::Params saved = khop::params_of(g);
         struct Cleanup {
             Bench &b;
             khop_graph *g;
@@ -191,12 +233,17 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         }
         KHOP_HIP(hipMemcpy(b.d_seeds, seeds.data(), seeds.size() * 4, hipMemcpyHostToDevice));
         b.pc = khop::plain_ctx_create(g);
-        khop::Params &P = g->params;
-        const int saved_dir = P.dir_mode;
+        // the search works on a copy; each timing installs it (other callers see a consistent set)
+        khop::Params P = saved;
         P.dir_mode = KHOP_DIR_AUTO;
+        auto install = [&] { khop::params_set(g, P); };
 
         // ---- plain path: coordinate descent
-        auto plain_cost = [&] { return best_of([&] { return time_plain(b, plain_seeds); }, 2); };
+        auto plain_cost = [&] {
+            install();
+            return best_of([&] { return time_plain(b, plain_seeds); }, 2);
+        };
+        install();
         time_plain(b, plain_seeds);  // warm-up (contexts, chunk tables)
         struct Knob {
             int *field;
@@ -206,26 +253,36 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
                                    {&P.beta, {6, 12, 24, 48, 96}},
                                    {&P.pull_light, {8, 16, 32, 64, 128}},
                                    {&P.pull_heavy, {512, 1024, 4096, 16384, 65536}},
-                                   {&P.push_atomic_max, {4096, 16384, 65536, 262144, 1048576}}};
-        float best = plain_cost();
-        for (int sweep = 0; sweep < 2; ++sweep)
-            for (auto &kn : knobs) {
-                int keep = *kn.field;
-                for (int v : kn.values) {
-                    if (v == keep) continue;
-                    *kn.field = v;
-                    float t = plain_cost();
-                    if (t < best * 0.98f) {
-                        best = t;
-                        keep = v;
+                                   {&P.push_atomic_max, {4096, 16384, 65536, 262144, 1048576}},
+                                   {&P.plain_grid, {2, 4, 8, 16}}};
+        auto descend = [&](std::vector<Knob> &ks, auto &&cost, int sweeps) {
+            float best = cost();
+            for (int sweep = 0; sweep < sweeps; ++sweep)
+                for (auto &kn : ks) {
+                    int keep = *kn.field;
+                    for (int v : kn.values) {
+                        if (v == keep) continue;
+                        *kn.field = v;
+                        float t = cost();
+                        if (t < best * 0.98f) {
+                            best = t;
+                            keep = v;
+                        }
                     }
+                    *kn.field = keep;
                 }
-                *kn.field = keep;
-            }
+            return best;
+        };
+        descend(knobs, plain_cost, 2);
 
-        // ---- batched path
-        std::vector<int32_t> ks(seeds.size(), 3);
-        auto batch_cost = [&] { return best_of([&] { return time_batched(b, ks); }, 2); };
+        // ---- batched path: a batch of mixed k, as queries arrive in practice
+        static const int32_t kMix[4] = {2, 3, 3, 6};
+        std::vector<int32_t> ks(seeds.size());
+        for (size_t i = 0; i < ks.size(); ++i) ks[i] = kMix[i % 4];
+        auto batch_cost = [&] {
+            install();
+            return best_of([&] { return time_batched(b, ks); }, 2);
+        };
         std::vector<int> per = seeds_per_launch ? std::vector<int>{seeds_per_launch}
                                                 : std::vector<int>{64, 128, 256, 512, 1024};
         float bbest = 1e30f;
@@ -244,12 +301,19 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         }
         P.batch_seeds = best_per;
         P.batch_heavy = best_heavy;
-        P.dir_mode = saved_dir;
+        std::vector<Knob> bknobs = {{&P.batch_push_div, {16, 32, 64, 128, 256, 1024}},
+                                    {&P.batch_grid, {4, 8, 16, 32}}};
+        descend(bknobs, batch_cost, 1);
+        P.dir_mode = saved.dir_mode;
+        khop::params_set(g, P);
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
             g_cache[key] = current(P);
             save_cache();
         }
+        timespec t_end;
+        clock_gettime(CLOCK_MONOTONIC, &t_end);
+        g_last_seconds = (double)(t_end.tv_sec - t_start.tv_sec) + 1e-9 * (double)(t_end.tv_nsec - t_start.tv_nsec);
         return KHOP_OK;
     } catch (const khop::Error &e) {
         khop::set_last_error(e.msg);
