@@ -116,6 +116,26 @@ int khop_count_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int
                    int64_t *d_traversed_edges, void *hip_stream);
 
 /*
+ * khop_count_dev for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation and outputs, with the query context placed in a static
+ * device scratch array of the library (160 MiB per device, held from the
+ * library's load until the process ends), so the call makes no hipMalloc,
+ * hipFree or other allocation, and waits on nothing.  Limits: the graph's
+ * query context must fit the scratch (about 69 bytes per vertex: up to about
+ * 2.4 million vertices) and k must be at most 32; otherwise KHOP_ERANGE with
+ * nothing enqueued.  Other errors as khop_count_dev.  Every call on one GPU
+ * shares that GPU's scratch, which keeps the last call's contents (each call
+ * clears what must start at zero): calls that overlap on one GPU, from two
+ * streams or two threads, race and must not be made.  Options are read as in
+ * khop_count_dev, but a changed bottom-up chunk threshold
+ * (KHOP_OPT_PULL_HEAVY) does not rebuild the chunk table here; the table the
+ * graph already has is used, which changes no count.  Not profiled.
+ */
+int khop_count_dev_noalloc(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
+                           int64_t *d_traversed_edges, void *hip_stream);
+
+/*
  * Label-filtered count: the k-hop count of each seed in the subgraph of the
  * vertices whose bit is set in label_bits (bit v % 64 of word v / 64; the
  * seed itself is always the start, labeled or not), i.e. counts[i] =

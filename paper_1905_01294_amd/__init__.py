@@ -55,7 +55,7 @@ KHOP_PATH_SINGLE = 1
 
 # Every entry point declared in include/khop.h.
 EXPORTS = ("graph_load_csr", "graph_load_csr_typed", "graph_free", "graph_info", "graph_degrees",
-           "khop_count", "khop_count_dev", "khop_count_labeled", "khop_count_labeled_dev",
+           "khop_count", "khop_count_dev", "khop_count_dev_noalloc", "khop_count_labeled", "khop_count_labeled_dev",
            "khop_count_batched", "khop_count_batched_dev", "khop_count_batched_labeled",
            "khop_bfs", "khop_bfs_dev", "khop_levels", "khop_levels_dev", "khop_neighborhood", "khop_neighborhood_dev",
            "khop_set_option", "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read",
@@ -114,6 +114,7 @@ def _load():
         "graph_degrees": ([_vp, _i64p],),
         "khop_count": ([_vp, _i32p, ctypes.c_int64, ctypes.c_int32, _i64p, _i64p],),
         "khop_count_dev": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp],),
+        "khop_count_dev_noalloc": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp],),
         "khop_count_labeled": ([_vp, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64), _i64p,
                                 _i64p],),
         "khop_count_labeled_dev": ([_vp, _vp, ctypes.c_int64, ctypes.c_int32, _vp, _vp, _vp, _vp],),
@@ -254,6 +255,16 @@ def khop_count(h, seeds, k: int, with_te: bool = False):
     _check(_lib.khop_count(h, sp, s.shape[0], int(k), counts.ctypes.data_as(_i64p),
                            te.ctypes.data_as(_i64p) if te is not None else None))
     return (counts, te) if with_te else counts
+
+
+def khop_count_dev_noalloc(h, d_seeds, k: int, d_counts, d_te=None, stream=None) -> None:
+    """khop_count_dev with the query context in the library's static scratch (no allocation)."""
+    n = int(d_seeds.numel())
+    if int(d_counts.numel()) < n or (d_te is not None and int(d_te.numel()) < n):
+        raise ValueError("output tensors shorter than the seed tensor")
+    _check(_lib.khop_count_dev_noalloc(h, _dev_ptr(d_seeds, "torch.int32"), n, int(k),
+                                       _dev_ptr(d_counts, "torch.int64"), _dev_ptr(d_te, "torch.int64"),
+                                       _stream_ptr(stream)))
 
 
 def khop_count_dev(h, d_seeds, k: int, d_counts, d_te=None, stream=None) -> None:
@@ -458,6 +469,9 @@ class Graph:
 
     def count_dev(self, d_seeds, k: int, d_counts, d_te=None, stream=None):
         khop_count_dev(self._h, d_seeds, k, d_counts, d_te, stream)
+
+    def count_dev_noalloc(self, d_seeds, k: int, d_counts, d_te=None, stream=None):
+        khop_count_dev_noalloc(self._h, d_seeds, k, d_counts, d_te, stream)
 
     def count_labeled(self, seeds, k: int, labeled, with_te: bool = False):
         """Counts in the subgraph of the vertices with labeled[v] true (the seeds exempt)."""

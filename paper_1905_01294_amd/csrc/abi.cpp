@@ -70,6 +70,7 @@ static void check_graph(const khop_graph *g) {
 // ---------------------------------------------------------------- profiling
 
 ProfScope::ProfScope(khop_graph *g, int kind, hipStream_t st) : g_(g), kind_(kind), st_(st) {
+    if (!g) return;  // an unprofiled launch
     Profiler &P = g->prof;
     if (!P.on) return;
     std::lock_guard<std::mutex> lk(g->prof_mu);
@@ -468,6 +469,9 @@ static void load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, 
             g->d_in_colidx = g->d_colidx;
         }
         KHOP_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+        // the bottom-up chunk table for the default threshold, so that a path
+        // which may not allocate finds one
+        (void)plain_heavy_table(g, g->params.pull_heavy);
     } catch (...) {
         graph_free(g);
         throw;
@@ -605,6 +609,19 @@ int khop_count_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int
             throw;
         }
         give_plain(g, s, st);
+    });
+}
+
+int khop_count_dev_noalloc(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
+                           int64_t *d_traversed_edges, void *hip_stream) {
+    return guard([&] {
+        check_graph(g);
+        if (num_seeds < 0) fail(KHOP_EINVAL, "num_seeds < 0");
+        if (k < 0) fail(KHOP_EINVAL, "k < 0");
+        if (num_seeds == 0) return;
+        if (!d_seeds || !d_counts) fail(KHOP_EINVAL, "d_seeds or d_counts is NULL");
+        KHOP_HIP(hipSetDevice(g->device));
+        plain_run_noalloc(g, d_seeds, num_seeds, k, d_counts, d_traversed_edges, (hipStream_t)hip_stream);
     });
 }
 

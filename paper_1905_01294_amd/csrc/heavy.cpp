@@ -77,6 +77,11 @@ HeavyTable plain_heavy_table(khop_graph *g, int threshold) { return build(g, g->
 
 HeavyTable batch_heavy_table(khop_graph *g, int threshold) { return build(g, g->batch_heavy, threshold, 1024); }
 
+HeavyTable plain_heavy_table_current(khop_graph *g) {
+    std::lock_guard<std::mutex> lk(g->heavy_mu);
+    return g->plain_heavy;
+}
+
 // Called by graph_free after the device has finished all work.
 void heavy_tables_free(khop_graph *g) {
     std::lock_guard<std::mutex> lk(g->heavy_mu);

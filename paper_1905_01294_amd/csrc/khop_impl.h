@@ -176,6 +176,13 @@ void plain_ctx_destroy(PlainCtx *c);
 void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k,
                int64_t *d_counts, int64_t *d_te, hipStream_t st, const uint64_t *d_vmask = nullptr);
 void plain_fill_zero_outputs(int64_t *d_counts, int64_t *d_te, int64_t n, hipStream_t st);
+// plain_run on a query context laid out in the library's static device
+// scratch: allocates nothing.  Throws KHOP_ERANGE when the graph's context
+// does not fit the scratch or k exceeds the pipelined path's depth.
+void plain_run_noalloc(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
+                       int64_t *d_te, hipStream_t st);
+size_t plain_noalloc_capacity();  // bytes of that scratch
+int plain_noalloc_max_k();
 // Breadth-first search from one (valid) seed, up to max_depth hops (< 0: no
 // limit), on the context's first state.  Distances go to d_dist[n] and the
 // size of each level 1..level_cap to d_levels when those are not null; the
@@ -223,6 +230,8 @@ void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, 
 // changes.  The copy returned stays valid until graph_free.
 HeavyTable plain_heavy_table(khop_graph *g, int threshold);
 HeavyTable batch_heavy_table(khop_graph *g, int threshold);
+// The plain table as it stands, never rebuilt (graph_load_csr builds one for the default threshold).
+HeavyTable plain_heavy_table_current(khop_graph *g);
 void heavy_tables_free(khop_graph *g);
 // A consistent copy of the graph's options, and their replacement (options
 // change between calls; a call runs on the copy it took when it started).

@@ -1276,6 +1276,10 @@ struct PlainCtx {
     int64_t set_blocks = 0;
     void *arena = nullptr;
     int32_t *h_flags = nullptr;  // pinned: a deep query's reached level and frontier-nonempty flag
+    // A context in the no-allocation scratch: its runs are not profiled (that
+    // creates events) and take the chunk table the graph already has instead
+    // of building one for a changed threshold.
+    bool fixed = false;
 };
 
 namespace {
@@ -1307,9 +1311,9 @@ Grids grids(const khop_graph *g, const Params &P) {
 
 }  // namespace
 
-PlainCtx *plain_ctx_create(khop_graph *g) {
-    PlainCtx *c = new PlainCtx();
-    c->g = g;
+// The layout of a query context in one device allocation: the total bytes,
+// and when base is not null, every pointer of c set into it.
+static size_t plain_layout(const khop_graph *g, PlainCtx *c, char *base) {
     const int64_t n = g->n, nw = (n + 63) / 64;
     const int nreg = (int)std::min<int64_t>(kMaxRegions, nw);
     const int rw = (int)((nw + nreg - 1) / nreg);
@@ -1345,13 +1349,9 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
             o_qoff[j][i] = off;
             off += al(slots * 8);
         }
-    hipError_t e = hipMalloc(&c->arena, off);
-    if (e != hipSuccess) {
-        delete c;
-        (void)hipGetLastError();
-        fail(KHOP_ENOMEM, "device allocation of " + std::to_string(off) + " bytes for a query context failed");
-    }
-    char *base = (char *)c->arena;
+    if (!base) return off;
+    c->g = const_cast<khop_graph *>(g);
+    c->arena = base;
     c->ctl = (PlainCtl *)(base + o_ctl);
     c->set_partial = (int64_t *)(base + o_part);
     c->set_blocks = set_blocks;
@@ -1372,13 +1372,26 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
         st.rc = rc;
     }
     c->init_grid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kBlock - 1) / kBlock, 512));
+    return off;
+}
+
+PlainCtx *plain_ctx_create(khop_graph *g) {
+    PlainCtx *c = new PlainCtx();
+    const size_t bytes = plain_layout(g, c, nullptr);
+    void *arena = nullptr;
+    if (hipMalloc(&arena, bytes) != hipSuccess) {
+        delete c;
+        (void)hipGetLastError();
+        fail(KHOP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes for a query context failed");
+    }
+    plain_layout(g, c, (char *)arena);
     if (hipHostMalloc((void **)&c->h_flags, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
-        (void)hipFree(c->arena);
+        (void)hipFree(arena);
         delete c;
         fail(KHOP_ENOMEM, "pinned host allocation for a query context failed");
     }
-    KHOP_HIP(hipMemset(c->arena, 0, off));
+    KHOP_HIP(hipMemset(arena, 0, bytes));
     KHOP_HIP(hipDeviceSynchronize());
     return c;
 }
@@ -1470,7 +1483,8 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         return;
     }
     const Params P = params_of(g);
-    const HeavyTable ht = plain_heavy_table(g, P.pull_heavy);
+    const HeavyTable ht = c->fixed ? plain_heavy_table_current(g) : plain_heavy_table(g, P.pull_heavy);
+    khop_graph *const pg = c->fixed ? nullptr : g;  // profiled launches (none for a fixed context)
     const Grids gd = grids(g, P);
     Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
              ht.threshold};
@@ -1488,7 +1502,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     auto state = [&](int64_t q) { return query_state(c, q, d_vmask, nullptr); };
     auto slot = [&](int64_t q) { return query_slot(c, q); };
     {
-        ProfScope ps(g, KK_PLAIN_INIT, st);
+        ProfScope ps(pg, KK_PLAIN_INIT, st);
         hipLaunchKernelGGL(plain_init_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, slot(0), gr, state(0),
                            d_seeds, (int64_t)0, (int)k, P.dir_mode, P.alpha, P.beta, pam, nnz_in, d_counts, d_te,
                            ps.units());
@@ -1507,7 +1521,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         const int64_t nb_last = ps_j.last >= 0 ? gd.hop : 0, nb_h1 = ps_j.h1 >= 0 ? h1_grid : 0;
         const int64_t nb_book = (qm >= 0 || qn >= 0) ? c->init_grid : 0;
         {
-            ProfScope ps(g, KK_PLAIN_HOP, st);
+            ProfScope ps(pg, KK_PLAIN_HOP, st);
             hipLaunchKernelGGL(plain_step_kernel, dim3((unsigned)(nb_last + nb_h1 + nb_book)), dim3(kBlock), 0, st,
                                ps_j.last >= 0 ? slot(ps_j.last) : nullptr,
                                ps_j.last >= 0 ? state(ps_j.last) : State{}, nb_last,
@@ -1521,12 +1535,12 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         const State sq = state(ps_j.h1);
         for (int L = 2; L < k; ++L) {
             {
-                ProfScope ps(g, KK_PLAIN_HOP, st);
+                ProfScope ps(pg, KK_PLAIN_HOP, st);
                 hipLaunchKernelGGL(plain_hop_kernel, dim3(gd.hop), dim3(kBlock), 0, st, cq, L, gr, sq,
                                    P.pull_light, hc, ps.units());
                 ps.end(0, 1);
             }
-            ProfScope ps(g, KK_PLAIN_COMPACT, st);
+            ProfScope ps(pg, KK_PLAIN_COMPACT, st);
             hipLaunchKernelGGL(plain_compact_kernel, dim3(gd.compact), dim3(kBlock), 0, st, cq, L, gr, sq,
                                ps.units());
             ps.end(0, 1);
@@ -1535,7 +1549,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     // the last query's marks and the count of the one before it, then the last count
     {
         const PlainStep cl = plain_plan_close(m);
-        ProfScope ps(g, KK_PLAIN_INIT, st);
+        ProfScope ps(pg, KK_PLAIN_INIT, st);
         hipLaunchKernelGGL(plain_close_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, slot(cl.marks),
                            cl.fin >= 0 ? slot(cl.fin) : nullptr, (int)(cl.fin >= 0), gr, state(cl.marks),
                            ps.units());
@@ -1623,6 +1637,85 @@ void plain_set(khop_graph *g, PlainCtx *c, int32_t seed, int32_t *d_ids, int64_t
     // the visited bitmap read once per pass, the block counts written, scanned and read
     ps.end((double)(write ? 2 : 1) * 8.0 * (double)nw + (write ? 4.0 : 2.0) * 8.0 * (double)nb, 1);
     KHOP_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ the no-allocation entry point
+
+// Scratch for one query context per device, for callers that cannot
+// allocate: 160 MiB holds the context of a graph of up to about 2.4 million
+// vertices (69 bytes per vertex plus fixed parts).  Each device holds its own
+// copy from the library's load until the process ends.  In host code the
+// array's name is not a device address: its address on each device comes from
+// hipGetSymbolAddress, made once per device with that device current.
+constexpr size_t kScratchBytes = (size_t)160 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<char *> g_scratch_ptr;  // by device
+
+char *scratch_on(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+    if (!g_scratch_ptr[(size_t)device]) {
+        void *p = nullptr;
+        KHOP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) fail(KHOP_EDEVICE, "hipGetSymbolAddress returned no address for the query scratch");
+        g_scratch_ptr[(size_t)device] = (char *)p;
+    }
+    return g_scratch_ptr[(size_t)device];
+}
+
+// Byte ranges to zero, each 8-byte aligned and padded to a multiple of 8.
+struct ZeroRanges {
+    uint64_t *p[8];
+    int64_t words[8];
+    int n;
+};
+
+__global__ void __launch_bounds__(kBlock) zero_ranges_kernel(ZeroRanges z) {
+    for (int r = 0; r < z.n; ++r)
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < z.words[r]; i += (int64_t)gridDim.x * kBlock)
+            z.p[r][i] = 0;
+}
+
+}  // namespace
+
+size_t plain_noalloc_capacity() { return kScratchBytes; }
+int plain_noalloc_max_k() { return kDeepHops; }
+
+void plain_run_noalloc(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
+                       int64_t *d_te, hipStream_t st) {
+    if (k > kDeepHops)
+        fail(KHOP_ERANGE, "k = " + std::to_string(k) + " is deeper than the " + std::to_string(kDeepHops) +
+                              " hops the no-allocation path runs (deeper queries need host-checked hop groups)");
+    PlainCtx c;
+    const size_t bytes = plain_layout(g, &c, nullptr);
+    if (bytes > kScratchBytes)
+        fail(KHOP_ERANGE, "a query context for " + std::to_string(g->n) + " vertices needs " + std::to_string(bytes) +
+                              " bytes, more than the " + std::to_string(kScratchBytes) + "-byte no-allocation scratch");
+    if (plain_heavy_table_current(g).threshold < 0) fail(KHOP_EINTERNAL, "the graph has no bottom-up chunk table");
+    if (num_seeds <= 0) return;
+    plain_layout(g, &c, scratch_on(g->device));
+    c.fixed = true;
+    // an earlier call (perhaps on another graph) left the scratch in any
+    // state: the byte marks, their summaries and the control records, which
+    // the path expects zero between queries, start clear
+    const int64_t nw = (g->n + 63) / 64;
+    ZeroRanges z{};
+    for (int p = 0; p < kStates; ++p) {
+        z.p[z.n] = (uint64_t *)c.s[p].nextb;
+        z.words[z.n++] = nw * 8;  // nw * 64 bytes
+        z.p[z.n] = (uint64_t *)c.s[p].nsum;
+        z.words[z.n++] = (nw + 7) / 8;  // inside the 256-byte padding of the summary
+    }
+    z.p[z.n] = (uint64_t *)c.ctl;
+    z.words[z.n++] = (int64_t)(kSlots * sizeof(PlainCtl) + 7) / 8;
+    const int zgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nw * 8 + kBlock - 1) / kBlock, 1024));
+    hipLaunchKernelGGL(zero_ranges_kernel, dim3(zgrid), dim3(kBlock), 0, st, z);
+    KHOP_HIP(hipGetLastError());
+    plain_run(g, &c, d_seeds, num_seeds, k, d_counts, d_te, st, nullptr);
 }
 
 }  // namespace khop

@@ -84,6 +84,7 @@ def test_null_graph_calls():
     s = (ctypes.c_int32 * 4)()
     assert lib.khop_count(None, s, 1, 1, c, None) == K.KHOP_EINVAL
     assert lib.khop_count_dev(None, None, 1, 1, None, None, None) == K.KHOP_EINVAL
+    assert lib.khop_count_dev_noalloc(None, None, 1, 1, None, None, None) == K.KHOP_EINVAL
     assert lib.khop_count_batched(None, s, s, 1, c) == K.KHOP_EINVAL
     assert lib.khop_count_batched_dev(None, None, None, 1, None, None) == K.KHOP_EINVAL
     assert lib.graph_info(None, None, None, None) == K.KHOP_EINVAL
