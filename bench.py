@@ -8,16 +8,23 @@ at k = 1 and at k = 2, 10 seeds at k = 3 and at k = 6.
 
 One step answers that query set twice, with the graph and the seeds already
 resident in device memory:
-  plain    one launch sequence per query, queries one after another;
+  plain    the plain single-query path in one device call per k: queries are
+           answered in order, and consecutive queries overlap by one launch
+           (the last hop of one beside hop 1 of the next);
   batched  all queries in seed-bitset launches (mixed k).
 value = traversed edges credited to every answered query / step time (GTEPS),
 where a query's credit is the out-degree sum of the vertices at distance
 0..k-1 (the edges a top-down search inspects).
 
-After the timed steps, three more steps run with per-kernel HIP-event profiling
-for the roofline figure, per-query latencies are taken through the
-host entry point, and (N = 1 only) the CPU oracle answers the query set on the
-host for the baseline; its counts are also compared with the GPU's.
+Beside the step: the strictly sequential plain form (one launch sequence per
+query, each complete before the next starts), the 32-seed scale-10 case, the
+autotuner's search (live, unless a cache is named), per-kernel HIP-event
+profiling for the roofline figure, per-query latencies through the host entry
+point, the batched seeds-per-launch sweep, full-depth search, neighborhood
+sets and label-filtered counts, the 41.6M-vertex power-law graph (its plain
+protocol and a 256-seed batch), serving (the scale-21 graph alone, then both
+graphs resident), and (N = 1 only) the CPU oracle answering the query set on
+the host for the baseline, its counts compared with the GPU's.
 """
 import argparse
 import json
@@ -71,8 +78,10 @@ def main():
     ap.add_argument("--only-bfs", action="store_true",
                     help="print only the breadth-first search, neighborhood-set and level measurements (one JSON "
                          "line, not the benchmark line)")
-    ap.add_argument("--twitter", action="store_true",
-                    help="also load the 41.6M-vertex power-law graph and serve both graphs")
+    ap.add_argument("--no-twitter", action="store_true",
+                    help="skip the 41.6M-vertex power-law graph (its legs and two-graph serving)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file to read and write (default: a fresh one, so the search runs)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window per offered-load level")
     ap.add_argument("--no-autotune", action="store_true", help="time the default settings instead of tuned ones")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -91,9 +100,17 @@ def main():
               "described but not built", file=sys.stderr)
         sys.exit(2)
 
-    # tuned settings are cached per (architecture, graph content); the package ships the
-    # cache that khop_autotune wrote for the bench graphs on an MI355X
-    os.environ.setdefault("KHOP_TUNE_CACHE", os.path.join(ROOT, "paper_1905_01294_amd", "tuned.txt"))
+    # the autotuner's cache: a fresh file unless one is named, so the settings are searched for the
+    # kernels being timed (the cache key also carries a hash of the library's sources)
+    import tempfile
+    tune_dir = None
+    if args.tune_cache:
+        os.environ["KHOP_TUNE_CACHE"] = args.tune_cache
+    else:
+        tune_dir = tempfile.mkdtemp(prefix="khop_tune_")
+        os.environ["KHOP_TUNE_CACHE"] = os.path.join(tune_dir, "tune.txt")
+    legs = {}
+    t_bench = time.time()
     import torch
 
     import graphgen
@@ -106,15 +123,8 @@ def main():
     t0 = time.time()
     g = K.Graph.from_edgelist(el)
     log(f"device graph: n={g.n} arcs={g.num_arcs} in {time.time() - t0:.1f}s")
-    if not args.no_autotune:
-        t0 = time.time()
-        g.autotune(0)
-        log(f"autotuned in {time.time() - t0:.1f}s: " + ", ".join(
-            f"{name}={g.get_option(opt)}" for name, opt in (
-                ("alpha", K.KHOP_OPT_ALPHA), ("beta", K.KHOP_OPT_BETA), ("pull_light", K.KHOP_OPT_PULL_LIGHT),
-                ("pull_heavy", K.KHOP_OPT_PULL_HEAVY), ("push_atomic", K.KHOP_OPT_PUSH_ATOMIC),
-                ("batch_seeds", K.KHOP_OPT_BATCH_SEEDS),
-                ("batch_heavy", K.KHOP_OPT_BATCH_HEAVY))))
+    tuning = {"rmat21": run_autotune(g, K, "rmat21")} if not args.no_autotune else None
+    legs["load_and_tune_s"] = round(time.time() - t_bench, 2)
 
     if args.only_bfs:
         cpu_leg = not args.no_cpu_baseline
@@ -182,6 +192,27 @@ def main():
     log(f"timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.2f} GTEPS")
     p_ms = float(np.mean(plain_ms))
     b_ms = float(np.mean(batched_ms))
+    legs["step_s"] = round(time.time() - t_bench - legs["load_and_tune_s"], 2)
+
+    # ---- the strictly sequential plain form: one launch sequence per query, each complete (count
+    # written) before the next query's first launch, on the same device-resident queries
+    t_leg = time.time()
+    g.set_option(K.KHOP_OPT_PLAIN_PIPELINE, 0)
+    plain_pass()
+    torch.cuda.synchronize()
+    seq_counts = torch.cat([dc for _, _, dc, _ in d_groups]).cpu().numpy()
+    ev[0].record(stream)
+    for _ in range(3):
+        plain_pass()
+    ev[1].record(stream)
+    ev[1].synchronize()
+    g.set_option(K.KHOP_OPT_PLAIN_PIPELINE, 1)
+    s_ms = ev[0].elapsed_time(ev[1]) / 3
+    if not np.array_equal(seq_counts, plain_counts):
+        raise SystemExit("sequential plain counts differ from the pipelined ones")
+    log(f"sequential plain pass: {s_ms:.3f} ms ({nq / (s_ms / 1e3):.0f} queries/s)")
+    g0_leg = g0_bench(K, torch, cpu_leg=not args.no_cpu_baseline)
+    legs["sequential_and_g0_s"] = round(time.time() - t_leg, 2)
 
     # ---- profiled replay for the per-kernel roofline
     roofline = None
@@ -234,33 +265,42 @@ def main():
                 g.count(np.array([s], np.int32), k)
                 lat.append((time.perf_counter() - t) * 1000.0)
             latency[f"k{k}"] = {"mean_ms": round(float(np.mean(lat)), 4), "p50_ms": round(pct(lat, 50), 4),
-                                "p99_ms": round(pct(lat, 99), 4), "n": len(lat)}
+                                "p99_ms": round(pct(lat, 99), 4), "max_ms": round(float(np.max(lat)), 4),
+                                "n": len(lat)}
 
+    t_leg = time.time()
     sweep = None if args.no_sweep else batched_sweep(g, el, K, torch)
     bfs = None if args.no_bfs else bfs_bench(g, el, K, torch, cpu_leg=not args.no_cpu_baseline)
     sets = None if args.no_bfs else sets_bench(g, el, groups, K, torch, cpu_leg=not args.no_cpu_baseline)
     filtered = None if args.no_bfs else filtered_bench(g, el, groups, K, torch, cpu_leg=not args.no_cpu_baseline)
+    legs["sweep_bfs_sets_filtered_s"] = round(time.time() - t_leg, 2)
     g2 = el2 = None
     power_law = None
-    if args.twitter:
-        t0 = time.time()
+    if not args.no_twitter:
+        t_leg = time.time()
         el2 = graphgen.twitter_like(seed=1)
         g2 = K.Graph.from_edgelist(el2)
-        log(f"power-law graph: n={g2.n} arcs={g2.num_arcs} in {time.time() - t0:.1f}s")
+        log(f"power-law graph: n={g2.n} arcs={g2.num_arcs} in {time.time() - t_leg:.1f}s")
+        legs["power_law_load_s"] = round(time.time() - t_leg, 2)
+        t_leg = time.time()
         if not args.no_autotune:
-            g2.autotune(0)
+            tuning["chunglu41.6M"] = run_autotune(g2, K, "chunglu41.6M")
         power_law = power_law_bench(g2, el2, K, torch)
+        legs["power_law_s"] = round(time.time() - t_leg, 2)
     serving = None
     if not args.no_serving:
-        graphs = [("rmat21", g, el)]
+        t_leg = time.time()
+        serving = {"rmat21": serving_bench(K, [("rmat21", g, el)], args.serve_seconds)}
         if g2 is not None:
-            graphs.append(("chunglu41.6M", g2, el2))
-        serving = serving_bench(K, graphs, args.serve_seconds)
+            serving["rmat21+chunglu41.6M"] = serving_bench(K, [("rmat21", g, el), ("chunglu41.6M", g2, el2)],
+                                                           args.serve_seconds)
+        legs["serving_s"] = round(time.time() - t_leg, 2)
     if g2 is not None:
         g2.free()
 
     # ---- CPU oracle baseline (host cores, same queries)
     cpu = None
+    t_leg = time.time()
     if not args.no_cpu_baseline:
         import oracle
         t0 = time.time()
@@ -299,6 +339,11 @@ def main():
                         "gteps": round(sum(o_te) / pool_s / 1e9, 4)}}
         if not parity:
             log("WARNING: oracle counts differ from the GPU counts")
+    legs["cpu_baseline_s"] = round(time.time() - t_leg, 2)
+    legs["total_s"] = round(time.time() - t_bench, 2)
+    if tune_dir:
+        import shutil
+        shutil.rmtree(tune_dir, ignore_errors=True)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
@@ -310,11 +355,19 @@ def main():
                    "vertices": g.n, "arcs": g.num_arcs, "queries_per_pass": nq,
                    "k_mix": {"1": 300, "2": 300, "3": 10, "6": 10}, "passes_per_step": ["plain", "batched"],
                    "traversed_edges_per_pass": te_set},
-        "plain": {"gteps": round(te_set / (p_ms / 1000.0) / 1e9, 3), "qps": round(nq / (p_ms / 1000.0), 1),
+        "plain": {"form": "pipelined: queries in order, consecutive queries overlap by one launch",
+                  "gteps": round(te_set / (p_ms / 1000.0) / 1e9, 3), "qps": round(nq / (p_ms / 1000.0), 1),
                   "ms_per_pass": round(p_ms, 3)},
+        "plain_sequential": {"form": "one launch sequence per query, each complete before the next starts",
+                             "gteps": round(te_set / (s_ms / 1000.0) / 1e9, 3),
+                             "qps": round(nq / (s_ms / 1000.0), 1), "ms_per_pass": round(s_ms, 3)},
         "batched": {"gteps": round(te_set / (b_ms / 1000.0) / 1e9, 3), "qps": round(nq / (b_ms / 1000.0), 1),
                     "ms_per_pass": round(b_ms, 3), "seeds_per_launch": g.get_option(K.KHOP_OPT_BATCH_SEEDS)},
         "batched_vs_plain_qps": round(p_ms / b_ms, 3),
+        "batched_vs_plain_sequential_qps": round(s_ms / b_ms, 3),
+        "g0_plain": g0_leg,
+        "tuning": tuning,
+        "legs_seconds": legs,
         "latency_host_api": latency,
         "batched_sweep": sweep,
         "serving": serving,
@@ -329,6 +382,57 @@ def main():
     }
     print(json.dumps(out), flush=True)
     g.free()
+
+
+TUNED_OPTIONS = (("alpha", "KHOP_OPT_ALPHA"), ("beta", "KHOP_OPT_BETA"), ("pull_light", "KHOP_OPT_PULL_LIGHT"),
+                 ("pull_heavy", "KHOP_OPT_PULL_HEAVY"), ("push_atomic", "KHOP_OPT_PUSH_ATOMIC"),
+                 ("plain_grid", "KHOP_OPT_PLAIN_GRID"), ("batch_seeds", "KHOP_OPT_BATCH_SEEDS"),
+                 ("batch_heavy", "KHOP_OPT_BATCH_HEAVY"), ("batch_push_div", "KHOP_OPT_BATCH_PUSH"),
+                 ("batch_grid", "KHOP_OPT_BATCH_GRID"))
+
+
+def run_autotune(g, K, name):
+    """khop_autotune on a graph: whether it searched or read the cache, how long it took, what it chose."""
+    t0 = time.time()
+    g.autotune(0)
+    secs = time.time() - t0
+    searched = K.khop_autotune_seconds()
+    settings = {key: g.get_option(getattr(K, opt)) for key, opt in TUNED_OPTIONS}
+    log(f"{name}: autotune {'searched' if searched > 0 else 'read from the cache'} in {secs:.1f}s: {settings}")
+    return {"source": "search" if searched > 0 else "cache", "seconds": round(secs, 2), "settings": settings,
+            "library": K.khop_version()}
+
+
+def g0_bench(K, torch, cpu_leg=True):
+    """The 32-seed scale-10 case (R-MAT scale 10, edge factor 16) through the plain path at k = 1, 2, 3, 6."""
+    import graphgen
+    el0 = graphgen.rmat(10, 16, seed=1)
+    seeds = graphgen.draw_seeds(el0, 32, seed=7)
+    g0 = K.Graph.from_edgelist(el0)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    d_s = torch.from_numpy(seeds).to(dev)
+    out = {"graph": "R-MAT scale 10, edge factor 16", "seeds": 32}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    counts = {}
+    for k in (1, 2, 3, 6):
+        d_c = torch.empty(32, dtype=torch.int64, device=dev)
+        g0.count_dev(d_s, k, d_c, stream=stream)
+        e0.record(stream)
+        for _ in range(10):
+            g0.count_dev(d_s, k, d_c, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        counts[k] = d_c.cpu().numpy()
+        out[f"k{k}"] = {"ms": round(ms, 4), "qps": round(32 / (ms / 1e3), 1)}
+    if cpu_leg:
+        import oracle
+        og = oracle.OracleGraph.from_edgelist(el0)
+        out["equal_oracle"] = all(bool(np.array_equal(counts[k], og.count(seeds, k)[0])) for k in counts)
+    g0.free()
+    log(f"scale-10 plain: {out}")
+    return out
 
 
 KERNEL_SOURCES = {"plain": "paper_1905_01294_amd/csrc/plain.hip", "batch": "paper_1905_01294_amd/csrc/batched.hip"}
@@ -738,6 +842,19 @@ def batched_sweep(g, el, K, torch):
     return out
 
 
+def _lane_delta(before, after):
+    """Per-lane counters accumulated between two khop_server_stats snapshots."""
+    out = {}
+    for b0, a0 in zip(before, after):
+        n = a0["launches"] - b0["launches"]
+        q = a0["queries"] - b0["queries"]
+        ms = a0["busy_ms"] - b0["busy_ms"]
+        out[f"g{a0['graph_id']}_{a0['lane']}"] = {
+            "launches": n, "queries": q, "queries_per_launch": round(q / n, 1) if n else 0,
+            "ms_per_launch": round(ms / n, 3) if n else 0, "words_held": a0["words"]}
+    return out
+
+
 def serving_bench(K, graphs, seconds):
     """Open-loop Poisson arrivals at 0.25, 0.5 and 0.8 of the closed-loop saturation rate, at least
     10^4 queries per level.
@@ -751,8 +868,7 @@ def serving_bench(K, graphs, seconds):
     import graphgen
     rng = np.random.default_rng(2024)
     pools = [graphgen.draw_seeds(el, 50000, seed=21) for _, _, el in graphs]
-    srv = K.Server(96 << 30, 1024)
-    ids = [srv.add_graph(g) for _, g, _ in graphs]
+    names = [name for name, _, _ in graphs]
 
     def make(n):
         gi = rng.integers(0, len(graphs), size=n)
@@ -760,7 +876,7 @@ def serving_bench(K, graphs, seconds):
         si = rng.integers(0, 50000, size=n)
         return [(int(a), int(pools[a][b]), int(c)) for a, b, c in zip(gi, si, ks)]
 
-    def collect(n, deadline_s=120.0):
+    def collect(srv, n, deadline_s=120.0):
         got = {}
         t_end = time.time() + deadline_s
         while len(got) < n and time.time() < t_end:
@@ -769,18 +885,36 @@ def serving_bench(K, graphs, seconds):
             time.sleep(0.0005)
         return got
 
-    # warm-up and closed-loop saturation
-    for gi, s, k in make(2000):
-        srv.submit(ids[gi], s, k)
-    collect(2000)
+    def closed_loop(route, n_sat=20000):
+        srv = K.Server(96 << 30, 1024)
+        srv.set_option(K.KHOP_SERVER_ROUTE, route)
+        ids = [srv.add_graph(g) for _, g, _ in graphs]
+        for gi, sd, k in make(2000):  # warm-up
+            srv.submit(ids[gi], sd, k)
+        collect(srv, 2000)
+        qs = make(n_sat)
+        t0 = time.perf_counter()
+        for gi, sd, k in qs:
+            srv.submit(ids[gi], sd, k)
+        got = collect(srv, n_sat)
+        rate = len(got) / (time.perf_counter() - t0)
+        srv.close()
+        return rate
+
+    sat_batch = closed_loop(K.KHOP_ROUTE_BATCH)
+    srv = K.Server(96 << 30, 1024)
+    ids = [srv.add_graph(g) for _, g, _ in graphs]
+    for gi, sd, k in make(2000):
+        srv.submit(ids[gi], sd, k)
+    collect(srv, 2000)
     n_sat = 20000
     qs = make(n_sat)
     t0 = time.perf_counter()
-    for gi, s, k in qs:
-        srv.submit(ids[gi], s, k)
-    got = collect(n_sat)
+    for gi, sd, k in qs:
+        srv.submit(ids[gi], sd, k)
+    got = collect(srv, n_sat)
     sat = len(got) / (time.perf_counter() - t0)
-    log(f"serving: closed-loop {sat:.0f} queries/s")
+    log(f"serving {'+'.join(names)}: closed loop {sat:.0f} queries/s (batch lanes only: {sat_batch:.0f})")
     levels = []
     check = []
     for frac in (0.25, 0.5, 0.8):
@@ -790,19 +924,21 @@ def serving_bench(K, graphs, seconds):
         gaps = rng.exponential(1.0 / qps, size=n)
         sched = np.cumsum(gaps)
         tick = {}
+        st0 = srv.stats()
         t_base = K.monotonic_ns() + 2_000_000
 
         def producer():
-            for i, (gi, s, k) in enumerate(qs):
+            for i, (gi, sd, k) in enumerate(qs):
                 due = t_base + int(sched[i] * 1e9)
                 while K.monotonic_ns() < due:
                     pass
-                tick[srv.submit(ids[gi], s, k)] = (due, i)
+                tick[srv.submit(ids[gi], sd, k)] = (due, i)
 
         th = threading.Thread(target=producer)
         th.start()
         th.join()
-        got = collect(n)
+        got = collect(srv, n)
+        st1 = srv.stats()
         lat = []
         by_gk = {}
         single = 0
@@ -814,27 +950,32 @@ def serving_bench(K, graphs, seconds):
             ms = (r.t_done_ns - due) / 1e6
             lat.append(ms)
             single += r.path == K.KHOP_PATH_SINGLE
-            by_gk.setdefault(f"{graphs[qs[i][0]][0]}_k{qs[i][2]}", []).append(ms)
+            by_gk.setdefault(f"{names[qs[i][0]]}_k{qs[i][2]}", []).append(ms)
             done_last = max(done_last, r.t_done_ns)
             if len(check) < 400 and i % 25 == 0:
                 check.append((qs[i], r.count))
         span = (done_last - t_base) / 1e9 if done_last else float("nan")
-        levels.append({"offered_qps": round(qps, 1), "achieved_qps": round(len(lat) / span, 1), "n": n,
-                       "completed": len(lat), "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
+        offered_span = float(sched[-1])
+        levels.append({"offered_qps": round(qps, 1), "achieved_qps": round(len(lat) / span, 1),
+                       "arrival_span_s": round(offered_span, 3), "completion_span_s": round(span, 3),
+                       "n": n, "completed": len(lat), "p50_ms": round(pct(lat, 50), 3),
+                       "p99_ms": round(pct(lat, 99), 3), "max_ms": round(float(np.max(lat)), 3),
                        "mean_ms": round(float(np.mean(lat)), 3),
                        "single_query_share": round(single / max(len(lat), 1), 3),
+                       "lanes": _lane_delta(st0, st1),
                        "by_graph_k": {key: {"n": len(v), "mean_ms": round(float(np.mean(v)), 3),
                                             "p50_ms": round(pct(v, 50), 3), "p99_ms": round(pct(v, 99), 3)}
                                       for key, v in sorted(by_gk.items())}})
-        log(f"serving at {qps:.0f} q/s offered: p50 {levels[-1]['p50_ms']} ms, p99 {levels[-1]['p99_ms']} ms")
+        log(f"serving {'+'.join(names)} at {qps:.0f} q/s offered: {levels[-1]['achieved_qps']:.0f} served, "
+            f"p50 {levels[-1]['p50_ms']} ms, p99 {levels[-1]['p99_ms']} ms")
     srv.close()
     # served counts against the plain path, query by query
     ok = 0
-    for (gi, s, k), c in check:
-        ok += int(graphs[gi][1].count(np.array([s], np.int32), k)[0] == c)
-    return {"graphs": [name for name, _, _ in graphs], "k_weights": {"1": 0.4, "2": 0.3, "3": 0.2, "6": 0.1},
-            "max_batch_seeds": 1024, "saturation_qps": round(sat, 1), "levels": levels,
-            "checked_against_plain": len(check), "equal": ok}
+    for (gi, sd, k), c in check:
+        ok += int(graphs[gi][1].count(np.array([sd], np.int32), k)[0] == c)
+    return {"graphs": names, "k_weights": {"1": 0.4, "2": 0.3, "3": 0.2, "6": 0.1},
+            "max_batch_seeds": 1024, "saturation_qps": round(sat, 1), "saturation_qps_batch_lanes_only":
+            round(sat_batch, 1), "levels": levels, "checked_against_plain": len(check), "equal": ok}
 
 
 def _cpu_model():

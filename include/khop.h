@@ -109,8 +109,12 @@ int khop_count(khop_graph *g, const int32_t *seeds, int64_t num_seeds, int32_t k
  * device pointers of length num_seeds.  Seeds are validated on the device:
  * a seed outside [0, n) yields count -1 and traversed edges -1 for that query.
  * The caller synchronises the stream before reading the outputs.  The seeds
- * are answered in order, and consecutive queries overlap by one launch: the
- * last hop of one runs beside hop 1 of the next.
+ * are answered in order, and consecutive queries overlap by one launch (the
+ * last hop of one runs beside hop 1 of the next) unless the option
+ * KHOP_OPT_PLAIN_PIPELINE is 0.  With k > 32 the queries run one at a time
+ * as searches whose hops are launched in groups, and the call waits on the
+ * stream between groups to learn whether the frontier has emptied (a query
+ * never runs more hops than its search has levels, so any k is cheap).
  */
 int khop_count_dev(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
                    int64_t *d_traversed_edges, void *hip_stream);
@@ -259,7 +263,10 @@ enum khop_option {
     KHOP_OPT_PUSH_ATOMIC = 9,   /* top-down: frontier edges up to which heads are claimed atomically
                                    (else byte marks) */
     KHOP_OPT_PLAIN_GRID = 10,   /* plain hop and compaction launches: blocks per compute unit (1..64) */
-    KHOP_OPT_BATCH_GRID = 11    /* batched bottom-up launches: blocks per compute unit (1..64) */
+    KHOP_OPT_BATCH_GRID = 11,   /* batched bottom-up launches: blocks per compute unit (1..64) */
+    KHOP_OPT_PLAIN_PIPELINE = 12 /* 1 (default): consecutive plain queries overlap by one launch;
+                                    0: each query runs its own launch sequence, start to count, before the
+                                    next starts (the paper's strictly sequential protocol) */
 };
 enum { KHOP_DIR_AUTO = 0, KHOP_DIR_PUSH = 1, KHOP_DIR_PULL = 2 };
 
@@ -321,37 +328,63 @@ enum { KHOP_PATH_BATCH = 0, KHOP_PATH_SINGLE = 1 };
 /*
  * A continuous-batching server for k-hop queries (the throughput-oriented
  * serving model of the paper's Section II, where a pool of workers answers
- * concurrent queries).  Graphs stay resident; requests of mixed seed and k are
- * admitted into free bit slots of running batched traversals at hop
- * boundaries, while the batch keeps advancing.  Each graph runs two such
- * batches, one for queries with k <= 2 and one for deeper ones, each on its
- * own HIP stream, so short queries do not wait behind deep ones and work for
- * different graphs overlaps on the device.  Each graph also has a
- * single-query lane on a third stream that answers queries one at a time
- * through the plain path (the paper's one query per worker), in groups of
- * one k.  A single query costs more device time than its share of a batch,
- * so that lane takes arrivals only while the device time it would need stays
- * low (decayed sums over about 5 ms of the arrivals' measured single-query
- * costs: cheap queries, up to 0.05 ms, while theirs stays under half the
- * device; dearer ones while all arrivals' stays under the whole, with
- * hysteresis) and its backlog would still answer before k + 1 measured batch
- * iterations.  So queries get the single-query latency at low load and the
- * batches' throughput at high load; khop_result.path says which answered,
- * and khop_server_set_option can force one path.
- * mem_budget_bytes bounds the bitset memory of all running batches (each
- * 64 slots of a graph with n vertices and nnz arcs take 3 * 8 * n bytes, and
- * each batch 3 * 8 * ceil(n / 64) bytes of frontier bitmaps plus
- * 3 * 8 * (n + nnz / 256 + 64) bytes of frontier queues); requests wait
- * while no slot fits.  max_batch_seeds (64..1024, a multiple of 64) bounds
- * the slots of one batch.
+ * concurrent queries).  Graphs stay resident.  Each graph has two batch
+ * lanes, one for queries with k <= 2 and one for deeper ones (short queries
+ * never wait behind deep traversals), and each lane has two run slots with a
+ * HIP stream each.  A free slot takes the requests waiting in its lane (FIFO,
+ * up to 64 per word of its batch context) as one batched launch sequence:
+ * the computation of khop_count_batched, seeds as bit columns of one bitset
+ * product per hop.  Requests that arrive while a lane's slots are busy join
+ * its next launch as soon as a slot frees, so launches of a lane, of all
+ * lanes and of all graphs overlap on the device and the batch size follows
+ * the load.  Each graph also has a single-query lane on a stream of its own
+ * that answers queries one at a time through the plain path (the paper's one
+ * query per worker), in groups of one k.  A single query costs more device
+ * time than its share of a batch, so that lane takes arrivals only while the
+ * device time it would need stays low (decayed sums over about 5 ms of the
+ * arrivals' measured single-query costs: cheap queries, up to 0.05 ms, while
+ * theirs stays under half the device; dearer ones while all arrivals' stays
+ * under the whole, with hysteresis) and it would still answer before the
+ * batch lane (its backlog against the lane's measured launch time and the
+ * wait for a free slot).  So queries get the single-query latency at low
+ * load and the batches' throughput at high load; khop_result.path says which
+ * answered, and khop_server_set_option can force one path.
+ * mem_budget_bytes bounds the device memory of the batch contexts the slots
+ * hold (khop_server_batch_bytes gives one context's size; a slot takes the
+ * widest context, up to max_batch_seeds / 64 words, that the budget left
+ * allows, and gives it back when it has been idle for 50 ms or another lane
+ * waits for memory); requests wait while no context fits, and time out at
+ * their deadline.  max_batch_seeds (64..1024, a multiple of 64) bounds the
+ * queries of one launch.
  */
 int khop_server_create(int64_t mem_budget_bytes, int32_t max_batch_seeds, khop_server **out);
 /*
  * Register a loaded graph (borrowed; it must outlive the server).  Its
- * single-query lane's state (about 35 bytes per vertex: bitmaps, byte marks
- * and frontier queues) is allocated here, outside mem_budget_bytes.
+ * single-query lane's query context (about 69 bytes per vertex: bitmaps,
+ * byte marks and frontier queues) and the lanes' small staging buffers are
+ * allocated here, outside mem_budget_bytes.
  */
 int khop_server_add_graph(khop_server *s, khop_graph *g, int32_t *graph_id);
+
+/* Device bytes of one batch context of `words` 64-query words (1..16) for graph g: what a run slot
+ * of the server charges to its memory budget.  Errors: NULL arguments or words out of range -> KHOP_EINVAL. */
+int khop_server_batch_bytes(const khop_graph *g, int32_t words, int64_t *bytes);
+
+/* Counters of one lane of a server, since it was created. */
+typedef struct {
+    int32_t graph_id;
+    int32_t lane;      /* KHOP_LANE_SHORT (batches of k <= 2), KHOP_LANE_DEEP (k > 2) or KHOP_LANE_SINGLE */
+    int64_t launches;  /* batched launches (single-query lane: launch sequences) completed */
+    int64_t queries;   /* queries they answered */
+    double busy_ms;    /* their summed time from enqueue to completion (launches may overlap) */
+    double max_ms;     /* the longest */
+    int32_t words;     /* 64-query words of the widest batch context the lane holds now (0: none) */
+    int32_t queued;    /* requests waiting in the lane */
+} khop_server_stat;
+enum { KHOP_LANE_SHORT = 0, KHOP_LANE_DEEP = 1, KHOP_LANE_SINGLE = 2 };
+/* Copy up to max lane counters (two batch lanes per graph, then one single-query lane per graph)
+ * into out (host); *n_out receives how many were written. */
+int khop_server_stats(khop_server *s, khop_server_stat *out, int32_t max, int32_t *n_out);
 
 /* Server options. */
 enum khop_server_option {

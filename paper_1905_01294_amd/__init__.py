@@ -43,6 +43,7 @@ KHOP_OPT_PULL_HEAVY = 8
 KHOP_OPT_PUSH_ATOMIC = 9
 KHOP_OPT_PLAIN_GRID = 10
 KHOP_OPT_BATCH_GRID = 11
+KHOP_OPT_PLAIN_PIPELINE = 12
 KHOP_DIR_AUTO = 0
 KHOP_DIR_PUSH = 1
 KHOP_DIR_PULL = 2
@@ -52,6 +53,10 @@ KHOP_ROUTE_BATCH = 1
 KHOP_ROUTE_PLAIN = 2
 KHOP_PATH_BATCH = 0
 KHOP_PATH_SINGLE = 1
+KHOP_LANE_SHORT = 0
+KHOP_LANE_DEEP = 1
+KHOP_LANE_SINGLE = 2
+LANE_NAMES = {KHOP_LANE_SHORT: "batch_k_le_2", KHOP_LANE_DEEP: "batch_k_gt_2", KHOP_LANE_SINGLE: "single"}
 
 # Every entry point declared in include/khop.h.
 EXPORTS = ("graph_load_csr", "graph_load_csr_typed", "graph_free", "graph_info", "graph_degrees",
@@ -61,7 +66,7 @@ EXPORTS = ("graph_load_csr", "graph_load_csr_typed", "graph_free", "graph_info",
            "khop_set_option", "khop_get_option", "khop_autotune", "khop_profile", "khop_profile_read",
            "khop_server_create", "khop_server_add_graph", "khop_server_set_option", "khop_server_submit",
            "khop_server_poll", "khop_server_drain", "khop_server_destroy", "khop_last_error", "khop_version",
-           "khop_autotune_seconds")
+           "khop_autotune_seconds", "khop_server_batch_bytes", "khop_server_stats")
 
 
 class KhopError(RuntimeError):
@@ -73,6 +78,12 @@ class KhopError(RuntimeError):
 class KernelStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
                 ("algorithmic_bytes", ctypes.c_double)]
+
+
+class ServerStat(ctypes.Structure):
+    _fields_ = [("graph_id", ctypes.c_int32), ("lane", ctypes.c_int32), ("launches", ctypes.c_int64),
+                ("queries", ctypes.c_int64), ("busy_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("words", ctypes.c_int32), ("queued", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -138,6 +149,8 @@ def _load():
         "khop_server_submit": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                 ctypes.POINTER(ctypes.c_uint64)],),
         "khop_server_poll": ([_vp, ctypes.POINTER(Result), ctypes.c_int64, _i64p],),
+        "khop_server_stats": ([_vp, ctypes.POINTER(ServerStat), ctypes.c_int32, _i32p],),
+        "khop_server_batch_bytes": ([_vp, ctypes.c_int32, _i64p],),
         "khop_server_drain": ([_vp, ctypes.c_int64],),
         "khop_server_destroy": ([_vp],),
     }
@@ -554,6 +567,11 @@ class Server:
     def drain(self, timeout_ms: int = 60000):
         khop_server_drain(self._h, timeout_ms)
 
+    def stats(self):
+        """Per-lane counters: a list of dicts (graph_id, lane name, launches, queries, busy_ms, max_ms, words,
+        queued)."""
+        return khop_server_stats(self._h)
+
     def close(self):
         if self._h is not None:
             khop_server_destroy(self._h)
@@ -564,6 +582,22 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def khop_server_stats(h, max_lanes: int = 256):
+    buf = (ServerStat * max_lanes)()
+    n = ctypes.c_int32(0)
+    _check(_lib.khop_server_stats(h, buf, max_lanes, ctypes.byref(n)))
+    return [{"graph_id": x.graph_id, "lane": LANE_NAMES.get(x.lane, x.lane), "launches": x.launches,
+             "queries": x.queries, "busy_ms": x.busy_ms, "max_ms": x.max_ms, "words": x.words, "queued": x.queued}
+            for x in buf[:n.value]]
+
+
+def khop_server_batch_bytes(graph_handle, words: int) -> int:
+    """Device bytes of one server batch context of `words` 64-query words for the graph."""
+    b = ctypes.c_int64(0)
+    _check(_lib.khop_server_batch_bytes(graph_handle, int(words), ctypes.byref(b)))
+    return int(b.value)
 
 
 def monotonic_ns() -> int:

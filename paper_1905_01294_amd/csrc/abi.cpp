@@ -7,6 +7,7 @@
 #include <thread>
 
 #include "khop_impl.h"
+#include "serve_policy.h"
 
 namespace khop {
 
@@ -354,12 +355,9 @@ static void validate_seeds(const khop_graph *g, const int32_t *seeds, int64_t nu
 // Runs a sorted batch plan: slots grouped in launches of at most `per` seeds.
 void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int64_t num,
                         int64_t *d_counts, hipStream_t st, const uint64_t *d_vmask) {
-    std::vector<int32_t> order((size_t)num);
-    std::iota(order.begin(), order.end(), 0);
     // by k, largest first, except that one-hop queries go last: they take no
     // bit (a launch answers them from their seeds' rows)
-    auto key = [&](int32_t i) { return h_ks[i] == 1 ? -1 : h_ks[i]; };
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return key(a) > key(b); });
+    const std::vector<int32_t> order = batch_order(h_ks, num);
     const int per = std::max(64, std::min(1024, params_of(g).batch_seeds));
     for (int64_t at = 0; at < num; at += per) {
         const int64_t cnt = std::min<int64_t>(per, num - at);
@@ -993,6 +991,10 @@ int khop_set_option(khop_graph *g, int32_t option, int64_t value) {
                 if (value < 1 || value > 64) fail(KHOP_EINVAL, "batch grid out of range [1, 64] blocks per CU");
                 P.batch_grid = (int)value;
                 break;
+            case KHOP_OPT_PLAIN_PIPELINE:
+                if (value != 0 && value != 1) fail(KHOP_EINVAL, "plain pipeline must be 0 or 1");
+                P.plain_pipeline = (int)value;
+                break;
             default:
                 fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
@@ -1016,6 +1018,7 @@ int khop_get_option(const khop_graph *g, int32_t option, int64_t *value) {
             case KHOP_OPT_PUSH_ATOMIC: *value = P.push_atomic_max; break;
             case KHOP_OPT_PLAIN_GRID: *value = P.plain_grid; break;
             case KHOP_OPT_BATCH_GRID: *value = P.batch_grid; break;
+            case KHOP_OPT_PLAIN_PIPELINE: *value = P.plain_pipeline; break;
             default: fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
     });

@@ -575,34 +575,6 @@ __global__ void __launch_bounds__(kBlock) batch_push_kernel(
     if (units && lane == 0) unit_add(units, 1, edges);
 }
 
-// After a bottom-up hop: the queue of the frontier it found (every vertex
-// whose bitmap bit is set), so that the next hop may go top-down.  One wave
-// per bitmap word, one lane per vertex.  A frontier of more than n / 64
-// vertices is not queued: its out-edge sum is set past nnz instead, which
-// sends the next hop bottom-up.
-__global__ void __launch_bounds__(kBlock) queue_from_bitmap_kernel(const int64_t *__restrict__ rowptr,
-                                                                  const uint64_t *__restrict__ fb,
-                                                                  const int64_t *__restrict__ fb_cnt, int64_t n,
-                                                                  int64_t nnz, ChunkQueue q,
-                                                                  const int32_t *mode_l) {
-    if (*mode_l != HOP_PULL) return;
-    const int lane = lane_id();
-    if (wave_sum(fb_cnt[lane & (kCntLanes - 1)]) * 64 > n) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) q.mf[0] = nnz + 1;
-        return;
-    }
-    const int64_t nw = (n + kWave - 1) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
-    for (int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; w < nw; w += nwaves) {
-        const uint64_t bits = fb[w];
-        if (!bits) continue;  // wave-uniform
-        const int64_t v = w * kWave + lane;
-        const bool app = (bits >> lane) & 1ull;
-        const int64_t deg = app ? rowptr[v + 1] - rowptr[v] : 0;
-        cq_append(q, app, (int32_t)v, deg);
-    }
-}
-
 // One butterfly stage of a 64x64 bit transpose held one row per lane: the
 // block of columns with bit s clear in the rows with bit s set trades places
 // with the block of columns with bit s set in the rows with bit s clear.
@@ -683,91 +655,6 @@ __global__ void __launch_bounds__(kBlock) batch_mask_kernel(uint64_t *V, int64_t
     }
 }
 
-// Serving: counts of the finished seed bits of the words in `fin` (word w's
-// finished bits fin[w]), then those bits cleared from V, F and N so their slots
-// can take new seeds.  counts_acc[w*64 + bit] accumulates vertex counts.
-__global__ void __launch_bounds__(kBlock) serve_harvest_kernel(uint64_t *V, uint64_t *F, uint64_t *N, int64_t n, int W,
-                                                              const uint64_t *fin, int64_t *counts_acc) {
-    const int w = blockIdx.y;
-    const uint64_t fm = fin[w];
-    if (!fm) return;
-    const int lane = lane_id();
-    __shared__ int64_t s_acc[kWavesPerBlock][kWave];
-    int64_t acc = 0;
-    const int64_t nchunks = (n + kWave - 1) / kWave;
-    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c < nchunks;
-         c += (int64_t)gridDim.x * kWavesPerBlock) {
-        const int64_t v = c * kWave + lane;
-        const int64_t at = v * W + w;
-        const uint64_t x = v < n ? V[at] : 0ull;
-        const uint64_t xf = x & fm;
-        if (ballot(xf != 0)) acc += __popcll(transpose64(xf));
-        if (v < n) {
-            if (xf) V[at] = x & ~fm;
-            if (F[at] & fm) F[at] &= ~fm;
-            if (N[at] & fm) N[at] &= ~fm;
-        }
-    }
-    s_acc[threadIdx.x / kWave][lane] = acc;
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-        int64_t t = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) t += s_acc[i][threadIdx.x];
-        if (t) atomicAdd((unsigned long long *)&counts_acc[w * kWave + threadIdx.x], (unsigned long long)t);
-    }
-}
-
-// Serving: slot slots[i] gets seed seeds[i] (bit set in V and F).
-__global__ void serve_admit_kernel(uint64_t *V, uint64_t *F, int W, const int32_t *slots, const int32_t *seeds,
-                                   int count) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    const int j = slots[i];
-    const int64_t at = (int64_t)seeds[i] * W + (j >> 6);
-    const unsigned long long bit = 1ull << (j & 63);
-    atomicOr((unsigned long long *)&V[at], bit);
-    atomicOr((unsigned long long *)&F[at], bit);
-}
-
-// Serving: first hop of newly admitted slots, pushed from their seeds into the
-// next frontier Fn, V and the next frontier bitmap, after the running slots'
-// hop; vertices new to the next frontier join its queue.
-__global__ void __launch_bounds__(kBlock) serve_push_kernel(const int64_t *__restrict__ rowptr,
-                                                           const int32_t *__restrict__ colidx, int W,
-                                                           const int32_t *slots, const int32_t *seeds, int count,
-                                                           uint64_t *Fn, uint64_t *V, uint64_t *Fbn, int64_t *fb_cnt,
-                                                           ChunkQueue q) {
-    int64_t fresh = 0;
-    for (int i = blockIdx.x; i < count; i += gridDim.x) {
-        const int j = slots[i];
-        const int32_t s = seeds[i];
-        const int64_t b = rowptr[s], e = rowptr[s + 1];
-        const unsigned long long bit = 1ull << (j & 63);
-        for (int64_t x0 = b; x0 < e; x0 += kBlock) {  // block-uniform: every lane reaches the append
-            const int64_t x = x0 + threadIdx.x;
-            bool app = false;
-            int32_t v = 0;
-            int64_t deg = 0;
-            if (x < e) {
-                v = colidx[x];
-                const int64_t at = (int64_t)v * W + (j >> 6);
-                atomicOr((unsigned long long *)&Fn[at], bit);
-                atomicOr((unsigned long long *)&V[at], bit);
-                app = fb_set(Fbn, v);
-                if (app) deg = rowptr[v + 1] - rowptr[v];
-            }
-            fresh += app;
-            cq_append(q, app, v, deg);
-        }
-    }
-    fresh = wave_sum(fresh);
-    if (lane_id() == 0) fb_count(fb_cnt, fresh);
-}
-
-__global__ void fill_zero_i64(int64_t *a, int64_t n) {
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a[i] = 0;
-}
-
 __global__ void __launch_bounds__(kBlock) fill_zero_u64(uint64_t *a, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) a[i] = 0;
 }
@@ -804,13 +691,12 @@ struct BatchCtx {
     int act_rows = 0;          // 64 * W + 1: seeds sorted by k make the active sets a chain of prefixes
 };
 
-BatchCtx *batch_ctx_create(khop_graph *g, int words) {
-    BatchCtx *c = new BatchCtx();
-    c->g = g;
-    c->W = words;
-    const int64_t n = g->n;
+// The layout of a batch context's device arena: its total bytes, and when
+// base is not null, every device pointer of c set into it.
+static size_t batch_layout(int64_t n, int64_t nnz, int words, BatchCtx *c, char *base) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t bits = al((size_t)n * words * 8);
+    const int act_rows = 64 * words + 1;
     size_t off = 0;
     const size_t oV = off;
     off += bits;
@@ -826,14 +712,13 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     off += al(3 * kCntLanes * 8);
     const size_t oacc = off;
     off += al(64 * (size_t)words * 8);
-    c->act_rows = 64 * words + 1;
     const size_t oact = off;
-    off += al((size_t)c->act_rows * words * 8);
+    off += al((size_t)act_rows * words * 8);
     const size_t oflags = off;
     off += al(BatchCtx::kRing * 4);
     const size_t omode = off;
     off += al(BatchCtx::kRing * 4);
-    const int64_t cq_cap = n + g->nnz / kChunk + kWave;
+    const int64_t cq_cap = n + nnz / kChunk + kWave;
     size_t ocq[3];
     for (int i = 0; i < 3; ++i) {
         ocq[i] = off;
@@ -847,28 +732,41 @@ BatchCtx *batch_ctx_create(khop_graph *g, int words) {
     off += al(64 * (size_t)words * 4);
     const size_t oks = off;
     off += al(64 * (size_t)words * 4);
-    hipError_t e = hipMalloc(&c->arena, off);
-    if (e != hipSuccess) {
+    if (!base) return off;
+    c->arena = base;
+    c->act_rows = act_rows;
+    c->V = (uint64_t *)(base + oV);
+    c->F = (uint64_t *)(base + oF);
+    c->N = (uint64_t *)(base + oN);
+    c->Fb = (uint64_t *)(base + oFb);
+    c->Fs = (void *)(base + oFs);
+    c->Fc = (int64_t *)(base + oFc);
+    c->acc = (int64_t *)(base + oacc);
+    c->act = (uint64_t *)(base + oact);
+    c->flags = (int32_t *)(base + oflags);
+    c->mode = (int32_t *)(base + omode);
+    for (int i = 0; i < 3; ++i) c->cq_rec[i] = (uint64_t *)(base + ocq[i]);
+    c->cq_len = (int64_t *)(base + ocql);
+    c->cq_mf = (int64_t *)(base + ocqm);
+    c->perm = (int32_t *)(base + operm);
+    c->ks = (int32_t *)(base + oks);
+    return off;
+}
+
+size_t batch_ctx_bytes(int64_t n, int64_t nnz, int words) { return batch_layout(n, nnz, words, nullptr, nullptr); }
+
+BatchCtx *batch_ctx_create(khop_graph *g, int words) {
+    BatchCtx *c = new BatchCtx();
+    c->g = g;
+    c->W = words;
+    const size_t bytes = batch_layout(g->n, g->nnz, words, c, nullptr);
+    void *arena = nullptr;
+    if (hipMalloc(&arena, bytes) != hipSuccess) {
         delete c;
         (void)hipGetLastError();
-        fail(KHOP_ENOMEM, "device allocation of " + std::to_string(off) + " bytes for a batch context failed");
+        fail(KHOP_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes for a batch context failed");
     }
-    char *b = (char *)c->arena;
-    c->V = (uint64_t *)(b + oV);
-    c->F = (uint64_t *)(b + oF);
-    c->N = (uint64_t *)(b + oN);
-    c->Fb = (uint64_t *)(b + oFb);
-    c->Fs = (void *)(b + oFs);
-    c->Fc = (int64_t *)(b + oFc);
-    c->acc = (int64_t *)(b + oacc);
-    c->act = (uint64_t *)(b + oact);
-    c->flags = (int32_t *)(b + oflags);
-    c->mode = (int32_t *)(b + omode);
-    for (int i = 0; i < 3; ++i) c->cq_rec[i] = (uint64_t *)(b + ocq[i]);
-    c->cq_len = (int64_t *)(b + ocql);
-    c->cq_mf = (int64_t *)(b + ocqm);
-    c->perm = (int32_t *)(b + operm);
-    c->ks = (int32_t *)(b + oks);
+    batch_layout(g->n, g->nnz, words, c, (char *)arena);
     const size_t hbytes = (size_t)c->act_rows * words * 8 + 2 * 64 * (size_t)words * 4;
     if (hipHostMalloc(&c->h_arena, hbytes, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
@@ -1156,225 +1054,6 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     count_words(0, Wr);
     hipLaunchKernelGGL(batch_output_kernel, dim3((nslots + 255) / 256), dim3(256), 0, st, c->acc, c->perm, nslots,
                        d_seeds, d_vmask, d_counts);
-    KHOP_HIP(hipGetLastError());
-}
-
-// ---------------------------------------------------------------- serving
-
-struct ServeCtx {
-    khop_graph *g = nullptr;
-    int W = 0;
-    uint64_t *V = nullptr, *F = nullptr, *N = nullptr;
-    uint64_t *Fb = nullptr;  // three frontier bitmaps of nw words; slot fbi holds F's
-    int64_t *Fc = nullptr;   // their set-bit counts, 64 lanes each
-    int fbi = 0;
-    uint64_t *cq_rec[3] = {};  // frontier chunk queues, by the same rotation as Fb
-    int64_t *cq_len = nullptr;
-    int64_t *cq_mf = nullptr;
-    int32_t *d_mode = nullptr;  // [1]: this iteration's direction
-    int64_t *acc = nullptr;     // 64 * W counters
-    uint64_t *d_act = nullptr;  // W active masks of the bottom-up pass
-    uint64_t *d_fin = nullptr;  // W finished masks
-    int32_t *d_slots = nullptr, *d_seeds = nullptr;  // admitted (slot, seed) pairs
-    int32_t *d_one = nullptr;   // a flag that is always 1, d_one[1] a scratch flag
-    void *arena = nullptr;
-    // pinned staging
-    uint64_t *h_act = nullptr, *h_fin = nullptr;
-    int32_t *h_slots = nullptr, *h_seeds = nullptr;
-    int64_t *h_counts = nullptr;
-    void *h_arena = nullptr;
-};
-
-static int64_t queue_cap(int64_t n, int64_t nnz) { return n + nnz / kChunk + kWave; }
-
-size_t serve_ctx_bytes(int64_t n, int64_t nnz, int words) {
-    return (size_t)3 * 8 * (size_t)n * words + (size_t)3 * 8 * (size_t)((n + 63) / 64) +
-           (size_t)3 * 8 * (size_t)queue_cap(n, nnz);
-}
-
-ServeCtx *serve_ctx_create(khop_graph *g, int words) {
-    ServeCtx *c = new ServeCtx();
-    c->g = g;
-    c->W = words;
-    const int64_t n = g->n;
-    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t bits = al((size_t)n * words * 8);
-    const int slots = 64 * words;
-    size_t off = 0;
-    const size_t oV = off;
-    off += bits;
-    const size_t oF = off;
-    off += bits;
-    const size_t oN = off;
-    off += bits;
-    const size_t oFb = off;
-    off += al((size_t)3 * ((n + 63) / 64) * 8);
-    const size_t oFc = off;
-    off += al(3 * kCntLanes * 8);
-    const int64_t cq_cap = queue_cap(n, g->nnz);
-    size_t ocq[3];
-    for (int i = 0; i < 3; ++i) {
-        ocq[i] = off;
-        off += al((size_t)cq_cap * 8);
-    }
-    const size_t ocql = off;
-    off += al(3 * 8);
-    const size_t ocqm = off;
-    off += al(3 * kCntLanes * 8);
-    const size_t omode = off;
-    off += al(2 * 4);
-    const size_t oacc = off;
-    off += al(slots * 8);
-    const size_t oact = off;
-    off += al(words * 8);
-    const size_t ofin = off;
-    off += al(words * 8);
-    const size_t osl = off;
-    off += al(slots * 4);
-    const size_t ose = off;
-    off += al(slots * 4);
-    const size_t oone = off;
-    off += al(16);
-    if (hipMalloc(&c->arena, off) != hipSuccess) {
-        (void)hipGetLastError();
-        delete c;
-        fail(KHOP_ENOMEM, "device allocation for a serving batch failed");
-    }
-    char *b = (char *)c->arena;
-    c->V = (uint64_t *)(b + oV);
-    c->F = (uint64_t *)(b + oF);
-    c->N = (uint64_t *)(b + oN);
-    c->Fb = (uint64_t *)(b + oFb);
-    c->Fc = (int64_t *)(b + oFc);
-    for (int i = 0; i < 3; ++i) c->cq_rec[i] = (uint64_t *)(b + ocq[i]);
-    c->cq_len = (int64_t *)(b + ocql);
-    c->cq_mf = (int64_t *)(b + ocqm);
-    c->d_mode = (int32_t *)(b + omode);
-    c->acc = (int64_t *)(b + oacc);
-    c->d_act = (uint64_t *)(b + oact);
-    c->d_fin = (uint64_t *)(b + ofin);
-    c->d_slots = (int32_t *)(b + osl);
-    c->d_seeds = (int32_t *)(b + ose);
-    c->d_one = (int32_t *)(b + oone);
-    const size_t hb = 2 * words * 8 + 2 * slots * 4 + slots * 8;
-    if (hipHostMalloc(&c->h_arena, hb, hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        (void)hipFree(c->arena);
-        delete c;
-        fail(KHOP_ENOMEM, "pinned allocation for a serving batch failed");
-    }
-    char *h = (char *)c->h_arena;
-    c->h_act = (uint64_t *)h;
-    c->h_fin = c->h_act + words;
-    c->h_counts = (int64_t *)(c->h_fin + words);
-    c->h_slots = (int32_t *)(c->h_counts + slots);
-    c->h_seeds = c->h_slots + slots;
-    KHOP_HIP(hipMemset(c->arena, 0, off));
-    const int32_t one = 1;
-    KHOP_HIP(hipMemcpy(c->d_one, &one, 4, hipMemcpyHostToDevice));
-    KHOP_HIP(hipDeviceSynchronize());
-    return c;
-}
-
-void serve_ctx_destroy(ServeCtx *c) {
-    if (!c) return;
-    if (c->h_arena) (void)hipHostFree(c->h_arena);
-    if (c->arena) (void)hipFree(c->arena);
-    delete c;
-}
-
-int serve_ctx_words(const ServeCtx *c) { return c->W; }
-int64_t *serve_ctx_counts(ServeCtx *c) { return c->h_counts; }
-
-static ChunkQueue serve_queue(ServeCtx *c, int slot) {
-    return ChunkQueue{c->cq_rec[slot], c->cq_len + slot, c->cq_mf + slot * kCntLanes};
-}
-
-// The running slots' hop over the first wact words of each row (the words
-// holding live slots): top-down from the frontier's queue when its out-edges
-// are few, else bottom-up (the first kernel decides; the others follow its
-// record), then the queue of what a bottom-up hop found.
-template <int G>
-static void serve_hop(ServeCtx *c, int wact, hipStream_t st) {
-    khop_graph *g = c->g;
-    const int64_t n = g->n;
-    const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
-                                                                 (int64_t)g->cu_count * 16));
-    const Params P = params_of(g);
-    const HeavyTable ht = batch_heavy_table(g, P.batch_heavy);
-    const int64_t nw = (n + 63) / 64;
-    const int i0 = c->fbi, i1 = (c->fbi + 1) % 3, i2 = (c->fbi + 2) % 3;
-    const FrontierBits fb{c->Fb + i0 * nw, c->Fb + i1 * nw, c->Fb + i2 * nw,
-                          c->Fc + i0 * kCntLanes, c->Fc + i1 * kCntLanes, c->Fc + i2 * kCntLanes};
-    hipLaunchKernelGGL((batch_push_kernel<G>), dim3(g->cu_count * 8), dim3(kBlock), 0, st, g->d_rowptr, g->d_colidx,
-                       c->V, c->F, c->N, n, g->nnz, c->W, wact, c->d_act, P.batch_push_div,
-                       serve_queue(c, i0), serve_queue(c, i1), serve_queue(c, i2), fb, nullptr, c->d_mode + 1, c->d_one,
-                       c->d_one + 1, nullptr);
-    hipLaunchKernelGGL((batch_pull_kernel<G>), dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, c->V,
-                       c->F, (const void *)nullptr, c->N, n, c->W, wact, c->d_act, ht.threshold, fb, c->d_mode + 1,
-                       c->d_one, c->d_one + 1, nullptr);
-    if (ht.n > 0) {
-        const int hgrid = (int)std::max<int64_t>(
-            1, std::min<int64_t>((ht.n + kWavesPerBlock - 1) / kWavesPerBlock, (int64_t)g->cu_count * 8));
-        hipLaunchKernelGGL((batch_pull_heavy_kernel<G>), dim3(hgrid), dim3(kBlock), 0, st, g->d_in_colidx, c->V, c->F,
-                           (const void *)nullptr, c->N, c->W, wact, c->d_act, ht.d_vert, ht.d_begin, ht.d_end,
-                           ht.n, n, fb, c->d_mode + 1, c->d_one, c->d_one + 1, nullptr);
-    }
-    const int qgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nw + kWavesPerBlock - 1) / kWavesPerBlock,
-                                                                  (int64_t)g->cu_count * 8));
-    hipLaunchKernelGGL(queue_from_bitmap_kernel, dim3(qgrid), dim3(kBlock), 0, st, g->d_rowptr, fb.next, fb.cnt_next,
-                       n, g->nnz, serve_queue(c, i1), c->d_mode + 1);
-}
-
-void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
-                     const int32_t *seeds, int n_new, int wact, hipStream_t st) {
-    khop_graph *g = c->g;
-    const int W = c->W;
-    const int64_t n = g->n;
-    bool any_fin = false;
-    for (int w = 0; w < W; ++w) any_fin |= fin[w] != 0;
-    if (any_fin) {
-        std::copy(fin, fin + W, c->h_fin);
-        KHOP_HIP(hipMemcpyAsync(c->d_fin, c->h_fin, W * 8, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(fill_zero_i64, dim3(1), dim3(256), 0, st, c->acc, (int64_t)64 * W);
-        const int cgx = (int)std::max<int64_t>(
-            1, std::min<int64_t>((n + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock), (int64_t)g->cu_count * 2));
-        hipLaunchKernelGGL(serve_harvest_kernel, dim3(cgx, W), dim3(kBlock), 0, st, c->V, c->F, c->N, n, W, c->d_fin,
-                           c->acc);
-        KHOP_HIP(hipMemcpyAsync(c->h_counts, c->acc, (size_t)64 * W * 8, hipMemcpyDeviceToHost, st));
-    }
-    if (n_new > 0) {
-        std::copy(slots, slots + n_new, c->h_slots);
-        std::copy(seeds, seeds + n_new, c->h_seeds);
-        KHOP_HIP(hipMemcpyAsync(c->d_slots, c->h_slots, (size_t)n_new * 4, hipMemcpyHostToDevice, st));
-        KHOP_HIP(hipMemcpyAsync(c->d_seeds, c->h_seeds, (size_t)n_new * 4, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(serve_admit_kernel, dim3((n_new + 255) / 256), dim3(256), 0, st, c->V, c->F, W, c->d_slots,
-                           c->d_seeds, n_new);
-    }
-    if (any_old || n_new > 0) {
-        // the running slots' hop ...
-        std::copy(act_old, act_old + W, c->h_act);
-        KHOP_HIP(hipMemcpyAsync(c->d_act, c->h_act, W * 8, hipMemcpyHostToDevice, st));
-        wact = std::max(1, std::min(wact, W));
-        int G = 1;
-        while (G < wact) G <<= 1;
-        switch (G) {
-            case 1: serve_hop<1>(c, wact, st); break;
-            case 2: serve_hop<2>(c, wact, st); break;
-            case 4: serve_hop<4>(c, wact, st); break;
-            case 8: serve_hop<8>(c, wact, st); break;
-            default: serve_hop<16>(c, wact, st); break;
-        }
-        // ... then the first hop of the new slots, pushed from their seeds
-        if (n_new > 0)
-            hipLaunchKernelGGL(serve_push_kernel, dim3(std::min(n_new, 4096)), dim3(kBlock), 0, st, g->d_rowptr,
-                               g->d_colidx, W, c->d_slots, c->d_seeds, n_new, c->N, c->V,
-                               c->Fb + ((c->fbi + 1) % 3) * ((n + 63) / 64), c->Fc + ((c->fbi + 1) % 3) * kCntLanes,
-                               serve_queue(c, (c->fbi + 1) % 3));
-        std::swap(c->F, c->N);
-        c->fbi = (c->fbi + 1) % 3;
-    }
     KHOP_HIP(hipGetLastError());
 }
 

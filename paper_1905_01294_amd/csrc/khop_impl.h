@@ -55,6 +55,7 @@ struct Params {
     int batch_push_div = 64;   // batched: top-down level when frontier arcs * div < total arcs
     int plain_grid = 4;        // plain hop and compaction kernels: blocks per compute unit
     int batch_grid = 16;       // batched bottom-up kernel: blocks per compute unit
+    int plain_pipeline = 1;    // plain path: consecutive queries overlap by one launch (0: one at a time)
 };
 
 struct PlainCtx;
@@ -204,6 +205,8 @@ void run_batched(khop_graph *g, const int32_t *d_seeds, const int32_t *h_ks, int
 
 // batched.hip
 BatchCtx *batch_ctx_create(khop_graph *g, int words);
+// Device bytes of a batch context of `words` 64-seed words for a graph of n vertices and nnz arcs.
+size_t batch_ctx_bytes(int64_t n, int64_t nnz, int words);
 void batch_ctx_destroy(BatchCtx *c);
 int batch_ctx_words(const BatchCtx *c);
 // Runs one batch of at most 64 * words seeds.  Slot j is seed d_seeds[h_perm[j]]
@@ -212,19 +215,6 @@ int batch_ctx_words(const BatchCtx *c);
 void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t *h_perm,
                const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st,
                const uint64_t *d_vmask = nullptr);
-
-// Serving batches (batched.hip): one per resident graph, W words of seed slots.
-struct ServeCtx;
-size_t serve_ctx_bytes(int64_t n, int64_t nnz, int words);
-ServeCtx *serve_ctx_create(khop_graph *g, int words);
-void serve_ctx_destroy(ServeCtx *c);
-int serve_ctx_words(const ServeCtx *c);
-int64_t *serve_ctx_counts(ServeCtx *c);  // pinned; counts of the last harvest, valid after its stream work
-// One scheduler iteration on stream st: harvest (count + clear) the finished
-// bits fin[W]; admit n_new seeds into slots; one hop for the running slots
-// act_old[W] (bottom-up) and the new slots (top-down from their seeds).
-void serve_iteration(ServeCtx *c, const uint64_t *fin, const uint64_t *act_old, bool any_old, const int32_t *slots,
-                     const int32_t *seeds, int n_new, int wact, hipStream_t st);
 
 // heavy.cpp: the chunk table for a threshold, (re)built when the threshold
 // changes.  The copy returned stays valid until graph_free.

@@ -1494,6 +1494,12 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         plain_deep(g, c, P, gr, hc, gd, d_seeds, num_seeds, std::min<int64_t>(k, g->n), d_counts, d_te, st, d_vmask);
         return;
     }
+    if (!P.plain_pipeline && num_seeds > 1) {
+        // one query at a time: each a pipeline of one query, its own launch sequence
+        for (int64_t i = 0; i < num_seeds; ++i)
+            plain_run(g, c, d_seeds + i, 1, k, d_counts + i, d_te ? d_te + i : nullptr, st, d_vmask);
+        return;
+    }
     const int64_t nnz_in = g->nnz;
     const int64_t pam = (int64_t)P.push_atomic_max;
     // hop 1 starts from the seed alone (top-down unless forced): the set-up

@@ -2,43 +2,41 @@
 //
 // The paper serves many concurrent queries from a worker pool, one query per
 // worker, arguing that throughput under concurrency matters more than the
-// latency of one query on all cores (Section II).  Here the GPU analog: every
-// resident graph has one running batched traversal whose 64*W seed-bit slots
-// are refilled as queries finish.  A scheduler thread, per graph:
-//   - when the graph's previous iteration has completed on its stream, turns
-//     the counts it harvested into results;
-//   - harvests slots whose query reached its k (bit-column popcount, bits
-//     cleared), admits queued queries (FIFO) into free slots, and enqueues one
-//     hop for every running slot -- new seeds go top-down from their seed,
-//     running ones bottom-up in the shared bitset product;
-//   - allocates a graph's batch only while it has work, sized by what the
-//     memory budget still allows (3 bitsets of n words per 64 slots), so
-//     queries wait rather than fail when memory is short.
-// Each graph has two such batches ("lanes"), one for queries with k <= 2 and
-// one for deeper ones, each on its own HIP stream: a short query never waits
-// behind the hops of long ones, and lanes and graphs overlap on the device.
-// Each graph also has a single-query lane on a third stream, which runs
-// queries one after another through the plain path (the paper's one query
-// per worker), in groups of one k.  A single query costs more device time
-// than its share of a batch, the more so the deeper it goes, so the
-// single-query lanes take arrivals only while the device time they would need
-// stays low (decayed sums of the arrivals' uncontended costs: one for cheap
-// queries, one for all, with hysteresis), and then only while the lane is
-// expected to answer first (its backlog plus the query's cost, against k + 1
-// measured iterations of the batch lane: k hops and the harvest).  So at low
-// load every query gets the single-query latency; as load grows the deep ones
-// and then the rest move into the batches, for their throughput.
+// latency of one query on all cores (Section II).  The GPU analog here keeps
+// every graph resident and answers queries through two kinds of lanes per
+// graph (the rules are in serve_policy.h, where they can be checked without a
+// GPU):
+//   - two batch lanes, one for queries with k <= 2 and one for deeper ones,
+//     so short queries never wait behind deep traversals.  Each lane has two
+//     run slots, each with its own HIP stream.  A free slot takes what waits
+//     in its lane (FIFO, up to 64 queries per word of its context) and
+//     enqueues it as one batched launch sequence (batch_run: seeds as bit
+//     columns of one bitset product per hop, one-hop queries from their
+//     seeds' rows, finished seeds narrowed away); arrivals that come while
+//     both slots run join the next launch the moment a slot frees.  So the
+//     launches of a lane, and of all lanes and graphs, overlap on the device,
+//     and the batch size follows the load.  A slot holds its batch context
+//     only while it has work, sized by the memory budget left, so queries
+//     wait rather than fail when memory is short;
+//   - a single-query lane on a stream of its own, which runs queries one
+//     after another through the plain path (the paper's one query per
+//     worker), in groups of one k, and takes arrivals only while the device
+//     time it would need stays low and it would answer before a batch lane.
+// A scheduler thread runs the lanes: it turns completed launches into
+// results, routes arrivals, and plans the next launches.
 #include <time.h>
 
 #include <algorithm>
-#include <cmath>
 #include <condition_variable>
 #include <deque>
 #include <thread>
 
 #include "khop_impl.h"
+#include "serve_policy.h"
 
 namespace {
+
+using khop::ServeRequest;
 
 int64_t mono_ns() {
     timespec ts;
@@ -46,68 +44,44 @@ int64_t mono_ns() {
     return (int64_t)ts.tv_sec * 1000000000LL + ts.tv_nsec;
 }
 
-struct Request {
-    uint64_t ticket;
-    int32_t graph_id, seed, k;
-    int64_t t_submit, deadline;
-    double plain_ms = 0;  // single-query lane: the cost charged to its backlog
-};
-
-struct Slot {
-    bool used = false;
-    int level = 0;
-    Request req{};
-    int64_t t_admit = 0;
-};
-
-struct GraphServe {
-    khop_graph *g = nullptr;
-    int id = 0;
-    int lane = 0;  // 0: queries with k <= kShortK
-    hipStream_t stream = nullptr;
-    hipEvent_t ev = nullptr;
-    int64_t t_launch = 0;
-    double it_ms = 0.5;  // moving average of one iteration's time, enqueue to completion
-    khop::ServeCtx *ctx = nullptr;
-    size_t ctx_bytes = 0;
-    std::deque<Request> queue;
-    std::vector<Slot> slots;
-    bool inflight = false;
-    std::vector<std::pair<int, Slot>> harvesting;  // slots whose counts the in-flight iteration produces
-};
-
 constexpr size_t kMaxQueued = 1 << 22;
-constexpr int kLanes = 2;        // per graph
-constexpr int32_t kShortK = 2;   // queries with k up to this go to lane 0
 constexpr int kPlainGroup = 64;  // queries of one k per plain launch sequence
 constexpr int kCostBuckets = 17; // per-k cost estimates; k >= 16 share the last
-// Single-query demand: the device time the single-query lanes would need for
-// the arrivals, as a fraction of wall time, averaged over kDemandNs.  Cheap
-// queries (uncontended cost up to kCheapMs) take those lanes while their own
-// demand stays below kCheapLoad; dearer ones only while the demand of all
-// arrivals stays below the device (entered below kDemandLow, left above
-// kDemandHigh).  Beyond that the batches are the cheaper way to answer.
-constexpr double kDemandNs = 5e6;
-constexpr double kCheapMs = 0.05;
-constexpr double kCheapLoad = 0.5;
-constexpr double kDemandLow = 0.8, kDemandHigh = 1.0;
 
-// An exponentially decayed sum of device ms over wall time.
-struct Demand {
-    double acc = 0;
-    int64_t t = 0;
-    double add(int64_t now, double ms) {
-        acc = acc * std::exp(-(double)(now - t) / kDemandNs) + ms;
-        t = now;
-        return acc / (kDemandNs / 1e6);  // device ms per wall ms
+// Counters of one lane, read by khop_server_stats (guarded by the server's mutex).
+struct LaneStats {
+    int64_t launches = 0, queries = 0;
+    double busy_ms = 0, max_ms = 0;
+    int32_t words = 0, queued = 0;
+    void add(int64_t q, double ms) {
+        launches += 1;
+        queries += q;
+        busy_ms += ms;
+        max_ms = std::max(max_ms, ms);
     }
 };
 
-int lane_of(int32_t graph_id, int32_t k) { return graph_id * kLanes + (k > kShortK ? 1 : 0); }
+// Device side of one run slot of a batch lane.
+struct RunRes {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    khop::BatchCtx *ctx = nullptr;
+    int32_t *d_seeds = nullptr, *h_seeds = nullptr;  // 64 * max_words entries
+    int64_t *d_counts = nullptr, *h_counts = nullptr;
+};
+
+struct BatchLane {
+    khop_graph *g = nullptr;
+    int graph_id = 0, lane = 0;
+    khop::LanePlan plan;
+    RunRes res[khop::kRunsPerLane];
+    LaneStats stats;
+};
 
 // The single-query lane of one graph.
 struct PlainLane {
     khop_graph *g = nullptr;
+    int graph_id = 0;
     hipStream_t stream = nullptr;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // timing only, around the launch sequence
     hipEvent_t ev_end = nullptr;                        // completion, after the counts' copy
@@ -116,13 +90,14 @@ struct PlainLane {
     int64_t *d_counts = nullptr;
     int32_t *h_seeds = nullptr;  // pinned staging
     int64_t *h_counts = nullptr;
-    std::deque<Request> queue;
-    std::vector<Request> running;
+    std::deque<ServeRequest> queue;
+    std::vector<ServeRequest> running;
     int64_t t_admit = 0;
     bool inflight = false;
     double cost_ms[kCostBuckets];   // moving average of one query's device time by k
     double floor_ms[kCostBuckets];  // the least per-query device time a group of that k took (uncontended)
     double backlog_ms = 0;          // expected device time of the queued and running queries
+    LaneStats stats;
     PlainLane() {
         // optimistic until measured: the first queries are answered here and set the figures
         for (int k = 0; k < kCostBuckets; ++k) cost_ms[k] = floor_ms[k] = 0.005 * (k + 1);
@@ -135,29 +110,28 @@ struct PlainLane {
 
 struct khop_server {
     int64_t budget = 0;
-    int64_t used = 0;
+    int64_t used = 0;  // device bytes of the batch contexts held (scheduler thread only)
     int max_words = 16;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::vector<GraphServe *> graphs;  // kLanes lanes per graph, graph i's at [i * kLanes, (i + 1) * kLanes)
-    std::vector<PlainLane *> plains;   // one per graph
+    std::vector<BatchLane *> lanes;   // kServeLanes per graph, graph i's at [i * kServeLanes, ...)
+    std::vector<PlainLane *> plains;  // one per graph
     int ngraphs = 0;
     std::atomic<int> route{KHOP_ROUTE_AUTO};
-    Demand demand_all, demand_cheap;  // arrivals' uncontended single-query cost
-    bool plain_mode = true;           // the single-query lanes take queries that are not cheap
-    std::deque<Request> incoming;
+    khop::SingleRouter router;
+    bool waiting_mem = false;  // some lane found no memory in the last pass
+    std::deque<ServeRequest> incoming;
     std::deque<khop_result> done;
     uint64_t next_ticket = 1;
     int64_t submitted = 0, completed = 0;
     bool stop = false;
-    int device = 0;
     std::thread th;
     std::string thread_error;
 };
 
 namespace {
 
-void finish(khop_server *s, const Request &r, int status, int64_t count, int64_t t_admit,
+void finish(khop_server *s, const ServeRequest &r, int status, int64_t count, int64_t t_admit,
             int path = KHOP_PATH_BATCH) {
     khop_result res{};
     res.ticket = r.ticket;
@@ -176,122 +150,90 @@ void finish(khop_server *s, const Request &r, int status, int64_t count, int64_t
     s->cv_done.notify_all();
 }
 
-// Results of the iteration that just completed on gs's stream.
-void complete_iteration(khop_server *s, GraphServe &gs) {
-    if (gs.harvesting.empty()) return;
-    const int64_t *counts = khop::serve_ctx_counts(gs.ctx);
-    for (auto &h : gs.harvesting) finish(s, h.second.req, KHOP_OK, counts[h.first] - 1, h.second.t_admit);
-    gs.harvesting.clear();
+void finish_late(khop_server *s, const std::vector<ServeRequest> &late, int path) {
+    for (const ServeRequest &r : late) finish(s, r, KHOP_ETIMEDOUT, -1, 0, path);
 }
 
-bool ensure_ctx(khop_server *s, GraphServe &gs) {
-    if (gs.ctx) return true;
-    const int64_t avail = s->budget - s->used;
-    if ((int64_t)khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, 1) > avail) return false;
-    int words = 1;
-    while (words * 2 <= s->max_words && (int64_t)khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, words * 2) <= avail)
-        words *= 2;
-    gs.ctx = khop::serve_ctx_create(gs.g, words);
-    gs.ctx_bytes = khop::serve_ctx_bytes(gs.g->n, gs.g->nnz, words);
-    s->used += (int64_t)gs.ctx_bytes;
-    gs.slots.assign((size_t)64 * words, Slot{});
-    return true;
+// Enqueues one batched launch of `batch` on slot i of the lane.
+void launch_batch(BatchLane &L, int i, const std::vector<ServeRequest> &batch) {
+    RunRes &R = L.res[i];
+    const int64_t n = (int64_t)batch.size();
+    std::vector<int32_t> ks((size_t)n);
+    for (int64_t j = 0; j < n; ++j) {
+        R.h_seeds[j] = batch[j].seed;
+        ks[j] = batch[j].k;
+    }
+    const std::vector<int32_t> perm = khop::batch_order(ks.data(), n);
+    std::vector<int32_t> ks_sorted((size_t)n);
+    for (int64_t j = 0; j < n; ++j) ks_sorted[j] = ks[perm[j]];
+    KHOP_HIP(hipMemcpyAsync(R.d_seeds, R.h_seeds, (size_t)n * 4, hipMemcpyHostToDevice, R.stream));
+    khop::batch_run(L.g, R.ctx, R.d_seeds, perm.data(), ks_sorted.data(), n, R.d_counts, R.stream);
+    KHOP_HIP(hipMemcpyAsync(R.h_counts, R.d_counts, (size_t)n * 8, hipMemcpyDeviceToHost, R.stream));
+    KHOP_HIP(hipEventRecord(R.done, R.stream));
 }
 
-void release_ctx(khop_server *s, GraphServe &gs) {
-    if (!gs.ctx) return;
-    KHOP_HIP(hipStreamSynchronize(gs.stream));
-    khop::serve_ctx_destroy(gs.ctx);
-    gs.ctx = nullptr;
-    s->used -= (int64_t)gs.ctx_bytes;
-    gs.ctx_bytes = 0;
-    gs.slots.clear();
-}
-
-// Plans and enqueues one iteration; returns true if work was enqueued.
-bool plan(khop_server *s, GraphServe &gs, int64_t now) {
-    // queued requests past their deadline time out; k == 0 needs no traversal
-    for (auto it = gs.queue.begin(); it != gs.queue.end();) {
-        if (it->deadline > 0 && now > it->deadline) {
-            finish(s, *it, KHOP_ETIMEDOUT, -1, 0);
-            it = gs.queue.erase(it);
-        } else if (it->k == 0) {
-            finish(s, *it, KHOP_OK, 0, now);
-            it = gs.queue.erase(it);
-        } else {
-            ++it;
+// Completed launches of a lane become results.
+bool poll_lane(khop_server *s, BatchLane &L, int64_t now) {
+    bool busy = false;
+    for (int i = 0; i < khop::kRunsPerLane; ++i) {
+        khop::LanePlan::Run &r = L.plan.runs[i];
+        if (!r.busy) continue;
+        if (hipEventQuery(L.res[i].done) != hipSuccess) {
+            busy = true;
+            continue;
         }
-    }
-    bool running = false;
-    for (auto &sl : gs.slots) running |= sl.used;
-    if (!running && gs.queue.empty()) {
-        release_ctx(s, gs);  // idle: give the memory back
-        return false;
-    }
-    if (!ensure_ctx(s, gs)) return false;  // waits for budget
-    const int W = khop::serve_ctx_words(gs.ctx);
-    std::vector<uint64_t> fin((size_t)W, 0), act((size_t)W, 0);
-    std::vector<int32_t> new_slots, new_seeds;
-    bool any_old = false;
-    for (int j = 0; j < 64 * W; ++j) {
-        Slot &sl = gs.slots[j];
-        if (!sl.used) continue;
-        if (sl.level >= sl.req.k) {
-            fin[j >> 6] |= 1ull << (j & 63);
-            gs.harvesting.push_back({j, sl});
-            sl.used = false;
-        } else {
-            act[j >> 6] |= 1ull << (j & 63);
-            any_old = true;
+        const int64_t *counts = L.res[i].h_counts;
+        for (size_t j = 0; j < r.reqs.size(); ++j) finish(s, r.reqs[j], KHOP_OK, counts[j], r.t_launch);
+        const double ms = (double)(now - r.t_launch) / 1e6;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            L.stats.add((int64_t)r.reqs.size(), ms);
         }
+        khop::complete_run(L.plan, i, now);
     }
-    for (int j = 0; j < 64 * W && !gs.queue.empty(); ++j) {
-        Slot &sl = gs.slots[j];
-        if (sl.used) continue;
-        // a slot being harvested this iteration is cleared before the admission (stream order)
-        sl.used = true;
-        sl.level = 0;
-        sl.req = gs.queue.front();
-        sl.t_admit = now;
-        gs.queue.pop_front();
-        new_slots.push_back(j);
-        new_seeds.push_back(sl.req.seed);
-    }
-    if (gs.harvesting.empty() && !any_old && new_slots.empty()) return false;
-    // admission takes the lowest free slots, so the words holding live slots
-    // are a prefix; the hop only works on it
-    int wact = 1;
-    for (int j = 0; j < 64 * W; ++j)
-        if (gs.slots[j].used) wact = std::max(wact, (j >> 6) + 1);
-    gs.t_launch = mono_ns();
-    khop::serve_iteration(gs.ctx, fin.data(), act.data(), any_old, new_slots.data(), new_seeds.data(),
-                          (int)new_slots.size(), wact, gs.stream);
-    for (auto &sl : gs.slots)
-        if (sl.used) sl.level += 1;
-    KHOP_HIP(hipEventRecord(gs.ev, gs.stream));
-    gs.inflight = true;
-    return true;
+    return busy;
 }
 
-// Which path answers request r first (the caller holds no lock; only the
-// scheduler thread touches lanes).
-bool route_plain(khop_server *s, const Request &r, int64_t now) {
-    const int route = s->route.load();
-    if (route == KHOP_ROUTE_BATCH) return false;
-    if (route == KHOP_ROUTE_PLAIN) return true;
-    const PlainLane &pl = *s->plains[r.graph_id];
-    const double c = pl.floor_cost(r.k);
-    const double load = s->demand_all.add(now, c);
-    if (s->plain_mode && load > kDemandHigh) s->plain_mode = false;
-    if (!s->plain_mode && load < kDemandLow) s->plain_mode = true;
-    if (c <= kCheapMs) {
-        if (s->demand_cheap.add(now, c) > kCheapLoad) return false;
-    } else if (!s->plain_mode) {
-        return false;
+// Plans and enqueues a lane's next launches; returns whether it still has work.
+bool plan_batch_lane(khop_server *s, BatchLane &L, int64_t now, int64_t &avail, bool &waiting) {
+    const khop_graph *g = L.g;
+    auto bytes_of = [g](int w) { return (int64_t)khop::batch_ctx_bytes(g->n, g->nnz, w); };
+    khop::LaneActions a = khop::plan_lane(L.plan, now, avail, s->max_words, s->waiting_mem, bytes_of);
+    for (int i : a.releases) {
+        KHOP_HIP(hipStreamSynchronize(L.res[i].stream));
+        khop::batch_ctx_destroy(L.res[i].ctx);
+        L.res[i].ctx = nullptr;
     }
-    const GraphServe &gs = *s->graphs[lane_of(r.graph_id, r.k)];
-    const double t_batch = (r.k + 1.5) * gs.it_ms;  // half an iteration in flight, k hops, the harvest
-    return pl.backlog_ms + pl.cost(r.k) <= t_batch;
+    finish_late(s, a.late, KHOP_PATH_BATCH);
+    for (auto &ln : a.launches) {
+        RunRes &R = L.res[ln.run];
+        if (ln.alloc_words) {
+            try {
+                R.ctx = khop::batch_ctx_create(L.g, ln.alloc_words);
+            } catch (const khop::Error &e) {
+                if (e.status != KHOP_ENOMEM) throw;
+                // the device had less free memory than the budget: wait, as for the budget
+                khop::LanePlan::Run &r = L.plan.runs[ln.run];
+                avail += r.bytes;
+                r = khop::LanePlan::Run{};
+                for (auto it = ln.batch.rbegin(); it != ln.batch.rend(); ++it) L.plan.queue.push_front(*it);
+                a.waiting = true;
+                continue;
+            }
+        }
+        launch_batch(L, ln.run, ln.batch);
+    }
+    waiting |= a.waiting;
+    int words = 0;
+    for (auto &r : L.plan.runs) words = std::max(words, r.words);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        L.stats.words = words;
+        L.stats.queued = (int32_t)std::min<size_t>(L.plan.queue.size(), INT32_MAX);
+    }
+    bool busy = !L.plan.queue.empty();
+    for (auto &r : L.plan.runs) busy |= r.busy;
+    return busy;
 }
 
 // Results of the plain group that just completed, and the cost estimate it updates.
@@ -307,6 +249,10 @@ void complete_plain(khop_server *s, PlainLane &pl) {
         pl.backlog_ms = std::max(0.0, pl.backlog_ms - pl.running[i].plain_ms);
         finish(s, pl.running[i], KHOP_OK, pl.h_counts[i], pl.t_admit, KHOP_PATH_SINGLE);
     }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        pl.stats.add(m, (double)(mono_ns() - pl.t_admit) / 1e6);
+    }
     pl.running.clear();
 }
 
@@ -314,13 +260,17 @@ void complete_plain(khop_server *s, PlainLane &pl) {
 // more of the same k, one launch sequence.  Returns true if work was enqueued.
 bool plan_plain(khop_server *s, PlainLane &pl, int64_t now) {
     for (auto it = pl.queue.begin(); it != pl.queue.end();) {
-        if (it->deadline > 0 && now > it->deadline) {
+        if (khop::expired(*it, now)) {
             pl.backlog_ms = std::max(0.0, pl.backlog_ms - it->plain_ms);
             finish(s, *it, KHOP_ETIMEDOUT, -1, 0, KHOP_PATH_SINGLE);
             it = pl.queue.erase(it);
         } else {
             ++it;
         }
+    }
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        pl.stats.queued = (int32_t)std::min<size_t>(pl.queue.size(), INT32_MAX);
     }
     if (pl.queue.empty()) return false;
     const int32_t k = pl.queue.front().k;
@@ -349,64 +299,65 @@ void scheduler(khop_server *s) {
     try {
         bool device_set = false;
         while (true) {
-            std::vector<GraphServe *> graphs;
+            std::vector<BatchLane *> lanes;
             std::vector<PlainLane *> plains;
-            std::deque<Request> arrived;
+            std::deque<ServeRequest> arrived;
             {
                 std::unique_lock<std::mutex> lk(s->mu);
                 if (s->stop) break;
-                graphs = s->graphs;
+                lanes = s->lanes;
                 plains = s->plains;
                 arrived.swap(s->incoming);
             }
-            for (const Request &r : arrived) {
+            if (!lanes.empty() && !device_set) {
+                KHOP_HIP(hipSetDevice(lanes[0]->g->device));
+                device_set = true;
+            }
+            bool busy = false;
+            // completed work first: it frees slots and sharpens the estimates the routing uses
+            for (PlainLane *pl : plains) {
+                if (!pl->inflight) continue;
+                if (hipEventQuery(pl->ev_end) != hipSuccess) {
+                    busy = true;
+                    continue;
+                }
+                pl->inflight = false;
+                complete_plain(s, *pl);
+            }
+            int64_t now = mono_ns();
+            for (BatchLane *L : lanes) busy |= poll_lane(s, *L, now);
+            const int route = s->route.load();
+            for (const ServeRequest &r : arrived) {
                 if (r.k == 0) {
-                    finish(s, r, KHOP_OK, 0, mono_ns());
-                } else if (route_plain(s, r, mono_ns())) {
-                    PlainLane &pl = *plains[r.graph_id];
-                    Request q = r;
+                    finish(s, r, KHOP_OK, 0, now);
+                    continue;
+                }
+                PlainLane &pl = *plains[r.graph_id];
+                BatchLane &L = *lanes[khop::serve_lane_of(r.graph_id, r.k)];
+                if (s->router.take(route, now, pl.floor_cost(r.k), pl.cost(r.k), pl.backlog_ms,
+                                   khop::lane_latency_ms(L.plan, now))) {
+                    ServeRequest q = r;
                     q.plain_ms = pl.cost(r.k);
                     pl.backlog_ms += q.plain_ms;
                     pl.queue.push_back(q);
                 } else {
-                    graphs[lane_of(r.graph_id, r.k)]->queue.push_back(r);
+                    L.plan.queue.push_back(r);
                 }
             }
-            const int64_t now = mono_ns();
-            bool busy = false;
-            if (!graphs.empty() && !device_set) {
-                KHOP_HIP(hipSetDevice(graphs[0]->g->device));
-                device_set = true;
-            }
+            now = mono_ns();
             for (PlainLane *pl : plains) {
-                if (pl->inflight) {
-                    if (hipEventQuery(pl->ev_end) != hipSuccess) {
-                        busy = true;
-                        continue;
-                    }
-                    pl->inflight = false;
-                    complete_plain(s, *pl);
-                }
+                if (pl->inflight) continue;
                 busy |= plan_plain(s, *pl, now);
                 busy |= !pl->queue.empty();
             }
-            for (GraphServe *gs : graphs) {
-                if (gs->inflight) {
-                    if (hipEventQuery(gs->ev) != hipSuccess) {
-                        busy = true;
-                        continue;
-                    }
-                    gs->inflight = false;
-                    gs->it_ms = 0.7 * gs->it_ms + 0.3 * (double)(mono_ns() - gs->t_launch) / 1e6;
-                    complete_iteration(s, *gs);
-                }
-                busy |= plan(s, *gs, now);
-                busy |= !gs->queue.empty();
-            }
+            int64_t avail = s->budget - s->used;
+            bool waiting = false;
+            for (BatchLane *L : lanes) busy |= plan_batch_lane(s, *L, now, avail, waiting);
+            s->used = s->budget - avail;
+            s->waiting_mem = waiting;
             if (!busy) {
                 std::unique_lock<std::mutex> lk(s->mu);
-                if (!s->stop && s->incoming.empty())
-                    s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+                if (!s->stop && s->incoming.empty()) s->cv_work.wait_for(lk, std::chrono::milliseconds(1));
             } else {
                 std::this_thread::sleep_for(std::chrono::microseconds(5));
             }
@@ -437,6 +388,21 @@ void free_plain_lane(PlainLane *pl) {
     if (pl->ev_end) (void)hipEventDestroy(pl->ev_end);
     if (pl->stream) (void)hipStreamDestroy(pl->stream);
     delete pl;
+}
+
+void free_batch_lane(BatchLane *L) {
+    if (!L) return;
+    for (RunRes &R : L->res) {
+        if (R.stream) (void)hipStreamSynchronize(R.stream);
+        if (R.ctx) khop::batch_ctx_destroy(R.ctx);
+        if (R.d_seeds) (void)hipFree(R.d_seeds);
+        if (R.d_counts) (void)hipFree(R.d_counts);
+        if (R.h_seeds) (void)hipHostFree(R.h_seeds);
+        if (R.h_counts) (void)hipHostFree(R.h_counts);
+        if (R.done) (void)hipEventDestroy(R.done);
+        if (R.stream) (void)hipStreamDestroy(R.stream);
+    }
+    delete L;
 }
 
 template <class F>
@@ -474,16 +440,27 @@ int khop_server_create(int64_t mem_budget_bytes, int32_t max_batch_seeds, khop_s
     });
 }
 
+int khop_server_batch_bytes(const khop_graph *g, int32_t words, int64_t *bytes) {
+    return sguard([&] {
+        if (!g || !bytes) khop::fail(KHOP_EINVAL, "graph or bytes is NULL");
+        if (words < 1 || words > 16) khop::fail(KHOP_EINVAL, "words must be in [1, 16]");
+        *bytes = (int64_t)khop::batch_ctx_bytes(g->n, g->nnz, words);
+    });
+}
+
 int khop_server_add_graph(khop_server *s, khop_graph *g, int32_t *graph_id) {
     return sguard([&] {
         if (!s || !g || !graph_id) khop::fail(KHOP_EINVAL, "server, graph or graph_id is NULL");
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) khop::fail(KHOP_EINTERNAL, "server stopped: " + s->thread_error);
-        if (!s->graphs.empty() && s->graphs[0]->g->device != g->device)
+        if (!s->lanes.empty() && s->lanes[0]->g->device != g->device)
             khop::fail(KHOP_EINVAL, "all graphs of a server must live on one device");
         KHOP_HIP(hipSetDevice(g->device));
+        const int id = s->ngraphs;
         auto *pl = new PlainLane();
         pl->g = g;
+        pl->graph_id = id;
+        std::vector<BatchLane *> made;
         try {
             KHOP_HIP(hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking));
             // timing events without a system-scope fence, so recording them writes back no cache
@@ -498,21 +475,31 @@ int khop_server_add_graph(khop_server *s, khop_graph *g, int32_t *graph_id) {
                 khop::fail(KHOP_ENOMEM, "allocation for a single-query lane failed");
             }
             pl->ctx = khop::plain_ctx_create(g);
+            const size_t cap = (size_t)64 * s->max_words;
+            for (int l = 0; l < khop::kServeLanes; ++l) {
+                auto *L = new BatchLane();
+                made.push_back(L);
+                L->g = g;
+                L->graph_id = id;
+                L->lane = l;
+                for (RunRes &R : L->res) {
+                    KHOP_HIP(hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking));
+                    KHOP_HIP(hipEventCreateWithFlags(&R.done, hipEventDisableTiming));
+                    if (hipMalloc(&R.d_seeds, cap * 4) != hipSuccess || hipMalloc(&R.d_counts, cap * 8) != hipSuccess ||
+                        hipHostMalloc((void **)&R.h_seeds, cap * 4, hipHostMallocDefault) != hipSuccess ||
+                        hipHostMalloc((void **)&R.h_counts, cap * 8, hipHostMallocDefault) != hipSuccess) {
+                        (void)hipGetLastError();
+                        khop::fail(KHOP_ENOMEM, "allocation for a batch lane failed");
+                    }
+                }
+            }
         } catch (...) {
             free_plain_lane(pl);
+            for (BatchLane *L : made) free_batch_lane(L);
             throw;
         }
         s->plains.push_back(pl);
-        for (int l = 0; l < kLanes; ++l) {
-            auto *gs = new GraphServe();
-            gs->g = g;
-            gs->id = s->ngraphs;
-            gs->lane = l;
-            KHOP_HIP(hipStreamCreateWithFlags(&gs->stream, hipStreamNonBlocking));
-            KHOP_HIP(hipEventCreateWithFlags(&gs->ev, hipEventDisableTiming));
-            s->graphs.push_back(gs);
-        }
-        s->device = g->device;
+        for (BatchLane *L : made) s->lanes.push_back(L);
         *graph_id = s->ngraphs++;
     });
 }
@@ -525,10 +512,15 @@ int khop_server_submit(khop_server *s, int32_t graph_id, int32_t seed, int32_t k
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) khop::fail(KHOP_EINTERNAL, "server stopped: " + s->thread_error);
         if (graph_id < 0 || graph_id >= s->ngraphs) khop::fail(KHOP_EINVAL, "unknown graph_id");
-        if (seed < 0 || (int64_t)seed >= s->graphs[lane_of(graph_id, 0)]->g->n)
-            khop::fail(KHOP_EINVAL, "seed out of range");
+        if (seed < 0 || (int64_t)seed >= s->plains[graph_id]->g->n) khop::fail(KHOP_EINVAL, "seed out of range");
         if (s->incoming.size() >= kMaxQueued) khop::fail(KHOP_EBUSY, "request queue full");
-        Request r{s->next_ticket++, graph_id, seed, k, mono_ns(), deadline_ns};
+        ServeRequest r;
+        r.ticket = s->next_ticket++;
+        r.graph_id = graph_id;
+        r.seed = seed;
+        r.k = k;
+        r.t_submit = mono_ns();
+        r.deadline = deadline_ns;
         s->incoming.push_back(r);
         s->submitted += 1;
         *ticket = r.ticket;
@@ -559,6 +551,31 @@ int khop_server_poll(khop_server *s, khop_result *out, int64_t max, int64_t *n_o
     });
 }
 
+int khop_server_stats(khop_server *s, khop_server_stat *out, int32_t max, int32_t *n_out) {
+    return sguard([&] {
+        if (!s || !n_out || (max > 0 && !out)) khop::fail(KHOP_EINVAL, "server, out or n_out is NULL");
+        std::lock_guard<std::mutex> lk(s->mu);
+        int32_t n = 0;
+        auto put = [&](int32_t gid, int32_t lane, const LaneStats &st) {
+            if (n < max) {
+                khop_server_stat &o = out[n];
+                o.graph_id = gid;
+                o.lane = lane;
+                o.launches = st.launches;
+                o.queries = st.queries;
+                o.busy_ms = st.busy_ms;
+                o.max_ms = st.max_ms;
+                o.words = st.words;
+                o.queued = st.queued;
+            }
+            ++n;
+        };
+        for (BatchLane *L : s->lanes) put(L->graph_id, L->lane == 0 ? KHOP_LANE_SHORT : KHOP_LANE_DEEP, L->stats);
+        for (PlainLane *pl : s->plains) put(pl->graph_id, KHOP_LANE_SINGLE, pl->stats);
+        *n_out = std::min(n, std::max(max, 0));
+    });
+}
+
 int khop_server_drain(khop_server *s, int64_t timeout_ms) {
     return sguard([&] {
         if (!s) khop::fail(KHOP_EINVAL, "server is NULL");
@@ -579,13 +596,7 @@ int khop_server_destroy(khop_server *s) {
             s->cv_work.notify_all();
         }
         if (s->th.joinable()) s->th.join();
-        for (GraphServe *gs : s->graphs) {
-            if (gs->stream) (void)hipStreamSynchronize(gs->stream);
-            if (gs->ctx) khop::serve_ctx_destroy(gs->ctx);
-            if (gs->ev) (void)hipEventDestroy(gs->ev);
-            if (gs->stream) (void)hipStreamDestroy(gs->stream);
-            delete gs;
-        }
+        for (BatchLane *L : s->lanes) free_batch_lane(L);
         for (PlainLane *pl : s->plains) free_plain_lane(pl);
         delete s;
     });

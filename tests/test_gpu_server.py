@@ -123,10 +123,10 @@ def test_open_loop_arrivals_while_running(K, graphs):
 
 def test_small_budget_one_word(K, graphs):
     (el0, _), g, o = graphs
-    # exactly one 64-slot word for the scale-10 graph: V, F, N words, three
-    # frontier bitmaps and three frontier chunk queues (256 out-edges a chunk)
-    n, nnz = el0.n, g[0].num_arcs
-    budget = 3 * 8 * n + 3 * 8 * ((n + 63) // 64) + 3 * 8 * (n + nnz // 256 + 64)
+    # room for exactly one one-word batch context of the scale-10 graph: the
+    # lanes' slots take turns with it
+    budget = K.khop_server_batch_bytes(g[0].handle, 1)
+    assert K.khop_server_batch_bytes(g[0].handle, 2) > budget
     srv = K.Server(budget, 1024)
     gid = srv.add_graph(g[0])
     seeds = np.nonzero(o[0].degrees() > 0)[0][:300]
@@ -135,7 +135,46 @@ def test_small_budget_one_word(K, graphs):
     got = _collect(srv, len(ticks))
     for t, s in ticks:
         assert got[t].count == o[0].khop(s, 2)[0]
+    st = srv.stats()
+    assert max(x["words"] for x in st) <= 1
     srv.close()
+
+
+def test_one_word_budget_both_lanes(K, graphs):
+    """Short and deep queries compete for one one-word context; both lanes finish, all equal the oracle."""
+    (el0, _), g, o = graphs
+    srv = K.Server(K.khop_server_batch_bytes(g[0].handle, 1), 1024)
+    srv.set_option(K.KHOP_SERVER_ROUTE, K.KHOP_ROUTE_BATCH)
+    gid = srv.add_graph(g[0])
+    seeds = np.nonzero(o[0].degrees() > 0)[0][:400]
+    ticks = [(srv.submit(gid, int(s), (1, 2, 3, 6)[i % 4]), int(s), (1, 2, 3, 6)[i % 4]) for i, s in enumerate(seeds)]
+    srv.drain(60000)
+    got = _collect(srv, len(ticks))
+    for t, s, k in ticks:
+        assert got[t].status == K.KHOP_OK and got[t].count == o[0].khop(s, k)[0]
+    lanes = {x["lane"]: x for x in srv.stats() if x["graph_id"] == gid}
+    assert lanes["batch_k_le_2"]["queries"] == 200 and lanes["batch_k_gt_2"]["queries"] == 200
+    srv.close()
+
+
+def test_deep_k_is_answered(K, graphs):
+    """k far past every eccentricity, on both paths: the count of everything within reach."""
+    (el0, el1), g, o = graphs
+    for route in (K.KHOP_ROUTE_BATCH, K.KHOP_ROUTE_PLAIN):
+        srv = K.Server(1 << 30, 256)
+        srv.set_option(K.KHOP_SERVER_ROUTE, route)
+        ids = [srv.add_graph(x) for x in g]
+        ticks = []
+        for gi, el in enumerate((el0, el1)):
+            for s in graphgen.draw_seeds(el, 6, seed=gi + 40):
+                for k in (40, 10**6, 2**31 - 1):
+                    ticks.append((srv.submit(ids[gi], int(s), k), gi, int(s), k))
+        srv.drain(60000)
+        got = _collect(srv, len(ticks))
+        for t, gi, s, k in ticks:
+            assert got[t].status == K.KHOP_OK
+            assert got[t].count == o[gi].count(np.array([s], np.int32), k)[0][0], (route, gi, s, k)
+        srv.close()
 
 
 def test_deadlines_when_no_memory(K, graphs):
