@@ -108,7 +108,9 @@ struct LanePlan {
 // What the scheduler does with one lane in one pass.  Launches are made on
 // free slots, those already holding a context first; a slot without one gets
 // the widest that the budget left (avail, updated) allows, or none, which
-// sets waiting.  Each launch takes up to 64 * words queued requests.  Idle
+// sets waiting.  Each launch takes up to 64 * words queued requests; while
+// another launch of the lane is in flight, a slot launches only when at least
+// 16 * words requests wait (its width, or max_words without a context).  Idle
 // slots give their context back after kIdleReleaseNs, or at once when some
 // lane waits for memory (others_waiting).  Requests still queued after the
 // launches whose deadline has passed leave the queue, at most every
@@ -145,10 +147,17 @@ LaneActions plan_lane(LanePlan &L, int64_t now, int64_t &avail, int max_words, b
     std::stable_sort(order, order + kRunsPerLane, [&](int x, int y) {
         return (L.runs[x].words > 0) > (L.runs[y].words > 0);
     });
+    int in_flight = 0;
+    for (const auto &r : L.runs) in_flight += r.busy;
     for (int oi = 0; oi < kRunsPerLane && !L.queue.empty(); ++oi) {
         const int i = order[oi];
         LanePlan::Run &r = L.runs[i];
         if (r.busy) continue;
+        // beside a running launch, a second one starts only for a backlog of
+        // a quarter of its width: a launch's fixed cost (one pass over the
+        // graph per hop) is paid once for every query it holds
+        const int width = r.words ? r.words : std::max(1, max_words);
+        if (in_flight > 0 && (int64_t)L.queue.size() < 16 * (int64_t)width) break;
         int alloc = 0;
         if (r.words == 0) {
             alloc = words_for_budget(avail, max_words, bytes_of);
@@ -169,6 +178,7 @@ LaneActions plan_lane(LanePlan &L, int64_t now, int64_t &avail, int max_words, b
         r.reqs = batch;
         r.t_launch = now;
         a.launches.push_back({i, alloc, std::move(batch)});
+        ++in_flight;
     }
     if (!L.queue.empty() && (a.waiting || now - L.last_sweep >= kSweepNs)) {
         L.last_sweep = now;
@@ -219,12 +229,17 @@ enum { ROUTE_AUTO = 0, ROUTE_BATCH = 1, ROUTE_PLAIN = 2 };
 
 struct SingleRouter {
     static constexpr double kCheapMs = 0.05, kCheapLoad = 0.5, kDemandLow = 0.8, kDemandHigh = 1.0;
+    // The single-query lane is for latency at light load: it never queues more
+    // than this much of its measured per-query device time (its costs rise
+    // when batches share the device, so a long queue there would wait longer
+    // than the batches take).
+    static constexpr double kMaxBacklogMs = 3.0;
     Demand all, cheap;
     bool plain_mode = true;  // the single-query lanes take queries that are not cheap
     // Whether the single-query lane answers a request: its uncontended cost
     // floor_ms, the lane's current per-query estimate cost_ms and backlog, and
     // the latency a batch lane would give it.  The lane must also be expected
-    // to answer first.
+    // to answer first, within kMaxBacklogMs.
     bool take(int route, int64_t now, double floor_ms, double cost_ms, double backlog_ms, double batch_ms) {
         if (route == ROUTE_BATCH) return false;
         if (route == ROUTE_PLAIN) return true;
@@ -236,7 +251,7 @@ struct SingleRouter {
         } else if (!plain_mode) {
             return false;
         }
-        return backlog_ms + cost_ms <= batch_ms;
+        return backlog_ms + cost_ms <= std::min(batch_ms, kMaxBacklogMs);
     }
 };
 

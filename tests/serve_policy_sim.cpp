@@ -4,6 +4,7 @@
 //
 // Usage: serve_policy_sim SEED BUDGET MAX_WORDS LANES ARRIVALS
 //        serve_policy_sim order K...   (prints batch_order of the ks)
+//        serve_policy_sim route ROUTE GAP_NS FLOOR_MS COST_MS BATCH_MS N   (single-query routing)
 //   Requests arrive at random times (seeded xorshift), each for a random lane
 //   with a random k and, for one in five, a deadline.  A context of w words
 //   costs 1000 + 300 * w bytes.  A launch of b requests completes
@@ -36,6 +37,25 @@ int main(int argc, char **argv) {
         const std::vector<int32_t> o = batch_order(ks.data(), (int64_t)ks.size());
         for (size_t i = 0; i < o.size(); ++i) std::printf("%s%d", i ? " " : "", o[i]);
         std::printf("\n");
+        return 0;
+    }
+    if (argc >= 2 && std::string(argv[1]) == "route") {
+        // serve_policy_sim route ROUTE GAP_NS FLOOR_MS COST_MS BATCH_MS N : N arrivals GAP_NS apart; the
+        // single-query lane serves its backlog at one device ms per wall ms.  One line per arrival:
+        // taken (0/1) and the backlog after it.
+        const int route = std::atoi(argv[2]);
+        const int64_t gap = std::atoll(argv[3]);
+        const double floor_ms = std::atof(argv[4]), cost_ms = std::atof(argv[5]), batch_ms = std::atof(argv[6]);
+        const int n = std::atoi(argv[7]);
+        SingleRouter router;
+        double backlog = 0;
+        int64_t now = 1;
+        for (int i = 0; i < n; ++i, now += gap) {
+            backlog = std::max(0.0, backlog - (double)gap / 1e6);
+            const bool take = router.take(route, now, floor_ms, cost_ms, backlog, batch_ms);
+            if (take) backlog += cost_ms;
+            std::printf("%d %.6f\n", take ? 1 : 0, backlog);
+        }
         return 0;
     }
     if (argc < 6) return 2;

@@ -52,10 +52,16 @@ def test_policy_invariants(sim, seed, budget, max_words, lanes):
     last_ticket = {}
     busy = {}
     held = {}  # (lane, run) -> bytes
+    queued = {}  # lane -> tickets waiting
     for e in ev:
+        if e["ev"] == "arrive":
+            queued.setdefault(e["lane"], set()).add(e["ticket"])
         if e["ev"] == "launch":
             key = (e["lane"], e["run"])
             assert not busy.get(key), "a slot launched while busy"
+            others = sum(v for (l, r), v in busy.items() if l == e["lane"] and r != e["run"])
+            if others:  # beside a running launch only for a backlog of a quarter of its width
+                assert len(queued[e["lane"]]) >= 16 * e["words"], (len(queued[e["lane"]]), e)
             busy[key] = True
             w = e["words"]
             assert w & (w - 1) == 0 and 1 <= w <= max_words
@@ -72,6 +78,7 @@ def test_policy_invariants(sim, seed, budget, max_words, lanes):
             for t in e["tickets"]:
                 assert t not in launched and t not in late
                 launched[t] = e["t"]
+                queued[e["lane"]].discard(t)
                 a = arrive[t]
                 assert a["lane"] == e["lane"]
                 assert a["deadline"] == 0 or e["t"] <= a["deadline"], "launched after its deadline"
@@ -87,6 +94,7 @@ def test_policy_invariants(sim, seed, budget, max_words, lanes):
         elif e["ev"] == "late":
             t = e["ticket"]
             assert t not in launched and t not in late
+            queued[e["lane"]].discard(t)
             assert 0 < arrive[t]["deadline"] < e["t"], "timed out before its deadline"
             late[t] = e["t"]
         elif e["ev"] == "pass":
@@ -130,3 +138,41 @@ def test_batch_order(sim, ks):
     for a, b in zip(order, order[1:]):
         if key[order.index(a)] == key[order.index(b)]:
             assert a < b  # stable
+
+
+def route(sim, route_opt, gap_ns, floor_ms, cost_ms, batch_ms, n=2000):
+    out = subprocess.run([sim, "route", str(route_opt), str(gap_ns), str(floor_ms), str(cost_ms), str(batch_ms),
+                          str(n)], check=True, capture_output=True, text=True).stdout
+    rows = [line.split() for line in out.splitlines()]
+    return [int(a) for a, _ in rows], [float(b) for _, b in rows]
+
+
+MAX_BACKLOG_MS = 3.0  # SingleRouter::kMaxBacklogMs
+
+
+def test_router_forced_routes(sim):
+    assert route(sim, 1, 1000, 0.01, 0.01, 50)[0] == [0] * 2000  # ROUTE_BATCH
+    assert route(sim, 2, 1000, 5.0, 5.0, 0.1)[0] == [1] * 2000   # ROUTE_PLAIN
+
+
+def test_router_light_load_takes_everything(sim):
+    """A trickle of cheap queries (0.01 ms each, one every 100 us) all go to the single-query lane."""
+    taken, backlog = route(sim, 0, 100_000, 0.01, 0.01, 5.0)
+    assert all(taken) and max(backlog) < 0.1
+
+
+def test_router_backlog_is_bounded(sim):
+    """Cheap by their uncontended cost but slow in practice (0.3 ms each under contention), arriving every
+    20 us: the lane keeps at most its backlog bound and sends the rest to the batches."""
+    taken, backlog = route(sim, 0, 20_000, 0.01, 0.3, 200.0)
+    assert 0 < sum(taken) < len(taken)
+    assert max(backlog) <= MAX_BACKLOG_MS + 1e-9
+
+
+def test_router_heavy_demand_goes_to_batches(sim):
+    """Dear queries (2 ms uncontended) arriving faster than one device can answer them: once the decayed
+    demand passes the device, none is taken until it falls back below 0.8."""
+    taken, _ = route(sim, 0, 500_000, 2.0, 2.0, 1000.0, n=4000)
+    assert sum(taken[-1000:]) < 0.5 * 1000 * 0.5  # at most about what one device keeps up with
+    taken2, _ = route(sim, 0, 10_000_000, 2.0, 2.0, 1000.0, n=200)
+    assert all(taken2)  # one every 10 ms: well under the device
