@@ -352,7 +352,7 @@ enum { KHOP_PATH_BATCH = 0, KHOP_PATH_SINGLE = 1 };
  * mem_budget_bytes bounds the device memory of the batch contexts the slots
  * hold (khop_server_batch_bytes gives one context's size; a slot takes the
  * widest context, up to max_batch_seeds / 64 words, that the budget left
- * allows, and gives it back when it has been idle for 50 ms or another lane
+ * allows, and gives it back when it has been idle for 2 s or another lane
  * waits for memory); requests wait while no context fits, and time out at
  * their deadline.  max_batch_seeds (64..1024, a multiple of 64) bounds the
  * queries of one launch.

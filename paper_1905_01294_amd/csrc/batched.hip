@@ -228,18 +228,32 @@ __device__ __forceinline__ uint64_t group_any(uint64_t m) {
     }
 }
 
-// The frontier word of vertex u that lane word wi gathers.  With one-word
-// rows whose active seeds all sit in the low 16 or 32 bits, the bottom-up
-// kernels read a narrow copy Fs instead (fs_bits = 16 or 32, else 0): a hit
-// then costs 2 or 4 bytes of a line shared by 64 or 32 vertices, and the copy
-// (4 or 8 MB for two million vertices) stays far more in L2 than F does.
+// A 64-bit zero that loads of lanes with nothing to read point at, so that a
+// group of loads can be issued unconditionally, all in flight at once, with
+// no branch (and no wait) between them.
+__device__ const uint64_t kZeroWords[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+// The frontier word of vertex u that lane word wi gathers, or 0 when take is
+// false (the load then reads the shared zero word).  With one-word rows whose
+// active seeds all sit in the low 16 or 32 bits, the bottom-up kernels read a
+// narrow copy Fs instead (FS = 16 or 32, else 0): a hit then costs 2 or 4
+// bytes of a line shared by 64 or 32 vertices, and the copy (4 or 8 MB for two
+// million vertices) stays far more in L2 than F does.
 template <int FS>
 __device__ __forceinline__ uint64_t frontier_word(const uint64_t *__restrict__ F, const void *__restrict__ Fs,
-                                                  int64_t u, int W, int wi) {
-    if constexpr (FS == 16) return ((const uint16_t *)Fs)[u];
-    else if constexpr (FS == 32) return ((const uint32_t *)Fs)[u];
-    else return F[u * W + wi];
+                                                  int64_t u, int W, int wi, bool take) {
+    if constexpr (FS == 16) {
+        return *(take ? (const uint16_t *)Fs + u : (const uint16_t *)kZeroWords);
+    } else if constexpr (FS == 32) {
+        return *(take ? (const uint32_t *)Fs + u : (const uint32_t *)kZeroWords);
+    } else {
+        return *(take ? F + u * W + wi : kZeroWords);
+    }
 }
+
+__device__ const uint64_t kOnesWords[8] = {~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull};
+
+constexpr int kPullR = 4;  // in-edges per lane per step of the bottom-up kernels (loads in flight)
 
 // Builds that narrow copy of a one-word frontier (bits = 16 or 32); it exits
 // at once when the hop went top-down or the frontier is empty.
@@ -255,12 +269,38 @@ __global__ void __launch_bounds__(kBlock) batch_frontier_copy_kernel(const uint6
     }
 }
 
+// The bitmap tests of a step's kPullR in-edges: all loads first, then the
+// bits, so that no branch separates the loads and all are in flight at once.
+__device__ __forceinline__ void test_bits(const uint64_t *__restrict__ bm, const int32_t (&u)[kPullR], bool all,
+                                          bool (&hit)[kPullR]) {
+    uint64_t w[kPullR];
+#pragma unroll
+    for (int r = 0; r < kPullR; ++r) {
+        const uint32_t uu = u[r] >= 0 ? (uint32_t)u[r] : 0u;
+        w[r] = *(all ? kOnesWords : bm + (uu >> 6));
+    }
+#pragma unroll
+    for (int r = 0; r < kPullR; ++r) hit[r] = u[r] >= 0 && ((w[r] >> ((uint32_t)u[r] & 63u)) & 1ull);
+}
+
+// The LDS row of a wave between the bitmap tests and the gathers of a step.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+
 // Hop >= 2, light vertices: G lanes per vertex (lane word = lane % G).  Each
-// step the group's lanes read R rounds of G consecutive in-edges and test them
-// against the frontier bitmap Fbc; for every hit the G lanes gather their
-// words of F[u] (of the narrow copy Fs when FS is 16 or 32).  Vertices with a
-// new bit are marked in Fbn; Fbz (the bitmap of the hop after this one) is
-// cleared on the way.
+// step every lane of a group loads kPullR of the vertex's in-edges (the group
+// covers kPullR * G consecutive ones) and tests them against the frontier
+// bitmap Fbc; the group's hits are packed into its part of the wave's LDS
+// row, and each lane gathers its word of F[u] for four hits at a time (of the
+// narrow copy Fs when FS is 16 or 32).  Every load of a step is unconditional
+// (lanes with nothing to load read a valid dummy address), so the step keeps
+// kPullR loads in flight per lane instead of one.  The group stops once every
+// lane holds all of its needed bits.  Vertices with a new bit are marked in
+// Fbn; Fbz (the bitmap of the hop after this one) is cleared on the way.
 template <int G, int FS = 0>
 __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__restrict__ in_rowptr,
                                                            const int32_t *__restrict__ in_colidx,
@@ -282,18 +322,23 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
     // skipping the bitmap test pays only with one-word rows: a wider row costs
     // far more to gather than the test
     const bool dense = wact == 1 && fb_dense(fb.cnt_cur, n);
-    constexpr int VPW = kWave / G;                          // vertices per wave
-    constexpr int R = G == 1 ? 4 : (G >= 16 ? 1 : 16 / G);  // rounds of G in-edges per step
+    constexpr int VPW = kWave / G;       // vertices per wave
+    constexpr int SLOTS = kPullR * G;    // hits a group can hold per step
+    __shared__ int32_t s_hit[kWavesPerBlock][kPullR * kWave];
+    __shared__ int32_t s_junk[kWavesPerBlock][kWave];
     const int lane = lane_id();
+    const int wv = threadIdx.x / kWave;
     const int grp = lane / G;
     const int wi = lane % G;
     const uint64_t grp_bits = ((G == 64) ? ~0ull : ((1ull << G) - 1)) << (grp * G);
+    const uint64_t below = lane == 0 ? 0ull : ((~0ull) >> (kWave - lane));  // lanes below this one
     const uint64_t actw = wi < wact ? act[wi] : 0ull;
+    int32_t *const hits = &s_hit[wv][grp * SLOTS];
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     bool any = false;
     int64_t examined = 0, scanned = 0, gathered = 0, fresh = 0;
-    for (int64_t wv = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; wv * VPW < n; wv += nwaves) {
-        const int64_t v = wv * VPW + grp;
+    for (int64_t wvi = (int64_t)blockIdx.x * kWavesPerBlock + wv; wvi * VPW < n; wvi += nwaves) {
+        const int64_t v = wvi * VPW + grp;
         const bool valid = v < n && wi < wact;
         const int64_t at = v * W + wi;
         uint64_t need = 0;
@@ -311,40 +356,45 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
         if (active) scanned += (wi == 0);
         int64_t x0 = b;
         while (ballot(active)) {
-            int32_t u[R];
-            bool hit[R];
+            // the step's in-edge loads, all issued before any is used: the
+            // indices first (some group of the wave is active, so the graph
+            // has arcs and index 0 exists), then the loads, then the selects
+            const int64_t left = active ? e - x0 - wi : 0;  // in-edges of the group at or after this lane's first
+            int32_t u[kPullR];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t x = x0 + (int64_t)r * G + wi;
-                u[r] = (active && x < e) ? in_colidx[x] : -1;
+            for (int r = 0; r < kPullR; ++r) u[r] = in_colidx[(int64_t)r * G < left ? x0 + (int64_t)r * G + wi : 0];
+#pragma unroll
+            for (int r = 0; r < kPullR; ++r) u[r] = (int64_t)r * G < left ? u[r] : -1;
+            bool hit[kPullR];
+            test_bits(Fbc, u, dense, hit);
+            // pack the group's hits, in edge order, into its LDS slots (misses
+            // write to the lane's junk slot: no branch)
+            int nh = 0;
+#pragma unroll
+            for (int r = 0; r < kPullR; ++r) {
+                const uint64_t hm = ballot(hit[r]) & grp_bits;
+                *(hit[r] ? &hits[nh + __popcll(hm & below)] : &s_junk[wv][lane]) = u[r];
+                nh += __popcll(hm);
             }
+            wave_lds_sync();
+            // four gathers in flight per lane; a lane whose word already holds
+            // every needed bit reads the zero word instead
+            const bool lane_open = (acc & need) != need;
+            for (int j0 = 0; ballot(j0 < nh); j0 += 4) {
+                uint64_t f[4];
 #pragma unroll
-            for (int r = 0; r < R; ++r) hit[r] = u[r] >= 0 && (dense || test_bit(Fbc, u[r]));
-            if constexpr (G == 1) {
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    if (hit[r]) {
-                        acc |= frontier_word<FS>(F, Fs, u[r], W, 0);
-                        ++gathered;
-                    }
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    uint64_t mine = ballot(hit[r]) & grp_bits;
-                    while (ballot(mine != 0)) {
-                        const int h = mine ? __builtin_ctzll(mine) : lane;
-                        const int32_t uh = __shfl(u[r], h, kWave);
-                        if (mine) {
-                            if (wi < wact) acc |= F[(int64_t)uh * W + wi];
-                            gathered += (wi == 0);
-                            mine &= mine - 1;
-                        }
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const bool take = j0 + q < nh && lane_open;
+                    const int32_t hu = hits[take ? j0 + q : 0];  // an index inside the group's slots either way
+                    f[q] = frontier_word<FS>(F, Fs, take ? hu : 0, W, wi, take);
                 }
+                acc |= (f[0] | f[1]) | (f[2] | f[3]);
             }
+            if (wi == 0) gathered += nh;
+            wave_lds_sync();  // the slots are rewritten next step only after every lane has read them
             if (active) {
-                if (wi == 0) examined += std::min<int64_t>((int64_t)R * G, e - x0);
-                x0 += (int64_t)R * G;
+                if (wi == 0) examined += std::min<int64_t>((int64_t)SLOTS, e - x0);
+                x0 += SLOTS;
                 if (x0 >= e) active = false;
             }
             // the group stops once every lane holds all of its needed bits
@@ -364,7 +414,7 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
         }
         const uint64_t gm = group_any<G>(ballot(nx != 0));
         if (gm && lane == 0) {
-            const int64_t v0 = wv * VPW;  // VPW divides 64: the wave's vertices share one bitmap word
+            const int64_t v0 = wvi * VPW;  // VPW divides 64: the wave's vertices share one bitmap word
             const uint64_t old = atomicOr((unsigned long long *)&fb.next[v0 >> 6], (unsigned long long)(gm << (v0 & 63)));
             fresh += __popcll(gm << (v0 & 63) & ~old);
         }
@@ -389,10 +439,12 @@ __device__ __forceinline__ uint64_t subgroup_or(uint64_t v) {
 }
 
 // Hop >= 2, heavy vertices: one wave per edge chunk of a heavy vertex.  The
-// wave tests 64 in-edges per round against the frontier bitmap, packs the hits
-// of four rounds in LDS and gathers their words with 64/G streams of G lanes;
-// the chunk's findings are ORed into the vertex's next-frontier and visited
-// words atomically (the light kernel left zeros).  FS as in the light kernel.
+// wave loads 64 in-edges per round, four rounds at a time, tests them against
+// the frontier bitmap, packs the hits of the four rounds in LDS and gathers
+// their words with 64/G streams of G lanes, four hits per stream at a time;
+// every load is unconditional, so a lane keeps four in flight.  The chunk's
+// findings are ORed into the vertex's next-frontier and visited words
+// atomically (the light kernel left zeros).  FS as in the light kernel.
 template <int G, int FS = 0>
 __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     const int32_t *__restrict__ in_colidx, uint64_t *V, const uint64_t *__restrict__ F, const void *__restrict__ Fs,
@@ -407,7 +459,8 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     // far more to gather than the test
     const bool dense = wact == 1 && fb_dense(fb.cnt_cur, n);
     constexpr int S = kWave / G;  // gather streams
-    __shared__ int32_t s_hit[kWavesPerBlock][4 * kWave];
+    __shared__ int32_t s_hit[kWavesPerBlock][kPullR * kWave];
+    __shared__ int32_t s_junk[kWavesPerBlock][kWave];
     const int lane = lane_id();
     const int wv = threadIdx.x / kWave;
     const int wi = lane % G;
@@ -422,53 +475,47 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
         uint64_t need = 0;
         if (wi < wact) need = ~__hip_atomic_load(&V[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & actw;
         if (!ballot(need != 0)) continue;
-        const int64_t b = hbegin[i], e = hend[i];
-        uint64_t acc = 0;
-        const int64_t ex0 = examined;
-        if (dense) {
-            // every in-edge gathered: stream sg takes edges sg, sg + S, ...
-            for (int64_t x0 = b; x0 < e; x0 += 4 * S) {
+        const int64_t b = hbegin[i], e = hend[i];  // e > b
+        uint64_t acc = 0, full = 0;
+        for (int64_t x0 = b; x0 < e; x0 += kPullR * kWave) {
+            int32_t u[kPullR];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t x = x0 + r * S + sg;
-                    if (x < e && wi < wact) acc |= frontier_word<FS>(F, Fs, in_colidx[x], W, wi);
-                }
-                examined += std::min<int64_t>(4 * S, e - x0);
-                const uint64_t full = subgroup_or<G>(acc);
-                if (!ballot((full & need) != need)) break;
-            }
-            gathered += examined - ex0;  // every examined in-edge is gathered
-        }
-        for (int64_t x0 = dense ? e : b; x0 < e; x0 += 4 * kWave) {
-            int32_t u[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < kPullR; ++r) {
                 const int64_t x = x0 + r * kWave + lane;
-                u[r] = x < e ? in_colidx[x] : -1;
+                const int32_t uu = in_colidx[x < e ? x : b];
+                u[r] = x < e ? uu : -1;
             }
-            bool hit[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) hit[r] = u[r] >= 0 && test_bit(Fbc, u[r]);
-            // pack the hits of the four rounds, in order, into the wave's LDS row
+            bool hit[kPullR];
+            test_bits(Fbc, u, dense, hit);
+            // pack the hits of the four rounds, in order, into the wave's LDS
+            // row (misses write to the lane's junk slot: no branch)
             int nh = 0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < kPullR; ++r) {
                 const uint64_t hm = ballot(hit[r]);
-                if (hit[r]) s_hit[wv][nh + mask_rank(hm)] = u[r];
+                *(hit[r] ? &s_hit[wv][nh + mask_rank(hm)] : &s_junk[wv][lane]) = u[r];
                 nh += __popcll(hm);
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (wi < wact)
-                for (int j = sg; j < nh; j += S) acc |= frontier_word<FS>(F, Fs, s_hit[wv][j], W, wi);
+            wave_lds_sync();
+            // stream sg takes hits sg, sg + S, ...: four of its hits in flight at
+            // a time; words that hold every needed bit (over all streams, as of
+            // the last round) are not gathered again
+            const bool lane_open = (full & need) != need;
+            for (int j0 = sg; j0 < nh; j0 += 4 * S) {
+                uint64_t f[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int j = j0 + q * S;
+                    const bool take = j < nh && lane_open;
+                    const int32_t hu = s_hit[wv][take ? j : 0];  // an index inside the wave's row either way
+                    f[q] = frontier_word<FS>(F, Fs, take ? hu : 0, W, wi, take);
+                }
+                acc |= (f[0] | f[1]) | (f[2] | f[3]);
+            }
             gathered += nh;
-            examined += std::min<int64_t>(4 * kWave, e - x0);
-            // the row is rewritten next round only after every lane has read it
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const uint64_t full = subgroup_or<G>(acc);
+            examined += std::min<int64_t>(kPullR * kWave, e - x0);
+            wave_lds_sync();  // the row is rewritten next round only after every lane has read it
+            full = subgroup_or<G>(acc);
             if (!ballot((full & need) != need)) break;
         }
         acc = subgroup_or<G>(acc);
@@ -595,29 +642,46 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t x) {
 }
 
 // counts_acc[w*64 + bit] += number of vertices whose word w has that bit, for
-// words w = w0 + blockIdx.y of rows W words long.
+// words w0 .. w0 + nwords - 1 (at most 16) of rows W words long.  A wave takes
+// 64 vertices at a time and all the words asked for: lane i loads vertex i's
+// words (one row, so the words after the first come from lines already in
+// cache), and for each word the wave's 64 values are transposed and popcounted.
 // With a vertex mask (vmask, one bit per vertex) only the vertices in it are counted.
+constexpr int kCountMaxWords = 16;
 __global__ void __launch_bounds__(kBlock) batch_count_kernel(const uint64_t *__restrict__ V, int64_t n, int W, int w0,
-                                                            const uint64_t *__restrict__ vmask, int64_t *counts_acc) {
-    const int w = w0 + blockIdx.y;
+                                                            int nwords, const uint64_t *__restrict__ vmask,
+                                                            int64_t *counts_acc) {
     const int lane = lane_id();
     __shared__ int64_t s_acc[kWavesPerBlock][kWave];
-    int64_t acc = 0;
+    int64_t acc[kCountMaxWords];
+#pragma unroll
+    for (int j = 0; j < kCountMaxWords; ++j) acc[j] = 0;
     const int64_t nchunks = (n + kWave - 1) / kWave;
     for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave; c < nchunks;
          c += (int64_t)gridDim.x * kWavesPerBlock) {
         const int64_t v = c * kWave + lane;
         const bool in = v < n && (!vmask || ((vmask[c] >> lane) & 1ull));
-        const uint64_t x = in ? V[v * W + w] : 0ull;
-        if (!ballot(x != 0)) continue;
-        acc += __popcll(transpose64(x));
+        const uint64_t *row = V + (in ? v : 0) * W + w0;
+        uint64_t x[kCountMaxWords];
+#pragma unroll
+        for (int j = 0; j < kCountMaxWords; ++j) x[j] = j < nwords ? row[j] : 0ull;  // (vertex 0's row when out)
+#pragma unroll
+        for (int j = 0; j < kCountMaxWords; ++j) x[j] = in ? x[j] : 0ull;
+#pragma unroll
+        for (int j = 0; j < kCountMaxWords; ++j)
+            if (j < nwords && ballot(x[j] != 0)) acc[j] += __popcll(transpose64(x[j]));
     }
-    s_acc[threadIdx.x / kWave][lane] = acc;
-    __syncthreads();
-    if (threadIdx.x < kWave) {
-        int64_t t = 0;
-        for (int i = 0; i < kWavesPerBlock; ++i) t += s_acc[i][threadIdx.x];
-        if (t) atomicAdd((unsigned long long *)&counts_acc[w * kWave + threadIdx.x], (unsigned long long)t);
+#pragma unroll
+    for (int j = 0; j < kCountMaxWords; ++j) {
+        if (j >= nwords) break;
+        s_acc[threadIdx.x / kWave][lane] = acc[j];
+        __syncthreads();
+        if (threadIdx.x < kWave) {
+            int64_t t = 0;
+            for (int i = 0; i < kWavesPerBlock; ++i) t += s_acc[i][threadIdx.x];
+            if (t) atomicAdd((unsigned long long *)&counts_acc[(w0 + j) * kWave + threadIdx.x], (unsigned long long)t);
+        }
+        __syncthreads();
     }
 }
 
@@ -967,8 +1031,10 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
     auto count_words = [&](int w0, int nwords) {
         ProfScope ps(g, KK_BATCH_COUNT, st);
         const int cgx = (int)std::max<int64_t>(1, std::min<int64_t>((n + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock),
-                                                                     (int64_t)g->cu_count * 2));
-        hipLaunchKernelGGL(batch_count_kernel, dim3(cgx, nwords), dim3(kBlock), 0, st, V, n, Wr, w0, d_vmask, c->acc);
+                                                                     (int64_t)g->cu_count * 8));
+        for (int w = w0; w < w0 + nwords; w += kCountMaxWords)
+            hipLaunchKernelGGL(batch_count_kernel, dim3(cgx), dim3(kBlock), 0, st, V, n, Wr, w,
+                               std::min(kCountMaxWords, w0 + nwords - w), d_vmask, c->acc);
         ps.end(8.0 * n * nwords);
     };
     int r = rows - 1;  // the table row of the current level

@@ -564,6 +564,25 @@ __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const 
 
 // ------------------------------------------------------------------ bottom-up
 
+// Whether any of the in-edges x, x + 64, x + 128, x + 192 below end comes
+// from the frontier Fc.  The four index loads, then the four bitmap loads,
+// are made unconditionally (an edge past end reads edge safe, a valid index
+// whose result is dropped), so that no branch separates them and all four
+// are in flight at once.
+__device__ __forceinline__ bool any_hit4(const uint64_t *__restrict__ Fc, const int32_t *__restrict__ colidx,
+                                         int64_t x, int64_t end, int64_t safe) {
+    int32_t u[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) u[r] = colidx[x + r * kWave < end ? x + r * kWave : safe];
+    uint64_t w[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w[r] = Fc[(uint32_t)u[r] >> 6];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) any |= x + r * kWave < end && ((w[r] >> ((uint32_t)u[r] & 63u)) & 1ull);
+    return any;
+}
+
 // Each wave takes 64-vertex words in turn.  Every unvisited vertex of
 // in-degree up to g.heavy scans its first `light` in-edges alone (4 per
 // round); those with more edges and no hit yet have the rest scanned by the
@@ -630,12 +649,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
             bool hit = false;
             int64_t scanned = 0;
             for (int64_t x0 = hb; x0 < he; x0 += 4 * kWave) {
-                bool any = false;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t x = x0 + r * kWave + lane;
-                    if (x < he) any |= test_bit(Fc, g.in_colidx[x]);
-                }
+                const bool any = any_hit4(Fc, g.in_colidx, x0 + lane, he, hb);
                 scanned += std::min<int64_t>(4 * kWave, he - x0);
                 if (ballot(any)) {
                     hit = true;
@@ -683,12 +697,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
         const int64_t b = hc.begin[i], e = hc.end[i];
         bool hit = false;
         for (int64_t x0 = b; x0 < e; x0 += 4 * kWave) {
-            bool any = false;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t x = x0 + r * kWave + lane;
-                if (x < e) any |= test_bit(Fc, g.in_colidx[x]);
-            }
+            const bool any = any_hit4(Fc, g.in_colidx, x0 + lane, e, b);
             h_ex += std::min<int64_t>(4 * kWave, e - x0);
             if (ballot(any)) {
                 hit = true;

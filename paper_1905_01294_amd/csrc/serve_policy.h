@@ -36,7 +36,11 @@ struct ServeRequest {
 constexpr int kServeLanes = 2;        // batch lanes per graph
 constexpr int32_t kServeShortK = 2;   // queries with k up to this take lane 0
 constexpr int kRunsPerLane = 2;       // batched launches a lane may have in flight
-constexpr int64_t kIdleReleaseNs = 50'000'000;  // an idle slot keeps its context this long
+// An idle slot keeps its context this long (allocating and freeing a context
+// of gigabytes costs milliseconds and synchronises the device, so a slot
+// that is idle between launches at light load keeps it), unless another lane
+// waits for memory.
+constexpr int64_t kIdleReleaseNs = 2'000'000'000;
 constexpr int64_t kSweepNs = 1'000'000;         // queued requests are checked for deadlines this often
 
 inline int serve_lane_of(int32_t graph_id, int32_t k) {
