@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--only-bfs", action="store_true",
                     help="print only the breadth-first search, neighborhood-set and level measurements (one JSON "
                          "line, not the benchmark line)")
+    ap.add_argument("--step-only", action="store_true",
+                    help="run only the timed steps and their profiled replay (for profiling the step with rocprofv3)")
     ap.add_argument("--only-serving", action="store_true",
                     help="print only the serving measurements (one JSON line, not the benchmark line)")
     ap.add_argument("--no-twitter", action="store_true",
@@ -210,24 +212,29 @@ def main():
     b_ms = float(np.mean(batched_ms))
     legs["step_s"] = round(time.time() - t_bench - legs["load_and_tune_s"], 2)
 
+    if args.step_only:
+        for flag in ("no_cpu_baseline", "no_latency", "no_sweep", "no_serving", "no_bfs", "no_twitter"):
+            setattr(args, flag, True)
     # ---- the strictly sequential plain form: one launch sequence per query, each complete (count
     # written) before the next query's first launch, on the same device-resident queries
     t_leg = time.time()
-    g.set_option(K.KHOP_OPT_PLAIN_PIPELINE, 0)
-    plain_pass()
-    torch.cuda.synchronize()
-    seq_counts = torch.cat([dc for _, _, dc, _ in d_groups]).cpu().numpy()
-    ev[0].record(stream)
-    for _ in range(3):
+    s_ms, g0_leg = float("nan"), None
+    if not args.step_only:
+        g.set_option(K.KHOP_OPT_PLAIN_PIPELINE, 0)
         plain_pass()
-    ev[1].record(stream)
-    ev[1].synchronize()
-    g.set_option(K.KHOP_OPT_PLAIN_PIPELINE, 1)
-    s_ms = ev[0].elapsed_time(ev[1]) / 3
-    if not np.array_equal(seq_counts, plain_counts):
-        raise SystemExit("sequential plain counts differ from the pipelined ones")
-    log(f"sequential plain pass: {s_ms:.3f} ms ({nq / (s_ms / 1e3):.0f} queries/s)")
-    g0_leg = g0_bench(K, torch, cpu_leg=not args.no_cpu_baseline)
+        torch.cuda.synchronize()
+        seq_counts = torch.cat([dc for _, _, dc, _ in d_groups]).cpu().numpy()
+        ev[0].record(stream)
+        for _ in range(3):
+            plain_pass()
+        ev[1].record(stream)
+        ev[1].synchronize()
+        g.set_option(K.KHOP_OPT_PLAIN_PIPELINE, 1)
+        s_ms = ev[0].elapsed_time(ev[1]) / 3
+        if not np.array_equal(seq_counts, plain_counts):
+            raise SystemExit("sequential plain counts differ from the pipelined ones")
+        log(f"sequential plain pass: {s_ms:.3f} ms ({nq / (s_ms / 1e3):.0f} queries/s)")
+        g0_leg = g0_bench(K, torch, cpu_leg=not args.no_cpu_baseline)
     legs["sequential_and_g0_s"] = round(time.time() - t_leg, 2)
 
     # ---- profiled replay for the per-kernel roofline
@@ -253,8 +260,9 @@ def main():
         tr = traffic_per_launch(dom_name)
         copy_gbs = measure_copy_gbs(torch)
         # time-weighted aggregate over the traversal kernels
-        trav = [kv for name, kv in kernels.items()
-                if name in ("plain_hop", "plain_compact", "batch_pull", "batch_pull_heavy")]
+        trav_kinds = ("plain_step", "plain_hop_push", "plain_hop_pull", "plain_compact", "batch_pull",
+                      "batch_pull_heavy")
+        trav = [kv for name, kv in kernels.items() if name in trav_kinds]
         trav_s = sum(kv["avg_us"] * kv["launches"] for kv in trav) * 1e-6
         trav_gbs = sum(kv["algorithmic_bytes"] for kv in trav) / trav_s / 1e9 if trav_s > 0 else 0.0
         roofline = {"kernel": dom_name, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
@@ -264,16 +272,28 @@ def main():
                     "event_avg_launch_us": dom["event_avg_us"], "event_overhead_us": round(overhead_us, 3),
                     "algorithmic_bytes_per_launch": round(dom["algorithmic_bytes"] / dom["launches"], 1),
                     "copy_ceiling_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
-                    "traversal_aggregate": {"kernels": ["plain_hop", "plain_compact", "batch_pull",
-                                                        "batch_pull_heavy"],
+                    "traversal_aggregate": {"kernels": list(trav_kinds),
                                             "achieved": round(trav_gbs, 1),
                                             "frac": round(trav_gbs / HBM_PEAK_GBS, 4),
-                                            "frac_of_copy": round(trav_gbs / copy_gbs, 4)}}
+                                            "frac_of_copy": round(trav_gbs / copy_gbs, 4)},
+                    # the plain path's hops 2..k-1 (the levels that carry its bytes) and the batched
+                    # bottom-up kernels, each against the peak
+                    "by_role": {name: {"achieved": kernels[name]["gbs"],
+                                       "frac": round(kernels[name]["gbs"] / HBM_PEAK_GBS, 4),
+                                       "avg_launch_us": kernels[name]["avg_us"],
+                                       "launches": kernels[name]["launches"]}
+                                for name in ("plain_step", "plain_hop_push", "plain_hop_pull", "plain_compact",
+                                             "batch_pull", "batch_pull_heavy") if name in kernels}}
 
     # ---- per-query latency through the host entry point (PCIe round trip included)
     latency = None
     if not args.no_latency:
         latency = {}
+        # Python's cyclic garbage collector, not the library, can pause a call for tens of milliseconds
+        # in a process this size: it is run first and kept off while calls are timed
+        import gc
+        gc.collect()
+        gc.disable()
         for k, seeds in groups:
             lat = []
             for s in seeds:
@@ -284,6 +304,7 @@ def main():
             latency[f"k{k}"] = {"mean_ms": round(float(np.mean(lat)), 4), "p50_ms": round(pct(lat, 50), 4),
                                 "p99_ms": round(pct(lat, 99), 4), "max_ms": round(float(np.max(lat)), 4),
                                 "max_at": {"index": worst, "seed": int(seeds[worst])}, "n": len(lat)}
+        gc.enable()
 
     t_leg = time.time()
     sweep = None if args.no_sweep else batched_sweep(g, el, K, torch)
@@ -375,13 +396,14 @@ def main():
         "plain": {"form": "pipelined: queries in order, consecutive queries overlap by one launch",
                   "gteps": round(te_set / (p_ms / 1000.0) / 1e9, 3), "qps": round(nq / (p_ms / 1000.0), 1),
                   "ms_per_pass": round(p_ms, 3)},
-        "plain_sequential": {"form": "one launch sequence per query, each complete before the next starts",
-                             "gteps": round(te_set / (s_ms / 1000.0) / 1e9, 3),
-                             "qps": round(nq / (s_ms / 1000.0), 1), "ms_per_pass": round(s_ms, 3)},
+        "plain_sequential": None if args.step_only else {
+            "form": "one launch sequence per query, each complete before the next starts",
+            "gteps": round(te_set / (s_ms / 1000.0) / 1e9, 3), "qps": round(nq / (s_ms / 1000.0), 1),
+            "ms_per_pass": round(s_ms, 3)},
         "batched": {"gteps": round(te_set / (b_ms / 1000.0) / 1e9, 3), "qps": round(nq / (b_ms / 1000.0), 1),
                     "ms_per_pass": round(b_ms, 3), "seeds_per_launch": g.get_option(K.KHOP_OPT_BATCH_SEEDS)},
         "batched_vs_plain_qps": round(p_ms / b_ms, 3),
-        "batched_vs_plain_sequential_qps": round(s_ms / b_ms, 3),
+        "batched_vs_plain_sequential_qps": None if args.step_only else round(s_ms / b_ms, 3),
         "g0_plain": g0_leg,
         "tuning": tuning,
         "legs_seconds": legs,
@@ -463,7 +485,7 @@ def _source_sha(kernel):
 
 
 # GPU kernel name stem -> the kernel kind khop_profile reports it under
-KERNEL_KIND = {"plain_close": "plain_init", "plain_final": "plain_init", "plain_step": "plain_hop",
+KERNEL_KIND = {"plain_close": "plain_init", "plain_final": "plain_init", "plain_step": "plain_step",
                "batch_zero": "batch_init", "batch_narrow": "batch_init", "batch_push_seeds": "batch_push",
                "batch_row_count": "batch_push", "batch_seed": "batch_init", "batch_frontier_copy": "batch_init",
                "batch_output": "batch_count"}
@@ -494,10 +516,10 @@ def pmc_summary(d, copy_bytes=256 << 20):
 
 
 def traffic_per_launch(kernel):
-    """HBM bytes per launch of `kernel` from profiles/pmc_traffic.md, or None when absent or
+    """HBM bytes per launch of `kernel` from the step kernels PMC summary under profiles/, or None when absent or
     when the kernel's source changed after the counters were taken."""
     import re
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.md")
+    path = os.path.join(ROOT, "profiles", "step_kernels_rmat21_pmc_traffic.md")
     if not os.path.exists(path):
         return None
     m = re.search(r"```json\n(.*?)```", open(path).read(), re.S)
@@ -566,6 +588,24 @@ def power_law_bench(g2, el2, K, torch):
         tot_q += len(seeds)
     out["plain_protocol"] = {"queries": tot_q, "ms": round(tot_ms, 3), "qps": round(tot_q / (tot_ms / 1e3), 1),
                              "gteps": round(tot_te / (tot_ms / 1e3) / 1e9, 3)}
+    # per-kernel roles of the deep queries (k = 3 and 6), whose inner hops carry the bytes
+    d36 = torch.from_numpy(s10).to(dev)
+    c36 = torch.empty(10, dtype=torch.int64, device=dev)
+    g2.profile(True)
+    for k in (3, 6):
+        g2.count_dev(d36, k, c36)
+    torch.cuda.synchronize()
+    kern = g2.profile_read()
+    g2.profile(False)
+    empty = kern.pop("empty_launch", None)
+    overhead_us = 1000.0 * empty["total_ms"] / empty["launches"] if empty and empty["launches"] else 0.0
+    roles = {}
+    for name, kv in kern.items():
+        avg = max(1000.0 * kv["total_ms"] / max(kv["launches"], 1) - overhead_us, 0.0)
+        gbs = kv["algorithmic_bytes"] / kv["launches"] / (avg * 1e-6) / 1e9 if avg > 0 else 0.0
+        roles[name] = {"launches": kv["launches"], "avg_us": round(avg, 3), "achieved_gbs": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["plain_deep_roles"] = roles
     s256 = graphgen.draw_seeds(el2, 256, seed=13)
     d = torch.from_numpy(s256).to(dev)
     ks = torch.full((256,), 3, dtype=torch.int32, device=dev)
@@ -941,6 +981,9 @@ def serving_bench(K, graphs, seconds):
     log(f"serving {'+'.join(names)}: closed loop {sat:.0f} queries/s (batch lanes only: {sat_batch:.0f})")
     levels = []
     check = []
+    import gc
+    gc.collect()
+    gc.disable()  # a collector pause in the producer thread would delay arrivals
     for frac in (0.25, 0.5, 0.8):
         qps = frac * sat
         n = int(min(max(qps * seconds, 10000), 60000))  # at least 10^4 queries per level
@@ -997,6 +1040,7 @@ def serving_bench(K, graphs, seconds):
                                       for key, v in sorted(by_gk.items())}})
         log(f"serving {'+'.join(names)} at {qps:.0f} q/s offered: {levels[-1]['achieved_qps']:.0f} served, "
             f"p50 {levels[-1]['p50_ms']} ms, p99 {levels[-1]['p99_ms']} ms")
+    gc.enable()
     srv.close()
     # served counts against the plain path, query by query
     ok = 0

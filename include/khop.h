@@ -70,9 +70,10 @@ int graph_load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, in
  * Typed form of graph_load_csr: tuple i carries a relation type rel[i] in
  * [0, 64), and only the tuples whose type has its bit set in rel_mask are
  * kept.  The graph is the union of the selected relations' adjacency
- * matrices (the paper's storage model keeps one matrix per relation type,
- * Section II), so every count, search and server entry point traverses only
- * those relations.  rel is a host array of num_edges bytes.  Errors as
+ * matrices (a traversal over several relation types follows any of them), so
+ * every count, search and server entry point traverses only those
+ * relations: the typed form of a query plan's traversal, whose plans the
+ * paper turns into sparse-matrix operations (Section II).  rel is a host array of num_edges bytes.  Errors as
  * graph_load_csr, plus KHOP_EINVAL for rel NULL with num_edges > 0 or a type
  * of 64 or more; endpoints are checked on the kept tuples only.
  */
@@ -232,7 +233,8 @@ int khop_levels_dev(khop_graph *g, int32_t seed, int32_t k, int64_t *d_level_cou
 
 /*
  * The k-hop neighborhood itself, { v : 1 <= dist(seed, v) <= k }, as
- * ascending vertex ids (the result set a graph query returns, Section III;
+ * ascending vertex ids (the result set a graph query returns; large result
+ * sets are among the costs the paper's Section IV names;
  * k < 0: everything the seed reaches).  The first min(count, capacity) ids go
  * to ids (host, capacity int32), and *count receives the full size, so a
  * caller with too small a buffer learns the size it needs.  Errors: seed

@@ -25,8 +25,8 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line) {
 }
 
 const char *const kKernelNames[KK_COUNT_KINDS] = {
-    "plain_init", "plain_hop", "plain_compact", "batch_init", "batch_push", "batch_pull", "batch_pull_heavy",
-    "batch_count", "plain_set", "empty_launch"};
+    "plain_init", "plain_step", "plain_hop_push", "plain_hop_pull", "plain_compact", "batch_init", "batch_push",
+    "batch_pull", "batch_pull_heavy", "batch_count", "plain_set", "empty_launch"};
 
 template <class F>
 static int guard(F &&f) {
@@ -104,8 +104,17 @@ void ProfScope::end(double fixed_bytes, double w0, double w1, double w2, double 
     hipEvent_t e1 = P.events.back();
     P.events.pop_back();
     KHOP_HIP(hipEventRecord(e1, st_));
-    P.pending.push_back({kind_, e0_, e1, fixed_bytes, slot_, {w0, w1, w2, w3}});
+    P.pending.push_back({kind_, e0_, e1, fixed_bytes, slot_, {w0, w1, w2, w3}, -1, 0});
     e0_ = nullptr;
+}
+
+void ProfScope::end_split(double fixed_bytes, double w0, int alt_kind, int alt_field) {
+    if (!e0_) return;
+    end(fixed_bytes, w0);
+    std::lock_guard<std::mutex> lk(g_->prof_mu);
+    Profiler::Pending &p = g_->prof.pending.back();
+    p.alt_kind = alt_kind;
+    p.alt_field = alt_field;
 }
 
 // Waits for every pending profiled launch and folds it into the totals.
@@ -122,15 +131,16 @@ void prof_collect(khop_graph *g) {
         float ms = 0;
         KHOP_HIP(hipEventElapsedTime(&ms, p.e0, p.e1));
         double bytes = p.fixed_bytes;
+        int64_t field[4] = {0, 0, 0, 0};
         if (p.slot >= 0)
             for (int i = 0; i < 4; ++i) {
-                int64_t f = 0;
-                for (int l = 0; l < kLanes; ++l) f += units[((size_t)p.slot * 4 + i) * kLanes + l];
-                bytes += p.w[i] * (double)f;
+                for (int l = 0; l < kLanes; ++l) field[i] += units[((size_t)p.slot * 4 + i) * kLanes + l];
+                bytes += p.w[i] * (double)field[i];
             }
-        P.launches[p.kind] += 1;
-        P.ms[p.kind] += ms;
-        P.bytes[p.kind] += bytes;
+        const int kind = (p.alt_kind >= 0 && field[p.alt_field] != 0) ? p.alt_kind : p.kind;
+        P.launches[kind] += 1;
+        P.ms[kind] += ms;
+        P.bytes[kind] += bytes;
         P.events.push_back(p.e0);
         P.events.push_back(p.e1);
     }

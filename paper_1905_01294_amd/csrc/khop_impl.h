@@ -80,7 +80,9 @@ struct CtxUse {
 
 enum KernelKind {
     KK_PLAIN_INIT = 0,
-    KK_PLAIN_HOP,
+    KK_PLAIN_STEP,      // a step launch of the plain pipeline: a query's hop 1 beside the last hop of the one before
+    KK_PLAIN_HOP_PUSH,  // a hop 2..k-1 (or of a search) that went top-down, or found an empty frontier
+    KK_PLAIN_HOP_PULL,  // a hop 2..k-1 (or of a search) that went bottom-up
     KK_PLAIN_COMPACT,
     KK_BATCH_INIT,
     KK_BATCH_PUSH,
@@ -108,6 +110,8 @@ struct Profiler {
         double fixed_bytes;
         int64_t slot;
         double w[4];
+        int alt_kind;   // counted under this kind instead when counter field alt_field is nonzero (-1: never)
+        int alt_field;
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> events;
@@ -124,6 +128,9 @@ class ProfScope {
     int64_t *units() const { return units_; }
     // bytes = fixed + sum_i w[i] * units[i]
     void end(double fixed_bytes, double w0 = 0, double w1 = 0, double w2 = 0, double w3 = 0);
+    // As end(fixed_bytes, w0), but the launch counts under alt_kind when the
+    // kernel set counter field alt_field (a role it chose on the device).
+    void end_split(double fixed_bytes, double w0, int alt_kind, int alt_field);
 
    private:
     khop_graph *g_;

@@ -960,6 +960,7 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
         ctl->te_acc += E;
         if (units) unit_add(units, 0, 16 * s.nreg);
     }
+    if (mode == MODE_PULL && pt.bid == 0 && t == 0) unit_add(units, 1, 1);  // the launch's role, for profiling
     if (mode == MODE_IDLE) return;  // empty frontier: nothing left to find
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
     int64_t found = 0;  // final bottom-up hop: discoveries of this wave
@@ -1445,7 +1446,7 @@ static void plain_deep(khop_graph *g, PlainCtx *c, const Params &P, const Graph 
         while (H < k) {
             const int64_t upto = std::min(k, H + group);
             for (int64_t L = H + 1; L <= upto; ++L) {
-                ProfScope ps(g, KK_PLAIN_HOP, st);
+                ProfScope ps(g, L == 1 ? KK_PLAIN_STEP : KK_PLAIN_HOP_PUSH, st);
                 if (L == 1) {
                     const StepBook bk{nullptr, nullptr, nullptr, -1, nullptr, nullptr, nullptr, pam, g->nnz,
                                       INT32_MAX, (int32_t)P.dir_mode, (int32_t)P.alpha, (int32_t)P.beta};
@@ -1457,7 +1458,7 @@ static void plain_deep(khop_graph *g, PlainCtx *c, const Params &P, const Graph 
                 }
                 hipLaunchKernelGGL(plain_hop_kernel, dim3(gd.hop), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
                                    P.pull_light, hc, ps.units());
-                ps.end(0, 1);
+                ps.end_split(0, 1, KK_PLAIN_HOP_PULL, 1);
                 ProfScope pc(g, KK_PLAIN_COMPACT, st);
                 hipLaunchKernelGGL(plain_compact_kernel, dim3(gd.compact), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
                                    pc.units());
@@ -1536,7 +1537,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         const int64_t nb_last = ps_j.last >= 0 ? gd.hop : 0, nb_h1 = ps_j.h1 >= 0 ? h1_grid : 0;
         const int64_t nb_book = (qm >= 0 || qn >= 0) ? c->init_grid : 0;
         {
-            ProfScope ps(pg, KK_PLAIN_HOP, st);
+            ProfScope ps(pg, KK_PLAIN_STEP, st);
             hipLaunchKernelGGL(plain_step_kernel, dim3((unsigned)(nb_last + nb_h1 + nb_book)), dim3(kBlock), 0, st,
                                ps_j.last >= 0 ? slot(ps_j.last) : nullptr,
                                ps_j.last >= 0 ? state(ps_j.last) : State{}, nb_last,
@@ -1550,10 +1551,10 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
         const State sq = state(ps_j.h1);
         for (int L = 2; L < k; ++L) {
             {
-                ProfScope ps(pg, KK_PLAIN_HOP, st);
+                ProfScope ps(pg, KK_PLAIN_HOP_PUSH, st);
                 hipLaunchKernelGGL(plain_hop_kernel, dim3(gd.hop), dim3(kBlock), 0, st, cq, L, gr, sq,
                                    P.pull_light, hc, ps.units());
-                ps.end(0, 1);
+                ps.end_split(0, 1, KK_PLAIN_HOP_PULL, 1);
             }
             ProfScope ps(pg, KK_PLAIN_COMPACT, st);
             hipLaunchKernelGGL(plain_compact_kernel, dim3(gd.compact), dim3(kBlock), 0, st, cq, L, gr, sq,
@@ -1599,7 +1600,7 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
     while (H < limit) {
         const int64_t upto = h_flags ? std::min(limit, H + group) : limit;
         for (int64_t L = H + 1; L <= upto; ++L) {
-            ProfScope ps(g, KK_PLAIN_HOP, st);
+            ProfScope ps(g, L == 1 ? KK_PLAIN_STEP : KK_PLAIN_HOP_PUSH, st);
             if (L == 1) {
                 // hop 1 alone: the set-up above replaces the pipeline's other work
                 const StepBook bk{nullptr, nullptr, nullptr, -1, nullptr, nullptr, nullptr, pam, g->nnz, INT32_MAX,
@@ -1612,7 +1613,7 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
             }
             hipLaunchKernelGGL(plain_hop_kernel, dim3(gd.hop), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
                                P.pull_light, hc, ps.units());
-            ps.end(0, 1);
+            ps.end_split(0, 1, KK_PLAIN_HOP_PULL, 1);
             ProfScope pc(g, KK_PLAIN_COMPACT, st);
             hipLaunchKernelGGL(plain_compact_kernel, dim3(gd.compact), dim3(kBlock), 0, st, ctl, (int)L, gr, s,
                                pc.units());

@@ -251,10 +251,22 @@ def test_profile_reports_kernels_and_event_cost(K, g0, g0_gpu, g0_oracle):
     assert np.array_equal(b, g0_oracle.count(seeds, 3)[0])
     assert stats["empty_launch"]["launches"] == 16
     assert stats["empty_launch"]["algorithmic_bytes"] == 0
-    assert stats["plain_hop"]["launches"] == 2 * 16  # hop 1 and hop 2 of each query
-    assert stats["plain_hop"]["algorithmic_bytes"] > 0 and stats["plain_hop"]["total_ms"] > 0
+    # one query per call: hop 1 in one step launch, the last hop in the next
+    assert stats["plain_step"]["launches"] == 2 * 16
+    assert stats["plain_step"]["algorithmic_bytes"] > 0 and stats["plain_step"]["total_ms"] > 0
+    assert "plain_hop_push" not in stats and "plain_hop_pull" not in stats
     assert stats["batch_pull"]["launches"] >= 2 and stats["batch_pull"]["algorithmic_bytes"] > 0
     assert "batch_count" in stats and "batch_push" in stats
+    # k = 3: hop 2 runs on its own, counted by the direction it took; forced bottom-up, all pull
+    for mode, kind in ((K.KHOP_DIR_PUSH, "plain_hop_push"), (K.KHOP_DIR_PULL, "plain_hop_pull")):
+        g0_gpu.set_option(K.KHOP_OPT_DIRECTION, mode)
+        g0_gpu.profile(True)
+        c3 = g0_gpu.count(seeds, 3)
+        s3 = g0_gpu.profile_read()
+        g0_gpu.profile(False)
+        g0_gpu.set_option(K.KHOP_OPT_DIRECTION, K.KHOP_DIR_AUTO)
+        assert np.array_equal(c3, g0_oracle.count(seeds, 3)[0])
+        assert s3[kind]["launches"] == 16 and s3["plain_compact"]["launches"] == 16
 
 
 @pytest.mark.parametrize("mode", MODES)

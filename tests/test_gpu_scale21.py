@@ -65,23 +65,36 @@ def test_plain_10_seeds(g1, k):
     assert np.array_equal(te, ote)
 
 
+_ORACLE = {}
+
+
+def _oracle_counts(og, seeds, k):
+    """Oracle counts and traversed edges of the protocol seeds, computed once per (seeds, k)."""
+    key = (seeds.tobytes(), k)
+    if key not in _ORACLE:
+        _ORACLE[key] = og.count(seeds, k)
+    return _ORACLE[key]
+
+
 @pytest.mark.parametrize("mode", ["push", "pull"])
-def test_forced_directions_equal_auto(g1, mode):
+@pytest.mark.parametrize("k", [1, 2, 3, 6])
+def test_forced_directions_match_oracle(g1, mode, k):
+    """Every hop top-down, or every hop bottom-up, on the ten deep protocol seeds: counts and traversed
+    edges equal the oracle's at each protocol depth."""
     el, og, g, s12, s36, K = g1
+    oc, ote = _oracle_counts(og, s36, k)
     g.set_option(K.KHOP_OPT_DIRECTION, K.KHOP_DIR_PUSH if mode == "push" else K.KHOP_DIR_PULL)
     try:
-        for k in (1, 2, 3):
-            c = g.count(s36, k)
-            g.set_option(K.KHOP_OPT_DIRECTION, K.KHOP_DIR_AUTO)
-            a = g.count(s36, k)
-            g.set_option(K.KHOP_OPT_DIRECTION, K.KHOP_DIR_PUSH if mode == "push" else K.KHOP_DIR_PULL)
-            assert np.array_equal(c, a), k
+        c, te = g.count(s36, k, with_te=True)
     finally:
         g.set_option(K.KHOP_OPT_DIRECTION, K.KHOP_DIR_AUTO)
+    assert np.array_equal(c, oc) and np.array_equal(te, ote)
 
 
 @pytest.mark.parametrize("per", [64, 256, 1024])
 def test_batched_1024_seeds(g1, per):
+    """All 1024 seeds at k = 3 and 6, at 64, 256 and 1024 seeds per launch: every count equals the plain
+    path's, and a sample equals the oracle's at both depths."""
     el, og, g, s12, s36, K = g1
     seeds = graphgen.draw_seeds(el, 1024, seed=11)
     g.set_option(K.KHOP_OPT_BATCH_SEEDS, per)
@@ -90,10 +103,9 @@ def test_batched_1024_seeds(g1, per):
             t = time.time()
             b = g.count_batched(seeds, np.full(len(seeds), k))
             _say("batched", per, "k", k, round(time.time() - t, 3), "s")
-            p = g.count(seeds[:64], k)
-            assert np.array_equal(b[:64], p)
-        sample = seeds[:2]
-        assert np.array_equal(g.count_batched(sample, [3, 3]), og.count(sample, 3)[0])
+            assert np.array_equal(b, g.count(seeds, k))
+            sample = seeds[::341]  # seeds 0, 341, 682, 1023: one in each quarter of the launch's words
+            assert np.array_equal(b[::341], _oracle_counts(og, sample, k)[0])
     finally:
         g.set_option(K.KHOP_OPT_BATCH_SEEDS, 1024)
 
