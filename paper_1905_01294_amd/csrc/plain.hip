@@ -167,8 +167,9 @@ __device__ __forceinline__ void append_one(const State &s, RegRec *regs, int L, 
 // returning atomic per region instead of one per word.
 constexpr int kBufCap = 512;
 struct WaveBuf {
-    int64_t *v;    // LDS, kBufCap row begins of the buffered vertices
+    int64_t *v;    // LDS, cap row begins of the buffered vertices
     int32_t *d;    // their out-degrees
+    int cap;       // entries the buffer holds (at least 64)
     int cnt;       // buffered entries (wave-uniform)
     int reg;       // region of the buffered entries, -1 if none
     int64_t nf;    // discovered in that region (all, wave-uniform)
@@ -214,7 +215,7 @@ __device__ __forceinline__ void wb_word(WaveBuf &b, const State &s, RegRec *regs
     const bool qd = found && od > 0;
     const uint64_t qm = ballot(qd);
     const int nq = __popcll(qm);
-    if (r != b.reg || b.cnt + nq > kBufCap) {
+    if (r != b.reg || b.cnt + nq > b.cap) {
         wb_flush(b, s, regs, L);
         b.reg = r;
     }
@@ -428,10 +429,11 @@ __device__ __forceinline__ void push_edge(int L, int mode, const Graph &g, const
     }
 }
 
-constexpr int kWin = 4;  // windows of 64 frontier edges in flight per wave (short queues)
+constexpr int kWin = 4;  // windows of 64 frontier edges in flight per wave
 
 __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const int32_t *qcnt, const Graph &g,
-                         const State &s, RegRec *cur, uint64_t *smask, int64_t *units, const Part &pt) {
+                         const State &s, RegRec *cur, uint64_t *smask, int64_t *ent, int64_t *units,
+                         const Part &pt) {
     const int lane = lane_id();
     const int64_t nwaves = pt.nb * kWavesPerBlock;
     const int64_t wid = pt.bid * kWavesPerBlock + threadIdx.x / kWave;
@@ -520,41 +522,69 @@ __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const 
             lo += __popcll(ballot(less));
         }
         int64_t base = lo;
-        int64_t carry_beg = 0, carry_off = 0;
+        int64_t carry_beg = 0, carry_off = 0;  // the entry whose list holds the edge before the window
         if (base > 0) {
             carry_beg = qb[base - 1];
             carry_off = qoff[base - 1];
         }
-        for (int64_t b = a0; b < a1; b += kWave) {
-            const int64_t j = base + lane;
-            bool inwin = false;
-            int64_t offj = 0, begj = 0;
-            if (j < qlen) {
-                offj = qoff[j];
-                begj = qb[j];
-                inwin = offj < b + kWave;
+        // kWin windows of 64 edges at a time.  Their lists start at most
+        // kWin * 64 times, so entries base .. base + kWin*64 - 1 (staged in
+        // LDS: row begins in ent[0..255], offsets in ent[256..511]) own every
+        // edge of them; bit i of smask[r] marks a list starting at edge
+        // b + 64r + i.  The column-index loads of all the windows are then
+        // issued together.
+        int64_t *const eb = ent, *const eo = ent + kWin * kWave;
+        for (int64_t b = a0; b < a1; b += kWin * kWave) {
+#pragma unroll
+            for (int i = 0; i < kWin; ++i) {
+                const int64_t j = base + lane + (int64_t)i * kWave;
+                eo[lane + i * kWave] = j < qlen ? qoff[j] : INT64_MAX;
+                eb[lane + i * kWave] = j < qlen ? qb[j] : 0;
             }
-            if (lane == 0) *smask = 0;
+            if (lane < kWin) smask[lane] = 0;
             __builtin_amdgcn_wave_barrier();
-            if (inwin) atomicOr((unsigned long long *)smask, 1ull << (offj - b));
+#pragma unroll
+            for (int i = 0; i < kWin; ++i) {
+                const int64_t o = eo[lane + i * kWave] - b;  // >= 0: the entries start at or after b
+                if (o < kWin * kWave) atomicOr((unsigned long long *)&smask[o >> 6], 1ull << (o & 63));
+            }
             __builtin_amdgcn_wave_barrier();
-            const uint64_t starts = *smask;
-            const int ns = __popcll(ballot(inwin));
-            const int c = __popcll(starts & le);
-            const int src = c > 0 ? c - 1 : 0;
-            const int64_t sb = shfl64(begj, src), so = shfl64(offj, src);
-            const int64_t e = b + lane;
-            if (e < a1) {
-                const int64_t beg = c ? sb : carry_beg;
-                const int64_t off = c ? so : carry_off;
-                push_edge(L, mode, g, s, cur, Fn, g.colidx[beg + (e - off)]);
+            int64_t at[kWin];
+            int before = 0;  // staged entries starting before window r
+#pragma unroll
+            for (int r = 0; r < kWin; ++r) {
+                const uint64_t sm = smask[r];
+                const int c = __popcll(sm & le);
+                const int idx = before + c - 1;  // staged entry of edge b + 64r + lane, -1: the carry
+                const int64_t ob = idx >= 0 ? eb[idx] : carry_beg, oo = idx >= 0 ? eo[idx] : carry_off;
+                const int64_t br = b + (int64_t)r * kWave, e = br + lane;
+                at[r] = e < a1 ? ob + (e - oo) : -1;
+                if (br < a1) {
+                    before += __popcll(sm);
+                    // lists starting in this wave's range (a1 may cut the window)
+                    starts_seen += __popcll(a1 - br >= kWave ? sm : sm & ((1ull << (a1 - br)) - 1));
+                }
             }
-            if (ns > 0) {
-                carry_beg = shfl64(begj, ns - 1);
-                carry_off = shfl64(offj, ns - 1);
+            int32_t v[kWin];
+#pragma unroll
+            for (int r = 0; r < kWin; ++r) v[r] = at[r] >= 0 ? g.colidx[at[r]] : -1;
+            if (mode == MODE_PUSH_BYTES) {
+#pragma unroll
+                for (int r = 0; r < kWin; ++r)
+                    if (v[r] >= 0) mark(s, v[r]);
+            } else {
+                uint64_t vw[kWin];
+#pragma unroll
+                for (int r = 0; r < kWin; ++r) vw[r] = v[r] >= 0 ? s.V[v[r] >> 6] : ~0ull;
+#pragma unroll
+                for (int r = 0; r < kWin; ++r)
+                    if (!((vw[r] >> (v[r] & 63)) & 1ull)) push_claim(L, g, s, cur, Fn, v[r]);
             }
-            base += ns;
-            starts_seen += ns;
+            if (before > 0) {
+                carry_beg = eb[before - 1];
+                carry_off = eo[before - 1];
+            }
+            base += before;
             __builtin_amdgcn_wave_barrier();
         }
     }
@@ -964,14 +994,16 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
     if (mode == MODE_IDLE) return;  // empty frontier: nothing left to find
     RegRec *cur = s.regs + (int64_t)(L % 3) * s.nreg;
     int64_t found = 0;  // final bottom-up hop: discoveries of this wave
+    // a bottom-up hop's discovery buffers, or a top-down hop's staged queue entries
+    __shared__ int64_t s_bv[kWavesPerBlock][kBufCap];
+    static_assert(kBufCap >= 2 * kWin * kWave, "staged queue entries fit the buffer");
     if (mode == MODE_PULL) {
-        __shared__ int64_t s_bv[kWavesPerBlock][kBufCap];
         __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
-        WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
+        WaveBuf wb{s_bv[wv], s_bd[wv], kBufCap, 0, -1, 0, 0};
         pull_hop(L, last, g, s, light, hc, cur, wb, &found, units, pt);
         found = shfl64(found, 0);
     } else {
-        push_hop(L, mode, E, s_epre, s_qcnt, g, s, cur, s_mask[wv], units, pt);
+        push_hop(L, mode, E, s_epre, s_qcnt, g, s, cur, s_mask[wv], s_bv[wv], units, pt);
     }
     if (last && lane == 0) add_tail(ctl, wid, found);
 }
@@ -1055,7 +1087,13 @@ __global__ void __launch_bounds__(kBlock) plain_hop_kernel(PlainCtl *ctl, int L,
 
 // After a byte-mode push: ballot(mark AND NOT visited) per 64-vertex word is
 // the word's new frontier bits; visited |= them, marks cleared, and the word's
-// discoveries appended to its region's queue.
+// discoveries appended to its region's queue.  Each wave takes a contiguous
+// run of words: their summary bytes in one load (one word per lane), then the
+// marked words four at a time, whose marks and visited words are loaded
+// together, then the row pointers of all their new vertices together.  The
+// grid is what the device holds at once (its small discovery buffers let
+// eight blocks share a compute unit), so every wave works from the start.
+constexpr int kCompactBuf = 256;
 __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *ctl, int L, Graph g, State s,
                                                               int64_t *units) {
     if (!ctl->valid || ctl->hdr[L % 3].mode != MODE_PUSH_BYTES) return;
@@ -1065,54 +1103,65 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     const int64_t wid = (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     if (units && wid == 0 && lane == 0) unit_add(units, 0, g.nw);  // the summary bytes
-    __shared__ int64_t s_bv[kWavesPerBlock][kBufCap];
-    __shared__ int32_t s_bd[kWavesPerBlock][kBufCap];
+    __shared__ int64_t s_bv[kWavesPerBlock][kCompactBuf];
+    __shared__ int32_t s_bd[kWavesPerBlock][kCompactBuf];
     const int wv = threadIdx.x / kWave;
-    WaveBuf wb{s_bv[wv], s_bd[wv], 0, -1, 0, 0};
+    WaveBuf wb{s_bv[wv], s_bd[wv], kCompactBuf, 0, -1, 0, 0};
     const int64_t wpw = (g.nw + nwaves - 1) / nwaves;
     const int64_t wb0 = std::min(wid * wpw, g.nw), wb1 = std::min(wb0 + wpw, g.nw);
     int64_t found_total = 0;
-    // four words per round: their marks and visited words are loaded before any is used
-    for (int64_t w0 = wb0; w0 < wb1; w0 += 4) {
-        uint8_t nb[4], sm[4];
+    for (int64_t c0 = wb0; c0 < wb1; c0 += kWave) {
+        const int64_t wl = c0 + lane;
+        const bool flagged = wl < wb1 && s.nsum[wl];
+        uint64_t pend = ballot(flagged);
+        if (flagged) s.nsum[wl] = 0;
+        // the word's marks, visited and frontier words
+        if (lane == 0 && pend) unit_add(units, 0, 80 * (int64_t)__popcll(pend));
+        while (pend) {
+            int64_t w[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) sm[i] = w0 + i < wb1 ? s.nsum[w0 + i] : 0;
-        if (!(sm[0] | sm[1] | sm[2] | sm[3])) continue;  // no marks in these words
-        uint64_t vis[4];
+            for (int i = 0; i < 4; ++i) {
+                w[i] = pend ? c0 + __builtin_ctzll(pend) : -1;
+                pend &= pend - 1;
+            }
+            uint8_t nb[4];
+            uint64_t vis[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t v = (w0 + i) * kWave + lane;
-            nb[i] = (sm[i] && v < g.n) ? s.nextb[v] : 0;
-        }
+            for (int i = 0; i < 4; ++i) {
+                const int64_t v = w[i] * kWave + lane;
+                nb[i] = (w[i] >= 0 && v < g.n) ? s.nextb[v] : 0;
+                vis[i] = w[i] >= 0 ? s.V[w[i]] : ~0ull;
+            }
+            bool fresh[4];
+            int64_t vb[4], od[4], id[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (sm[i] && lane == 0) {
-                s.nsum[w0 + i] = 0;
-                unit_add(units, 0, 80);  // the word's marks, visited and frontier words
+            for (int i = 0; i < 4; ++i) {
+                const int64_t v = w[i] * kWave + lane;
+                fresh[i] = nb[i] && !((vis[i] >> lane) & 1ull);
+                vb[i] = 0;
+                od[i] = 0;
+                id[i] = 0;
+                if (fresh[i]) {
+                    vb[i] = g.rowptr[v];
+                    od[i] = g.rowptr[v + 1];
+                    id[i] = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : 0;
+                }
             }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) vis[i] = ballot(nb[i]) ? s.V[w0 + i] : 0ull;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t w = w0 + i;
-            if (!ballot(nb[i])) continue;
-            const int64_t v = w * kWave + lane;
-            const bool fresh = nb[i] && !((vis[i] >> lane) & 1ull);
-            const uint64_t m = ballot(fresh);
-            if (nb[i]) s.nextb[v] = 0;
-            if (fresh && s.dist) s.dist[v] = L;
-            if (lane == 0 && m) {
-                s.V[w] = vis[i] | m;
-                Fn[w] = m;
+            for (int i = 0; i < 4; ++i) {
+                if (w[i] < 0) break;  // uniform
+                const int64_t v = w[i] * kWave + lane;
+                const uint64_t m = ballot(fresh[i]);
+                if (nb[i]) s.nextb[v] = 0;
+                if (fresh[i] && s.dist) s.dist[v] = L;
+                if (lane == 0 && m) {
+                    s.V[w[i]] = vis[i] | m;
+                    Fn[w[i]] = m;
+                }
+                const int64_t d = od[i] - vb[i];
+                wb_word(wb, s, cur, L, w[i], fresh[i], vb[i], d, g.directed ? id[i] : d);
+                found_total += __popcll(m);
             }
-            int64_t vb = 0, od = 0, id = 0;
-            if (fresh) {
-                vb = g.rowptr[v];
-                od = g.rowptr[v + 1] - vb;
-                id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
-            }
-            wb_word(wb, s, cur, L, w, fresh, vb, od, id);
-            found_total += __popcll(m);
         }
     }
     wb_flush(wb, s, cur, L);
@@ -1315,8 +1364,9 @@ struct Grids {
 };
 Grids grids(const khop_graph *g, const Params &P) {
     const int64_t nw = (g->n + 63) / 64, cap = (int64_t)g->cu_count * P.plain_grid;
+    // compaction: eight words per wave, up to eight blocks per compute unit
     return Grids{(int)std::max<int64_t>(1, std::min<int64_t>((nw + 7) / 8, cap)),
-                 (int)std::max<int64_t>(1, std::min<int64_t>((nw + 15) / 16, cap))};
+                 (int)std::max<int64_t>(1, std::min<int64_t>((nw + 31) / 32, (int64_t)g->cu_count * 8))};
 }
 
 }  // namespace

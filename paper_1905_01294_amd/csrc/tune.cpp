@@ -4,8 +4,8 @@
 // Plain path: coordinate descent (two sweeps) over the push->pull threshold
 // alpha, the pull->push threshold beta, the lane-serial bottom-up degree, the
 // chunked bottom-up degree, the atomic top-down edge limit and the hop
-// kernels' blocks per compute unit, timing queries at k = 2 and 3 from sample
-// seeds.  Batched path: seeds per launch and the heavy-vertex threshold
+// kernels' blocks per compute unit, timing queries at k = 2 and 3 from 48
+// sample seeds and at k = 6 from four of them.  Batched path: seeds per launch and the heavy-vertex threshold
 // (jointly), then the top-down/bottom-up switch and the bottom-up kernel's
 // blocks per compute unit, timing a batch of mixed k (2, 3, 3, 6).  Results
 // are cached per (library sources, device architecture, graph content hash,
@@ -133,9 +133,13 @@ struct Bench {
     khop::PlainCtx *pc;
 };
 
-float time_plain(Bench &b, int n_seeds) {
+// Queries at k = 2 and 3 from n_seeds sample seeds, and at k = 6 from the
+// first n_deep of them (deep queries expand the large frontiers that the hop
+// and compaction grids are sized for).
+float time_plain(Bench &b, int n_seeds, int n_deep) {
     KHOP_HIP(hipEventRecord(b.e0, b.st));
     for (int k : {2, 3}) khop::plain_run(b.g, b.pc, b.d_seeds, n_seeds, k, b.d_counts, b.d_te, b.st);
+    khop::plain_run(b.g, b.pc, b.d_seeds, n_deep, 6, b.d_counts, b.d_te, b.st);
     KHOP_HIP(hipEventRecord(b.e1, b.st));
     KHOP_HIP(hipEventSynchronize(b.e1));
     float ms = 0;
@@ -200,7 +204,7 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         }
         timespec t_start;
         clock_gettime(CLOCK_MONOTONIC, &t_start);
-        const int plain_seeds = 48, batch_seeds = 1024;
+        const int plain_seeds = 48, deep_seeds = 4, batch_seeds = 1024;
         std::vector<int32_t> seeds = sample_seeds(g, batch_seeds);
         if (seeds.empty()) return KHOP_OK;  // no edges: nothing to tune
         Bench b{g, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, g->n, nullptr};
@@ -241,10 +245,10 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         // ---- plain path: coordinate descent
         auto plain_cost = [&] {
             install();
-            return best_of([&] { return time_plain(b, plain_seeds); }, 2);
+            return best_of([&] { return time_plain(b, plain_seeds, deep_seeds); }, 2);
         };
         install();
-        time_plain(b, plain_seeds);  // warm-up (contexts, chunk tables)
+        time_plain(b, plain_seeds, deep_seeds);  // warm-up (contexts, chunk tables)
         struct Knob {
             int *field;
             std::vector<int> values;

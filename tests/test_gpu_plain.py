@@ -204,6 +204,31 @@ def test_directed_power_law_small(K, heavy):
     g.free()
 
 
+@pytest.mark.parametrize("grid", [1, 16])
+@pytest.mark.parametrize("pam", [0, 2**31 - 1])
+def test_top_down_queues_split_over_waves(K, grid, pam):
+    """Forced top-down hops over region queues longer than a wave, whose edges are split between few
+    (one block per compute unit) or many waves at arbitrary points, with heads claimed by byte marks
+    and compaction (pam 0) or by atomics only: counts, traversed edges and BFS distances equal the
+    oracle's."""
+    el = graphgen.chung_lu(60_000, 900_000, 6.0, seed=8)
+    g = K.Graph.from_edgelist(el)
+    og = oracle.OracleGraph.from_edgelist(el)
+    g.set_option(K.KHOP_OPT_PLAIN_GRID, grid)
+    g.set_option(K.KHOP_OPT_PUSH_ATOMIC, pam)
+    _set_mode(K, g, "push")
+    seeds = graphgen.draw_seeds(el, 24, seed=2)
+    for k in KS:
+        _say("chung-lu 60k push windows, grid", grid, "pam", pam, "k", k)
+        c, te = g.count(seeds, k, with_te=True)
+        oc, ote = og.count(seeds, k)
+        assert np.array_equal(c, oc) and np.array_equal(te, ote), k
+    for s in seeds[:3]:
+        dist, count, depth = g.bfs(int(s), -1)
+        assert np.array_equal(dist, og.distances(int(s), 2**31 - 1))
+    g.free()
+
+
 @pytest.mark.parametrize("heavy", [1, 4, 64, 128])
 def test_g0_pull_heavy_chunks(K, g0, g0_oracle, heavy):
     """Low chunk thresholds send many scale-10 vertices through the chunk kernel."""
