@@ -613,16 +613,21 @@ __device__ __forceinline__ bool any_hit4(const uint64_t *__restrict__ Fc, const 
     return any;
 }
 
-// Each wave takes 64-vertex words in turn.  Every unvisited vertex of
-// in-degree up to g.heavy scans its first `light` in-edges alone (4 per
-// round); those with more edges and no hit yet have the rest scanned by the
-// whole wave, 256 in-edges per round; heavier vertices come from the chunk
-// table after the words.
+// Each wave takes its run of 64-vertex words two at a time.  Every unvisited
+// vertex of in-degree up to g.heavy scans its first `light` in-edges alone,
+// four per round, the rounds of a lane's two vertices issued together (an
+// edge past the scan reads in-edge 0 and is ignored), so that a round's eight
+// index loads, then its eight bitmap loads, are in flight at once; those with
+// more edges and no hit yet have the rest scanned by the whole wave, 256
+// in-edges per round; heavier vertices come from the chunk table after the
+// words.
+constexpr int kPullWords = 1;
 __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int light, const HeavyChunks &hc,
                          RegRec *cur, WaveBuf &wb, int64_t *found_out, int64_t *units, const Part &pt) {
     const int lane = lane_id();
     light = std::min(light, g.heavy);  // the chunk table alone takes vertices above g.heavy
     const uint64_t *__restrict__ Fc = s.F[(L - 1) % 3];
+    const int32_t *__restrict__ icol = g.in_colidx;
     uint64_t *Fn = s.F[L % 3];
     const int64_t nwaves = pt.nb * kWavesPerBlock;
     const int64_t wid = pt.bid * kWavesPerBlock + threadIdx.x / kWave;
@@ -630,90 +635,123 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
     // a contiguous run of words per wave keeps its discoveries in one or two regions
     const int64_t wpw = (g.nw + nwaves - 1) / nwaves;
     const int64_t wb0 = std::min(wid * wpw, g.nw), wb1 = std::min(wb0 + wpw, g.nw);
-    for (int64_t w = wb0; w < wb1; ++w) {
-        const uint64_t vis = s.V[w];
-        const int64_t v = w * kWave + lane;
-        const bool unv = v < g.n && !((vis >> lane) & 1ull);
-        if (!ballot(unv)) continue;
-        int64_t b = 0, e = 0;
-        if (unv) {
-            b = g.in_rowptr[v];
-            e = g.in_rowptr[v + 1];
+    for (int64_t w0 = wb0; w0 < wb1; w0 += kPullWords) {
+        uint64_t vis[kPullWords];
+        bool unv[kPullWords];
+#pragma unroll
+        for (int i = 0; i < kPullWords; ++i) {
+            const int64_t w = w0 + i, v = w * kWave + lane;
+            vis[i] = w < wb1 ? s.V[w] : ~0ull;
+            unv[i] = w < wb1 && v < g.n && !((vis[i] >> lane) & 1ull);
         }
-        const int64_t d = e - b;
-        bool found = false;
-        int64_t examined = 0;
+        bool anyu = false;
+#pragma unroll
+        for (int i = 0; i < kPullWords; ++i) anyu |= unv[i];
+        if (!ballot(anyu)) continue;
+        int64_t b[kPullWords], e[kPullWords];
+#pragma unroll
+        for (int i = 0; i < kPullWords; ++i) {
+            const int64_t v = (w0 + i) * kWave + lane;
+            b[i] = unv[i] ? g.in_rowptr[v] : 0;
+            e[i] = unv[i] ? g.in_rowptr[v + 1] : 0;
+        }
         // every unvisited vertex first scans up to `light` in-edges alone: on a
         // wide frontier most find a hit there, whatever their degree
-        const int64_t le = b + std::min<int64_t>(d, light);
-        if (unv && d <= g.heavy) {
-            int64_t x = b;
-            for (; x + 4 <= le; x += 4) {
-                const int32_t u0 = g.in_colidx[x], u1 = g.in_colidx[x + 1];
-                const int32_t u2 = g.in_colidx[x + 2], u3 = g.in_colidx[x + 3];
-                const bool h0 = test_bit(Fc, u0), h1 = test_bit(Fc, u1);
-                const bool h2 = test_bit(Fc, u2), h3 = test_bit(Fc, u3);
-                if (h0 | h1 | h2 | h3) {
-                    examined += h0 ? 1 : h1 ? 2 : h2 ? 3 : 4;
-                    found = true;
-                    break;
+        bool found[kPullWords], act[kPullWords];
+        int64_t examined[kPullWords], x[kPullWords], le[kPullWords];
+#pragma unroll
+        for (int i = 0; i < kPullWords; ++i) {
+            const int64_t d = e[i] - b[i];
+            found[i] = false;
+            examined[i] = 0;
+            x[i] = b[i];
+            le[i] = b[i] + std::min<int64_t>(d, light);
+            act[i] = unv[i] && d > 0 && d <= g.heavy;
+        }
+        bool going = false;
+#pragma unroll
+        for (int i = 0; i < kPullWords; ++i) going |= act[i];
+        while (going) {
+            int32_t u[kPullWords][4];
+#pragma unroll
+            for (int i = 0; i < kPullWords; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) u[i][r] = icol[act[i] && x[i] + r < le[i] ? x[i] + r : 0];
+            uint64_t fw[kPullWords][4];
+#pragma unroll
+            for (int i = 0; i < kPullWords; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) fw[i][r] = Fc[(uint32_t)u[i][r] >> 6];
+            going = false;
+#pragma unroll
+            for (int i = 0; i < kPullWords; ++i) {
+                if (!act[i]) continue;
+                int pos = 4;  // first hit of the round
+#pragma unroll
+                for (int r = 3; r >= 0; --r)
+                    if (x[i] + r < le[i] && ((fw[i][r] >> ((uint32_t)u[i][r] & 63u)) & 1ull)) pos = r;
+                if (pos < 4) {
+                    examined[i] += pos + 1;
+                    found[i] = true;
+                    act[i] = false;
+                } else {
+                    examined[i] += std::min<int64_t>(4, le[i] - x[i]);
+                    x[i] += 4;
+                    act[i] = x[i] < le[i];
                 }
-                examined += 4;
+                going |= act[i];
             }
-            if (!found) {
-                for (; x < le; ++x) {
-                    ++examined;
-                    if (test_bit(Fc, g.in_colidx[x])) {
-                        found = true;
+        }
+#pragma unroll
+        for (int i = 0; i < kPullWords; ++i) {
+            const int64_t w = w0 + i;
+            if (w >= wb1) break;  // uniform
+            const int64_t v = w * kWave + lane, d = e[i] - b[i];
+            // the rest of the in-edges of vertices with no hit yet: the whole wave, 256 per round
+            uint64_t medium = ballot(unv[i] && !found[i] && d > light && d <= g.heavy);
+            while (medium) {
+                const int h = __builtin_ctzll(medium);
+                medium &= medium - 1;
+                const int64_t hb = shfl64(b[i], h) + light, he = shfl64(e[i], h);
+                bool hit = false;
+                int64_t scanned = 0;
+                for (int64_t x0 = hb; x0 < he; x0 += 4 * kWave) {
+                    const bool any = any_hit4(Fc, icol, x0 + lane, he, hb);
+                    scanned += std::min<int64_t>(4 * kWave, he - x0);
+                    if (ballot(any)) {
+                        hit = true;
                         break;
                     }
                 }
-            }
-        }
-        // the rest of the in-edges of vertices with no hit yet: the whole wave, 256 per round
-        uint64_t medium = ballot(unv && !found && d > light && d <= g.heavy);
-        while (medium) {
-            const int h = __builtin_ctzll(medium);
-            medium &= medium - 1;
-            const int64_t hb = shfl64(b, h) + light, he = shfl64(e, h);
-            bool hit = false;
-            int64_t scanned = 0;
-            for (int64_t x0 = hb; x0 < he; x0 += 4 * kWave) {
-                const bool any = any_hit4(Fc, g.in_colidx, x0 + lane, he, hb);
-                scanned += std::min<int64_t>(4 * kWave, he - x0);
-                if (ballot(any)) {
-                    hit = true;
-                    break;
+                if (lane == h) {
+                    found[i] = hit;
+                    examined[i] += scanned;
                 }
             }
-            if (lane == h) {
-                found = hit;
-                examined += scanned;
+            const uint64_t fm = ballot(found[i]);
+            if (last) {
+                // final hop: only the count matters (chunk vertices are counted below)
+                if (lane == 0) *found_out += __popcll(fm);
+            } else {
+                if (fm && lane == 0) {
+                    // chunk waves may set heavy bits of the same words concurrently
+                    atomicOr((unsigned long long *)&s.V[w], (unsigned long long)fm);
+                    atomicOr((unsigned long long *)&Fn[w], (unsigned long long)fm);
+                }
+                if (found[i] && s.dist) s.dist[v] = L;
+                int64_t od = 0, vb = b[i];  // undirected: the in-row is the out-row
+                if (found[i] && g.directed) {
+                    vb = g.rowptr[v];
+                    od = g.rowptr[v + 1] - vb;
+                } else if (found[i]) {
+                    od = d;
+                }
+                wb_word(wb, s, cur, L, w, found[i], vb, od, d);
             }
-        }
-        const uint64_t fm = ballot(found);
-        if (last) {
-            // final hop: only the count matters (chunk vertices are counted below)
-            if (lane == 0) *found_out += __popcll(fm);
-        } else {
-            if (fm && lane == 0) {
-                // chunk waves may set heavy bits of the same words concurrently
-                atomicOr((unsigned long long *)&s.V[w], (unsigned long long)fm);
-                atomicOr((unsigned long long *)&Fn[w], (unsigned long long)fm);
+            if (units) {
+                c_pe += wave_sum(examined[i]);
+                c_pv += __popcll(ballot(unv[i] && d <= g.heavy));
             }
-            if (found && s.dist) s.dist[v] = L;
-            int64_t od = 0, vb = b;  // undirected: the in-row is the out-row
-            if (found && g.directed) {
-                vb = g.rowptr[v];
-                od = g.rowptr[v + 1] - vb;
-            } else if (found) {
-                od = d;
-            }
-            wb_word(wb, s, cur, L, w, found, vb, od, d);
-        }
-        if (units) {
-            c_pe += wave_sum(examined);
-            c_pv += __popcll(ballot(unv && d <= g.heavy));
         }
     }
     wb_flush(wb, s, cur, L);
