@@ -613,14 +613,16 @@ __device__ __forceinline__ bool any_hit4(const uint64_t *__restrict__ Fc, const 
     return any;
 }
 
-// Each wave takes its run of 64-vertex words two at a time.  Every unvisited
-// vertex of in-degree up to g.heavy scans its first `light` in-edges alone,
-// four per round, the rounds of a lane's two vertices issued together (an
-// edge past the scan reads in-edge 0 and is ignored), so that a round's eight
-// index loads, then its eight bitmap loads, are in flight at once; those with
-// more edges and no hit yet have the rest scanned by the whole wave, 256
-// in-edges per round; heavier vertices come from the chunk table after the
-// words.
+// Each wave takes its run of 64-vertex words kPullWords at a time.  Every
+// unvisited vertex of in-degree up to g.heavy scans its first `light`
+// in-edges alone, four per round (an edge past the scan reads in-edge 0 and is
+// ignored, so a round's four index loads, then its four bitmap loads, are in
+// flight at once, whatever the degree; the rounds of a lane's vertices in the
+// words taken together are issued together); those with more edges and no hit
+// yet have the rest scanned by the whole wave, 256 in-edges per round; heavier
+// vertices come from the chunk table after the words.  One word at a time:
+// two raise the hop and step kernels' registers past what five waves per SIMD
+// allow, and a step launch's blocks then no longer fit the device at once.
 constexpr int kPullWords = 1;
 __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int light, const HeavyChunks &hc,
                          RegRec *cur, WaveBuf &wb, int64_t *found_out, int64_t *units, const Part &pt) {
