@@ -301,8 +301,15 @@ __device__ __forceinline__ void wave_lds_sync() {
 // kPullR loads in flight per lane instead of one.  The group stops once every
 // lane holds all of its needed bits.  Vertices with a new bit are marked in
 // Fbn; Fbz (the bitmap of the hop after this one) is cleared on the way.
+// With `order` (ascending in-degree) the groups take the vertices in that
+// order, so the groups of a wave scan lists of one length and finish
+// together; without it, in id order, so that a wave's rows are contiguous and
+// its vertices share one frontier bitmap word (one-word rows: the scattered
+// row accesses and per-vertex bitmap claims of the sorted order cost more than
+// the uneven scans).
 template <int G, int FS = 0>
-__global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__restrict__ in_rowptr,
+__global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int32_t *__restrict__ order,
+                                                           const int64_t *__restrict__ in_rowptr,
                                                            const int32_t *__restrict__ in_colidx,
                                                            uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
                                                            const void *__restrict__ Fs,
@@ -338,7 +345,8 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
     bool any = false;
     int64_t examined = 0, scanned = 0, gathered = 0, fresh = 0;
     for (int64_t wvi = (int64_t)blockIdx.x * kWavesPerBlock + wv; wvi * VPW < n; wvi += nwaves) {
-        const int64_t v = wvi * VPW + grp;
+        const int64_t idx = wvi * VPW + grp;
+        const int64_t v = idx >= n ? n : order ? order[idx] : idx;
         const bool valid = v < n && wi < wact;
         const int64_t at = v * W + wi;
         uint64_t need = 0;
@@ -413,12 +421,16 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int64_t *__res
             Fn[at] = 0;
         }
         const uint64_t gm = group_any<G>(ballot(nx != 0));
-        if (gm && lane == 0) {
+        if (order) {
+            // one bitmap claim per vertex with a new bit (the lane of its word 0)
+            if (wi == 0 && ((gm >> grp) & 1ull) && fb_set(fb.next, (int32_t)v)) ++fresh;
+        } else if (gm && lane == 0) {
             const int64_t v0 = wvi * VPW;  // VPW divides 64: the wave's vertices share one bitmap word
             const uint64_t old = atomicOr((unsigned long long *)&fb.next[v0 >> 6], (unsigned long long)(gm << (v0 & 63)));
             fresh += __popcll(gm << (v0 & 63) & ~old);
         }
     }
+    fresh = wave_sum(fresh);  // counted by the lanes of word 0, or by lane 0
     if (lane == 0) fb_count(fb.cnt_next, fresh);
     if (ballot(any) && lane == 0) atomicOr(flag, 1);
     if (units) {
@@ -470,12 +482,12 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
     bool any = false;
     int64_t examined = 0, gathered = 0, fresh = 0;
     for (int64_t i = (int64_t)blockIdx.x * kWavesPerBlock + wv; i < n_items; i += nwaves) {
-        const int64_t v = hvert[i];
+        // the chunk's record in one round trip, then its vertex's visited word
+        const int64_t v = hvert[i], b = hbegin[i], e = hend[i];  // e > b
         const int64_t at = v * W + wi;
         uint64_t need = 0;
         if (wi < wact) need = ~__hip_atomic_load(&V[at], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & actw;
         if (!ballot(need != 0)) continue;
-        const int64_t b = hbegin[i], e = hend[i];  // e > b
         uint64_t acc = 0, full = 0;
         for (int64_t x0 = b; x0 < e; x0 += kPullR * kWave) {
             int32_t u[kPullR];
@@ -897,7 +909,9 @@ static void launch_pull(khop_graph *g, BatchCtx *c, const HeavyTable &ht, int gr
         ProfScope ps(g, KK_BATCH_PULL, st);
         auto k = fs_bits == 16 ? batch_pull_kernel<G, 16> : fs_bits == 32 ? batch_pull_kernel<G, 32>
                                                                            : batch_pull_kernel<G, 0>;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, st, g->d_in_rowptr, g->d_in_colidx, V, F,
+        // rows of two or more words: the vertices by in-degree (one-word rows: in id order)
+        const int32_t *order = G >= 2 ? in_degree_order(g) : nullptr;
+        hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, st, order, g->d_in_rowptr, g->d_in_colidx, V, F,
                            (const void *)c->Fs, Fn, n, Wr, wact, lc.act, ht.threshold, fb, lc.mode_l, lc.flag_prev,
                            lc.flag_l, ps.units());
         // bytes: V read and write-back and Fn write per active word, the frontier bitmap once,

@@ -9,6 +9,7 @@
 // threshold ever used) and small (one record per 256 or 1024 in-edges of the
 // vertices above the threshold).
 #include <algorithm>
+#include <vector>
 
 #include "khop_impl.h"
 
@@ -82,9 +83,38 @@ HeavyTable plain_heavy_table_current(khop_graph *g) {
     return g->plain_heavy;
 }
 
+// A stable counting sort of the vertices by in-degree: the bottom-up batched
+// kernel gives each wave vertices of one degree, so that no lane of a wave
+// waits for a longer scan of another.
+const int32_t *in_degree_order(khop_graph *g) {
+    std::lock_guard<std::mutex> lk(g->heavy_mu);
+    if (g->d_in_order || g->n == 0) return g->d_in_order;
+    int64_t maxd = 0;
+    for (int64_t v = 0; v < g->n; ++v) maxd = std::max(maxd, g->h_indeg[v]);
+    std::vector<int64_t> start((size_t)maxd + 2, 0);
+    for (int64_t v = 0; v < g->n; ++v) ++start[(size_t)g->h_indeg[v] + 1];
+    for (size_t d = 1; d < start.size(); ++d) start[d] += start[d - 1];
+    std::vector<int32_t> order((size_t)g->n);
+    for (int64_t v = 0; v < g->n; ++v) order[(size_t)start[(size_t)g->h_indeg[v]]++] = (int32_t)v;
+    int32_t *d = nullptr;
+    if (hipMalloc(&d, order.size() * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(KHOP_ENOMEM, "device allocation for the in-degree order failed");
+    }
+    if (hipMemcpy(d, order.data(), order.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(d);
+        fail(KHOP_EINTERNAL, "copy of the in-degree order failed");
+    }
+    g->d_in_order = d;
+    return d;
+}
+
 // Called by graph_free after the device has finished all work.
 void heavy_tables_free(khop_graph *g) {
     std::lock_guard<std::mutex> lk(g->heavy_mu);
+    if (g->d_in_order) (void)hipFree(g->d_in_order);
+    g->d_in_order = nullptr;
     free_table(g->plain_heavy);
     free_table(g->batch_heavy);
     for (auto &t : g->heavy_retired) free_table(t);

@@ -158,6 +158,7 @@ struct khop_graph {
     int32_t *d_in_colidx = nullptr;
     khop::HeavyTable plain_heavy;    // chunks for the plain bottom-up hop
     khop::HeavyTable batch_heavy;    // chunks for the batched bottom-up hop
+    int32_t *d_in_order = nullptr;   // vertices by ascending in-degree (ties by id), built on first use
     std::vector<khop::HeavyTable> heavy_retired;  // replaced tables, freed with the graph
     std::mutex heavy_mu;             // guards the tables above
     std::vector<int64_t> h_outdeg;   // host copy of out-degrees
@@ -230,6 +231,9 @@ HeavyTable batch_heavy_table(khop_graph *g, int threshold);
 // The plain table as it stands, never rebuilt (graph_load_csr builds one for the default threshold).
 HeavyTable plain_heavy_table_current(khop_graph *g);
 void heavy_tables_free(khop_graph *g);
+// The graph's vertices sorted by in-degree, ascending, ties by id (device
+// array of n ids, built on first use, freed with the tables).
+const int32_t *in_degree_order(khop_graph *g);
 // A consistent copy of the graph's options, and their replacement (options
 // change between calls; a call runs on the copy it took when it started).
 Params params_of(khop_graph *g);
