@@ -5,10 +5,11 @@
 // alpha, the pull->push threshold beta, the lane-serial bottom-up degree, the
 // chunked bottom-up degree, the atomic top-down edge limit and the hop
 // kernels' blocks per compute unit, timing queries at k = 2 and 3 from 48
-// sample seeds and at k = 6 from four of them.  Batched path: seeds per launch and the heavy-vertex threshold
-// (jointly), then the top-down/bottom-up switch and the bottom-up kernel's
-// blocks per compute unit, timing a batch of mixed k (2, 3, 3, 6).  Results
-// are cached per (library sources, device architecture, graph content hash,
+// sample seeds and at k = 6 from four of them.  Batched path: seeds per
+// launch and the heavy-vertex threshold (jointly), then the top-down/bottom-up
+// switch and the bottom-up kernel's blocks per compute unit, timing a batch of
+// mixed k (2, 3, 3, 6) and one with the paper's protocol mix.  Results are
+// cached per (library sources, device architecture, graph content hash,
 // seeds per launch) in memory and in a text file ($KHOP_TUNE_CACHE, default
 // ~/.cache/khop/tune.txt); the source hash keeps settings tuned for other
 // kernels from being reused.
@@ -279,13 +280,17 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         };
         descend(knobs, plain_cost, 2);
 
-        // ---- batched path: a batch of mixed k, as queries arrive in practice
+        // ---- batched path: a batch of mixed k, as queries arrive in practice,
+        // and a batch with the depth mix of the paper's protocol (as many
+        // queries at k = 1 as at k = 2, one in thirty at each of k = 3 and 6)
         static const int32_t kMix[4] = {2, 3, 3, 6};
         std::vector<int32_t> ks(seeds.size());
         for (size_t i = 0; i < ks.size(); ++i) ks[i] = kMix[i % 4];
+        std::vector<int32_t> ks_proto(620);
+        for (int i = 0; i < 620; ++i) ks_proto[(size_t)i] = i < 300 ? 1 : i < 600 ? 2 : i < 610 ? 3 : 6;
         auto batch_cost = [&] {
             install();
-            return best_of([&] { return time_batched(b, ks); }, 2);
+            return best_of([&] { return time_batched(b, ks) + time_batched(b, ks_proto); }, 2);
         };
         std::vector<int> per = seeds_per_launch ? std::vector<int>{seeds_per_launch}
                                                 : std::vector<int>{64, 128, 256, 512, 1024};
