@@ -123,6 +123,11 @@ struct State {
     int64_t *qb[2];    // region queues by hop parity, nreg * rc slots: the row begin of each queued vertex
     int64_t *qoff[2];  // out-degree prefix within each region's queue
     RegRec *regs;      // 3 * nreg region counters
+    // One byte per block of 64 words (4096 vertices): some visited or frontier
+    // bit of the block may be set beyond the query's start (its seed; under a
+    // vertex mask, the vertices outside it).  A query's set-up rewrites only
+    // the flagged blocks and the seed's.  Null: every set-up rewrites every word.
+    uint8_t *dirty;
     int nreg;          // regions
     int rw;            // words per region
     int64_t rc;        // slots per region (rw * 64)
@@ -355,6 +360,18 @@ __device__ __forceinline__ void reset_word(const State &s, const Graph &g, int64
     s.F[1][w] = 0;
 }
 
+// Flags the block of word w: a visited or frontier bit of it is being set.
+__device__ __forceinline__ void mark_dirty(const State &s, int64_t w) {
+    if (s.dirty) s.dirty[w >> 6] = 1;
+}
+
+// The block flag after a set-up that reset word w (every lane of the wave,
+// whose 64 words are the block; the lane of its first word writes): set for
+// the seed's block and, under a vertex mask, for every block.
+__device__ __forceinline__ void reset_dirty(const State &s, int64_t w, int64_t sw) {
+    if (s.dirty && (w & 63) == 0) s.dirty[w >> 6] = (s.vmask || (sw >= 0 && (w >> 6) == (sw >> 6))) ? 1 : 0;
+}
+
 // Set-up of the first query of a run (later queries are set up by the hop 1
 // of the query before them).
 __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph g, State s, const int32_t *seeds,
@@ -365,8 +382,10 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
     const bool valid = seed >= 0 && (int64_t)seed < g.n;
     const int64_t sw = valid ? (seed >> 6) : -1;
     const uint64_t sbit = valid ? (1ull << (seed & 63)) : 0;
-    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock)
+    for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock) {
         reset_word(s, g, w, sw, sbit);
+        reset_dirty(s, w, sw);
+    }
     if (blockIdx.x == 0)
         setup_query(ctl, g, s, seed, qi, k, dir_mode, alpha, beta, push_atomic_max, nnz_in, out_count, out_te,
                     units);
@@ -411,6 +430,7 @@ __device__ __forceinline__ void push_claim(int L, const Graph &g, const State &s
     const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
     if (old & bit) return;
     atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+    mark_dirty(s, v >> 6);
     if (s.dist) s.dist[v] = L;
     const int64_t vb = g.rowptr[v];
     const int64_t od = g.rowptr[v + 1] - vb;
@@ -739,6 +759,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
                     // chunk waves may set heavy bits of the same words concurrently
                     atomicOr((unsigned long long *)&s.V[w], (unsigned long long)fm);
                     atomicOr((unsigned long long *)&Fn[w], (unsigned long long)fm);
+                    mark_dirty(s, w);
                 }
                 if (found[i] && s.dist) s.dist[v] = L;
                 int64_t od = 0, vb = b[i];  // undirected: the in-row is the out-row
@@ -776,6 +797,7 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
         }
         if (hit && lane == 0) {
             const uint64_t old = atomicOr((unsigned long long *)&s.V[v >> 6], (unsigned long long)bit);
+            mark_dirty(s, v >> 6);
             if (!(old & bit)) {
                 if (last) {
                     *found_out += 1;
@@ -826,6 +848,7 @@ __device__ void hop1_push_free(const Graph &g, const State &s, int64_t beg, int6
             const uint64_t bit = 1ull << (v & 63);
             __hip_atomic_fetch_or(&s.V[v >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_fetch_or(&s.F[1][v >> 6], bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            mark_dirty(s, v >> 6);
             if (s.dist) s.dist[v] = 1;
         }
         const uint64_t qm = ballot(od > 0);
@@ -869,6 +892,7 @@ __device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E
             const int64_t id = g.directed ? g.in_rowptr[v + 1] - g.in_rowptr[v] : od;
             if (!(old & bit)) {
                 atomicOr((unsigned long long *)&Fn[v >> 6], (unsigned long long)bit);
+                mark_dirty(s, v >> 6);
                 if (s.dist) s.dist[v] = 1;
                 append_one(s, cur, 1, v, vb, od, id);
             }
@@ -930,8 +954,9 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
     const int64_t push_atomic_max = ctl->push_atomic_max;
     const HopHdr hp = ctl->hdr[(L - 1) % 3];
     const bool last = L >= k;  // the final hop only counts
-    if (!last) {
-        // the slots hop l+1 writes start clear
+    if (L + 1 < k) {
+        // the slots hop l+1 writes start clear (a last hop only counts: it
+        // writes no frontier word or region counter)
         RegRec *nx = s.regs + (int64_t)((L + 1) % 3) * s.nreg;
         for (int64_t i = pt.bid * kBlock + t; i < s.nreg; i += pt.nb * kBlock) {
             nx[i].qpack = 0;
@@ -1094,12 +1119,18 @@ __global__ void __launch_bounds__(kBlock) plain_step_kernel(PlainCtl *ctl_last, 
     const int64_t nsw = nvalid ? (nseed >> 6) : -1;
     const uint64_t nsbit = nvalid ? (1ull << (nseed & 63)) : 0;
     int64_t fresh = 0, flagged = 0;
+    // each wave takes whole 64-word blocks (kBlock is a multiple of 64)
     for (int64_t w = pt.bid * kBlock + t; w < g.nw; w += pt.nb * kBlock) {
         if (marks && sm.nsum[w]) {
             fresh += close_marks_word(sm, w, sm.V[w]);
             ++flagged;
         }
-        if (bk.qn >= 0) reset_word(sr, g, w, nsw, nsbit);
+        if (bk.qn >= 0) {
+            // only the blocks the state's last query set bits in, and the new seed's
+            const bool stale = !sr.dirty || sr.vmask || sr.dirty[w >> 6] || (nsw >= 0 && (w >> 6) == (nsw >> 6));
+            if (stale) reset_word(sr, g, w, nsw, nsbit);
+            reset_dirty(sr, w, nsw);
+        }
     }
     if (marks) {
         fresh = wave_sum(fresh);
@@ -1197,6 +1228,7 @@ __global__ void __launch_bounds__(kBlock) plain_compact_kernel(const PlainCtl *c
                 if (lane == 0 && m) {
                     s.V[w[i]] = vis[i] | m;
                     Fn[w[i]] = m;
+                    mark_dirty(s, w[i]);
                 }
                 const int64_t d = od[i] - vb[i];
                 wb_word(wb, s, cur, L, w[i], fresh[i], vb[i], d, g.directed ? id[i] : d);
@@ -1226,7 +1258,10 @@ __global__ void __launch_bounds__(kBlock) plain_bfs_init_kernel(PlainCtl *ctl, G
     const uint64_t sbit = 1ull << (seed & 63);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t t0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    for (int64_t w = t0; w < g.nw; w += stride) reset_word(s, g, w, sw, sbit);
+    for (int64_t w = t0; w < g.nw; w += stride) {
+        reset_word(s, g, w, sw, sbit);
+        reset_dirty(s, w, sw);
+    }
     if (s.dist)
         for (int64_t v = t0; v < g.n; v += stride) s.dist[v] = v == seed ? 0 : -1;
     if (levels)
@@ -1423,12 +1458,14 @@ static size_t plain_layout(const khop_graph *g, PlainCtx *c, char *base) {
     size_t off = 0;
     const size_t o_ctl = off;
     off += al(kSlots * sizeof(PlainCtl));
-    size_t o_V[kStates], o_F[kStates][3], o_regs[kStates], o_nb[kStates], o_ns[kStates];
+    size_t o_V[kStates], o_F[kStates][3], o_regs[kStates], o_nb[kStates], o_ns[kStates], o_dirty[kStates];
     for (int p = 0; p < kStates; ++p) {
         o_nb[p] = off;
         off += al(nw * 64);  // the byte map, padded to whole words
         o_ns[p] = off;
         off += al(nw);
+        o_dirty[p] = off;
+        off += al((nw + 63) / 64);
         o_V[p] = off;
         off += al(nw * 8);
         for (int i = 0; i < 3; ++i) {
@@ -1467,6 +1504,7 @@ static size_t plain_layout(const khop_graph *g, PlainCtx *c, char *base) {
         st.regs = (RegRec *)(base + o_regs[p]);
         st.nextb = (uint8_t *)(base + o_nb[p]);
         st.nsum = (uint8_t *)(base + o_ns[p]);
+        st.dirty = (uint8_t *)(base + o_dirty[p]);
         st.nreg = nreg;
         st.rw = rw;
         st.rc = rc;
@@ -1805,6 +1843,9 @@ void plain_run_noalloc(khop_graph *g, const int32_t *d_seeds, int64_t num_seeds,
     if (num_seeds <= 0) return;
     plain_layout(g, &c, scratch_on(g->device));
     c.fixed = true;
+    // the scratch's bitmaps hold whatever an earlier call left: no block
+    // flags, so that every set-up rewrites every word
+    for (int p = 0; p < kStates; ++p) c.s[p].dirty = nullptr;
     // an earlier call (perhaps on another graph) left the scratch in any
     // state: the byte marks, their summaries and the control records, which
     // the path expects zero between queries, start clear

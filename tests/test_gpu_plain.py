@@ -229,6 +229,46 @@ def test_top_down_queues_split_over_waves(K, grid, pam):
     g.free()
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_context_reuse_across_entry_points(K, mode):
+    """One graph's pooled query context serves, in turn, pipelined counts at several k, breadth-first
+    searches, label-filtered counts, level sizes, neighborhood listings and one-at-a-time counts: a query's
+    set-up rewrites only the blocks of its state that earlier uses set bits in, so each result must equal
+    the oracle's whatever ran on the context before it."""
+    el = graphgen.chung_lu(300_000, 2_400_000, 4.0, seed=21)
+    g = K.Graph.from_edgelist(el)
+    og = oracle.OracleGraph.from_edgelist(el)
+    _set_mode(K, g, mode)
+    rng = np.random.default_rng(5)
+    lab = rng.random(el.n) < 0.6
+    deg = og.degrees()
+    hub = int(np.argmax(deg))
+    for rnd in range(2):
+        seeds = graphgen.draw_seeds(el, 40, seed=30 + rnd)
+        _say("context reuse", mode, "round", rnd)
+        for k in (3, 1, 2, 6):
+            c, te = g.count(seeds, k, with_te=True)
+            oc, ote = og.count(seeds, k)
+            assert np.array_equal(c, oc) and np.array_equal(te, ote), (rnd, "count", k)
+        s0 = int(seeds[rnd])
+        dist, cnt, depth = g.bfs(s0, -1)
+        assert np.array_equal(dist, og.distances(s0, 2**31 - 1)), (rnd, "bfs")
+        lc = g.count_labeled(seeds[:12], 2, lab)
+        assert list(lc) == [og.khop_filtered(int(x), 2, lab)[0] for x in seeds[:12]], (rnd, "labeled")
+        assert np.array_equal(g.count(np.array([hub, s0, hub], np.int32), 2), og.count(np.array([hub, s0, hub]), 2)[0])
+        assert list(g.levels(s0, 6)) == list(og.khop(s0, 6)[2]), (rnd, "levels")
+        ref = og.distances(s0, 2)
+        assert np.array_equal(g.neighborhood(s0, 2), np.nonzero(ref > 0)[0]), (rnd, "neighborhood")
+        g.set_option(K.KHOP_OPT_PLAIN_PIPELINE, 0)
+        try:
+            assert np.array_equal(g.count(seeds[:16], 3), og.count(seeds[:16], 3)[0]), (rnd, "sequential")
+        finally:
+            g.set_option(K.KHOP_OPT_PLAIN_PIPELINE, 1)
+        lc = g.count_labeled(seeds[:12], 3, lab)
+        assert list(lc) == [og.khop_filtered(int(x), 3, lab)[0] for x in seeds[:12]], (rnd, "labeled 3")
+    g.free()
+
+
 @pytest.mark.parametrize("heavy", [1, 4, 64, 128])
 def test_g0_pull_heavy_chunks(K, g0, g0_oracle, heavy):
     """Low chunk thresholds send many scale-10 vertices through the chunk kernel."""
