@@ -340,7 +340,6 @@ __device__ void setup_query(PlainCtl *ctl, const Graph &g, const State &s, int32
     ctl->hdr[0].mu_before = nnz_in;
     ctl->hdr[0].dir = dir_mode == DIR_PULL ? DIR_PULL : DIR_PUSH;
     ctl->hdr[0].mode = MODE_IDLE;
-    unit_add(units, 0, 3 * 8 * g.nw);
 }
 
 // Word w of a query's visited and frontier bitmaps at its start: the seed's
@@ -386,9 +385,11 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
         reset_word(s, g, w, sw, sbit);
         reset_dirty(s, w, sw);
     }
-    if (blockIdx.x == 0)
+    if (blockIdx.x == 0) {
         setup_query(ctl, g, s, seed, qi, k, dir_mode, alpha, beta, push_atomic_max, nnz_in, out_count, out_te,
                     units);
+        if (threadIdx.x == 0) unit_add(units, 0, 3 * 8 * g.nw);  // every word of V, F[0] and F[1]
+    }
 }
 
 // End of a run: the last query's byte marks (if its last hop left any), and
@@ -1118,7 +1119,7 @@ __global__ void __launch_bounds__(kBlock) plain_step_kernel(PlainCtl *ctl_last, 
     const bool nvalid = nseed >= 0 && (int64_t)nseed < g.n;
     const int64_t nsw = nvalid ? (nseed >> 6) : -1;
     const uint64_t nsbit = nvalid ? (1ull << (nseed & 63)) : 0;
-    int64_t fresh = 0, flagged = 0;
+    int64_t fresh = 0, flagged = 0, rewritten = 0;
     // each wave takes whole 64-word blocks (kBlock is a multiple of 64)
     for (int64_t w = pt.bid * kBlock + t; w < g.nw; w += pt.nb * kBlock) {
         if (marks && sm.nsum[w]) {
@@ -1128,9 +1129,18 @@ __global__ void __launch_bounds__(kBlock) plain_step_kernel(PlainCtl *ctl_last, 
         if (bk.qn >= 0) {
             // only the blocks the state's last query set bits in, and the new seed's
             const bool stale = !sr.dirty || sr.vmask || sr.dirty[w >> 6] || (nsw >= 0 && (w >> 6) == (nsw >> 6));
-            if (stale) reset_word(sr, g, w, nsw, nsbit);
+            if (stale) {
+                reset_word(sr, g, w, nsw, nsbit);
+                ++rewritten;
+            }
             reset_dirty(sr, w, nsw);
         }
+    }
+    if (units && bk.qn >= 0) {
+        // 24 B per rewritten word of V, F[0] and F[1]; the block flags once
+        rewritten = wave_sum(rewritten);
+        if (lane_id() == 0) unit_add(units, 0, 24 * rewritten);
+        if (pt.bid == 0 && t == 0 && sr.dirty) unit_add(units, 0, (g.nw + 63) / 64);
     }
     if (marks) {
         fresh = wave_sum(fresh);
@@ -1273,6 +1283,7 @@ __global__ void __launch_bounds__(kBlock) plain_bfs_init_kernel(PlainCtl *ctl, G
             ctl->level_out = levels;
             ctl->level_cap = levels ? level_cap : 0;
             if (units && s.dist) unit_add(units, 0, 4 * g.n);
+            unit_add(units, 0, 3 * 8 * g.nw);  // every word of V, F[0] and F[1]
         }
     }
 }
