@@ -458,15 +458,18 @@ static void load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, 
     } else {
         g->h_indeg = g->h_outdeg;
     }
+    // column arrays carry kColidxPad zero entries past the end: the kernels
+    // read a lane's next four in-edges with one 16-byte load
     auto upload = [&](const HostCSR &c, int64_t **rp, int32_t **ci) {
-        if (hipMalloc(rp, (c.rowptr.size()) * 8) != hipSuccess ||
-            hipMalloc(ci, std::max<size_t>(c.colidx.size(), 1) * 4) != hipSuccess) {
+        const size_t ncol = c.colidx.size() + (size_t)khop::kColidxPad;
+        if (hipMalloc(rp, (c.rowptr.size()) * 8) != hipSuccess || hipMalloc(ci, ncol * 4) != hipSuccess) {
             (void)hipGetLastError();
             fail(KHOP_ENOMEM, "device allocation for the CSR failed");
         }
         KHOP_HIP(hipMemcpy(*rp, c.rowptr.data(), c.rowptr.size() * 8, hipMemcpyHostToDevice));
         if (!c.colidx.empty())
             KHOP_HIP(hipMemcpy(*ci, c.colidx.data(), c.colidx.size() * 4, hipMemcpyHostToDevice));
+        KHOP_HIP(hipMemset(*ci + c.colidx.size(), 0, (size_t)khop::kColidxPad * 4));
     };
     try {
         upload(out_csr, &g->d_rowptr, &g->d_colidx);

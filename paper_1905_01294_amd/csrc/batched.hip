@@ -231,7 +231,7 @@ __device__ __forceinline__ uint64_t group_any(uint64_t m) {
 // A 64-bit zero that loads of lanes with nothing to read point at, so that a
 // group of loads can be issued unconditionally, all in flight at once, with
 // no branch (and no wait) between them.
-__device__ const uint64_t kZeroWords[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+__device__ uint64_t kZeroWords[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
 // The frontier word of vertex u that lane word wi gathers, or 0 when take is
 // false (the load then reads the shared zero word).  With one-word rows whose
@@ -251,7 +251,7 @@ __device__ __forceinline__ uint64_t frontier_word(const uint64_t *__restrict__ F
     }
 }
 
-__device__ const uint64_t kOnesWords[8] = {~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull};
+__device__ uint64_t kOnesWords[8] = {~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull, ~0ull};
 
 constexpr int kPullR = 4;  // in-edges per lane per step of the bottom-up kernels (loads in flight)
 
@@ -292,11 +292,12 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 
 // Hop >= 2, light vertices: G lanes per vertex (lane word = lane % G).  Each
-// step every lane of a group loads kPullR of the vertex's in-edges (the group
-// covers kPullR * G consecutive ones) and tests them against the frontier
-// bitmap Fbc; the group's hits are packed into its part of the wave's LDS
-// row, and each lane gathers its word of F[u] for four hits at a time (of the
-// narrow copy Fs when FS is 16 or 32).  Every load of a step is unconditional
+// step every lane of a group loads kPullR consecutive in-edges of the vertex
+// with one 16-byte load (the group covers kPullR * G consecutive ones) and
+// tests them against the frontier bitmap Fbc; the group's hits are packed
+// into its part of the wave's LDS row, and each lane gathers its word of F[u]
+// for four hits at a time (of the narrow copy Fs when FS is 16 or 32; with
+// one lane per vertex a lane gathers its own hits, with no LDS).  Every load of a step is unconditional
 // (lanes with nothing to load read a valid dummy address), so the step keeps
 // kPullR loads in flight per lane instead of one.  The group stops once every
 // lane holds all of its needed bits.  Vertices with a new bit are marked in
@@ -367,39 +368,57 @@ __global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int32_t *__res
             // the step's in-edge loads, all issued before any is used: the
             // indices first (some group of the wave is active, so the graph
             // has arcs and index 0 exists), then the loads, then the selects
-            const int64_t left = active ? e - x0 - wi : 0;  // in-edges of the group at or after this lane's first
+            // lane wi takes in-edges x0 + 4 wi .. x0 + 4 wi + 3 of the group's
+            // 4 G, in one 16-byte load
+            const int64_t base = x0 + (int64_t)kPullR * wi;
+            const int64_t left = active ? e - base : 0;  // of them, those before the vertex's end
+            static_assert(kPullR == 4, "one 16-byte load per lane and step");
+            const i32x4_u q = load4(in_colidx, left > 0 ? base : 0);
             int32_t u[kPullR];
 #pragma unroll
-            for (int r = 0; r < kPullR; ++r) u[r] = in_colidx[(int64_t)r * G < left ? x0 + (int64_t)r * G + wi : 0];
-#pragma unroll
-            for (int r = 0; r < kPullR; ++r) u[r] = (int64_t)r * G < left ? u[r] : -1;
+            for (int r = 0; r < kPullR; ++r) u[r] = r < left ? q[r] : -1;
             bool hit[kPullR];
             test_bits(Fbc, u, dense, hit);
-            // pack the group's hits, in edge order, into its LDS slots (misses
-            // write to the lane's junk slot: no branch)
-            int nh = 0;
-#pragma unroll
-            for (int r = 0; r < kPullR; ++r) {
-                const uint64_t hm = ballot(hit[r]) & grp_bits;
-                *(hit[r] ? &hits[nh + __popcll(hm & below)] : &s_junk[wv][lane]) = u[r];
-                nh += __popcll(hm);
-            }
-            wave_lds_sync();
-            // four gathers in flight per lane; a lane whose word already holds
-            // every needed bit reads the zero word instead
+            // a lane whose word already holds every needed bit gathers nothing
+            // (it reads the zero word instead)
             const bool lane_open = (acc & need) != need;
-            for (int j0 = 0; ballot(j0 < nh); j0 += 4) {
-                uint64_t f[4];
+            if constexpr (G == 1) {
+                // a lane is its own group: it gathers its own hits, four in flight
+                uint64_t f[kPullR];
+                int nh = 0;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const bool take = j0 + q < nh && lane_open;
-                    const int32_t hu = hits[take ? j0 + q : 0];  // an index inside the group's slots either way
-                    f[q] = frontier_word<FS>(F, Fs, take ? hu : 0, W, wi, take);
+                for (int r = 0; r < kPullR; ++r) {
+                    const bool take = hit[r] && lane_open;
+                    f[r] = frontier_word<FS>(F, Fs, take ? u[r] : 0, W, wi, take);
+                    nh += hit[r];
                 }
                 acc |= (f[0] | f[1]) | (f[2] | f[3]);
+                gathered += nh;
+            } else {
+                // pack the group's hits into its LDS slots (misses write to
+                // the lane's junk slot: no branch)
+                int nh = 0;
+#pragma unroll
+                for (int r = 0; r < kPullR; ++r) {
+                    const uint64_t hm = ballot(hit[r]) & grp_bits;
+                    *(hit[r] ? &hits[nh + __popcll(hm & below)] : &s_junk[wv][lane]) = u[r];
+                    nh += __popcll(hm);
+                }
+                wave_lds_sync();
+                // four gathers in flight per lane
+                for (int j0 = 0; ballot(j0 < nh); j0 += 4) {
+                    uint64_t f[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool take = j0 + q < nh && lane_open;
+                        const int32_t hu = hits[take ? j0 + q : 0];  // an index inside the group's slots either way
+                        f[q] = frontier_word<FS>(F, Fs, take ? hu : 0, W, wi, take);
+                    }
+                    acc |= (f[0] | f[1]) | (f[2] | f[3]);
+                }
+                if (wi == 0) gathered += nh;
+                wave_lds_sync();  // the slots are rewritten next step only after every lane has read them
             }
-            if (wi == 0) gathered += nh;
-            wave_lds_sync();  // the slots are rewritten next step only after every lane has read them
             if (active) {
                 if (wi == 0) examined += std::min<int64_t>((int64_t)SLOTS, e - x0);
                 x0 += SLOTS;
@@ -499,34 +518,46 @@ __global__ void __launch_bounds__(kBlock) batch_pull_heavy_kernel(
             }
             bool hit[kPullR];
             test_bits(Fbc, u, dense, hit);
-            // pack the hits of the four rounds, in order, into the wave's LDS
-            // row (misses write to the lane's junk slot: no branch)
-            int nh = 0;
-#pragma unroll
-            for (int r = 0; r < kPullR; ++r) {
-                const uint64_t hm = ballot(hit[r]);
-                *(hit[r] ? &s_hit[wv][nh + mask_rank(hm)] : &s_junk[wv][lane]) = u[r];
-                nh += __popcll(hm);
-            }
-            wave_lds_sync();
-            // stream sg takes hits sg, sg + S, ...: four of its hits in flight at
-            // a time; words that hold every needed bit (over all streams, as of
-            // the last round) are not gathered again
+            // words that hold every needed bit (over all lanes, as of the last
+            // round) are not gathered again
             const bool lane_open = (full & need) != need;
-            for (int j0 = sg; j0 < nh; j0 += 4 * S) {
-                uint64_t f[4];
+            int nh = 0;
+            if constexpr (G == 1) {
+                // one-word rows: every lane gathers its own hits, four in flight
+                uint64_t f[kPullR];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int j = j0 + q * S;
-                    const bool take = j < nh && lane_open;
-                    const int32_t hu = s_hit[wv][take ? j : 0];  // an index inside the wave's row either way
-                    f[q] = frontier_word<FS>(F, Fs, take ? hu : 0, W, wi, take);
+                for (int r = 0; r < kPullR; ++r) {
+                    const bool take = hit[r] && lane_open;
+                    f[r] = frontier_word<FS>(F, Fs, take ? u[r] : 0, W, wi, take);
+                    nh += __popcll(ballot(hit[r]));
                 }
                 acc |= (f[0] | f[1]) | (f[2] | f[3]);
+            } else {
+                // pack the hits of the four rounds, in order, into the wave's
+                // LDS row (misses write to the lane's junk slot: no branch)
+#pragma unroll
+                for (int r = 0; r < kPullR; ++r) {
+                    const uint64_t hm = ballot(hit[r]);
+                    *(hit[r] ? &s_hit[wv][nh + mask_rank(hm)] : &s_junk[wv][lane]) = u[r];
+                    nh += __popcll(hm);
+                }
+                wave_lds_sync();
+                // stream sg takes hits sg, sg + S, ...: four of its hits in flight at a time
+                for (int j0 = sg; j0 < nh; j0 += 4 * S) {
+                    uint64_t f[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = j0 + q * S;
+                        const bool take = j < nh && lane_open;
+                        const int32_t hu = s_hit[wv][take ? j : 0];  // an index inside the wave's row either way
+                        f[q] = frontier_word<FS>(F, Fs, take ? hu : 0, W, wi, take);
+                    }
+                    acc |= (f[0] | f[1]) | (f[2] | f[3]);
+                }
+                wave_lds_sync();  // the row is rewritten next round only after every lane has read it
             }
             gathered += nh;
             examined += std::min<int64_t>(kPullR * kWave, e - x0);
-            wave_lds_sync();  // the row is rewritten next round only after every lane has read it
             full = subgroup_or<G>(acc);
             if (!ballot((full & need) != need)) break;
         }

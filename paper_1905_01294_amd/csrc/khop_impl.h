@@ -42,6 +42,10 @@ HostCSR build_csr(const int32_t *a, const int32_t *b, int64_t m, int64_t n, bool
 uint64_t csr_hash(const HostCSR &c);
 int host_threads();
 
+// Zero entries past the end of each device column array: kernels read four
+// consecutive column indices with one 16-byte load from any index.
+constexpr int64_t kColidxPad = 4;
+
 // Tunable engine parameters (per graph).
 struct Params {
     int dir_mode = KHOP_DIR_AUTO;

@@ -636,8 +636,8 @@ __device__ __forceinline__ bool any_hit4(const uint64_t *__restrict__ Fc, const 
 
 // Each wave takes its run of 64-vertex words kPullWords at a time.  Every
 // unvisited vertex of in-degree up to g.heavy scans its first `light`
-// in-edges alone, four per round (an edge past the scan reads in-edge 0 and is
-// ignored, so a round's four index loads, then its four bitmap loads, are in
+// in-edges alone, four per round (one 16-byte load of the round's indices,
+// whose entries past the scan are ignored, then its four bitmap loads, in
 // flight at once, whatever the degree; the rounds of a lane's vertices in the
 // words taken together are issued together); those with more edges and no hit
 // yet have the rest scanned by the whole wave, 256 in-edges per round; heavier
@@ -695,11 +695,15 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
 #pragma unroll
         for (int i = 0; i < kPullWords; ++i) going |= act[i];
         while (going) {
+            // the round's four in-edges in one 16-byte load (those past the
+            // scan are ignored below)
             int32_t u[kPullWords][4];
 #pragma unroll
-            for (int i = 0; i < kPullWords; ++i)
+            for (int i = 0; i < kPullWords; ++i) {
+                const i32x4_u q = load4(icol, act[i] ? x[i] : 0);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) u[i][r] = icol[act[i] && x[i] + r < le[i] ? x[i] + r : 0];
+                for (int r = 0; r < 4; ++r) u[i][r] = q[r];
+            }
             uint64_t fw[kPullWords][4];
 #pragma unroll
             for (int i = 0; i < kPullWords; ++i)

@@ -45,6 +45,14 @@ __device__ __forceinline__ int64_t wave_exclusive_sum(int64_t v) {
     return x - v;
 }
 
+// Column indices x .. x+3 in one 16-byte load (4-byte aligned).  The graph's
+// column arrays carry four zero entries past their last index (kColidxPad),
+// so that x may be any index below the array's length.
+typedef int32_t i32x4_u __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ i32x4_u load4(const int32_t *__restrict__ p, int64_t x) {
+    return *(const i32x4_u *)(p + x);
+}
+
 __device__ __forceinline__ bool test_bit(const uint64_t *__restrict__ bm, int32_t v) {
     return (bm[(uint32_t)v >> 6] >> ((uint32_t)v & 63u)) & 1ull;
 }

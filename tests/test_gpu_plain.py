@@ -229,6 +229,26 @@ def test_top_down_queues_split_over_waves(K, grid, pam):
     g.free()
 
 
+@pytest.mark.parametrize("alpha,beta", [(1, 2), (14, 24), (2, 1000), (1000, 2), (1, 100000)])
+def test_direction_switch_points(K, alpha, beta):
+    """Automatic direction with thresholds that move the top-down/bottom-up switches to other hops (a
+    top-down hop after a bottom-up one walks the queue that hop appended).  Counts, traversed edges and
+    full-depth distances equal the oracle's."""
+    el = graphgen.chung_lu(120_000, 900_000, 3.0, seed=17)
+    g = K.Graph.from_edgelist(el)
+    og = oracle.OracleGraph.from_edgelist(el)
+    g.set_option(K.KHOP_OPT_ALPHA, alpha)
+    g.set_option(K.KHOP_OPT_BETA, beta)
+    seeds = graphgen.draw_seeds(el, 24, seed=4)
+    for k in (2, 3, 4, 6, 9):
+        c, te = g.count(seeds, k, with_te=True)
+        oc, ote = og.count(seeds, k)
+        assert np.array_equal(c, oc) and np.array_equal(te, ote), (alpha, beta, k)
+    for s in seeds[:4]:
+        assert np.array_equal(g.bfs(int(s), -1)[0], og.distances(int(s), 2**31 - 1)), (alpha, beta, s)
+    g.free()
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_context_reuse_across_entry_points(K, mode):
     """One graph's pooled query context serves, in turn, pipelined counts at several k, breadth-first
