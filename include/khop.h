@@ -259,16 +259,24 @@ enum khop_option {
     KHOP_OPT_BETA = 3,          /* pull -> push when frontier vertices * beta < n */
     KHOP_OPT_PULL_LIGHT = 4,    /* bottom-up: degree up to which one lane scans a vertex alone */
     KHOP_OPT_BATCH_SEEDS = 5,   /* seeds per batched launch: 64, 128, 256, 512 or 1024 */
-    KHOP_OPT_BATCH_HEAVY = 6,   /* batched bottom-up: degree above which a whole wave takes a vertex */
+    KHOP_OPT_BATCH_HEAVY = 6,   /* batched bottom-up: in-degree above which a vertex's in-edges are split into
+                                   1024-edge chunks, a wave each (levels whose rows take G > 2 lanes per
+                                   vertex: G/2 times it) */
     KHOP_OPT_BATCH_PUSH = 7,    /* batched: frontier-degree fraction (1/x of arcs) under which a level goes top-down */
     KHOP_OPT_PULL_HEAVY = 8,    /* bottom-up: in-degree above which a vertex's in-edges are split into chunks */
     KHOP_OPT_PUSH_ATOMIC = 9,   /* top-down: frontier edges up to which heads are claimed atomically
                                    (else byte marks) */
     KHOP_OPT_PLAIN_GRID = 10,   /* plain hop and compaction launches: blocks per compute unit (1..64) */
     KHOP_OPT_BATCH_GRID = 11,   /* batched bottom-up launches: blocks per compute unit (1..64) */
-    KHOP_OPT_PLAIN_PIPELINE = 12 /* 1 (default): consecutive plain queries overlap by one launch;
+    KHOP_OPT_PLAIN_PIPELINE = 12, /* 1 (default): consecutive plain queries overlap by one launch;
                                     0: each query runs its own launch sequence, start to count, before the
                                     next starts (the paper's strictly sequential protocol) */
+    KHOP_OPT_PLAIN_GRAPHS = 13  /* 0 (default): every plain run launches its kernels directly; 1: a run
+                                   repeated with the same device pointers, sizes and settings replays its
+                                   launch sequence, captured as a HIP graph the second time it is seen (it
+                                   pays for long runs of shallow queries: 3.3 instead of 3.8 us per k = 1
+                                   query on R-MAT scale 21; a graph launch's own cost outweighs it for
+                                   short runs) */
 };
 enum { KHOP_DIR_AUTO = 0, KHOP_DIR_PUSH = 1, KHOP_DIR_PULL = 2 };
 

@@ -44,6 +44,7 @@ KHOP_OPT_PUSH_ATOMIC = 9
 KHOP_OPT_PLAIN_GRID = 10
 KHOP_OPT_BATCH_GRID = 11
 KHOP_OPT_PLAIN_PIPELINE = 12
+KHOP_OPT_PLAIN_GRAPHS = 13
 KHOP_DIR_AUTO = 0
 KHOP_DIR_PUSH = 1
 KHOP_DIR_PULL = 2

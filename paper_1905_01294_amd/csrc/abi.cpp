@@ -1008,6 +1008,10 @@ int khop_set_option(khop_graph *g, int32_t option, int64_t value) {
                 if (value != 0 && value != 1) fail(KHOP_EINVAL, "plain pipeline must be 0 or 1");
                 P.plain_pipeline = (int)value;
                 break;
+            case KHOP_OPT_PLAIN_GRAPHS:
+                if (value != 0 && value != 1) fail(KHOP_EINVAL, "plain graphs must be 0 or 1");
+                P.plain_graphs = (int)value;
+                break;
             default:
                 fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
@@ -1032,6 +1036,7 @@ int khop_get_option(const khop_graph *g, int32_t option, int64_t *value) {
             case KHOP_OPT_PLAIN_GRID: *value = P.plain_grid; break;
             case KHOP_OPT_BATCH_GRID: *value = P.batch_grid; break;
             case KHOP_OPT_PLAIN_PIPELINE: *value = P.plain_pipeline; break;
+            case KHOP_OPT_PLAIN_GRAPHS: *value = P.plain_graphs; break;
             default: fail(KHOP_EINVAL, "unknown option " + std::to_string(option));
         }
     });

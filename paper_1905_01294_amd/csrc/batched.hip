@@ -998,7 +998,11 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
                const int32_t *h_ks_sorted, int64_t num_seeds, int64_t *d_counts, hipStream_t st,
                const uint64_t *d_vmask) {
     const Params P = params_of(g);
-    const HeavyTable ht = batch_heavy_table(g, P.batch_heavy);
+    // A level whose rows take G lanes per vertex chunks the in-edges of
+    // vertices above G/2 times the one-lane threshold: a lane group scans 4 G
+    // in-edges per step, and wide rows take their vertices by degree, so
+    // their scans are even without chunking
+    auto heavy_for = [&](int G) { return batch_heavy_table(g, P.batch_heavy * std::max(1, G / 2)); };
     // Slots come sorted by k, largest first, with the one-hop queries last:
     // those are answered from their seeds' rows and take no bit, so the rows
     // of the bitsets are W words wide for the other nslots slots.
@@ -1133,24 +1137,24 @@ void batch_run(khop_graph *g, BatchCtx *c, const int32_t *d_seeds, const int32_t
                                        lc.mode_l, lc.flag_prev);
                     ps.end(8.0 * n + n * fs_bits / 8.0);
                 }
-                launch_pull<1>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, fs_bits);
+                launch_pull<1>(g, c, heavy_for(1), P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, fs_bits);
                 break;
             }
             case 2:
                 launch_push<2>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
-                launch_pull<2>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
+                launch_pull<2>(g, c, heavy_for(2), P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
                 break;
             case 4:
                 launch_push<4>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
-                launch_pull<4>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
+                launch_pull<4>(g, c, heavy_for(4), P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
                 break;
             case 8:
                 launch_push<8>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
-                launch_pull<8>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
+                launch_pull<8>(g, c, heavy_for(8), P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
                 break;
             default:
                 launch_push<16>(g, c, P.batch_push_div, L, lc, wa, Wr, st, V, F, Nb);
-                launch_pull<16>(g, c, ht, P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
+                launch_pull<16>(g, c, heavy_for(16), P.batch_grid, L, lc, wa, Wr, st, V, F, Nb, 0);
                 break;
         }
         std::swap(F, Nb);

@@ -76,7 +76,26 @@ static HeavyTable build(khop_graph *g, HeavyTable &t, int threshold, int64_t chu
 // 256-edge chunks: one round of 4 in-edges per lane of a wave
 HeavyTable plain_heavy_table(khop_graph *g, int threshold) { return build(g, g->plain_heavy, threshold, 256); }
 
-HeavyTable batch_heavy_table(khop_graph *g, int threshold) { return build(g, g->batch_heavy, threshold, 1024); }
+// One table per threshold, kept until the graph is freed: the batched hops
+// of one run use several (the threshold grows with the lanes per vertex), and
+// each holds one record per 1024 in-edges of its heavy vertices.
+HeavyTable batch_heavy_table(khop_graph *g, int threshold) {
+    {
+        std::lock_guard<std::mutex> lk(g->heavy_mu);
+        for (const auto &t : g->batch_heavy)
+            if (t.threshold == threshold) return t;
+    }
+    HeavyTable t;
+    build(g, t, threshold, 1024);
+    std::lock_guard<std::mutex> lk(g->heavy_mu);
+    for (const auto &x : g->batch_heavy)
+        if (x.threshold == threshold) {  // built meanwhile by another thread
+            g->heavy_retired.push_back(t);
+            return x;
+        }
+    g->batch_heavy.push_back(t);
+    return t;
+}
 
 HeavyTable plain_heavy_table_current(khop_graph *g) {
     std::lock_guard<std::mutex> lk(g->heavy_mu);
@@ -116,7 +135,8 @@ void heavy_tables_free(khop_graph *g) {
     if (g->d_in_order) (void)hipFree(g->d_in_order);
     g->d_in_order = nullptr;
     free_table(g->plain_heavy);
-    free_table(g->batch_heavy);
+    for (auto &t : g->batch_heavy) free_table(t);
+    g->batch_heavy.clear();
     for (auto &t : g->heavy_retired) free_table(t);
     g->heavy_retired.clear();
 }

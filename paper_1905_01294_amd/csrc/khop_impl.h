@@ -55,11 +55,12 @@ struct Params {
     int pull_heavy = 4096; // plain bottom-up: 256-edge chunks above this in-degree
     int push_atomic_max = 65536;  // plain top-down: claim heads atomically up to this many frontier edges
     int batch_seeds = 1024;    // batched: seeds per launch (64 * words)
-    int batch_heavy = 256;     // batched bottom-up: wave-per-vertex above this in-degree
+    int batch_heavy = 256;     // batched bottom-up: chunked above this in-degree (one lane per vertex; G lanes: G/2 times it)
     int batch_push_div = 64;   // batched: top-down level when frontier arcs * div < total arcs
     int plain_grid = 4;        // plain hop and compaction kernels: blocks per compute unit
     int batch_grid = 16;       // batched bottom-up kernel: blocks per compute unit
     int plain_pipeline = 1;    // plain path: consecutive queries overlap by one launch (0: one at a time)
+    int plain_graphs = 0;      // plain path: repeated runs replay captured HIP graphs
 };
 
 struct PlainCtx;
@@ -161,7 +162,7 @@ struct khop_graph {
     int64_t *d_in_rowptr = nullptr;  // == d_rowptr when undirected
     int32_t *d_in_colidx = nullptr;
     khop::HeavyTable plain_heavy;    // chunks for the plain bottom-up hop
-    khop::HeavyTable batch_heavy;    // chunks for the batched bottom-up hop
+    std::vector<khop::HeavyTable> batch_heavy;  // chunks for the batched bottom-up hops, one table per threshold
     int32_t *d_in_order = nullptr;   // vertices by ascending in-degree (ties by id), built on first use
     std::vector<khop::HeavyTable> heavy_retired;  // replaced tables, freed with the graph
     std::mutex heavy_mu;             // guards the tables above
@@ -185,6 +186,8 @@ namespace khop {
 // plain.hip
 PlainCtx *plain_ctx_create(khop_graph *g);
 void plain_ctx_destroy(PlainCtx *c);
+// Whether the context replays repeated runs from captured HIP graphs (on by default).
+void plain_ctx_set_graphs(PlainCtx *c, bool on);
 // d_vmask (may be null): one bit per vertex, the vertices the searches may enter (the seeds are exempt).
 void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k,
                int64_t *d_counts, int64_t *d_te, hipStream_t st, const uint64_t *d_vmask = nullptr);

@@ -1429,6 +1429,25 @@ struct PlainCtx {
     // creates events) and take the chunk table the graph already has instead
     // of building one for a changed threshold.
     bool fixed = false;
+    // Launch sequences captured as HIP graphs, replayed when a run repeats
+    // one (same pointers, sizes and settings; the inputs' contents may differ).
+    struct Captured {
+        const int32_t *seeds = nullptr;
+        int64_t num = 0;
+        int32_t k = 0;
+        int64_t *counts = nullptr, *te = nullptr;
+        const uint64_t *vmask = nullptr;
+        Params P{};
+        const int32_t *hvert = nullptr;
+        int heavy = -1;
+        hipGraphExec_t exec = nullptr;  // null: seen once, not captured yet
+        bool failed = false;            // capture did not succeed: always launch directly
+        uint64_t used = 0;
+    };
+    std::vector<Captured> captured;
+    uint64_t clock = 0;
+    bool graphs = true;                 // replay repeated runs from captured graphs
+    hipStream_t cap_stream = nullptr;   // the stream runs are captured on
 };
 
 namespace {
@@ -1549,8 +1568,13 @@ PlainCtx *plain_ctx_create(khop_graph *g) {
     return c;
 }
 
+void plain_ctx_set_graphs(PlainCtx *c, bool on) { c->graphs = on; }
+
 void plain_ctx_destroy(PlainCtx *c) {
     if (!c) return;
+    for (auto &e : c->captured)
+        if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (c->arena) (void)hipFree(c->arena);
     if (c->h_flags) (void)hipHostFree(c->h_flags);
     delete c;
@@ -1628,16 +1652,10 @@ static void plain_deep(khop_graph *g, PlainCtx *c, const Params &P, const Graph 
     KHOP_HIP(hipGetLastError());
 }
 
-void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
-               int64_t *d_te, hipStream_t st, const uint64_t *d_vmask) {
-    if (num_seeds <= 0) return;
-    if (k == 0) {
-        plain_fill_zero_outputs(d_counts, d_te, num_seeds, st);
-        return;
-    }
-    const Params P = params_of(g);
-    const HeavyTable ht = c->fixed ? plain_heavy_table_current(g) : plain_heavy_table(g, P.pull_heavy);
-    khop_graph *const pg = c->fixed ? nullptr : g;  // profiled launches (none for a fixed context)
+// The launches of a run of queries (k >= 1) with the settings P and chunk table ht.
+static void plain_launch(khop_graph *g, PlainCtx *c, const Params &P, const HeavyTable &ht, khop_graph *pg,
+                         const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts, int64_t *d_te,
+                         hipStream_t st, const uint64_t *d_vmask) {
     const Grids gd = grids(g, P);
     Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
              ht.threshold};
@@ -1650,7 +1668,7 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     if (!P.plain_pipeline && num_seeds > 1) {
         // one query at a time: each a pipeline of one query, its own launch sequence
         for (int64_t i = 0; i < num_seeds; ++i)
-            plain_run(g, c, d_seeds + i, 1, k, d_counts + i, d_te ? d_te + i : nullptr, st, d_vmask);
+            plain_launch(g, c, P, ht, pg, d_seeds + i, 1, k, d_counts + i, d_te ? d_te + i : nullptr, st, d_vmask);
         return;
     }
     const int64_t nnz_in = g->nnz;
@@ -1716,6 +1734,105 @@ void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_s
     }
     hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, slot(m - 1));
     KHOP_HIP(hipGetLastError());
+}
+
+// Whether two settings give the same launches.
+static bool same_params(const Params &a, const Params &b) {
+    return a.dir_mode == b.dir_mode && a.alpha == b.alpha && a.beta == b.beta && a.pull_light == b.pull_light &&
+           a.pull_heavy == b.pull_heavy && a.push_atomic_max == b.push_atomic_max && a.plain_grid == b.plain_grid &&
+           a.plain_pipeline == b.plain_pipeline;
+}
+
+void plain_run(khop_graph *g, PlainCtx *c, const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts,
+               int64_t *d_te, hipStream_t st, const uint64_t *d_vmask) {
+    if (num_seeds <= 0) return;
+    if (k == 0) {
+        plain_fill_zero_outputs(d_counts, d_te, num_seeds, st);
+        return;
+    }
+    const Params P = params_of(g);
+    const HeavyTable ht = c->fixed ? plain_heavy_table_current(g) : plain_heavy_table(g, P.pull_heavy);
+    khop_graph *const pg = c->fixed ? nullptr : g;  // profiled launches (none for a fixed context)
+    // With the graph option, a run that repeats an earlier one (the same
+    // pointers, sizes and settings) replays the launch sequence captured the
+    // second time it was seen, as one HIP graph: the host's work per launch
+    // is what bounds a k = 1 query, but a graph launch costs more than that
+    // saves unless the run is long.  Profiled runs (their launches are
+    // bracketed by events), runs on the no-allocation scratch and deep runs
+    // (host checks between hop groups) always launch directly.
+    const bool capturable = c->graphs && P.plain_graphs && !c->fixed && k <= kDeepHops && !g->prof.on;
+    if (!capturable) {
+        plain_launch(g, c, P, ht, pg, d_seeds, num_seeds, k, d_counts, d_te, st, d_vmask);
+        return;
+    }
+    constexpr size_t kMaxCaptured = 8, kMaxSeen = 64;
+    PlainCtx::Captured *e = nullptr;
+    for (auto &x : c->captured)
+        if (x.seeds == d_seeds && x.num == num_seeds && x.k == k && x.counts == d_counts && x.te == d_te &&
+            x.vmask == d_vmask && x.hvert == ht.d_vert && x.heavy == ht.threshold && same_params(x.P, P)) {
+            e = &x;
+            break;
+        }
+    if (!e) {
+        // first sight: launch directly and remember the run (a full list
+        // forgets its oldest run that holds no graph)
+        if (c->captured.size() >= kMaxSeen) {
+            auto old = c->captured.end();
+            for (auto it = c->captured.begin(); it != c->captured.end(); ++it)
+                if (!it->exec && (old == c->captured.end() || it->used < old->used)) old = it;
+            if (old != c->captured.end()) c->captured.erase(old);
+        }
+        if (c->captured.size() < kMaxSeen) {
+            PlainCtx::Captured n;
+            n.seeds = d_seeds;
+            n.num = num_seeds;
+            n.k = k;
+            n.counts = d_counts;
+            n.te = d_te;
+            n.vmask = d_vmask;
+            n.P = P;
+            n.hvert = ht.d_vert;
+            n.heavy = ht.threshold;
+            n.used = ++c->clock;
+            c->captured.push_back(n);
+        }
+        plain_launch(g, c, P, ht, pg, d_seeds, num_seeds, k, d_counts, d_te, st, d_vmask);
+        return;
+    }
+    e->used = ++c->clock;
+    if (!e->exec && !e->failed) {
+        size_t held = 0;
+        for (const auto &x : c->captured) held += x.exec != nullptr;
+        if (held >= kMaxCaptured) {
+            e->failed = true;  // the context holds its share of graphs: this run launches directly
+        } else {
+            if (!c->cap_stream) KHOP_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            hipError_t err = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+            if (err == hipSuccess) {
+                try {
+                    plain_launch(g, c, P, ht, nullptr, d_seeds, num_seeds, k, d_counts, d_te, c->cap_stream,
+                                 d_vmask);
+                } catch (...) {
+                    err = hipErrorUnknown;
+                }
+                const hipError_t end = hipStreamEndCapture(c->cap_stream, &graph);
+                if (err == hipSuccess) err = end;
+            }
+            if (err == hipSuccess) err = hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (err != hipSuccess) {
+                (void)hipGetLastError();
+                e->exec = nullptr;
+                e->failed = true;
+            }
+        }
+    }
+    if (!e->exec) {
+        plain_launch(g, c, P, ht, pg, d_seeds, num_seeds, k, d_counts, d_te, st, d_vmask);
+        return;
+    }
+    KHOP_HIP(hipGraphLaunch(e->exec, st));
 }
 
 void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int32_t *d_dist, int64_t *d_count,

@@ -238,6 +238,7 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         }
         KHOP_HIP(hipMemcpy(b.d_seeds, seeds.data(), seeds.size() * 4, hipMemcpyHostToDevice));
         b.pc = khop::plain_ctx_create(g);
+        khop::plain_ctx_set_graphs(b.pc, false);  // every timing launches its kernels as they are
         // the search works on a copy; each timing installs it (other callers see a consistent set)
         khop::Params P = saved;
         P.dir_mode = KHOP_DIR_AUTO;
@@ -290,7 +291,7 @@ extern "C" int khop_autotune(khop_graph *g, int32_t seeds_per_launch) {
         for (int i = 0; i < 620; ++i) ks_proto[(size_t)i] = i < 300 ? 1 : i < 600 ? 2 : i < 610 ? 3 : 6;
         auto batch_cost = [&] {
             install();
-            return best_of([&] { return time_batched(b, ks) + time_batched(b, ks_proto); }, 2);
+            return best_of([&] { return time_batched(b, ks) + time_batched(b, ks_proto); }, 3);
         };
         std::vector<int> per = seeds_per_launch ? std::vector<int>{seeds_per_launch}
                                                 : std::vector<int>{64, 128, 256, 512, 1024};

@@ -229,6 +229,40 @@ def test_top_down_queues_split_over_waves(K, grid, pam):
     g.free()
 
 
+@pytest.mark.parametrize("k", [1, 2, 3, 6])
+def test_repeated_runs_replay_captured_launches(K, k):
+    """A run repeated with the same device pointers, sizes and settings replays its launch sequence as a
+    captured HIP graph: every replay, with new seeds written into the same buffer, other work on the
+    context in between and a setting changed half way, equals the oracle."""
+    import torch
+    el = graphgen.chung_lu(60_000, 900_000, 6.0, seed=12)
+    g = K.Graph.from_edgelist(el)
+    og = oracle.OracleGraph.from_edgelist(el)
+    dev = torch.device("cuda:0")
+    g.set_option(K.KHOP_OPT_PLAIN_GRAPHS, 1)
+    assert g.get_option(K.KHOP_OPT_PLAIN_GRAPHS) == 1
+    pool = graphgen.draw_seeds(el, 400, seed=3)
+    d_s = torch.empty(64, dtype=torch.int32, device=dev)
+    d_c = torch.empty(64, dtype=torch.int64, device=dev)
+    d_te = torch.empty(64, dtype=torch.int64, device=dev)
+    for rep in range(6):
+        seeds = pool[64 * rep:64 * (rep + 1)] if rep < 6 else pool[:64]
+        d_s.copy_(torch.from_numpy(seeds))
+        d_c.fill_(-7)
+        d_te.fill_(-7)
+        if rep == 3:
+            g.set_option(K.KHOP_OPT_ALPHA, 3)  # new settings: a new launch sequence, seen, then captured
+        g.count_dev(d_s, k, d_c, d_te)
+        torch.cuda.synchronize()
+        oc, ote = og.count(seeds, k)
+        assert np.array_equal(d_c.cpu().numpy(), oc) and np.array_equal(d_te.cpu().numpy(), ote), (k, rep)
+        # other work on the graph's contexts between the replays
+        assert np.array_equal(g.count(pool[300:310], 2), og.count(pool[300:310], 2)[0])
+        dist = g.bfs(int(pool[350 + rep]), -1)[0]
+        assert np.array_equal(dist, og.distances(int(pool[350 + rep]), 2**31 - 1))
+    g.free()
+
+
 @pytest.mark.parametrize("alpha,beta", [(1, 2), (14, 24), (2, 1000), (1000, 2), (1, 100000)])
 def test_direction_switch_points(K, alpha, beta):
     """Automatic direction with thresholds that move the top-down/bottom-up switches to other hops (a
