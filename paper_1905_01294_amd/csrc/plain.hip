@@ -246,22 +246,34 @@ __device__ __forceinline__ uint32_t nonzero_bytes(uint4 x) {
     return f(x.x) | (f(x.y) << 4) | (f(x.z) << 8) | (f(x.w) << 12);
 }
 
-// Marks head v in the byte map and its word in the summary (plain stores).
-__device__ __forceinline__ void mark(const State &s, int32_t v) {
+// Marks head v in the byte map and, with `summary`, its word in the summary
+// (plain stores).
+__device__ __forceinline__ void mark(const State &s, int32_t v, bool summary) {
     s.nextb[v] = 1;
-    s.nsum[v >> 6] = 1;
+    if (summary) s.nsum[v >> 6] = 1;
 }
+
+// A last hop's marks are counted by a later launch that reads, on a graph of
+// up to this many 64-vertex words (a byte map of up to 4 MB), the whole byte
+// map: one sequential read costs less than a summary store beside every
+// scattered mark.  On larger graphs the marks keep a summary, and only the
+// flagged words are read.  (The marks of an inner hop always keep one: the
+// compaction after the hop reads them.)
+constexpr int64_t kMarkSummaryWords = 65536;
+__device__ __forceinline__ bool last_marks_summary(const Graph &g) { return g.nw > kMarkSummaryWords; }
 
 // The byte marks a byte-mode last hop left on the 64 vertices of word w that
 // were unvisited (visited word vis); the marks and the word's summary byte
-// are cleared.  The byte map is padded to whole words.
-__device__ __forceinline__ int64_t close_marks_word(const State &s, int64_t w, uint64_t vis) {
-    s.nsum[w] = 0;
+// are cleared, and `had` says whether there were any.  The byte map is padded
+// to whole words.
+__device__ __forceinline__ int64_t close_marks_word(const State &s, int64_t w, uint64_t vis, bool &had) {
     uint4 *mb = (uint4 *)(s.nextb + w * kWave);
     uint64_t m = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) m |= (uint64_t)nonzero_bytes(mb[j]) << (16 * j);
+    had = m != 0;
     if (!m) return 0;
+    s.nsum[w] = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) mb[j] = make_uint4(0, 0, 0, 0);
     return __popcll(m & ~vis);
@@ -397,17 +409,20 @@ __global__ void __launch_bounds__(kBlock) plain_init_kernel(PlainCtl *ctl, Graph
 __global__ void __launch_bounds__(kBlock) plain_close_kernel(PlainCtl *ctl_last, PlainCtl *ctl_before,
                                                             int fin_before, Graph g, State s_last, int64_t *units) {
     if (ctl_last->last_bytes) {
+        const bool summary = last_marks_summary(g);
         int64_t fresh = 0, flagged = 0;
         for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < g.nw; w += (int64_t)gridDim.x * kBlock)
-            if (s_last.nsum[w]) {
-                fresh += close_marks_word(s_last, w, s_last.V[w]);
-                ++flagged;
+            if (!summary || s_last.nsum[w]) {
+                bool had;
+                fresh += close_marks_word(s_last, w, s_last.V[w], had);
+                flagged += had;
             }
         fresh = wave_sum(fresh);
         flagged = wave_sum(flagged);
         if (lane_id() == 0) add_tail(ctl_last, (int64_t)blockIdx.x * kWavesPerBlock + threadIdx.x / kWave, fresh);
+        // the summary bytes (or the whole byte map), then the marks cleared and visited word of each flagged word
         if (lane_id() == 0) unit_add(units, 0, 72 * flagged);
-        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, g.nw);
+        if (blockIdx.x == 0 && threadIdx.x == 0) unit_add(units, 0, summary ? g.nw : 64 * g.nw);
     }
     if (blockIdx.x == 0 && threadIdx.x < kWave && fin_before) finalize(ctl_before);
 }
@@ -439,22 +454,15 @@ __device__ __forceinline__ void push_claim(int L, const Graph &g, const State &s
     append_one(s, cur, L, v, vb, od, id);
 }
 
-// One frontier edge's head v: a byte mark (the visited test happens when the
-// marks are turned into frontier words or counted), or a claim.
-__device__ __forceinline__ void push_edge(int L, int mode, const Graph &g, const State &s, RegRec *cur, uint64_t *Fn,
-                                          int32_t v) {
-    if (mode == MODE_PUSH_BYTES) {
-        mark(s, v);
-    } else if (!((s.V[v >> 6] >> (v & 63)) & 1ull)) {
-        push_claim(L, g, s, cur, Fn, v);
-    }
-}
-
 constexpr int kWin = 4;  // windows of 64 frontier edges in flight per wave
 
-__device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const int32_t *qcnt, const Graph &g,
-                         const State &s, RegRec *cur, uint64_t *smask, int64_t *ent, int64_t *units,
-                         const Part &pt) {
+// A top-down hop: in byte mode each frontier edge's head gets a byte mark
+// (the visited test happens when the marks are turned into frontier words or
+// counted; `summary` flags its word too), else heads seen unvisited are
+// claimed.
+__device__ void push_hop(int L, int mode, bool summary, int64_t E, const int64_t *epre, const int32_t *qcnt,
+                         const Graph &g, const State &s, RegRec *cur, uint64_t *smask, int64_t *ent,
+                         int64_t *units, const Part &pt) {
     const int lane = lane_id();
     const int64_t nwaves = pt.nb * kWavesPerBlock;
     const int64_t wid = pt.bid * kWavesPerBlock + threadIdx.x / kWave;
@@ -513,7 +521,7 @@ __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const 
                 if (mode == MODE_PUSH_BYTES) {
 #pragma unroll
                     for (int r = 0; r < kWin; ++r)
-                        if (v[r] >= 0) mark(s, v[r]);
+                        if (v[r] >= 0) mark(s, v[r], summary);
                 } else {
                     uint64_t vw[kWin];
 #pragma unroll
@@ -592,7 +600,7 @@ __device__ void push_hop(int L, int mode, int64_t E, const int64_t *epre, const 
             if (mode == MODE_PUSH_BYTES) {
 #pragma unroll
                 for (int r = 0; r < kWin; ++r)
-                    if (v[r] >= 0) mark(s, v[r]);
+                    if (v[r] >= 0) mark(s, v[r], summary);
             } else {
                 uint64_t vw[kWin];
 #pragma unroll
@@ -1073,7 +1081,8 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
         pull_hop(L, last, g, s, light, hc, cur, wb, &found, units, pt);
         found = shfl64(found, 0);
     } else {
-        push_hop(L, mode, E, s_epre, s_qcnt, g, s, cur, s_mask[wv], s_bv[wv], units, pt);
+        push_hop(L, mode, !last || last_marks_summary(g), E, s_epre, s_qcnt, g, s, cur, s_mask[wv], s_bv[wv], units,
+                 pt);
     }
     if (last && lane == 0) add_tail(ctl, wid, found);
 }
@@ -1124,11 +1133,13 @@ __global__ void __launch_bounds__(kBlock) plain_step_kernel(PlainCtl *ctl_last, 
     const int64_t nsw = nvalid ? (nseed >> 6) : -1;
     const uint64_t nsbit = nvalid ? (1ull << (nseed & 63)) : 0;
     int64_t fresh = 0, flagged = 0, rewritten = 0;
+    const bool summary = last_marks_summary(g);
     // each wave takes whole 64-word blocks (kBlock is a multiple of 64)
     for (int64_t w = pt.bid * kBlock + t; w < g.nw; w += pt.nb * kBlock) {
-        if (marks && sm.nsum[w]) {
-            fresh += close_marks_word(sm, w, sm.V[w]);
-            ++flagged;
+        if (marks && (!summary || sm.nsum[w])) {
+            bool had;
+            fresh += close_marks_word(sm, w, sm.V[w], had);
+            flagged += had;
         }
         if (bk.qn >= 0) {
             // only the blocks the state's last query set bits in, and the new seed's
@@ -1152,7 +1163,7 @@ __global__ void __launch_bounds__(kBlock) plain_step_kernel(PlainCtl *ctl_last, 
         if (lane_id() == 0) add_tail(bk.ctl_marks, pt.bid * kWavesPerBlock + t / kWave, fresh);
         // the summary bytes, then the marks and visited word of each flagged word
         if (lane_id() == 0) unit_add(units, 0, 72 * flagged);
-        if (pt.bid == 0 && t == 0) unit_add(units, 0, g.nw);
+        if (pt.bid == 0 && t == 0) unit_add(units, 0, summary ? g.nw : 64 * g.nw);
     }
     // the last block writes the finished count, then sets up the next query
     // (possibly in the same slot)
