@@ -1706,7 +1706,11 @@ static void plain_launch(khop_graph *g, PlainCtx *c, const Params &P, const Heav
         const StepBook bk{qm >= 0 ? slot(qm) : nullptr, ps_j.fin >= 0 ? slot(ps_j.fin) : nullptr,
                           qn >= 0 ? slot(qn) : nullptr, qn, d_seeds, d_counts, d_te, pam, nnz_in, (int32_t)k,
                           (int32_t)P.dir_mode, (int32_t)P.alpha, (int32_t)P.beta};
-        const int64_t nb_last = ps_j.last >= 0 ? gd.hop : 0, nb_h1 = ps_j.h1 >= 0 ? h1_grid : 0;
+        // a k = 2 query's last hop expands only its seed's neighbors' rows:
+        // two blocks per compute unit carry it with less per-block work
+        // (dispatch, region prefix) than the hop grid
+        const int64_t last_grid = k == 2 ? std::min<int64_t>(gd.hop, 2 * (int64_t)g->cu_count) : gd.hop;
+        const int64_t nb_last = ps_j.last >= 0 ? last_grid : 0, nb_h1 = ps_j.h1 >= 0 ? h1_grid : 0;
         const int64_t nb_book = (qm >= 0 || qn >= 0) ? c->init_grid : 0;
         {
             ProfScope ps(pg, KK_PLAIN_STEP, st);
