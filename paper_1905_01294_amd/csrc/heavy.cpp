@@ -26,24 +26,43 @@ static HeavyTable build(khop_graph *g, HeavyTable &t, int threshold, int64_t chu
     std::lock_guard<std::mutex> lk(g->heavy_mu);
     if (t.threshold == threshold && t.chunk == chunk) return t;
     HeavyTable nt;
-    std::vector<int32_t> vert;
-    std::vector<int64_t> begin, end;
+    // Items go chunk-major: the first chunk of every heavy vertex, then the
+    // second of every vertex that has one, and so on.  Waves take items in
+    // order, so a vertex's later chunks mostly start after its first one has
+    // finished, and a chunk whose vertex an earlier chunk already settled
+    // (found, or holding every needed bit) stops after one load.
+    std::vector<int64_t> at;  // at[j]: first item of the j-th chunks
+    int64_t items = 0;
     {
-        int64_t items = 0;
-        for (int64_t v = 0; v < g->n; ++v)
-            if (g->h_indeg[v] > threshold) items += (g->h_indeg[v] + chunk - 1) / chunk;
-        vert.reserve((size_t)items);
-        begin.reserve((size_t)items);
-        end.reserve((size_t)items);
+        std::vector<int64_t> nchunks;  // vertices with exactly c chunks, at c
+        for (int64_t v = 0; v < g->n; ++v) {
+            const int64_t d = g->h_indeg[v];
+            if (d <= threshold) continue;
+            const int64_t c = (d + chunk - 1) / chunk;
+            if ((int64_t)nchunks.size() <= c) nchunks.resize((size_t)c + 1, 0);
+            ++nchunks[(size_t)c];
+            items += c;
+        }
+        // the j-th chunks number the vertices with more than j chunks
+        at.assign(nchunks.size(), 0);
+        int64_t more = 0, pos = items;
+        for (size_t c = nchunks.size(); c-- > 1;) {
+            more += nchunks[c];
+            pos -= more;
+            at[c - 1] = pos;
+        }
     }
+    std::vector<int32_t> vert((size_t)items);
+    std::vector<int64_t> begin((size_t)items), end((size_t)items);
     int64_t off = 0;
     for (int64_t v = 0; v < g->n; ++v) {
         const int64_t d = g->h_indeg[v];
         if (d > threshold)
-            for (int64_t b = off; b < off + d; b += chunk) {
-                vert.push_back((int32_t)v);
-                begin.push_back(b);
-                end.push_back(std::min(off + d, b + chunk));
+            for (int64_t j = 0; j * chunk < d; ++j) {
+                const int64_t i = at[(size_t)j]++;
+                vert[(size_t)i] = (int32_t)v;
+                begin[(size_t)i] = off + j * chunk;
+                end[(size_t)i] = std::min(off + d, off + (j + 1) * chunk);
             }
         off += d;
     }
