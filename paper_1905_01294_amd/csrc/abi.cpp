@@ -471,7 +471,34 @@ static void load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, 
             KHOP_HIP(hipMemcpy(*ci, c.colidx.data(), c.colidx.size() * 4, hipMemcpyHostToDevice));
         KHOP_HIP(hipMemset(*ci + c.colidx.size(), 0, (size_t)khop::kColidxPad * 4));
     };
+    // the probe in-neighbor of each vertex (threads over vertex ranges)
+    std::vector<int32_t> probe((size_t)g->n, -1);
+    {
+        const HostCSR &in = directed ? in_csr : out_csr;
+        const int T = host_threads();
+        std::vector<std::thread> pool;
+        for (int t = 0; t < T; ++t)
+            pool.emplace_back([&, t] {
+                const int64_t lo = g->n * t / T, hi = g->n * (t + 1) / T;
+                for (int64_t v = lo; v < hi; ++v) {
+                    int64_t best = -1;
+                    for (int64_t x = in.rowptr[v]; x < in.rowptr[v + 1]; ++x) {
+                        const int32_t u = in.colidx[x];
+                        if (best < 0 || g->h_outdeg[u] > best) {
+                            best = g->h_outdeg[u];
+                            probe[(size_t)v] = u;
+                        }
+                    }
+                }
+            });
+        for (auto &th : pool) th.join();
+    }
     try {
+        if (hipMalloc(&g->d_probe, (size_t)g->n * 4) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(KHOP_ENOMEM, "device allocation for the probe in-neighbors failed");
+        }
+        KHOP_HIP(hipMemcpy(g->d_probe, probe.data(), (size_t)g->n * 4, hipMemcpyHostToDevice));
         upload(out_csr, &g->d_rowptr, &g->d_colidx);
         if (directed) {
             upload(in_csr, &g->d_in_rowptr, &g->d_in_colidx);
@@ -531,6 +558,7 @@ int graph_free(khop_graph *g) {
         if (g->d_in_colidx && g->d_in_colidx != g->d_colidx) (void)hipFree(g->d_in_colidx);
         if (g->d_rowptr) (void)hipFree(g->d_rowptr);
         if (g->d_colidx) (void)hipFree(g->d_colidx);
+        if (g->d_probe) (void)hipFree(g->d_probe);
         heavy_tables_free(g);
         if (g->prof.d_units) (void)hipFree(g->prof.d_units);
         for (auto e : g->prof.events) (void)hipEventDestroy(e);

@@ -103,6 +103,7 @@ struct Graph {
     const int32_t *__restrict__ colidx;
     const int64_t *__restrict__ in_rowptr;
     const int32_t *__restrict__ in_colidx;
+    const int32_t *__restrict__ probe;  // per vertex: its in-neighbor of largest out-degree, -1 with none
     int64_t n;
     int64_t nw;  // 64-vertex words
     int directed;
@@ -669,35 +670,45 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
     for (int64_t w0 = wb0; w0 < wb1; w0 += kPullWords) {
         uint64_t vis[kPullWords];
         bool unv[kPullWords];
+        int32_t pr[kPullWords];
 #pragma unroll
         for (int i = 0; i < kPullWords; ++i) {
+            // the visited word and the probe in-neighbors in one round trip; a
+            // vertex with no in-edge (probe -1) is never found bottom-up
             const int64_t w = w0 + i, v = w * kWave + lane;
+            const bool inr = w < wb1 && v < g.n;
             vis[i] = w < wb1 ? s.V[w] : ~0ull;
-            unv[i] = w < wb1 && v < g.n && !((vis[i] >> lane) & 1ull);
+            pr[i] = inr ? g.probe[v] : -1;
+            unv[i] = inr && !((vis[i] >> lane) & 1ull) && pr[i] >= 0;
         }
         bool anyu = false;
 #pragma unroll
         for (int i = 0; i < kPullWords; ++i) anyu |= unv[i];
         if (!ballot(anyu)) continue;
+        // the row pointers, and beside them the probe's frontier word
         int64_t b[kPullWords], e[kPullWords];
+        uint64_t pw[kPullWords];
 #pragma unroll
         for (int i = 0; i < kPullWords; ++i) {
             const int64_t v = (w0 + i) * kWave + lane;
             b[i] = unv[i] ? g.in_rowptr[v] : 0;
             e[i] = unv[i] ? g.in_rowptr[v + 1] : 0;
+            pw[i] = Fc[unv[i] ? (uint32_t)pr[i] >> 6 : 0u];
         }
-        // every unvisited vertex first scans up to `light` in-edges alone: on a
-        // wide frontier most find a hit there, whatever their degree
+        // a vertex whose probe is in the frontier is found without reading an
+        // in-edge; every other unvisited vertex first scans up to `light`
+        // in-edges alone: on a wide frontier most find a hit there, whatever
+        // their degree
         bool found[kPullWords], act[kPullWords];
         int64_t examined[kPullWords], x[kPullWords], le[kPullWords];
 #pragma unroll
         for (int i = 0; i < kPullWords; ++i) {
             const int64_t d = e[i] - b[i];
-            found[i] = false;
+            found[i] = unv[i] && d <= g.heavy && ((pw[i] >> ((uint32_t)pr[i] & 63u)) & 1ull);
             examined[i] = 0;
             x[i] = b[i];
             le[i] = b[i] + std::min<int64_t>(d, light);
-            act[i] = unv[i] && d > 0 && d <= g.heavy;
+            act[i] = unv[i] && !found[i] && d <= g.heavy;
         }
         bool going = false;
 #pragma unroll
@@ -826,8 +837,8 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
         }
     }
     if (units && lane == 0) {
-        // 4 B per examined in-edge, 16 B of row pointers per scanned vertex
-        unit_add(units, 0, 4 * (c_pe + h_ex) + 16 * c_pv);
+        // 4 B per examined in-edge, 16 B of row pointers and the 4-byte probe per scanned vertex
+        unit_add(units, 0, 4 * (c_pe + h_ex) + 20 * c_pv);
         if (wid == 0) unit_add(units, 0, 2 * ((g.n + 7) / 8));
     }
 }
@@ -1668,7 +1679,7 @@ static void plain_launch(khop_graph *g, PlainCtx *c, const Params &P, const Heav
                          const int32_t *d_seeds, int64_t num_seeds, int32_t k, int64_t *d_counts, int64_t *d_te,
                          hipStream_t st, const uint64_t *d_vmask) {
     const Grids gd = grids(g, P);
-    Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
+    Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->d_probe, g->n, (g->n + 63) / 64, g->directed,
              ht.threshold};
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
     if (k > kDeepHops) {
@@ -1855,7 +1866,7 @@ void plain_bfs(khop_graph *g, PlainCtx *c, int32_t seed, int32_t max_depth, int3
     const Params P = params_of(g);
     const HeavyTable ht = plain_heavy_table(g, P.pull_heavy);
     const Grids gd = grids(g, P);
-    Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->n, (g->n + 63) / 64, g->directed,
+    Graph gr{g->d_rowptr, g->d_colidx, g->d_in_rowptr, g->d_in_colidx, g->d_probe, g->n, (g->n + 63) / 64, g->directed,
              ht.threshold};
     HeavyChunks hc{ht.d_vert, ht.d_begin, ht.d_end, ht.n};
     const int64_t pam = (int64_t)P.push_atomic_max;
