@@ -471,24 +471,47 @@ static void load_csr(const int32_t *src, const int32_t *dst, int64_t num_edges, 
             KHOP_HIP(hipMemcpy(*ci, c.colidx.data(), c.colidx.size() * 4, hipMemcpyHostToDevice));
         KHOP_HIP(hipMemset(*ci + c.colidx.size(), 0, (size_t)khop::kColidxPad * 4));
     };
-    // the probe in-neighbor of each vertex (threads over vertex ranges)
+    // Each in-row starts with its four in-neighbors of largest out-degree
+    // (ties: the lowest id), in that order, the rest following in ascending
+    // order: a bottom-up scan that stops at its first frontier in-neighbor
+    // meets the likeliest ones first.  The first of them is the vertex's
+    // probe (-1: no in-edge).  Threads take vertex ranges.
     std::vector<int32_t> probe((size_t)g->n, -1);
     {
-        const HostCSR &in = directed ? in_csr : out_csr;
+        HostCSR &in = directed ? in_csr : out_csr;
         const int T = host_threads();
         std::vector<std::thread> pool;
         for (int t = 0; t < T; ++t)
             pool.emplace_back([&, t] {
+                constexpr int kTop = 4;
+                std::vector<int32_t> rest;
                 const int64_t lo = g->n * t / T, hi = g->n * (t + 1) / T;
                 for (int64_t v = lo; v < hi; ++v) {
-                    int64_t best = -1;
-                    for (int64_t x = in.rowptr[v]; x < in.rowptr[v + 1]; ++x) {
-                        const int32_t u = in.colidx[x];
-                        if (best < 0 || g->h_outdeg[u] > best) {
-                            best = g->h_outdeg[u];
-                            probe[(size_t)v] = u;
-                        }
+                    int32_t *row = in.colidx.data() + in.rowptr[v];
+                    const int64_t d = in.rowptr[v + 1] - in.rowptr[v];
+                    if (d == 0) continue;
+                    int64_t top[kTop];  // positions in the row, best first
+                    int nt = 0;
+                    for (int64_t x = 0; x < d; ++x) {
+                        const int64_t od = g->h_outdeg[row[x]];
+                        int j = nt;  // ascending ids: a later entry wins only with a larger degree
+                        while (j > 0 && g->h_outdeg[row[top[j - 1]]] < od) --j;
+                        if (j >= kTop) continue;
+                        for (int q = std::min(nt, kTop - 1); q > j; --q) top[q] = top[q - 1];
+                        top[j] = x;
+                        nt = std::min(nt + 1, kTop);
                     }
+                    rest.clear();
+                    int32_t first[kTop];
+                    for (int q = 0; q < nt; ++q) first[q] = row[top[q]];
+                    for (int64_t x = 0; x < d; ++x) {
+                        bool chosen = false;
+                        for (int q = 0; q < nt; ++q) chosen |= top[q] == x;
+                        if (!chosen) rest.push_back(row[x]);
+                    }
+                    std::copy(first, first + nt, row);
+                    std::copy(rest.begin(), rest.end(), row + nt);
+                    probe[(size_t)v] = row[0];
                 }
             });
         for (auto &th : pool) th.join();

@@ -162,8 +162,8 @@ struct khop_graph {
     int64_t *d_in_rowptr = nullptr;  // == d_rowptr when undirected
     int32_t *d_in_colidx = nullptr;
     // Per vertex, the in-neighbor of largest out-degree (ties: the lowest id),
-    // -1 for a vertex with no in-edge: the plain bottom-up hop tests it before
-    // reading the vertex's in-edges.
+    // which graph load puts first in the vertex's in-row; -1 for a vertex with
+    // no in-edge.  The plain bottom-up hop tests it before reading the row.
     int32_t *d_probe = nullptr;
     khop::HeavyTable plain_heavy;    // chunks for the plain bottom-up hop
     std::vector<khop::HeavyTable> batch_heavy;  // chunks for the batched bottom-up hops, one table per threshold

@@ -103,7 +103,7 @@ struct Graph {
     const int32_t *__restrict__ colidx;
     const int64_t *__restrict__ in_rowptr;
     const int32_t *__restrict__ in_colidx;
-    const int32_t *__restrict__ probe;  // per vertex: its in-neighbor of largest out-degree, -1 with none
+    const int32_t *__restrict__ probe;  // per vertex: the first entry of its in-row (largest out-degree), -1 with none
     int64_t n;
     int64_t nw;  // 64-vertex words
     int directed;
@@ -697,8 +697,8 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
         }
         // a vertex whose probe is in the frontier is found without reading an
         // in-edge; every other unvisited vertex first scans up to `light`
-        // in-edges alone: on a wide frontier most find a hit there, whatever
-        // their degree
+        // in-edges alone, after the probe (the first in-edge of its row): on a
+        // wide frontier most find a hit there, whatever their degree
         bool found[kPullWords], act[kPullWords];
         int64_t examined[kPullWords], x[kPullWords], le[kPullWords];
 #pragma unroll
@@ -706,9 +706,9 @@ __device__ void pull_hop(int L, bool last, const Graph &g, const State &s, int l
             const int64_t d = e[i] - b[i];
             found[i] = unv[i] && d <= g.heavy && ((pw[i] >> ((uint32_t)pr[i] & 63u)) & 1ull);
             examined[i] = 0;
-            x[i] = b[i];
+            x[i] = b[i] + 1;
             le[i] = b[i] + std::min<int64_t>(d, light);
-            act[i] = unv[i] && !found[i] && d <= g.heavy;
+            act[i] = unv[i] && !found[i] && d <= g.heavy && x[i] < le[i];
         }
         bool going = false;
 #pragma unroll
