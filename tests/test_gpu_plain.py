@@ -464,3 +464,40 @@ def test_pipeline_hub_and_leaf_seeds(K, mode):
         assert np.array_equal(c[ok], oc) and np.array_equal(t[ok], ote), (mode, k)
         assert (c[~ok] == -1).all() and (t[~ok] == -1).all(), (mode, k)
     g.free()
+
+
+@pytest.mark.parametrize("heavy", [2, 65536])
+@pytest.mark.parametrize("mode", MODES)
+def test_bottom_up_probe_hits_and_misses(K, mode, heavy):
+    # Each target t has two in-neighbors: the hub H (out-degree 200, so H is
+    # every target's probe) and its own low-degree vertex l_t.  From seed S1
+    # hop 1 reaches every l_t and H only at hop 3, so a bottom-up hop 2 finds
+    # the targets past a probe that is not in the frontier; from seed S2 hop 1
+    # reaches H, and the probe finds them.  Extra in-edges of low out-degree
+    # give some targets longer rows (past the reordered first four), and a
+    # small chunk threshold sends those to the chunk table instead.
+    H, T = 0, 200
+    tg = np.arange(1, T + 1)
+    lo = tg + T
+    s1, s2, c1, c2 = 2 * T + 1, 2 * T + 2, 2 * T + 3, 2 * T + 4
+    n = 2 * T + 5
+    src = [np.full(T, H), lo, np.full(T, s1), [s1, c1, c2, s2]]
+    dst = [tg, tg, lo, [c1, c2, H, H]]
+    rng = np.random.default_rng(7)
+    extra_t = rng.choice(tg, size=60, replace=False)
+    for t in extra_t:
+        src.append(rng.choice(lo, size=5, replace=False))
+        dst.append(np.full(5, t))
+    src = np.concatenate([np.asarray(x) for x in src]).astype(np.int32)
+    dst = np.concatenate([np.asarray(x) for x in dst]).astype(np.int32)
+    g = K.Graph(src, dst, n, True)
+    _set_mode(K, g, mode)
+    g.set_option(K.KHOP_OPT_PULL_HEAVY, heavy)
+    og = oracle.OracleGraph(src, dst, n, True)
+    seeds = np.array([s1, s2, H, c1, int(lo[0]), int(tg[0])], np.int32)
+    _say("probe graph", mode, "heavy", heavy)
+    for k in (1, 2, 3, 4, 6):
+        c, te = g.count(seeds, k, with_te=True)
+        oc, ote = og.count(seeds, k)
+        assert np.array_equal(c, oc) and np.array_equal(te, ote), (mode, heavy, k)
+    g.free()
