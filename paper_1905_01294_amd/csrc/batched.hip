@@ -307,17 +307,16 @@ __device__ __forceinline__ void wave_lds_sync() {
 // together; without it, in id order, so that a wave's rows are contiguous and
 // its vertices share one frontier bitmap word (one-word rows: the scattered
 // row accesses and per-vertex bitmap claims of the sorted order cost more than
-// the uneven scans).
+// the uneven scans).  Registers are capped for eight waves per SIMD: its
+// latency is hidden by waves in flight (at seven the 1024-seed batches ran 2%
+// slower).
 template <int G, int FS = 0>
-__global__ void __launch_bounds__(kBlock) batch_pull_kernel(const int32_t *__restrict__ order,
-                                                           const int64_t *__restrict__ in_rowptr,
-                                                           const int32_t *__restrict__ in_colidx,
-                                                           uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
-                                                           const void *__restrict__ Fs,
-                                                           uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
-                                                           const uint64_t *__restrict__ act, int heavy,
-                                                           FrontierBits fb, const int32_t *mode_l,
-                                                           const int32_t *prev_flag, int32_t *flag, int64_t *units) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8)))
+batch_pull_kernel(const int32_t *__restrict__ order, const int64_t *__restrict__ in_rowptr,
+                  const int32_t *__restrict__ in_colidx, uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
+                  const void *__restrict__ Fs, uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
+                  const uint64_t *__restrict__ act, int heavy, FrontierBits fb, const int32_t *mode_l,
+                  const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;  // empty frontier: nothing left to find
     if (mode_l && *mode_l == HOP_PUSH) return;  // this hop went top-down
     {
