@@ -315,8 +315,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 
 batch_pull_kernel(const int32_t *__restrict__ order, const int64_t *__restrict__ in_rowptr,
                   const int32_t *__restrict__ in_colidx, uint64_t *__restrict__ V, const uint64_t *__restrict__ F,
                   const void *__restrict__ Fs, uint64_t *__restrict__ Fn, int64_t n, int W, int wact,
-                  const uint64_t *__restrict__ act, int heavy, FrontierBits fb, const int32_t *mode_l,
-                  const int32_t *prev_flag, int32_t *flag, int64_t *units) {
+                  const uint64_t *__restrict__ act, int heavy, int64_t first, FrontierBits fb,
+                  const int32_t *mode_l, const int32_t *prev_flag, int32_t *flag, int64_t *units) {
     if (*prev_flag == 0) return;  // empty frontier: nothing left to find
     if (mode_l && *mode_l == HOP_PUSH) return;  // this hop went top-down
     {
@@ -344,8 +344,8 @@ batch_pull_kernel(const int32_t *__restrict__ order, const int64_t *__restrict__
     const int64_t nwaves = (int64_t)gridDim.x * kWavesPerBlock;
     bool any = false;
     int64_t examined = 0, scanned = 0, gathered = 0, fresh = 0;
-    for (int64_t wvi = (int64_t)blockIdx.x * kWavesPerBlock + wv; wvi * VPW < n; wvi += nwaves) {
-        const int64_t idx = wvi * VPW + grp;
+    for (int64_t wvi = (int64_t)blockIdx.x * kWavesPerBlock + wv; first + wvi * VPW < n; wvi += nwaves) {
+        const int64_t idx = first + wvi * VPW + grp;
         const int64_t v = idx >= n ? n : order ? order[idx] : idx;
         const bool valid = v < n && wi < wact;
         const int64_t at = v * W + wi;
@@ -443,7 +443,7 @@ batch_pull_kernel(const int32_t *__restrict__ order, const int64_t *__restrict__
             // one bitmap claim per vertex with a new bit (the lane of its word 0)
             if (wi == 0 && ((gm >> grp) & 1ull) && fb_set(fb.next, (int32_t)v)) ++fresh;
         } else if (gm && lane == 0) {
-            const int64_t v0 = wvi * VPW;  // VPW divides 64: the wave's vertices share one bitmap word
+            const int64_t v0 = wvi * VPW;  // (id order: first is 0) VPW divides 64: the wave's vertices share one bitmap word
             const uint64_t old = atomicOr((unsigned long long *)&fb.next[v0 >> 6], (unsigned long long)(gm << (v0 & 63)));
             fresh += __popcll(gm << (v0 & 63) & ~old);
         }
@@ -931,7 +931,12 @@ static void launch_pull(khop_graph *g, BatchCtx *c, const HeavyTable &ht, int gr
                         const LevelCtl &lc, int wact, int Wr, hipStream_t st, uint64_t *V, uint64_t *F, uint64_t *Fn,
                         int fs_bits) {
     const int64_t n = g->n, nw = (n + 63) / 64;
-    const int64_t waves_needed = (n + (kWave / G) - 1) / (kWave / G);
+    // rows of two or more words: the vertices by in-degree (one-word rows: in
+    // id order), past those with no in-edge, whose rows only ever hold zeros
+    // (F and N start zero, and no hop can find such a vertex)
+    int64_t first = 0;
+    const int32_t *order = G >= 2 ? in_degree_order(g, &first) : nullptr;
+    const int64_t waves_needed = (n - first + (kWave / G) - 1) / (kWave / G);
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((waves_needed + kWavesPerBlock - 1) / kWavesPerBlock,
                                                                  (int64_t)g->cu_count * grid_per_cu));
     const FrontierBits fb = frontier_bits(c, n, L);
@@ -939,15 +944,13 @@ static void launch_pull(khop_graph *g, BatchCtx *c, const HeavyTable &ht, int gr
         ProfScope ps(g, KK_BATCH_PULL, st);
         auto k = fs_bits == 16 ? batch_pull_kernel<G, 16> : fs_bits == 32 ? batch_pull_kernel<G, 32>
                                                                            : batch_pull_kernel<G, 0>;
-        // rows of two or more words: the vertices by in-degree (one-word rows: in id order)
-        const int32_t *order = G >= 2 ? in_degree_order(g) : nullptr;
         hipLaunchKernelGGL(k, dim3(grid), dim3(kBlock), 0, st, order, g->d_in_rowptr, g->d_in_colidx, V, F,
-                           (const void *)c->Fs, Fn, n, Wr, wact, lc.act, ht.threshold, fb, lc.mode_l, lc.flag_prev,
-                           lc.flag_l, ps.units());
-        // bytes: V read and write-back and Fn write per active word, the frontier bitmap once,
+                           (const void *)c->Fs, Fn, n, Wr, wact, lc.act, ht.threshold, first, fb, lc.mode_l,
+                           lc.flag_prev, lc.flag_l, ps.units());
+        // bytes: V read and write-back and Fn write per active word of the vertices taken, the frontier bitmap once,
         // 4 per examined in-edge, 16 per scanned vertex, 8 per gathered word (fs_bits / 8 from the narrow copy)
         const double gw = fs_bits ? fs_bits / 8.0 : 8.0 * wact;
-        ps.end(3.0 * 8.0 * (double)n * wact + 2.0 * 8.0 * nw, 0, 4.0, 16.0, gw);
+        ps.end(3.0 * 8.0 * (double)(n - first) * wact + 2.0 * 8.0 * nw, 0, 4.0, 16.0, gw);
     }
     if (ht.n > 0) {
         const int hgrid = (int)std::max<int64_t>(

@@ -124,14 +124,18 @@ HeavyTable plain_heavy_table_current(khop_graph *g) {
 // A stable counting sort of the vertices by in-degree: the bottom-up batched
 // kernel gives each wave vertices of one degree, so that no lane of a wave
 // waits for a longer scan of another.
-const int32_t *in_degree_order(khop_graph *g) {
+const int32_t *in_degree_order(khop_graph *g, int64_t *zero) {
     std::lock_guard<std::mutex> lk(g->heavy_mu);
-    if (g->d_in_order || g->n == 0) return g->d_in_order;
+    if (g->d_in_order || g->n == 0) {
+        if (zero) *zero = g->in_order_zero;
+        return g->d_in_order;
+    }
     int64_t maxd = 0;
     for (int64_t v = 0; v < g->n; ++v) maxd = std::max(maxd, g->h_indeg[v]);
     std::vector<int64_t> start((size_t)maxd + 2, 0);
     for (int64_t v = 0; v < g->n; ++v) ++start[(size_t)g->h_indeg[v] + 1];
     for (size_t d = 1; d < start.size(); ++d) start[d] += start[d - 1];
+    const int64_t zero_deg = start[1];  // vertices of in-degree 0
     std::vector<int32_t> order((size_t)g->n);
     for (int64_t v = 0; v < g->n; ++v) order[(size_t)start[(size_t)g->h_indeg[v]]++] = (int32_t)v;
     int32_t *d = nullptr;
@@ -145,6 +149,8 @@ const int32_t *in_degree_order(khop_graph *g) {
         fail(KHOP_EINTERNAL, "copy of the in-degree order failed");
     }
     g->d_in_order = d;
+    g->in_order_zero = zero_deg;
+    if (zero) *zero = g->in_order_zero;
     return d;
 }
 

@@ -168,6 +168,7 @@ struct khop_graph {
     khop::HeavyTable plain_heavy;    // chunks for the plain bottom-up hop
     std::vector<khop::HeavyTable> batch_heavy;  // chunks for the batched bottom-up hops, one table per threshold
     int32_t *d_in_order = nullptr;   // vertices by ascending in-degree (ties by id), built on first use
+    int64_t in_order_zero = 0;       // how many of them have no in-edge (they come first)
     std::vector<khop::HeavyTable> heavy_retired;  // replaced tables, freed with the graph
     std::mutex heavy_mu;             // guards the tables above
     std::vector<int64_t> h_outdeg;   // host copy of out-degrees
@@ -243,8 +244,9 @@ HeavyTable batch_heavy_table(khop_graph *g, int threshold);
 HeavyTable plain_heavy_table_current(khop_graph *g);
 void heavy_tables_free(khop_graph *g);
 // The graph's vertices sorted by in-degree, ascending, ties by id (device
-// array of n ids, built on first use, freed with the tables).
-const int32_t *in_degree_order(khop_graph *g);
+// array of n ids, built on first use, freed with the tables); *zero (when not
+// null) gets the number of them with no in-edge, which come first.
+const int32_t *in_degree_order(khop_graph *g, int64_t *zero = nullptr);
 // A consistent copy of the graph's options, and their replacement (options
 // change between calls; a call runs on the copy it took when it started).
 Params params_of(khop_graph *g);
