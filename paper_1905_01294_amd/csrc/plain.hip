@@ -1110,7 +1110,7 @@ __device__ void hop_body(PlainCtl *ctl, int L, const Graph &g, const State &s, i
 struct StepBook {
     PlainCtl *ctl_marks;  // the query whose marks are counted (null: none)
     PlainCtl *ctl_fin;    // the query whose count is written (null: none)
-    PlainCtl *ctl_setup;  // the record set up for query qn (may be ctl_fin's slot: written after it)
+    PlainCtl *ctl_setup;  // the record set up for query qn (never ctl_fin's slot)
     int64_t qn;           // next query, -1 if none
     const int32_t *seeds;
     int64_t *out_count;
@@ -1146,10 +1146,24 @@ __global__ void __launch_bounds__(kBlock) plain_step_kernel(PlainCtl *ctl_last, 
                  r == 0 ? Part{b, nb_last} : Part{b - nb_last, nb_h1});
         return;
     }
-    const Part pt{b - nb_last - nb_h1, (int64_t)gridDim.x - nb_last - nb_h1};
+    // the bookkeeping blocks: the word sweep, then one block that writes the
+    // finished count and one that sets up the next query (their control
+    // slots differ, and neither touches what the sweep reads or writes)
+    const int64_t nbk = (int64_t)gridDim.x - nb_last - nb_h1, bb = b - nb_last - nb_h1;
     const int t = threadIdx.x;
-    const bool marks = bk.ctl_marks && bk.ctl_marks->last_bytes;  // not written in this launch
+    if (bb == nbk - 2) {
+        if (bk.ctl_fin && t < kWave) finalize(bk.ctl_fin);
+        return;
+    }
     const int32_t nseed = bk.qn >= 0 ? bk.seeds[bk.qn] : -1;
+    if (bb == nbk - 1) {
+        if (bk.qn >= 0)
+            setup_query(bk.ctl_setup, g, sr, nseed, bk.qn, bk.k, bk.dir_mode, bk.alpha, bk.beta, bk.push_atomic_max,
+                        bk.nnz_in, bk.out_count, bk.out_te, units);
+        return;
+    }
+    const Part pt{bb, nbk - 2};
+    const bool marks = bk.ctl_marks && bk.ctl_marks->last_bytes;  // not written in this launch
     const bool nvalid = nseed >= 0 && (int64_t)nseed < g.n;
     const int64_t nsw = nvalid ? (nseed >> 6) : -1;
     const uint64_t nsbit = nvalid ? (1ull << (nseed & 63)) : 0;
@@ -1185,15 +1199,6 @@ __global__ void __launch_bounds__(kBlock) plain_step_kernel(PlainCtl *ctl_last, 
         // the summary bytes, then the marks and visited word of each flagged word
         if (lane_id() == 0) unit_add(units, 0, 72 * flagged);
         if (pt.bid == 0 && t == 0) unit_add(units, 0, summary ? g.nw : 64 * g.nw);
-    }
-    // the last block writes the finished count, then sets up the next query
-    // (possibly in the same slot)
-    if (pt.bid == pt.nb - 1) {
-        if (bk.ctl_fin && t < kWave) finalize(bk.ctl_fin);
-        __syncthreads();
-        if (bk.qn >= 0)
-            setup_query(bk.ctl_setup, g, sr, nseed, bk.qn, bk.k, bk.dir_mode, bk.alpha, bk.beta, bk.push_atomic_max,
-                        bk.nnz_in, bk.out_count, bk.out_te, units);
     }
 }
 
@@ -1732,7 +1737,8 @@ static void plain_launch(khop_graph *g, PlainCtx *c, const Params &P, const Heav
         // (dispatch, region prefix) than the hop grid
         const int64_t last_grid = k == 2 ? std::min<int64_t>(gd.hop, 2 * (int64_t)g->cu_count) : gd.hop;
         const int64_t nb_last = ps_j.last >= 0 ? last_grid : 0, nb_h1 = ps_j.h1 >= 0 ? h1_grid : 0;
-        const int64_t nb_book = (qm >= 0 || qn >= 0) ? c->init_grid : 0;
+        // the word sweep's blocks, then the count's and the set-up's
+        const int64_t nb_book = (qm >= 0 || qn >= 0) ? c->init_grid + 2 : 0;
         {
             ProfScope ps(pg, KK_PLAIN_STEP, st);
             hipLaunchKernelGGL(plain_step_kernel, dim3((unsigned)(nb_last + nb_h1 + nb_book)), dim3(kBlock), 0, st,

@@ -17,7 +17,7 @@
 namespace khop {
 
 constexpr int kPlanStates = 3;
-constexpr int kPlanSlots = 4;
+constexpr int kPlanSlots = 5;  // so that the count written and the query set up in a step never share one
 constexpr int kPlanQueueSets = 2;
 
 // The pieces of one launch; -1 where a piece is absent.
