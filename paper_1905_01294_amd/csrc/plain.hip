@@ -935,11 +935,18 @@ __device__ void hop1_push(const Graph &g, const State &s, int64_t beg, int64_t E
 // the visited bitmap (the seed and, under a vertex mask, the vertices outside
 // it) and the new heads are counted.  A row holds no duplicate, so each head
 // is counted once with no claim, and nothing is left for a later count.
+// Without a vertex mask the visited set is the seed alone, which its row (no
+// self-loop) does not hold: the count is the seed's out-degree, and the row
+// is not read.
 __device__ void hop1_last(PlainCtl *ctl, const Graph &g, const State &s, int64_t beg, int64_t E, int64_t *units,
                           const Part &pt) {
     const int lane = lane_id();
     const int64_t nwaves = pt.nb * kWavesPerBlock;
     const int64_t wid = pt.bid * kWavesPerBlock + threadIdx.x / kWave;
+    if (!s.vmask) {
+        if (wid == 0 && lane == 0) add_tail(ctl, 0, E);
+        return;
+    }
     int64_t found = 0, edges = 0;
     for (int64_t e0 = wid * kWave; e0 < E; e0 += nwaves * kWave) {
         const int64_t e = e0 + lane;
