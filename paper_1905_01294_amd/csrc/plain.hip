@@ -18,7 +18,7 @@
 // own for set-up, and one of k >= 2 hops costs k-1 launches plus
 // compactions.
 // Bitmaps and region counters rotate over three states, control records over
-// four slots and queues over two sets.  Every cross-block hand-off happens at
+// five slots and queues over two sets.  Every cross-block hand-off happens at
 // a kernel boundary (intra-kernel release fences would write back L2 on this
 // multi-XCD part).
 //
