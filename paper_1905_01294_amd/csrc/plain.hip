@@ -433,7 +433,12 @@ __global__ void __launch_bounds__(kBlock) plain_close_kernel(PlainCtl *ctl_last,
 }
 
 // The last query's count.
-__global__ void __launch_bounds__(kWave) plain_final_kernel(PlainCtl *ctl) { finalize(ctl); }
+// Writes the last query's count (wave 0) and, when given, the count of the
+// one before it (wave 1).
+__global__ void __launch_bounds__(2 * kWave) plain_final_kernel(PlainCtl *ctl, PlainCtl *ctl_before) {
+    if (threadIdx.x < kWave) finalize(ctl);
+    else if (ctl_before) finalize(ctl_before);
+}
 
 // ------------------------------------------------------------------ top-down
 
@@ -1773,16 +1778,19 @@ static void plain_launch(khop_graph *g, PlainCtx *c, const Params &P, const Heav
             ps.end(0, 1);
         }
     }
-    // the last query's marks and the count of the one before it, then the last count
-    {
-        const PlainStep cl = plain_plan_close(m);
+    // the last query's marks and the count of the one before it, then the last
+    // count.  A run of k = 1 leaves no marks (its only hop counts as it goes),
+    // so its last two counts are both written by the final launch.
+    const PlainStep cl = plain_plan_close(m);
+    if (k >= 2) {
         ProfScope ps(pg, KK_PLAIN_INIT, st);
         hipLaunchKernelGGL(plain_close_kernel, dim3(c->init_grid), dim3(kBlock), 0, st, slot(cl.marks),
                            cl.fin >= 0 ? slot(cl.fin) : nullptr, (int)(cl.fin >= 0), gr, state(cl.marks),
                            ps.units());
         ps.end(0, 1);
     }
-    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(kWave), 0, st, slot(m - 1));
+    hipLaunchKernelGGL(plain_final_kernel, dim3(1), dim3(2 * kWave), 0, st, slot(m - 1),
+                       k < 2 && cl.fin >= 0 ? slot(cl.fin) : nullptr);
     KHOP_HIP(hipGetLastError());
 }
 

@@ -44,7 +44,9 @@ inline PlainStep plain_plan_step(int32_t k, int64_t m, int64_t j) {
 }
 
 // The close launch after the last step: the last query's marks and the
-// count of the one before it.  (The final launch writes query m-1's count.)
+// count of the one before it.  (The final launch writes query m-1's count; a
+// run of k = 1, which leaves no marks, has no close launch, and its final
+// launch writes both counts.)
 inline PlainStep plain_plan_close(int64_t m) {
     return PlainStep{-1, -1, m - 1, m >= 2 ? m - 2 : -1, -1};
 }
