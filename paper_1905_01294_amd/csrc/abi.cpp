@@ -26,7 +26,7 @@ void hip_fail(hipError_t e, const char *what, const char *file, int line) {
 
 const char *const kKernelNames[KK_COUNT_KINDS] = {
     "plain_init", "plain_step", "plain_hop_push", "plain_hop_pull", "plain_compact", "batch_init", "batch_push",
-    "batch_pull", "batch_pull_heavy", "batch_count", "plain_set", "empty_launch"};
+    "batch_pull", "batch_pull_heavy", "batch_count", "plain_set", "plain_degree", "empty_launch"};
 
 template <class F>
 static int guard(F &&f) {

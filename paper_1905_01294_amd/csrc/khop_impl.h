@@ -95,6 +95,7 @@ enum KernelKind {
     KK_BATCH_PULL_HEAVY,
     KK_BATCH_COUNT,
     KK_PLAIN_SET,     // the three kernels that list one neighborhood as ids, timed together
+    KK_PLAIN_DEGREE,  // a one-hop query with no vertex mask: one launch that reads its seed's degree
     KK_EMPTY_LAUNCH,  // an empty kernel timed the same way: the event bracket's own cost
     KK_COUNT_KINDS
 };

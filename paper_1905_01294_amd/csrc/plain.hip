@@ -433,6 +433,21 @@ __global__ void __launch_bounds__(kBlock) plain_close_kernel(PlainCtl *ctl_last,
 }
 
 // The last query's count.
+// A one-hop query with no vertex mask, as one launch of its own: its visited
+// set is the seed alone, which a row (no self-loop, no duplicate) does not
+// hold, so every out-neighbor is new and the count is the out-degree (which
+// is also the edges it traverses).  An invalid seed gets -1.
+__global__ void __launch_bounds__(kWave) plain_degree_kernel(const int32_t *seeds, int64_t i,
+                                                            const int64_t *__restrict__ rowptr, int64_t n,
+                                                            int64_t *counts, int64_t *te) {
+    if (threadIdx.x != 0) return;
+    const int32_t seed = seeds[i];
+    const bool valid = seed >= 0 && (int64_t)seed < n;
+    const int64_t d = valid ? rowptr[seed + 1] - rowptr[seed] : -1;
+    counts[i] = d;
+    if (te) te[i] = d;
+}
+
 // Writes the last query's count (wave 0) and, when given, the count of the
 // one before it (wave 1).
 __global__ void __launch_bounds__(2 * kWave) plain_final_kernel(PlainCtl *ctl, PlainCtl *ctl_before) {
@@ -1712,6 +1727,18 @@ static void plain_launch(khop_graph *g, PlainCtx *c, const Params &P, const Heav
     if (k > kDeepHops) {
         // no search goes deeper than n - 1 hops: a larger k counts the same
         plain_deep(g, c, P, gr, hc, gd, d_seeds, num_seeds, std::min<int64_t>(k, g->n), d_counts, d_te, st, d_vmask);
+        return;
+    }
+    if (k == 1 && !d_vmask && P.dir_mode == KHOP_DIR_AUTO) {
+        // one-hop queries, each one launch that reads its seed's degree (a
+        // forced direction runs the hop itself)
+        for (int64_t i = 0; i < num_seeds; ++i) {
+            ProfScope ps(pg, KK_PLAIN_DEGREE, st);
+            hipLaunchKernelGGL(plain_degree_kernel, dim3(1), dim3(kWave), 0, st, d_seeds, i, g->d_rowptr, g->n,
+                               d_counts, d_te);
+            ps.end(4.0 + 16.0 + 8.0 * (d_te ? 2 : 1));
+        }
+        KHOP_HIP(hipGetLastError());
         return;
     }
     if (!P.plain_pipeline && num_seeds > 1) {

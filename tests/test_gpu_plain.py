@@ -150,14 +150,18 @@ def test_edge_cases(K):
     g.free()
 
 
-def test_device_path_marks_bad_seed(K):
+@pytest.mark.parametrize("k", [1, 2])
+def test_device_path_marks_bad_seed(K, k):
     import torch
     g = K.Graph(np.array([0], np.int32), np.array([1], np.int32), 3)
     d_s = torch.tensor([0, 7, 1, -1], dtype=torch.int32, device="cuda")
     d_c = torch.zeros(4, dtype=torch.int64, device="cuda")
-    g.count_dev(d_s, 2, d_c)
+    d_t = torch.zeros(4, dtype=torch.int64, device="cuda")
+    g.count_dev(d_s, k, d_c, d_t)
     torch.cuda.synchronize()
     assert d_c.cpu().tolist() == [1, -1, 1, -1]
+    # traversed edges: the out-degrees of levels 0 .. k-1 (one each here)
+    assert d_t.cpu().tolist() == [k, -1, k, -1]
     g.free()
 
 
@@ -376,6 +380,13 @@ def test_profile_reports_kernels_and_event_cost(K, g0, g0_gpu, g0_oracle):
     assert "plain_hop_push" not in stats and "plain_hop_pull" not in stats
     assert stats["batch_pull"]["launches"] >= 2 and stats["batch_pull"]["algorithmic_bytes"] > 0
     assert "batch_count" in stats and "batch_push" in stats
+    # k = 1, no vertex mask: one degree launch per query and no step launch
+    g0_gpu.profile(True)
+    c1 = g0_gpu.count(seeds, 1)
+    s1 = g0_gpu.profile_read()
+    g0_gpu.profile(False)
+    assert np.array_equal(c1, g0_oracle.count(seeds, 1)[0])
+    assert s1["plain_degree"]["launches"] == 16 and "plain_step" not in s1
     # k = 3: hop 2 runs on its own, counted by the direction it took; forced bottom-up, all pull
     for mode, kind in ((K.KHOP_DIR_PUSH, "plain_hop_push"), (K.KHOP_DIR_PULL, "plain_hop_pull")):
         g0_gpu.set_option(K.KHOP_OPT_DIRECTION, mode)
