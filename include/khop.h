@@ -112,7 +112,10 @@ int khop_count(khop_graph *g, const int32_t *seeds, int64_t num_seeds, int32_t k
  * The caller synchronises the stream before reading the outputs.  The seeds
  * are answered in order, and consecutive queries overlap by one launch (the
  * last hop of one runs beside hop 1 of the next) unless the option
- * KHOP_OPT_PLAIN_PIPELINE is 0.  With k > 32 the queries run one at a time
+ * KHOP_OPT_PLAIN_PIPELINE is 0.  With k = 1 and no forced direction each
+ * query is one launch that reads its seed's out-degree: a row holds no
+ * self-loop or duplicate, so that is its one-hop count (and its traversed
+ * edges).  With k > 32 the queries run one at a time
  * as searches whose hops are launched in groups, and the call waits on the
  * stream between groups to learn whether the frontier has emptied (a query
  * never runs more hops than its search has levels, so any k is cheap).
@@ -274,9 +277,8 @@ enum khop_option {
     KHOP_OPT_PLAIN_GRAPHS = 13  /* 0 (default): every plain run launches its kernels directly; 1: a run
                                    repeated with the same device pointers, sizes and settings replays its
                                    launch sequence, captured as a HIP graph the second time it is seen (it
-                                   pays for long runs of shallow queries: 3.3 instead of 3.8 us per k = 1
-                                   query on R-MAT scale 21; a graph launch's own cost outweighs it for
-                                   short runs) */
+                                   can pay for long runs of shallow queries, whose launches are short; a
+                                   graph launch's own cost outweighs it for short runs) */
 };
 enum { KHOP_DIR_AUTO = 0, KHOP_DIR_PUSH = 1, KHOP_DIR_PULL = 2 };
 
