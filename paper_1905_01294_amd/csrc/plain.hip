@@ -7,9 +7,10 @@
 // neighbors are new (a row has no duplicate and no self-loop), so hop 1
 // needs no claims unless the seed has more than 64 neighbors per region (it
 // queues them 64 to a region), and as a last hop it counts them straight
-// from the seed's row.  A later last hop only counts: bottom-up it counts
-// its finds, top-down it marks bytes that a later launch counts.  So no last
-// hop needs a compaction.
+// from the seed's row (with no vertex mask, a one-hop query is a single
+// launch that reads its seed's degree).  A later last hop only counts:
+// bottom-up it counts its finds, top-down it marks bytes that a later launch
+// counts.  So no last hop needs a compaction.
 // Consecutive queries are pipelined.  A step launch runs the last hop of
 // query i-1 and hop 1 of query i side by side on separate blocks, and on a
 // third set of blocks counts the byte marks an earlier query's last hop left,
@@ -39,8 +40,9 @@
 //      atomics) and the compaction kernel turns the marks into frontier words
 //      with ballots;
 //      bottom-up (pull): one wave per 64-vertex word, each unvisited vertex
-//      scans its in-neighbors against the frontier bitmap and stops at the
-//      first hit; the ballot of hits is the word's new frontier bits.
+//      tests its probe in-neighbor (largest out-degree), then scans its other
+//      in-neighbors against the frontier bitmap and stops at the first hit;
+//      the ballot of hits is the word's new frontier bits.
 //      In-edges of vertices above the heavy threshold are split into chunks
 //      that any wave may scan.
 // Block 0 keeps the running count and traversed-edge sum.  Within a query,
@@ -432,7 +434,6 @@ __global__ void __launch_bounds__(kBlock) plain_close_kernel(PlainCtl *ctl_last,
     if (blockIdx.x == 0 && threadIdx.x < kWave && fin_before) finalize(ctl_before);
 }
 
-// The last query's count.
 // A one-hop query with no vertex mask, as one launch of its own: its visited
 // set is the seed alone, which a row (no self-loop, no duplicate) does not
 // hold, so every out-neighbor is new and the count is the out-degree (which
